@@ -1,0 +1,86 @@
+"""Pins for the oracle's backward (gradient of y = x[argmed] w.r.t. x).
+
+  * the hand-derived case in tests/golden/hand_cases.json,
+  * integer-valued upstream gradients: every partial sum is exact, so the
+    result must equal an exact integer bincount,
+  * a dense Jacobian (one 1 per output row, at the brute-force argmed)
+    transposed times the upstream gradient,
+  * central finite differences of L(x) = sum_o g_o y_o(x), evaluated in
+    float64 through the forward oracle, on inputs whose close neighbours
+    differ by more than twice the step (so the step never changes the
+    order of the window items).
+"""
+import json
+import os
+
+import numpy as np
+
+import oracle
+from tests.brute import rank_count_argmed
+from paper_1406_1717_amd import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_cases.json")
+
+
+def test_hand_case_backward():
+    data = json.load(open(GOLDEN))
+    cases = {c["name"]: c for c in data["cases"]}
+    for b in data["backward"]:
+        c = cases[b["case"]]
+        x = np.array([int(v) for v in c["x"]], dtype=np.int32)
+        _, a = oracle.sortmedian(x, c["k"])
+        g32, g64 = oracle.backward(np.array(b["grad_y"], np.float32), a, len(x), c["k"])
+        assert np.array_equal(g32, np.array(b["grad_x"], np.float32))
+
+
+def test_integer_gradients_exact():
+    rng = np.random.default_rng(21)
+    for k in (1, 3, 31, 201):
+        n = 20_000
+        x = rng.integers(0, 50, n).astype(np.float32)
+        _, a = oracle.sortmedian(x, k)
+        g = rng.integers(-1000, 1000, n - k + 1)
+        g32, g64 = oracle.backward(g.astype(np.float32), a, n, k)
+        exact = np.zeros(n, dtype=np.int64)
+        np.add.at(exact, a, g)
+        assert np.array_equal(g64, exact.astype(np.float64))
+        assert np.array_equal(g32, exact.astype(np.float32))
+
+
+def test_dense_jacobian():
+    rng = np.random.default_rng(22)
+    for k in (3, 9, 31):
+        n = 400
+        x = rng.integers(0, 12, n).astype(np.float32)
+        am = rank_count_argmed(x, k)
+        J = np.zeros((n - k + 1, n))
+        J[np.arange(n - k + 1), am] = 1.0
+        g = rng.standard_normal(n - k + 1).astype(np.float32)
+        ref = J.T @ g.astype(np.float64)
+        _, a = oracle.sortmedian(x, k)
+        _, g64 = oracle.backward(g, a, n, k)
+        np.testing.assert_allclose(g64, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_finite_differences_fd_slice():
+    """4096-long slice, k = 31, step 1e-3 (the differentiable workload's
+    finite-difference check), divided by the step actually taken in float32."""
+    k, n, eps = 31, 4096, 1e-3
+    x = workloads.distinct_rows(1, n, workloads.SEEDS["fd_slice"], min_gap=2.5 * eps, window=k)[0]
+    g = workloads.normal_f32(n - k + 1, workloads.SEEDS["fd_slice"] + 1000)
+    _, a = oracle.sortmedian(x, k)
+    _, g64 = oracle.backward(g, a, n, k)
+
+    def L(v):
+        y, _ = oracle.sortmedian(v, k)
+        return float(np.dot(g.astype(np.float64), y.astype(np.float64)))
+
+    rng = np.random.default_rng(23)
+    probe = np.concatenate([rng.choice(n, 150, replace=False), np.unique(a)[:50]])
+    for j in probe:
+        xp = x.copy()
+        xm = x.copy()
+        xp[j] = np.float32(x[j] + eps)
+        xm[j] = np.float32(x[j] - eps)
+        fd = (L(xp) - L(xm)) / (float(xp[j]) - float(xm[j]))
+        assert abs(fd - g64[j]) <= 1e-4 * (1 + abs(fd)), (j, fd, g64[j])
