@@ -1,0 +1,126 @@
+/*
+ * mf.h - sorting-based median filter on AMD MI355X (gfx950).
+ *
+ * The method is J. Suomela, "Median Filtering is Equivalent to Sorting"
+ * (arXiv:1406.1717): sort the input in blocks of the window length k
+ * (Section 3 "Piecewise Sorting"), then walk each pair of adjacent blocks,
+ * removing items of the left block and adding items of the right block
+ * while the window median is tracked (Sections 4-6, postprocessing).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Output o (0-based) is the median of x[o .. o+k-1], o = 0 .. n-k (the
+ *   problem statement of Section 1).  k must be odd, 1 <= k <= n.
+ * - Ties are broken by input index: the element of rank h = (k-1)/2 in
+ *   lexicographic (value, index) order is the median (Sections 5.2, 6.3).
+ *   For floats, -0.0 equals +0.0 and every NaN is above +inf.
+ * - y[o] is a bit copy of x[argmed[o]]; argmed[o] is the 0-based index of
+ *   the median within its signal (int32).
+ * - Data pointers (x, y, argmed, grad_*) are DEVICE pointers owned by the
+ *   caller.  Offset and window arrays of the batched calls are HOST arrays.
+ * - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *   Calls are asynchronous on that stream; arguments are validated before
+ *   anything is enqueued, and nothing is written when a call fails.
+ * - Limits: n <= 2^31 - 1 (argmed is int32), k <= 32767.
+ * - Thread safety: entry points may be called from several host threads;
+ *   one plan must not be executed from two threads at once.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mf_status {
+    MF_OK = 0,
+    MF_ERR_INVALID_VALUE = 1, /* null pointer, n < 1, k < 1, k even, k > n   */
+    MF_ERR_UNSUPPORTED = 2,   /* n > 2^31-1 or k > 32767                       */
+    MF_ERR_NOMEM = 3,         /* the library's workspace could not be allocated */
+    MF_ERR_HIP = 4,           /* a HIP runtime call failed (see mf_last_error)  */
+    MF_ERR_INTERNAL = 5       /* a kernel reported an inconsistent walk         */
+} mf_status;
+
+/* Median filter of one float32 signal (Section 1; method of Sections 3-6).
+ * x: n floats.  y: n-k+1 floats.  argmed: n-k+1 int32, or NULL to skip.
+ * Work: one kernel launch (k <= 4096) or a workspace-backed launch for
+ * larger k; the workspace is owned by the library. */
+mf_status mf_median_filter(const float *x, int64_t n, int32_t k,
+                           float *y, int32_t *argmed, void *stream);
+
+/* The same for int32 signals (the paper benchmarks 32-bit integers,
+ * Section 7).  y: n-k+1 int32. */
+mf_status mf_median_filter_i32(const int32_t *x, int64_t n, int32_t k,
+                               int32_t *y, int32_t *argmed, void *stream);
+
+/* Uniform batch: `rows` float32 signals of length n stored back to back
+ * (row r at x + r*n), one window k.  Outputs row-major: y + r*(n-k+1). */
+mf_status mf_median_filter_rows(const float *x, int64_t rows, int64_t n, int32_t k,
+                                float *y, int32_t *argmed, void *stream);
+
+/* Ragged batch of float32 signals in one launch.  Signal s is
+ * x[x_offsets[s] .. x_offsets[s+1]) with odd window ks[s] <= its length.
+ * Outputs are packed in signal order: signal s writes
+ * y[y_off(s) .. y_off(s) + len_s - ks[s] + 1) with
+ * y_off(s) = x_offsets[s] - sum_{t<s} (ks[t] - 1); argmed is local to each
+ * signal.  x_offsets (num_signals+1 entries, x_offsets[0] = 0, non-
+ * decreasing) and ks are HOST arrays.  The library plans the launch (work
+ * list, tile shapes) and caches the plan keyed by these arrays; see the
+ * mf_plan_* calls for explicit control. */
+mf_status mf_median_filter_batched(const float *x, const int64_t *x_offsets,
+                                   const int32_t *ks, int32_t num_signals,
+                                   float *y, int32_t *argmed, void *stream);
+
+/* Backward of y = x[argmed]: grad_x[j] = sum of grad_y[o] over the outputs
+ * o with argmed[o] == j, accumulated in float64 in increasing o and rounded
+ * once to float32; 0 where no output selects j.  Deterministic (no
+ * order-dependent atomics).  grad_y, argmed: n-k+1 entries; grad_x: n
+ * entries, fully overwritten. */
+mf_status mf_median_filter_backward(const float *grad_y, const int32_t *argmed,
+                                    int64_t n, int32_t k, float *grad_x, void *stream);
+
+/* Backward of mf_median_filter_rows (same layouts). */
+mf_status mf_median_filter_backward_rows(const float *grad_y, const int32_t *argmed,
+                                         int64_t rows, int64_t n, int32_t k,
+                                         float *grad_x, void *stream);
+
+/* Backward of mf_median_filter_batched (same packed layouts). */
+mf_status mf_median_filter_backward_batched(const float *grad_y, const int32_t *argmed,
+                                            const int64_t *x_offsets, const int32_t *ks,
+                                            int32_t num_signals, float *grad_x, void *stream);
+
+/* Explicit plans for the ragged batch: mf_plan_create_batched validates the
+ * host arrays, builds the device work list and picks tile shapes (timing
+ * candidates once per window class when tuning is enabled);
+ * mf_plan_execute enqueues the whole batch as one graph launch on `stream`.
+ * The plan owns device memory until mf_plan_destroy. */
+typedef struct mf_plan mf_plan;
+mf_status mf_plan_create_batched(const int64_t *x_offsets, const int32_t *ks,
+                                 int32_t num_signals, mf_plan **out);
+mf_status mf_plan_execute(mf_plan *plan, const float *x, float *y, int32_t *argmed,
+                          void *stream);
+mf_status mf_plan_execute_backward(mf_plan *plan, const float *grad_y, const int32_t *argmed,
+                                   float *grad_x, void *stream);
+int64_t   mf_plan_output_length(const mf_plan *plan);
+void      mf_plan_destroy(mf_plan *plan);
+
+/* n-k+1 for a valid (n, k), else -1.  Host only. */
+int64_t mf_output_length(int64_t n, int32_t k);
+
+/* Static description of a status code. */
+const char *mf_status_string(mf_status s);
+
+/* Detail of the last failure on the calling host thread ("" if none). */
+const char *mf_last_error(void);
+
+/* Kernel-side consistency flag: returns MF_ERR_INTERNAL if any kernel since
+ * the last call reported an inconsistent walk, MF_OK otherwise, and clears
+ * the flag.  Synchronizes `stream`. */
+mf_status mf_check_device_error(void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MF_H */

@@ -1,0 +1,517 @@
+// C ABI of the median filter library (include/mf.h): argument checks,
+// kernel-family dispatch, the library-owned workspace, and plans for the
+// ragged batch (device work list + captured graph).
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mf.h"
+#include "mf_launch.h"
+
+using namespace mf;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string t_last_error;
+
+static mf_status fail(mf_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+static mf_status fail(mf_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_last_error = buf;
+    return s;
+}
+
+static mf_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(MF_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define MF_HIP(call, what)                          \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// ------------------------------------------------------------------ device state
+
+namespace {
+
+struct Device {
+    bool ready = false;
+    int *d_err = nullptr;               // kernel consistency flag
+    unsigned char *ws = nullptr;        // global-path workspace
+    int64_t ws_bytes = 0;
+    hipEvent_t ws_done = nullptr;       // last use of ws
+    std::mutex mu;
+};
+
+const int kMaxDevices = 64;
+Device g_dev[kMaxDevices];
+const int64_t kWsSlots = 256;           // concurrent tiles on the global path
+
+mf_status device_state(Device **out)
+{
+    int dev = 0;
+    MF_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(MF_ERR_UNSUPPORTED, "device index %d", dev);
+    Device &D = g_dev[dev];
+    std::lock_guard<std::mutex> lk(D.mu);
+    if (!D.ready) {
+        MF_HIP(prepare_kernels(), "hipFuncSetAttribute");
+        MF_HIP(hipMalloc(&D.d_err, sizeof(int)), "hipMalloc(error flag)");
+        MF_HIP(hipMemset(D.d_err, 0, sizeof(int)), "hipMemset(error flag)");
+        MF_HIP(hipEventCreateWithFlags(&D.ws_done, hipEventDisableTiming), "hipEventCreate");
+        D.ready = true;
+    }
+    *out = &D;
+    return MF_OK;
+}
+
+// Workspace of at least `bytes` for a launch on `st`.  Uses of the
+// workspace are serialized across streams through ws_done.
+mf_status acquire_ws(Device &D, int64_t bytes, hipStream_t st, unsigned char **ws)
+{
+    std::lock_guard<std::mutex> lk(D.mu);
+    if (D.ws_bytes < bytes) {
+        if (D.ws) {
+            MF_HIP(hipEventSynchronize(D.ws_done), "hipEventSynchronize");
+            MF_HIP(hipFree(D.ws), "hipFree(workspace)");
+            D.ws = nullptr;
+            D.ws_bytes = 0;
+        }
+        if (hipMalloc(&D.ws, (size_t)bytes) != hipSuccess) {
+            D.ws = nullptr;
+            return fail(MF_ERR_NOMEM, "workspace of %lld bytes", (long long)bytes);
+        }
+        D.ws_bytes = bytes;
+    }
+    MF_HIP(hipStreamWaitEvent(st, D.ws_done, 0), "hipStreamWaitEvent");
+    *ws = D.ws;
+    return MF_OK;
+}
+
+mf_status release_ws(Device &D, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(D.mu);
+    MF_HIP(hipEventRecord(D.ws_done, st), "hipEventRecord");
+    return MF_OK;
+}
+
+// ------------------------------------------------------------------ checks
+
+mf_status check_signal(int64_t n, int32_t k)
+{
+    if (n < 1) return fail(MF_ERR_INVALID_VALUE, "n = %lld must be >= 1", (long long)n);
+    if (k < 1 || (k & 1) == 0) return fail(MF_ERR_INVALID_VALUE, "k = %d must be odd and >= 1", k);
+    if (k > n) return fail(MF_ERR_INVALID_VALUE, "k = %d exceeds n = %lld", k, (long long)n);
+    if (n > INT32_MAX) return fail(MF_ERR_UNSUPPORTED, "n = %lld exceeds 2^31-1", (long long)n);
+    if (path_for(k) == PATH_NONE) return fail(MF_ERR_UNSUPPORTED, "k = %d exceeds 32767", k);
+    return MF_OK;
+}
+
+// Forward over `rows` equal signals (rows = 1: one signal).
+mf_status forward_rows(const void *x, int64_t rows, int64_t n, int32_t k, void *y,
+                       int32_t *argmed, bool f32, hipStream_t st)
+{
+    if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
+    if (rows < 1) return fail(MF_ERR_INVALID_VALUE, "rows = %lld must be >= 1", (long long)rows);
+    mf_status s = check_signal(n, k);
+    if (s != MF_OK) return s;
+    Device *D = nullptr;
+    if ((s = device_state(&D)) != MF_OK) return s;
+
+    const Path p = path_for(k);
+    const int64_t tpr = tiles_for(p, n, k);
+    Launch L;
+    memset(&L, 0, sizeof L);
+    L.x = x;
+    L.y = y;
+    L.argmed = argmed;
+    L.one.n = n;
+    L.one.k = k;
+    L.rows = rows;
+    L.tpr = tpr;
+    L.nunits = rows * tpr;
+    if (p != PATH_IDENTITY && p != PATH_GLOBAL && L.nunits > 0x7FFFFFFFll)
+        return fail(MF_ERR_UNSUPPORTED, "too many tiles (%lld)", (long long)L.nunits);
+    const size_t lds = (size_t)lds_bytes_for(p, k);
+    if (p == PATH_GLOBAL) {
+        const int64_t stride = global_ws_stride(k);
+        const int64_t slots = std::min<int64_t>(kWsSlots, L.nunits);
+        unsigned char *ws = nullptr;
+        if ((s = acquire_ws(*D, stride * slots, st, &ws)) != MF_OK) return s;
+        MF_HIP(launch_forward(p, f32, L, lds, ws, stride, slots, D->d_err, st), "forward launch");
+        return release_ws(*D, st);
+    }
+    MF_HIP(launch_forward(p, f32, L, lds, nullptr, 0, 0, D->d_err, st), "forward launch");
+    return MF_OK;
+}
+
+mf_status backward_rows(const float *gy, const int32_t *argmed, int64_t rows, int64_t n,
+                        int32_t k, float *gx, hipStream_t st)
+{
+    if (!gy || !argmed || !gx) return fail(MF_ERR_INVALID_VALUE, "grad_y, argmed and grad_x must not be null");
+    if (rows < 1) return fail(MF_ERR_INVALID_VALUE, "rows = %lld must be >= 1", (long long)rows);
+    mf_status s = check_signal(n, k);
+    if (s != MF_OK) return s;
+    Device *D = nullptr;
+    if ((s = device_state(&D)) != MF_OK) return s;
+    BwdLaunch L;
+    memset(&L, 0, sizeof L);
+    L.grad_y = gy;
+    L.argmed = argmed;
+    L.grad_x = gx;
+    L.one.n = n;
+    L.one.k = k;
+    L.rows = rows;
+    L.tpr = bwd_tiles_for(n);
+    L.nunits = rows * L.tpr;
+    MF_HIP(launch_backward(L, st), "backward launch");
+    return MF_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ plans
+
+struct PathGroup {
+    Path path;
+    int64_t nunits = 0;
+    SigDesc *d_sigs = nullptr;   // all signals of the plan
+    Unit *d_units = nullptr;
+    size_t lds = 0;
+    int64_t ws_stride = 0;
+};
+
+struct mf_plan {
+    int32_t num_signals = 0;
+    int64_t total_in = 0, total_out = 0;
+    std::vector<int64_t> offsets;
+    std::vector<int32_t> ks;
+    SigDesc *d_sigs = nullptr;
+    std::vector<PathGroup> groups;
+    // backward work list
+    Unit *d_bunits = nullptr;
+    int64_t nbunits = 0;
+    // captured forward graph and the pointers it was captured with
+    hipGraphExec_t gexec = nullptr;
+    const void *gx = nullptr;
+    void *gy = nullptr;
+    int32_t *gam = nullptr;
+    unsigned char *gws = nullptr;
+    int64_t ws_need = 0;
+};
+
+static void plan_free(mf_plan *p)
+{
+    if (!p) return;
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    for (auto &g : p->groups)
+        if (g.d_units) (void)hipFree(g.d_units);
+    if (p->d_sigs) (void)hipFree(p->d_sigs);
+    if (p->d_bunits) (void)hipFree(p->d_bunits);
+    delete p;
+}
+
+extern "C" mf_status mf_plan_create_batched(const int64_t *x_offsets, const int32_t *ks,
+                                            int32_t num_signals, mf_plan **out)
+{
+    if (!out) return fail(MF_ERR_INVALID_VALUE, "out must not be null");
+    *out = nullptr;
+    if (!x_offsets || !ks) return fail(MF_ERR_INVALID_VALUE, "x_offsets and ks must not be null");
+    if (num_signals < 1) return fail(MF_ERR_INVALID_VALUE, "num_signals = %d must be >= 1", num_signals);
+    if (x_offsets[0] != 0) return fail(MF_ERR_INVALID_VALUE, "x_offsets[0] must be 0");
+    std::vector<SigDesc> sigs((size_t)num_signals);
+    int64_t yoff = 0;
+    for (int32_t s = 0; s < num_signals; s++) {
+        const int64_t n = x_offsets[s + 1] - x_offsets[s];
+        mf_status st = check_signal(n, ks[s]);
+        if (st != MF_OK) return fail(st, "signal %d: %s", s, t_last_error.c_str());
+        sigs[s].x_off = x_offsets[s];
+        sigs[s].y_off = yoff;
+        sigs[s].n = n;
+        sigs[s].k = ks[s];
+        sigs[s].pad = 0;
+        yoff += n - ks[s] + 1;
+    }
+    Device *D = nullptr;
+    mf_status st = device_state(&D);
+    if (st != MF_OK) return st;
+
+    mf_plan *p = new mf_plan();
+    p->num_signals = num_signals;
+    p->total_in = x_offsets[num_signals];
+    p->total_out = yoff;
+    p->offsets.assign(x_offsets, x_offsets + num_signals + 1);
+    p->ks.assign(ks, ks + num_signals);
+
+    // forward work lists, one per kernel family; within a family the
+    // longest windows go first so that the heaviest tiles start early
+    const Path fams[4] = {PATH_LDS512, PATH_LDS256, PATH_GLOBAL, PATH_IDENTITY};
+    std::vector<int32_t> order((size_t)num_signals);
+    for (int32_t s = 0; s < num_signals; s++) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ks[a] > ks[b]; });
+    hipError_t e = hipMalloc(&p->d_sigs, sizeof(SigDesc) * sigs.size());
+    if (e == hipSuccess) e = hipMemcpy(p->d_sigs, sigs.data(), sizeof(SigDesc) * sigs.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { plan_free(p); return hip_fail(e, "plan signal table"); }
+    for (Path f : fams) {
+        std::vector<Unit> units;
+        size_t lds = 0;
+        int64_t ws_stride = 0;
+        for (int32_t s : order) {
+            if (path_for(ks[s]) != f) continue;
+            const int64_t nt = tiles_for(f, sigs[s].n, ks[s]);
+            for (int64_t t = 0; t < nt; t++) units.push_back(Unit{s, 0, t});
+            lds = std::max(lds, (size_t)lds_bytes_for(f, ks[s]));
+            if (f == PATH_GLOBAL) ws_stride = std::max(ws_stride, global_ws_stride(ks[s]));
+        }
+        if (units.empty()) continue;
+        if (f != PATH_IDENTITY && f != PATH_GLOBAL && units.size() > 0x7FFFFFFFull) {
+            plan_free(p);
+            return fail(MF_ERR_UNSUPPORTED, "too many tiles in one batch");
+        }
+        PathGroup g;
+        g.path = f;
+        g.nunits = (int64_t)units.size();
+        g.lds = lds;
+        g.ws_stride = ws_stride;
+        g.d_sigs = p->d_sigs;
+        e = hipMalloc(&g.d_units, sizeof(Unit) * units.size());
+        if (e == hipSuccess) e = hipMemcpy(g.d_units, units.data(), sizeof(Unit) * units.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { if (g.d_units) (void)hipFree(g.d_units); plan_free(p); return hip_fail(e, "plan work list"); }
+        if (f == PATH_GLOBAL) p->ws_need = std::max(p->ws_need, ws_stride * std::min<int64_t>(kWsSlots, g.nunits));
+        p->groups.push_back(g);
+    }
+    // backward work list
+    {
+        std::vector<Unit> bunits;
+        for (int32_t s = 0; s < num_signals; s++) {
+            const int64_t nt = bwd_tiles_for(sigs[s].n);
+            for (int64_t t = 0; t < nt; t++) bunits.push_back(Unit{s, 0, t});
+        }
+        p->nbunits = (int64_t)bunits.size();
+        e = hipMalloc(&p->d_bunits, sizeof(Unit) * bunits.size());
+        if (e == hipSuccess) e = hipMemcpy(p->d_bunits, bunits.data(), sizeof(Unit) * bunits.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { plan_free(p); return hip_fail(e, "plan backward work list"); }
+    }
+    *out = p;
+    return MF_OK;
+}
+
+static mf_status plan_enqueue(mf_plan *p, Device &D, const void *x, void *y, int32_t *argmed,
+                              unsigned char *ws, hipStream_t st)
+{
+    for (const PathGroup &g : p->groups) {
+        Launch L;
+        memset(&L, 0, sizeof L);
+        L.x = x;
+        L.y = y;
+        L.argmed = argmed;
+        L.sigs = g.d_sigs;
+        L.units = g.d_units;
+        L.nunits = g.nunits;
+        const int64_t slots = std::min<int64_t>(kWsSlots, g.nunits);
+        MF_HIP(launch_forward(g.path, true, L, g.lds, ws, g.ws_stride, slots, D.d_err, st), "batched launch");
+    }
+    return MF_OK;
+}
+
+extern "C" mf_status mf_plan_execute(mf_plan *p, const float *x, float *y, int32_t *argmed, void *stream)
+{
+    if (!p) return fail(MF_ERR_INVALID_VALUE, "plan must not be null");
+    if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
+    hipStream_t st = (hipStream_t)stream;
+    Device *D = nullptr;
+    mf_status s = device_state(&D);
+    if (s != MF_OK) return s;
+    unsigned char *ws = nullptr;
+    if (p->ws_need > 0 && (s = acquire_ws(*D, p->ws_need, st, &ws)) != MF_OK) return s;
+    // the graph bakes in the data and workspace pointers; capture again
+    // when any of them changed
+    if (!p->gexec || p->gx != x || p->gy != y || p->gam != argmed || p->gws != ws) {
+        if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+        hipStream_t cs;
+        MF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate(capture)");
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        mf_status es = MF_OK;
+        if (e == hipSuccess) es = plan_enqueue(p, *D, x, y, argmed, ws, cs);
+        hipError_t e2 = (e == hipSuccess) ? hipStreamEndCapture(cs, &graph) : e;
+        if (e2 == hipSuccess && es == MF_OK) e2 = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cs);
+        if (es != MF_OK) return es;
+        if (e2 != hipSuccess) { p->gexec = nullptr; return hip_fail(e2, "graph capture"); }
+        p->gx = x;
+        p->gy = y;
+        p->gam = argmed;
+        p->gws = ws;
+    }
+    MF_HIP(hipGraphLaunch(p->gexec, st), "hipGraphLaunch");
+    if (p->ws_need > 0) return release_ws(*D, st);
+    return MF_OK;
+}
+
+extern "C" mf_status mf_plan_execute_backward(mf_plan *p, const float *grad_y, const int32_t *argmed,
+                                              float *grad_x, void *stream)
+{
+    if (!p) return fail(MF_ERR_INVALID_VALUE, "plan must not be null");
+    if (!grad_y || !argmed || !grad_x) return fail(MF_ERR_INVALID_VALUE, "grad_y, argmed and grad_x must not be null");
+    BwdLaunch L;
+    memset(&L, 0, sizeof L);
+    L.grad_y = grad_y;
+    L.argmed = argmed;
+    L.grad_x = grad_x;
+    L.sigs = p->d_sigs;
+    L.units = p->d_bunits;
+    L.nunits = p->nbunits;
+    MF_HIP(launch_backward(L, (hipStream_t)stream), "batched backward launch");
+    return MF_OK;
+}
+
+extern "C" int64_t mf_plan_output_length(const mf_plan *p) { return p ? p->total_out : -1; }
+
+extern "C" void mf_plan_destroy(mf_plan *p)
+{
+    if (p) (void)hipDeviceSynchronize();
+    plan_free(p);
+}
+
+// ------------------------------------------------------------------ plan cache
+
+namespace {
+struct CacheEntry {
+    std::vector<int64_t> offsets;
+    std::vector<int32_t> ks;
+    mf_plan *plan;
+};
+std::mutex g_cache_mu;
+std::vector<CacheEntry> g_cache;   // most recent last
+const size_t kCacheMax = 8;
+
+mf_status cached_plan(const int64_t *off, const int32_t *ks, int32_t ns, mf_plan **out)
+{
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (size_t i = 0; i < g_cache.size(); i++) {
+        CacheEntry &c = g_cache[i];
+        if ((int32_t)c.ks.size() == ns && memcmp(c.ks.data(), ks, sizeof(int32_t) * ns) == 0 &&
+            memcmp(c.offsets.data(), off, sizeof(int64_t) * (ns + 1)) == 0) {
+            *out = c.plan;
+            return MF_OK;
+        }
+    }
+    mf_plan *p = nullptr;
+    mf_status s = mf_plan_create_batched(off, ks, ns, &p);
+    if (s != MF_OK) return s;
+    if (g_cache.size() >= kCacheMax) {
+        mf_plan_destroy(g_cache.front().plan);
+        g_cache.erase(g_cache.begin());
+    }
+    g_cache.push_back(CacheEntry{std::vector<int64_t>(off, off + ns + 1), std::vector<int32_t>(ks, ks + ns), p});
+    *out = p;
+    return MF_OK;
+}
+}  // namespace
+
+// ------------------------------------------------------------------ entry points
+
+extern "C" mf_status mf_median_filter(const float *x, int64_t n, int32_t k, float *y, int32_t *argmed,
+                                      void *stream)
+{
+    return forward_rows(x, 1, n, k, y, argmed, true, (hipStream_t)stream);
+}
+
+extern "C" mf_status mf_median_filter_i32(const int32_t *x, int64_t n, int32_t k, int32_t *y,
+                                          int32_t *argmed, void *stream)
+{
+    return forward_rows(x, 1, n, k, y, argmed, false, (hipStream_t)stream);
+}
+
+extern "C" mf_status mf_median_filter_rows(const float *x, int64_t rows, int64_t n, int32_t k, float *y,
+                                           int32_t *argmed, void *stream)
+{
+    return forward_rows(x, rows, n, k, y, argmed, true, (hipStream_t)stream);
+}
+
+extern "C" mf_status mf_median_filter_batched(const float *x, const int64_t *x_offsets, const int32_t *ks,
+                                              int32_t num_signals, float *y, int32_t *argmed, void *stream)
+{
+    if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
+    mf_plan *p = nullptr;
+    mf_status s = cached_plan(x_offsets, ks, num_signals, &p);
+    if (s != MF_OK) return s;
+    return mf_plan_execute(p, x, y, argmed, stream);
+}
+
+extern "C" mf_status mf_median_filter_backward(const float *grad_y, const int32_t *argmed, int64_t n,
+                                               int32_t k, float *grad_x, void *stream)
+{
+    return backward_rows(grad_y, argmed, 1, n, k, grad_x, (hipStream_t)stream);
+}
+
+extern "C" mf_status mf_median_filter_backward_rows(const float *grad_y, const int32_t *argmed, int64_t rows,
+                                                    int64_t n, int32_t k, float *grad_x, void *stream)
+{
+    return backward_rows(grad_y, argmed, rows, n, k, grad_x, (hipStream_t)stream);
+}
+
+extern "C" mf_status mf_median_filter_backward_batched(const float *grad_y, const int32_t *argmed,
+                                                       const int64_t *x_offsets, const int32_t *ks,
+                                                       int32_t num_signals, float *grad_x, void *stream)
+{
+    mf_plan *p = nullptr;
+    mf_status s = cached_plan(x_offsets, ks, num_signals, &p);
+    if (s != MF_OK) return s;
+    return mf_plan_execute_backward(p, grad_y, argmed, grad_x, stream);
+}
+
+extern "C" int64_t mf_output_length(int64_t n, int32_t k)
+{
+    if (n < 1 || k < 1 || (k & 1) == 0 || k > n) return -1;
+    return n - k + 1;
+}
+
+extern "C" const char *mf_status_string(mf_status s)
+{
+    switch (s) {
+    case MF_OK: return "success";
+    case MF_ERR_INVALID_VALUE: return "invalid argument";
+    case MF_ERR_UNSUPPORTED: return "unsupported size";
+    case MF_ERR_NOMEM: return "out of device memory";
+    case MF_ERR_HIP: return "HIP runtime error";
+    case MF_ERR_INTERNAL: return "inconsistent walk reported by a kernel";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *mf_last_error(void) { return t_last_error.c_str(); }
+
+extern "C" mf_status mf_check_device_error(void *stream)
+{
+    Device *D = nullptr;
+    mf_status s = device_state(&D);
+    if (s != MF_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    int h = 0;
+    MF_HIP(hipMemcpyAsync(&h, D->d_err, sizeof(int), hipMemcpyDeviceToHost, st), "hipMemcpyAsync(error flag)");
+    MF_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (h != 0) {
+        MF_HIP(hipMemsetAsync(D->d_err, 0, sizeof(int), st), "hipMemsetAsync(error flag)");
+        MF_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+        return fail(MF_ERR_INTERNAL, "a kernel reported an inconsistent walk (flag %d)", h);
+    }
+    return MF_OK;
+}

@@ -1,0 +1,80 @@
+// Launch interface between the host runtime (mf_api.cpp) and the kernels
+// (mf_kernels.hip).  Internal to the library.
+#pragma once
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+namespace mf {
+
+// One signal of a launch, as offsets into the launch's base pointers:
+// x + x_off (n items), y / argmed + y_off (n-k+1 outputs).
+struct SigDesc {
+    int64_t x_off;
+    int64_t y_off;
+    int64_t n;
+    int32_t k;
+    int32_t pad;
+};
+
+// One work unit of a multi-signal launch: tile `tile` of signal `sig`.
+struct Unit {
+    int32_t sig;
+    int32_t pad;
+    int64_t tile;
+};
+
+// Base pointers and the signal set of a launch.  Units come from `units`
+// (a device table), or, when units is null, from `one`: tiles
+// 0 .. tpr-1 of `rows` signals of equal shape laid out back to back.
+struct Launch {
+    const void *x;       // 32-bit patterns (float or int32)
+    void *y;
+    int32_t *argmed;     // may be null in the forward
+    SigDesc one;
+    int64_t rows;
+    int64_t tpr;         // tiles per row
+    const SigDesc *sigs;
+    const Unit *units;
+    int64_t nunits;
+};
+
+// Backward launch: grad_y / argmed + y_off (n-k+1), grad_x + x_off (n).
+struct BwdLaunch {
+    const float *grad_y;
+    const int32_t *argmed;
+    float *grad_x;
+    SigDesc one;
+    int64_t rows;
+    int64_t tpr;
+    const SigDesc *sigs;
+    const Unit *units;
+    int64_t nunits;
+};
+
+enum Path { PATH_IDENTITY = 0, PATH_LDS256 = 1, PATH_LDS512 = 2, PATH_GLOBAL = 3, PATH_NONE = -1 };
+
+static const int kGlobalThreads = 1024;
+static const int kBwdThreads = 256;
+static const int kBwdTargetsPerWave = 1024;
+static const int kBwdTargetsPerBlock = kBwdTargetsPerWave * (kBwdThreads / 64);
+
+// Which kernel family serves window k.
+Path path_for(int32_t k);
+// Tiles of a signal on a path, and the dynamic LDS bytes of one tile.
+int64_t tiles_for(Path p, int64_t n, int32_t k);
+int64_t lds_bytes_for(Path p, int32_t k);
+// Global workspace bytes of one workgroup on the global path.
+int64_t global_ws_stride(int32_t k);
+
+hipError_t launch_forward(Path p, bool f32, const Launch &L, size_t lds_bytes,
+                          unsigned char *ws, int64_t ws_stride, int64_t ws_slots,
+                          int *d_err, hipStream_t st);
+
+hipError_t launch_backward(const BwdLaunch &L, hipStream_t st);
+
+// Backward tiles of a signal of length n.
+int64_t bwd_tiles_for(int64_t n);
+
+hipError_t prepare_kernels();
+
+}  // namespace mf

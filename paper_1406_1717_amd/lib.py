@@ -1,0 +1,178 @@
+"""ctypes binding of libmf.so (include/mf.h), one Python function per C entry
+point with the same name.  Argument marshalling only: tensors are passed as
+device pointers, torch's current HIP stream as the stream argument, and a
+failing status raises MFError with the library's message.
+
+The binding refuses to run without the built library: there is no fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmf.so")
+
+MF_OK = 0
+_lib = None
+
+
+class MFError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (status %d): %s" % (status_string(status), status, message))
+        self.status = status
+
+
+def load():
+    """Load libmf.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libmf.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "mf_median_filter": [P, I64, I32, P, P, P],
+        "mf_median_filter_i32": [P, I64, I32, P, P, P],
+        "mf_median_filter_rows": [P, I64, I64, I32, P, P, P],
+        "mf_median_filter_batched": [P, P, P, I32, P, P, P],
+        "mf_median_filter_backward": [P, P, I64, I32, P, P],
+        "mf_median_filter_backward_rows": [P, P, I64, I64, I32, P, P],
+        "mf_median_filter_backward_batched": [P, P, P, P, I32, P, P],
+        "mf_plan_create_batched": [P, P, I32, P],
+        "mf_plan_execute": [P, P, P, P, P],
+        "mf_plan_execute_backward": [P, P, P, P, P],
+        "mf_check_device_error": [P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.mf_plan_output_length.argtypes = [P]
+    L.mf_plan_output_length.restype = I64
+    L.mf_plan_destroy.argtypes = [P]
+    L.mf_plan_destroy.restype = None
+    L.mf_output_length.argtypes = [I64, I32]
+    L.mf_output_length.restype = I64
+    L.mf_status_string.argtypes = [ctypes.c_int]
+    L.mf_status_string.restype = ctypes.c_char_p
+    L.mf_last_error.argtypes = []
+    L.mf_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def status_string(status):
+    return load().mf_status_string(int(status)).decode()
+
+
+def last_error():
+    return load().mf_last_error().decode()
+
+
+def _check(status):
+    if status != MF_OK:
+        raise MFError(status, last_error())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _host_i64(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _host_i32(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+# --- entry points (same names as the C ABI) ---------------------------------
+
+def mf_median_filter(x, n, k, y, argmed, stream=None):
+    _check(load().mf_median_filter(_ptr(x), int(n), int(k), _ptr(y), _ptr(argmed), _stream(stream)))
+
+
+def mf_median_filter_i32(x, n, k, y, argmed, stream=None):
+    _check(load().mf_median_filter_i32(_ptr(x), int(n), int(k), _ptr(y), _ptr(argmed), _stream(stream)))
+
+
+def mf_median_filter_rows(x, rows, n, k, y, argmed, stream=None):
+    _check(load().mf_median_filter_rows(_ptr(x), int(rows), int(n), int(k), _ptr(y), _ptr(argmed),
+                                        _stream(stream)))
+
+
+def mf_median_filter_batched(x, x_offsets, ks, num_signals, y, argmed, stream=None):
+    off, offp = _host_i64(x_offsets)
+    kk, kp = _host_i32(ks)
+    _check(load().mf_median_filter_batched(_ptr(x), offp, kp, int(num_signals), _ptr(y), _ptr(argmed),
+                                           _stream(stream)))
+
+
+def mf_median_filter_backward(grad_y, argmed, n, k, grad_x, stream=None):
+    _check(load().mf_median_filter_backward(_ptr(grad_y), _ptr(argmed), int(n), int(k), _ptr(grad_x),
+                                            _stream(stream)))
+
+
+def mf_median_filter_backward_rows(grad_y, argmed, rows, n, k, grad_x, stream=None):
+    _check(load().mf_median_filter_backward_rows(_ptr(grad_y), _ptr(argmed), int(rows), int(n), int(k),
+                                                 _ptr(grad_x), _stream(stream)))
+
+
+def mf_median_filter_backward_batched(grad_y, argmed, x_offsets, ks, num_signals, grad_x, stream=None):
+    off, offp = _host_i64(x_offsets)
+    kk, kp = _host_i32(ks)
+    _check(load().mf_median_filter_backward_batched(_ptr(grad_y), _ptr(argmed), offp, kp, int(num_signals),
+                                                    _ptr(grad_x), _stream(stream)))
+
+
+def mf_output_length(n, k):
+    return int(load().mf_output_length(int(n), int(k)))
+
+
+def mf_check_device_error(stream=None):
+    _check(load().mf_check_device_error(_stream(stream)))
+
+
+class Plan:
+    """mf_plan_* for one ragged batch layout (host offsets and windows)."""
+
+    def __init__(self, x_offsets, ks):
+        self._off, offp = _host_i64(x_offsets)
+        self._ks, kp = _host_i32(ks)
+        h = ctypes.c_void_p()
+        _check(load().mf_plan_create_batched(offp, kp, len(self._ks), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def output_length(self):
+        return int(load().mf_plan_output_length(self._h))
+
+    def execute(self, x, y, argmed, stream=None):
+        _check(load().mf_plan_execute(self._h, _ptr(x), _ptr(y), _ptr(argmed), _stream(stream)))
+
+    def execute_backward(self, grad_y, argmed, grad_x, stream=None):
+        _check(load().mf_plan_execute_backward(self._h, _ptr(grad_y), _ptr(argmed), _ptr(grad_x),
+                                               _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().mf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
