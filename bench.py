@@ -1,0 +1,238 @@
+"""Throughput of the sorting-based median filter on one MI355X.
+
+One step = one full median filter pass (piecewise sort + pair walks, every
+output and argmedian written) over the int32 workload of 2**26 items drawn
+uniformly over the full int32 range, window k = 1001, inputs resident in HBM
+before the timed region.  Prints one JSON line:
+
+  value         whole-job medians per second over the K timed steps
+  roofline      algorithmic bytes of the forward kernel (4 B read per input,
+                4 B median + 4 B argmedian written per output) divided by
+                its average duration measured with HIP events on the stream
+                it runs on, against the 8 TB/s HBM3E peak; `traffic` is the
+                HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE
+                counters recorded in profiles/ (null when not recorded for
+                the current kernel)
+  cpu_baseline  the CPU oracle (the paper's method in plain C, one thread) on
+                a bounded prefix of the same signal, in medians per second
+
+Flags: --gpus N (only 1 is supported: the method shards trivially, but this
+build runs on one GPU), --steps K, --warmup W, --extras (also time the
+duplicates-heavy input, the row batch with backward, and the ragged batch;
+minutes of host-side data generation).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "int32_full_64m"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_int32_full_64m_k1001.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run a plain 256 MiB device copy (known bytes) for counter calibration")
+    return ap.parse_args()
+
+
+def timed_steps(fn, steps, warmup, torch):
+    """Run fn warmup times, then time exactly `steps` calls.  Returns
+    (total seconds from synchronize to synchronize, per-step event times)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(st)
+        fn()
+        b.record(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = [a.elapsed_time(b) * 1e-3 for a, b in evs]
+    return t1 - t0, per
+
+
+def cpu_baseline(x, k, budget_s=10.0):
+    """The oracle on growing prefixes of x until ~budget_s of work."""
+    import oracle
+    chunk = 1 << 22
+    done_out = 0
+    spent = 0.0
+    m = 0
+    while m < len(x) and spent < budget_s:
+        m = min(len(x), m + chunk)
+        xs = x[:m]
+        t = time.perf_counter()
+        _, am = oracle.sortmedian(xs, k)
+        spent = time.perf_counter() - t
+        done_out = len(am)
+    return {"value": done_out / spent, "unit": "medians/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d items of the same signal (%d medians, %.1f s, single thread)"
+                      % (m, done_out, spent)}
+
+
+def load_traffic():
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        return t
+    except (OSError, ValueError):
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
+              "(the median filter shards by output range with a k-1 halo, see DESIGN.md)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1406_1717_amd as mf
+    from paper_1406_1717_amd import lib, workloads
+
+    dev = torch.device("cuda:0")
+    w = workloads.workload(WORKLOAD)
+    x_host, k = w["x"], w["k"]
+    n = len(x_host)
+    nout = n - k + 1
+    x = torch.from_numpy(x_host).to(dev)
+    y = torch.empty(nout, dtype=torch.int32, device=dev)
+    am = torch.empty(nout, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    if args.copy_probe:
+        src = torch.empty(64 << 20, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    def step():
+        lib.mf_median_filter_i32(x, n, k, y, am)
+
+    total, per = timed_steps(step, args.steps, args.warmup, torch)
+    lib.mf_check_device_error()
+    ms_per_step = total / args.steps * 1e3
+    value = nout * args.steps / total
+    kern_s = float(np.mean(per))
+    alg_bytes = 4.0 * n + 8.0 * nout
+    achieved = alg_bytes / kern_s / 1e9
+
+    # spot check of the timed output against the definition oracle
+    import oracle
+    rng = np.random.default_rng(0)
+    outs = np.sort(rng.integers(0, nout, 2000))
+    ref = oracle.window_median(x_host, k, outs)
+    got = am.cpu().numpy()[outs]
+    if not np.array_equal(ref, got):
+        print("bench.py: sampled argmedians differ from the oracle", file=sys.stderr)
+        sys.exit(3)
+
+    traffic = None
+    t = load_traffic()
+    if t and t.get("kernel_source_sha") == kernel_source_sha():
+        traffic = t.get("hbm_bytes_per_launch")
+
+    line = {
+        "metric": "median outputs/s",
+        "value": value,
+        "unit": "outputs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": n, "k": k, "values": "int32 uniform over the full range",
+                   "seed": workloads.SEEDS[WORKLOAD], "outputs_per_step": nout},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_tile_lds<256,int32>", "kernel_ms": kern_s * 1e3,
+                     "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(x_host, k)
+    if args.extras:
+        line["extras"] = extras(torch, mf, lib, workloads, args)
+    print(json.dumps(line), flush=True)
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("mf_tile.h", "mf_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_1406_1717_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def extras(torch, mf, lib, workloads, args):
+    """Secondary measurements (not part of the headline value)."""
+    dev = torch.device("cuda:0")
+    out = {}
+    # duplicates-heavy int32 (values 0..255)
+    w = workloads.workload("int32_bytes_64m")
+    xb = torch.from_numpy(w["x"]).to(dev)
+    n, k = len(w["x"]), w["k"]
+    y = torch.empty(n - k + 1, dtype=torch.int32, device=dev)
+    a = torch.empty(n - k + 1, dtype=torch.int32, device=dev)
+    total, per = timed_steps(lambda: lib.mf_median_filter_i32(xb, n, k, y, a), args.steps, args.warmup, torch)
+    out["int32_bytes_64m"] = {"outputs_per_s": (n - k + 1) * args.steps / total,
+                              "hbm_frac": (4.0 * n + 8.0 * (n - k + 1)) / np.mean(per) / 1e9 / HBM_PEAK_GBS}
+    del xb, y, a
+    # random walk, k sweep
+    for name in ("random_walk_f32_16m", "sorted_walk_f32_16m"):
+        w = workloads.workload(name)
+        xr = torch.from_numpy(w["x"]).to(dev)
+        n = len(w["x"])
+        res = {}
+        for k in w["ks"]:
+            y = torch.empty(n - k + 1, dtype=torch.float32, device=dev)
+            a = torch.empty(n - k + 1, dtype=torch.int32, device=dev)
+            total, per = timed_steps(lambda: lib.mf_median_filter(xr, n, k, y, a), 5, 1, torch)
+            res[str(k)] = {"outputs_per_s": (n - k + 1) * 5 / total,
+                           "hbm_frac": (4.0 * n + 8.0 * (n - k + 1)) / np.mean(per) / 1e9 / HBM_PEAK_GBS}
+        out[name] = res
+        del xr
+    # differentiable rows: forward vs forward + backward
+    rows, n, k = 256, 262_144, 201
+    xs = torch.randn(rows, n, device=dev)
+    g = torch.randn(rows, n - k + 1, device=dev)
+    ys = torch.empty(rows, n - k + 1, device=dev)
+    ams = torch.empty(rows, n - k + 1, dtype=torch.int32, device=dev)
+    gx = torch.empty(rows, n, device=dev)
+    tf, _ = timed_steps(lambda: lib.mf_median_filter_rows(xs, rows, n, k, ys, ams), 10, 2, torch)
+
+    def fb():
+        lib.mf_median_filter_rows(xs, rows, n, k, ys, ams)
+        lib.mf_median_filter_backward_rows(g, ams, rows, n, k, gx)
+    tfb, _ = timed_steps(fb, 10, 2, torch)
+    out["distinct_normal_256"] = {"fwd_ms": tf / 10 * 1e3, "fwd_bwd_ms": tfb / 10 * 1e3,
+                                  "ratio": tfb / tf}
+    return out
+
+
+if __name__ == "__main__":
+    main()
