@@ -260,7 +260,7 @@ extern "C" mf_status mf_plan_create_batched(const int64_t *x_offsets, const int3
 
     // forward work lists, one per kernel family; within a family the
     // longest windows go first so that the heaviest tiles start early
-    const Path fams[4] = {PATH_LDS512, PATH_LDS256, PATH_GLOBAL, PATH_IDENTITY};
+    const Path fams[4] = {PATH_LDS_LARGE, PATH_LDS_SMALL, PATH_GLOBAL, PATH_IDENTITY};
     std::vector<int32_t> order((size_t)num_signals);
     for (int32_t s = 0; s < num_signals; s++) order[s] = s;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ks[a] > ks[b]; });

@@ -2,8 +2,8 @@
 // gfx950.  The per-tile phases live in mf_tile.h; this file runs them:
 //
 //   k_tile_lds<NT>   k <= 4096: one workgroup per tile, every tile buffer
-//                    in LDS (NT = 256 threads for blocks up to 2048 slots,
-//                    512 above).
+//                    in LDS (NT = 512 threads for blocks up to 2048 slots,
+//                    1024 above).
 //   k_tile_global    4096 < k <= 32767: one pair per tile, the first sort
 //                    levels in LDS and the tile buffers in a per-workgroup
 //                    global workspace; workgroups loop over tiles.
@@ -28,6 +28,28 @@ __device__ __forceinline__ void store_regs(u64 *dst, const u64 (&v)[kRegs])
         pr.y = v[j + 1];
         *(ulonglong2 *)(dst + j) = pr;
     }
+}
+
+// Exclusive prefix of `tot` within segments of G consecutive threads (G a
+// power of two); wave_tot holds NT/64 wave totals when G > 64.
+template <int NT>
+__device__ __forceinline__ u32 seg_excl_scan(u32 tot, int G, u32 *wave_tot)
+{
+    const int lane = threadIdx.x & 63;
+    const int width = G < 64 ? G : 64;
+    u32 incl = tot;
+    for (int d = 1; d < width; d <<= 1) {
+        const u32 o = (u32)__shfl_up((int)incl, (unsigned)d, width);
+        if ((lane & (width - 1)) >= d) incl += o;
+    }
+    if (G <= 64) return incl - tot;
+    const int wave = threadIdx.x >> 6;
+    if (lane == 63) wave_tot[wave] = incl;
+    __syncthreads();
+    const int w0 = wave & ~((G >> 6) - 1);
+    u32 add = 0u;
+    for (int w = w0; w < wave; w++) add += wave_tot[w];
+    return incl - tot + add;
 }
 
 // Resolves work unit uidx of a launch into its signal and tile.
@@ -68,27 +90,31 @@ __device__ __forceinline__ Resolved unit_of(const Launch &L, int64_t uidx)
 // Phases 3-6 of a tile (pair merge, tables, walk, output); phases 1-2 have
 // filled m.xv and m.srt.  NT threads, barriers between phases.
 template <int NT>
-__device__ void tile_tail(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
-                          int *err)
+__device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
+                          int *err, bool merged)
 {
     const int tid = threadIdx.x;
-    const int ipp = merge_items_per_pair(s);
-    for (int it = tid; it < T.P * ipp; it += NT) pair_merge_item(s, T, m, it / ipp, it % ipp);
-    if (T.j0 == 1 && tid == 0) output_first(s, T, m, (u32 *)d.y, d.argmed);
-    __syncthreads();
+    if (!merged) {
+        const int ipp = merge_items_per_pair(s);
+        for (int it = tid; it < T.P * ipp; it += NT) pair_merge_item(s, T, m, it / ipp, it % ipp);
+        if (T.j0 == 1 && tid == 0) output_first(s, T, m, (u32 *)d.y, d.argmed);
+        __syncthreads();
+    }
 
-    for (int it = tid; it < T.P * s.Wn; it += NT) table_init_item(s, m, it / s.Wn, it % s.Wn);
+    const int ncnt = T.P * s.C * (s.Wn + 1);
+    for (int it = tid; it < ncnt; it += NT) table_zero_item(m, it);
     __syncthreads();
-    for (int it = tid; it < T.P * s.k; it += NT) {
-        const int p = it / s.k, i = it - p * s.k;
-        if (i < block_len(s, T, p + 1)) table_flip_item(s, T, m, p, i);
+    for (int p = 0; p < T.P; p++) {
+        const int lenB = block_len(s, T, p + 1), Cp = ceil_div32(lenB, s.L);
+        const u32 Lr = recip32(s.L);
+        for (int r = tid; r < s.k + lenB; r += NT) table_hist_item(s, m, p, r, Lr, Cp);
     }
     __syncthreads();
-    for (int it = tid; it < T.P * s.Wn; it += NT) table_prefix_item(s, T, m, it / s.Wn, it % s.Wn);
+    for (int it = tid; it < T.P * s.Wn; it += NT) { const int p = it / s.Wn; table_column_item(s, m, p, it - p * s.Wn, pair_chunks(s, T, p)); }
     __syncthreads();
     for (int it = tid; it < T.P * s.C; it += NT) {
         const int p = it / s.C, c = it - p * s.C;
-        if (c < pair_chunks(s, T, p)) table_count_item(s, m, p, c);
+        if (c < pair_chunks(s, T, p)) table_row_item(s, m, p, c);
     }
     __syncthreads();
 
@@ -99,8 +125,10 @@ __device__ void tile_tail(const Shape &s, const Tile &T, const TileMem &m, const
     }
     __syncthreads();
 
-    const int64_t no = tile_outputs(s, T);
-    for (int64_t u = tid; u < no; u += NT) output_item(s, T, m, u, (u32 *)d.y, d.argmed);
+    for (int p = 0; p < T.P; p++) {
+        const int lenB = block_len(s, T, p + 1);
+        for (int i = tid; i < lenB; i += NT) output_item(s, T, m, p, i, (u32 *)d.y, d.argmed);
+    }
 }
 
 // ------------------------------------------------------------------ LDS path
@@ -121,34 +149,66 @@ __global__ __launch_bounds__(NT) void k_tile_lds(Launch L, int *err)
     const Tile T = make_tile(s, tile);
     const u32 *x = d.x;
 
-    // 1. load (coalesced within each block)
-    for (int b = 0; b < T.NB; b++) {
-        const int len = block_len(s, T, b);
-        for (int t = tid; t < len; t += NT) load_item(s, T, m, x, b, t);
-    }
-    __syncthreads();
-
-    // 2. sort: registers, then merge-path levels up to the block slot size
+    // 1. load into registers
     u64 v[kRegs];
-#pragma unroll
-    for (int j = 0; j < kRegs; j++) v[j] = sort_value<F32>(s, T, m, tid * kRegs + j);
-    sort_regs(v);
-    for (int w = kRegs; w < s.S; w <<= 1) {
+    load_sort_values<F32>(s, T, m, x, tid, v);
+
+    // 2. bucket sort of every block, and the pair orders by lookup in the
+    // neighbour block's buckets; tiles with an overfull bucket (or blocks
+    // under 16 slots) take the merge sort and merge path below
+    for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
+    for (int b = tid; b < l.nbmax; b += NT) bucket_info_init(m, b);
+    __syncthreads();
+    bool fast = s.S >= kRegs;
+    if (fast) bucket_minmax(m, v);
+    __syncthreads();
+    if (fast && tid < T.NB) bucket_shift_item(s, m, tid);
+    __syncthreads();
+    u32 arr[kRegs];
+    if (fast) bucket_count(s, T, m, tid, v, arr);
+    __syncthreads();
+    fast = fast && (m.flag[0] == 0u);
+    if (fast) {
+        __shared__ u32 wave_tot[NT / 64];
+        u32 c[kRegs];
+        const u32 tot = bucket_scan_local(m, tid, c);
+        const u32 excl = seg_excl_scan<NT>(tot, s.S / kRegs, wave_tot);
+        bucket_scan_store(m, tid, excl, c);
+        __syncthreads();
+        bucket_scatter(s, T, m, tid, v, arr);
+        __syncthreads();
+        u32 fin[kRegs];
+        bucket_rank(s, T, m, tid, v, fin);
+        __syncthreads();
+        bucket_place(s, m, v, fin);
+        __syncthreads();
+        if (T.j0 == 1 && tid == 0) output_first(s, T, m, (u32 *)d.y, d.argmed);
+        int32_t pa[kRegs], pb[kRegs];
+        bucket_pair_positions(s, T, m, tid, v, fin, pa, pb);
+        __syncthreads();
+        bucket_pair_write(s, m, v, pa, pb);
+        for (int p = 0; p < T.P; p++)
+            for (int r = s.k + tid; r < s.Mstride; r += NT) pair_pad_item(s, T, m, p, r);
+        __syncthreads();
+    } else {
+        sort_regs(v);
+        for (int w = kRegs; w < s.S; w <<= 1) {
+            store_regs(m.srt + tid * kRegs, v);
+            __syncthreads();
+            merge_level(m.srt, w, tid, v);
+            __syncthreads();
+        }
         store_regs(m.srt + tid * kRegs, v);
         __syncthreads();
-        merge_level(m.srt, w, tid, v);
-        __syncthreads();
     }
-    store_regs(m.srt + tid * kRegs, v);
-    __syncthreads();
 
-    tile_tail<NT>(s, T, m, d, err);
+    tile_tail<NT>(s, T, m, d, err, fast);
 }
 
 // ------------------------------------------------------------------ global path
 
 struct GLayout {
-    int64_t xv, srt, srt2, M, pos, words, pc, stage, total;
+    int64_t xv, srt, srt2, M, pos, cnt, stage, total;
 };
 
 __host__ __device__ inline void make_glayout(const Shape &s, GLayout *g)
@@ -163,8 +223,7 @@ __host__ __device__ inline void make_glayout(const Shape &s, GLayout *g)
     off = (off + 255) & ~255ll;
     g->total = off;
     int64_t a = g->srt2;
-    g->words = a;  a += 8ll * s.Pmax * s.C * s.Wn;
-    g->pc = a;     a += 2ll * s.Pmax * s.C * (s.Wn + 1);
+    g->cnt = a;    a += 4ll * s.Pmax * s.C * (s.Wn + 1);
     a = (a + 15) & ~15ll;
     g->stage = a;
 }
@@ -198,8 +257,7 @@ __global__ __launch_bounds__(kGlobalThreads) void k_tile_global(Launch L, unsign
         m.srt = (u64 *)(base + g.srt);
         m.M = (u16 *)(base + g.M);
         m.pos = (u32 *)(base + g.pos);
-        m.words = (u64 *)(base + g.words);
-        m.pc = (u16 *)(base + g.pc);
+        m.cnt = (u32 *)(base + g.cnt);
         m.stage = (u16 *)(base + g.stage);
         u64 *srt2 = (u64 *)(base + g.srt2);
         const Tile T = make_tile(s, tile);
@@ -213,9 +271,12 @@ __global__ __launch_bounds__(kGlobalThreads) void k_tile_global(Launch L, unsign
         __syncthreads();
 
         // sort chunks of `chunk` slots in LDS; blocks larger than a chunk
-        // get their last merge level from srt2 into srt
-        const bool glevel = s.S > chunk;
-        u64 *dst0 = glevel ? srt2 : m.srt;
+        // get their last merge levels in global memory, alternating between
+        // srt2 and srt so that the last one lands in srt
+        int nlev = 0;
+        for (int w = chunk; w < s.S; w <<= 1) nlev++;
+        u64 *bufs[2] = {m.srt, srt2};
+        int cur = nlev & 1;                 // buffer the LDS pass writes
         const int wmax = s.S < chunk ? s.S : chunk;
         for (int z = 0; z < s.cap / chunk; z++) {
             const int vt = z * kGlobalThreads + tid;
@@ -229,19 +290,23 @@ __global__ __launch_bounds__(kGlobalThreads) void k_tile_global(Launch L, unsign
                 merge_level(sbuf, w, tid, v);
                 __syncthreads();
             }
-            store_regs(dst0 + (int64_t)vt * kRegs, v);
+            store_regs((cur ? srt2 : m.srt) + (int64_t)vt * kRegs, v);
         }
         __syncthreads();
-        if (glevel) {
+        for (int w = chunk; w < s.S; w <<= 1) {
+            const u64 *src = cur ? srt2 : m.srt;
+            u64 *dst = cur ? m.srt : srt2;
             const int vthreads = s.cap / kRegs;
             for (int vt = tid; vt < vthreads; vt += kGlobalThreads) {
                 u64 v[kRegs];
-                merge_level(srt2, chunk, vt, v);
-                store_regs(m.srt + (int64_t)vt * kRegs, v);
+                merge_level(src, w, vt, v);
+                store_regs(dst + (int64_t)vt * kRegs, v);
             }
+            cur ^= 1;
             __syncthreads();
         }
-        tile_tail<kGlobalThreads>(s, T, m, d, err);
+        (void)bufs;
+        tile_tail<kGlobalThreads>(s, T, m, d, err, false);
     }
 }
 
@@ -359,8 +424,8 @@ Path path_for(int32_t k)
     if (k == 1) return PATH_IDENTITY;
     int32_t S = 1;
     while (S < k) S <<= 1;
-    if (2 * S <= 256 * kRegs) return PATH_LDS256;
-    if (2 * S <= 512 * kRegs) return PATH_LDS512;
+    if (2 * S <= kLdsSmall * kRegs) return PATH_LDS_SMALL;
+    if (2 * S <= kLdsLarge * kRegs) return PATH_LDS_LARGE;
     if (k <= 32767) return PATH_GLOBAL;
     return PATH_NONE;
 }
@@ -370,8 +435,8 @@ int64_t tiles_for(Path p, int64_t n, int32_t k)
     Shape s;
     switch (p) {
     case PATH_IDENTITY: return (n + 65535) / 65536;
-    case PATH_LDS256: make_shape(n, k, 256, &s); return s.ntiles;
-    case PATH_LDS512: make_shape(n, k, 512, &s); return s.ntiles;
+    case PATH_LDS_SMALL: make_shape(n, k, kLdsSmall, &s); return s.ntiles;
+    case PATH_LDS_LARGE: make_shape(n, k, kLdsLarge, &s); return s.ntiles;
     case PATH_GLOBAL: global_shape(n, k, &s); return s.ntiles;
     default: return 0;
     }
@@ -382,8 +447,8 @@ int64_t lds_bytes_for(Path p, int32_t k)
     Shape s;
     Layout l;
     switch (p) {
-    case PATH_LDS256: make_shape(1ll << 20, k, 256, &s); make_layout(s, &l); return l.total;
-    case PATH_LDS512: make_shape(1ll << 20, k, 512, &s); make_layout(s, &l); return l.total;
+    case PATH_LDS_SMALL: make_shape(1ll << 20, k, kLdsSmall, &s); make_layout(s, &l); return l.total;
+    case PATH_LDS_LARGE: make_shape(1ll << 20, k, kLdsLarge, &s); make_layout(s, &l); return l.total;
     case PATH_GLOBAL: return 8ll * kGlobalThreads * kRegs;
     default: return 0;
     }
@@ -401,14 +466,14 @@ int64_t global_ws_stride(int32_t k)
 hipError_t prepare_kernels()
 {
     hipError_t e = hipSuccess;
-    const int big = 160 * 1024;
+    const int big = 156 * 1024;   // room for the kernels' small static LDS arrays
 #define MF_ATTR(kern)                                                                        \
     if (e == hipSuccess)                                                                     \
         e = hipFuncSetAttribute((const void *)(kern), hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    MF_ATTR((k_tile_lds<256, true>))
-    MF_ATTR((k_tile_lds<256, false>))
-    MF_ATTR((k_tile_lds<512, true>))
-    MF_ATTR((k_tile_lds<512, false>))
+    MF_ATTR((k_tile_lds<kLdsSmall, true>))
+    MF_ATTR((k_tile_lds<kLdsSmall, false>))
+    MF_ATTR((k_tile_lds<kLdsLarge, true>))
+    MF_ATTR((k_tile_lds<kLdsLarge, false>))
     MF_ATTR((k_tile_global<true>))
     MF_ATTR((k_tile_global<false>))
 #undef MF_ATTR
@@ -426,13 +491,13 @@ hipError_t launch_forward(Path p, bool f32, const Launch &L, size_t lds_bytes,
         hipLaunchKernelGGL(k_identity, dim3((unsigned)grid), dim3(256), 0, st, L);
         break;
     }
-    case PATH_LDS256:
-        if (f32) hipLaunchKernelGGL((k_tile_lds<256, true>), dim3((unsigned)L.nunits), dim3(256), lds_bytes, st, L, d_err);
-        else     hipLaunchKernelGGL((k_tile_lds<256, false>), dim3((unsigned)L.nunits), dim3(256), lds_bytes, st, L, d_err);
+    case PATH_LDS_SMALL:
+        if (f32) hipLaunchKernelGGL((k_tile_lds<kLdsSmall, true>), dim3((unsigned)L.nunits), dim3(kLdsSmall), lds_bytes, st, L, d_err);
+        else     hipLaunchKernelGGL((k_tile_lds<kLdsSmall, false>), dim3((unsigned)L.nunits), dim3(kLdsSmall), lds_bytes, st, L, d_err);
         break;
-    case PATH_LDS512:
-        if (f32) hipLaunchKernelGGL((k_tile_lds<512, true>), dim3((unsigned)L.nunits), dim3(512), lds_bytes, st, L, d_err);
-        else     hipLaunchKernelGGL((k_tile_lds<512, false>), dim3((unsigned)L.nunits), dim3(512), lds_bytes, st, L, d_err);
+    case PATH_LDS_LARGE:
+        if (f32) hipLaunchKernelGGL((k_tile_lds<kLdsLarge, true>), dim3((unsigned)L.nunits), dim3(kLdsLarge), lds_bytes, st, L, d_err);
+        else     hipLaunchKernelGGL((k_tile_lds<kLdsLarge, false>), dim3((unsigned)L.nunits), dim3(kLdsLarge), lds_bytes, st, L, d_err);
         break;
     case PATH_GLOBAL: {
         const int64_t grid = L.nunits < ws_slots ? L.nunits : ws_slots;

@@ -51,7 +51,12 @@ struct BwdLaunch {
     int64_t nunits;
 };
 
-enum Path { PATH_IDENTITY = 0, PATH_LDS256 = 1, PATH_LDS512 = 2, PATH_GLOBAL = 3, PATH_NONE = -1 };
+// Kernel families: k = 1; LDS tiles of kLdsSmall threads (blocks of up to
+// kLdsSmall*kRegs/2 slots) or kLdsLarge threads; the global-memory path.
+enum Path { PATH_IDENTITY = 0, PATH_LDS_SMALL = 1, PATH_LDS_LARGE = 2, PATH_GLOBAL = 3, PATH_NONE = -1 };
+
+static const int kLdsSmall = 512;
+static const int kLdsLarge = 1024;
 
 static const int kGlobalThreads = 1024;
 static const int kBwdThreads = 256;

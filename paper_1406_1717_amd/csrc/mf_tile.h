@@ -20,10 +20,12 @@
 //   3. pair merge  for each pair, the merged order of A and B by
 //                (key, A-before-B, t) -> M[r] = isB << 15 | t, and the
 //                merged positions posA[t], posB[t].
-//   4. tables    membership words of the merged order at the start of each
-//                walk chunk (steps c*L), by XOR of the flips of earlier
-//                steps, plus prefix popcounts.
-//   5. walk      one lane per chunk of L steps: the window of step i is
+//   4. tables    for every walk chunk (steps c*L ..), the number of window
+//                members below each 64-position word of the merged order at
+//                the chunk's start: one packed histogram over (time bucket
+//                t/L, word) of A and B items, then prefix sums.
+//   5. walk      one lane per chunk of L steps (short chunks, so that many
+//                lanes walk at once): the window of step i is
 //                A[i+1..] u B[..i] (Section 3 "Postprocessing").  In merged
 //                order, position r is a member after step i iff
 //                (isA and t > i) or (isB and t <= i).  Step i removes
@@ -42,6 +44,7 @@
 #define MF_HD __host__ __device__ __forceinline__
 #else
 #define MF_HD static inline
+struct uint4 { uint32_t x, y, z, w; };
 #endif
 
 namespace mf {
@@ -52,7 +55,7 @@ typedef uint16_t u16;
 
 static const u64 kPadAll = ~0ull;          // slot beyond the tile's blocks
 static const u32 kMPad = 0xFFFFu;          // merged-order padding: never a member
-static const int kRegs = 16;               // sort values per thread
+static const int kRegs = 8;                // sort values per thread
 static const int32_t kPairBudget = 48 * 1024; // bytes of M + pos per tile
 
 // ---------------------------------------------------------------- keys
@@ -127,10 +130,11 @@ struct Shape {
     int64_t nblocks; // ceil(n / k)
     int64_t npairs;  // nblocks - 1
     int64_t ntiles;  // tiles covering all pairs (1 when there is no pair)
-    int32_t L;       // walk chunk length (multiple of 64)
+    int32_t L;       // walk chunk length (multiple of 4)
     int32_t C;       // chunks of a full pair, ceil(k / L)
     int32_t Wn;      // 64-position words of a pair's merged order, ceil(2k/64)
     int32_t Mstride; // u16 entries per pair in M (= Wn * 64)
+    int32_t Pstride; // u32 entries per pair in pos (k rounded up to 4)
 };
 
 // LDS (or scratch) layout of a tile, in bytes from the base.
@@ -139,8 +143,10 @@ struct Layout {
     int32_t srt;     // u64[cap]
     int32_t M;       // u16[Pmax * Mstride]
     int32_t pos;     // u32[Pmax * k]     posA | posB << 16
-    int32_t words;   // u64[Pmax * C * Wn]         (aliases srt)
-    int32_t pc;      // u16[Pmax * C * (Wn + 1)]   (aliases srt)
+    int32_t cnt;     // u32[Pmax * C * (Wn + 1)]   (aliases srt)
+    int32_t bk;      // u32[cap] bucket counters   (aliases M, pos)
+    int32_t info;    // u32[3 * nbmax + 1]         (aliases M, pos)
+    int32_t nbmax;   // blocks of a full tile
     int32_t stage;   // u16[Pmax * k]              (aliases srt)
     int32_t total;   // bytes
 };
@@ -160,20 +166,30 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
     s->logS = logS;
     s->cap = threads * kRegs;
     if (2 * S > s->cap) return -1;
-    // chunk length: a multiple of 64 keeping at most 16 chunks per pair
-    int32_t L = 64;
-    while ((k + L - 1) / L > 16) L += 64;
-    s->L = L;
-    s->C = ceil_div32(k, L);
     s->Wn = ceil_div32(2 * (int64_t)k, 64);
     s->Mstride = s->Wn * 64;
+    s->Pstride = (k + 3) & ~3;
     // pairs per tile: as many blocks as the sort holds, but the merged
     // orders and position maps of all pairs stay within kPairBudget bytes
     int32_t P = s->cap / S - 1;
-    const int32_t per_pair = 2 * s->Mstride + 4 * k + 16;
+    const int32_t per_pair = 2 * s->Mstride + 4 * s->Pstride + 16;
     if (P * per_pair > kPairBudget) P = kPairBudget / per_pair;
     if (P < 1) P = 1;
     s->Pmax = P;
+    // chunk length: a multiple of 4, at least 16, large enough that the
+    // tile has no more chunks than threads and that the count tables and
+    // the staged medians of all pairs fit in the sort buffer they reuse
+    int32_t L = 16;
+    const int32_t per_thread = (int32_t)(((int64_t)P * k + threads - 1) / threads);
+    if (L < per_thread) L = (per_thread + 3) & ~3;
+    for (;;) {
+        const int64_t C = (k + L - 1) / L;
+        const int64_t need = (int64_t)P * (4 * C * (s->Wn + 1) + 2 * (int64_t)k + 32);
+        if (need <= 8ll * s->cap || L >= k) break;
+        L += 4;
+    }
+    s->L = L;
+    s->C = ceil_div32(k, L);
     s->nblocks = (n + k - 1) / k;
     s->npairs = s->nblocks - 1;
     s->ntiles = s->npairs > 0 ? (s->npairs + s->Pmax - 1) / s->Pmax : 1;
@@ -187,12 +203,17 @@ MF_HD void make_layout(const Shape &s, Layout *l)
     l->srt = off;    off += 8 * s.cap;
     l->M = off;      off += 2 * s.Pmax * s.Mstride;
     off = (off + 15) & ~15;
-    l->pos = off;    off += 4 * s.Pmax * s.k;
+    l->pos = off;    off += 4 * s.Pmax * s.Pstride;
     off = (off + 15) & ~15;
+    // bucket sort scratch, used before the pair orders are written
+    l->bk = l->M;
+    l->info = l->bk + 4 * s.cap;
+    l->nbmax = s.Pmax + 1;
+    const int32_t bend = l->info + 4 * (3 * (s.Pmax + 1) + 1);
+    if (off < bend) off = (bend + 15) & ~15;
     l->total = off;
     int32_t a = l->srt;
-    l->words = a;    a += 8 * s.Pmax * s.C * s.Wn;
-    l->pc = a;       a += 2 * s.Pmax * s.C * (s.Wn + 1);
+    l->cnt = a;      a += 4 * s.Pmax * s.C * (s.Wn + 1);
     a = (a + 15) & ~15;
     l->stage = a;    a += 2 * s.Pmax * s.k;
     if (a > l->srt + 8 * s.cap) l->total = -1;   // aliased region overflows
@@ -229,24 +250,32 @@ MF_HD int32_t block_len(const Shape &s, const Tile &T, int32_t b)
 // ---------------------------------------------------------------- views
 
 struct TileMem {
+    u32 *bk;         // bucket counters / starts, slot-indexed like srt
+    u32 *bmin;       // per block: smallest key
+    u32 *bmax;       // per block: largest key
+    u32 *bshift;     // per block: key -> bucket shift
+    u32 *flag;       // set when a bucket overflows
     u32 *xv;
     u64 *srt;
     u16 *M;
     u32 *pos;
-    u64 *words;
-    u16 *pc;
+    u32 *cnt;
     u16 *stage;
 };
 
 MF_HD TileMem tile_mem(unsigned char *base, const Layout &l)
 {
     TileMem m;
+    m.bk = (u32 *)(base + l.bk);
+    m.bmin = (u32 *)(base + l.info);
+    m.bmax = m.bmin + l.nbmax;
+    m.bshift = m.bmax + l.nbmax;
+    m.flag = m.bshift + l.nbmax;
     m.xv = (u32 *)(base + l.xv);
     m.srt = (u64 *)(base + l.srt);
     m.M = (u16 *)(base + l.M);
     m.pos = (u32 *)(base + l.pos);
-    m.words = (u64 *)(base + l.words);
-    m.pc = (u16 *)(base + l.pc);
+    m.cnt = (u32 *)(base + l.cnt);
     m.stage = (u16 *)(base + l.stage);
     return m;
 }
@@ -274,6 +303,37 @@ MF_HD u64 sort_value(const Shape &s, const Tile &T, const TileMem &m, int32_t u)
     const u32 raw = m.xv[u];
     const u32 key = F32 ? key_of_f32(raw) : key_of_i32(raw);
     return hb | ((u64)key << 16) | (u64)t;
+}
+
+// Phases 1 and 2 together: thread `tid` loads the inputs of its kRegs slots
+// straight into registers (all loads in flight at once), keeps the raw
+// patterns in xv for the output phase and returns the packed sort values.
+template <bool F32>
+MF_HD void load_sort_values(const Shape &s, const Tile &T, const TileMem &m, const u32 *x,
+                            int32_t tid, u64 (&v)[kRegs])
+{
+    u32 raw[kRegs];
+    int32_t len[kRegs];
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        const int32_t u = tid * kRegs + j;
+        const int32_t b = u >> s.logS;
+        const int32_t t = u & (s.S - 1);
+        len[j] = (b < T.NB) ? block_len(s, T, b) : 0;
+        raw[j] = (t < len[j]) ? x[T.e0 + (int64_t)b * s.k + t] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        const int32_t u = tid * kRegs + j;
+        const int32_t b = u >> s.logS;
+        const int32_t t = u & (s.S - 1);
+        if (b >= T.NB) { v[j] = kPadAll; continue; }
+        const u64 hb = (u64)b << 48;
+        if (t >= len[j]) { v[j] = hb | 0x0000FFFFFFFFFFFFull; continue; }
+        m.xv[u] = raw[j];
+        const u32 key = F32 ? key_of_f32(raw[j]) : key_of_i32(raw[j]);
+        v[j] = hb | ((u64)key << 16) | (u64)t;
+    }
 }
 
 MF_HD void cswap(u64 &a, u64 &b, bool up)
@@ -329,11 +389,307 @@ MF_HD void merge_level(const u64 *buf, int32_t w, int32_t tid, u64 (&out)[kRegs]
     }
 }
 
-// ---------------------------------------------------------------- 3. pair merge
-
-// Sort values carry the key in bits 16..47 and t in bits 0..15.
+// Sort values carry the block in bits 48..63, the key in bits 16..47 and
+// t in bits 0..15.
 MF_HD u32 sv_key(u64 v) { return (u32)(v >> 16); }
 MF_HD u32 sv_t(u64 v) { return (u32)(v & 0xFFFFu); }
+
+// ---------------------------------------------------------------- 2'. bucket sort
+//
+// The common path of phase 2 (any sort may serve as the piecewise sort,
+// Section 1 "Contribution"): each block's keys are spread over S buckets by
+// (key - min) >> shift; an item's arrival number in its bucket, the bucket
+// starts (a scan of the counts) and its rank among the bucket's items by
+// the full (key, t) value give its sorted position.  A tile whose buckets
+// hold more than kBucketMax items (heavy ties, narrow clusters) takes the
+// merge sort above instead.  Needs S >= 16, so that the kRegs slots of a
+// thread lie in one block.
+
+static const int kBucketMax = 32;
+
+MF_HD bool sv_valid(u64 v) { return (v & 0xFFFFu) != 0xFFFFu; }
+MF_HD int32_t sv_block(u64 v) { return (int32_t)(v >> 48); }
+
+// Item = one of the tile's cap counters, or block info entry b < nbmax.
+MF_HD void bucket_zero_item(const TileMem &m, int32_t e) { m.bk[e] = 0u; }
+MF_HD void bucket_info_init(const TileMem &m, int32_t b)
+{
+    m.bmin[b] = 0xFFFFFFFFu;
+    m.bmax[b] = 0u;
+    if (b == 0) m.flag[0] = 0u;
+}
+
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MF_MIN32(ptr, v) atomicMin((unsigned int *)(ptr), (unsigned int)(v))
+#define MF_MAX32(ptr, v) atomicMax((unsigned int *)(ptr), (unsigned int)(v))
+#define MF_ADDRTN32(ptr, v) atomicAdd((unsigned int *)(ptr), (unsigned int)(v))
+#else
+#define MF_MIN32(ptr, v) (*(ptr) = (*(ptr) < (v) ? *(ptr) : (v)))
+#define MF_MAX32(ptr, v) (*(ptr) = (*(ptr) > (v) ? *(ptr) : (v)))
+static inline u32 mf_addrtn32(u32 *p, u32 v) { u32 o = *p; *p += v; return o; }
+#define MF_ADDRTN32(ptr, v) mf_addrtn32((ptr), (v))
+#endif
+
+// Per thread: the thread's keys' minimum and maximum into its block's info.
+MF_HD void bucket_minmax(const TileMem &m, const u64 (&v)[kRegs])
+{
+    u32 mn = 0xFFFFFFFFu, mx = 0u;
+    int32_t b = -1;
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        if (sv_valid(v[j])) {
+            const u32 key = sv_key(v[j]);
+            mn = key < mn ? key : mn;
+            mx = key > mx ? key : mx;
+            b = sv_block(v[j]);
+        }
+    }
+    if (b >= 0) {
+        MF_MIN32(m.bmin + b, mn);
+        MF_MAX32(m.bmax + b, mx);
+    }
+}
+
+// Item = block b: bucket = (key - min) >> shift lands in [0, S).
+MF_HD void bucket_shift_item(const Shape &s, const TileMem &m, int32_t b)
+{
+    const u32 range = m.bmax[b] - m.bmin[b];
+    int32_t bits = 0;
+    while (bits < 32 && (range >> bits) != 0u) bits++;
+    m.bshift[b] = (u32)(bits > s.logS ? bits - s.logS : 0);
+}
+
+// A block's bucket parameters, read once per thread.
+struct BlockView {
+    u32 mn, mx, sh, len;
+    const u32 *start;      // bucket starts (after the scan)
+    const u64 *row;        // the block's sort buffer
+};
+
+MF_HD BlockView block_view(const Shape &s, const Tile &T, const TileMem &m, int32_t b)
+{
+    BlockView V;
+    V.mn = m.bmin[b];
+    V.mx = m.bmax[b];
+    V.sh = m.bshift[b];
+    V.len = (u32)block_len(s, T, b);
+    V.start = m.bk + (b << s.logS);
+    V.row = m.srt + (b << s.logS);
+    return V;
+}
+
+// Block of thread tid's slots (S >= kRegs), or -1 if they lie past the tile.
+MF_HD int32_t thread_block(const Shape &s, const Tile &T, int32_t tid)
+{
+    const int32_t b = (tid * kRegs) >> s.logS;
+    return b < T.NB ? b : -1;
+}
+
+// Per thread: count each item in its bucket; the old count is its arrival
+// number.  Sets the flag when a bucket passes kBucketMax.
+MF_HD void bucket_count(const Shape &s, const Tile &T, const TileMem &m, int32_t tid,
+                        const u64 (&v)[kRegs], u32 (&arr)[kRegs])
+{
+    const int32_t b = thread_block(s, T, tid);
+    const u32 mn = b >= 0 ? m.bmin[b] : 0u, sh = b >= 0 ? m.bshift[b] : 0u;
+    u32 *cnt = m.bk + (b >= 0 ? (b << s.logS) : 0);
+    bool over = false;
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        arr[j] = 0u;
+        if (sv_valid(v[j])) {
+            arr[j] = MF_ADDRTN32(cnt + ((sv_key(v[j]) - mn) >> sh), 1u);
+            over = over || (arr[j] >= (u32)kBucketMax);
+        }
+    }
+    if (over) m.flag[0] = 1u;
+}
+
+// Per thread: the local part of the bucket scan.  Thread tid owns counters
+// [tid*kRegs, tid*kRegs + kRegs) (one block); on return c holds their
+// exclusive prefix within the thread and the thread total is returned.
+MF_HD u32 bucket_scan_local(const TileMem &m, int32_t tid, u32 (&c)[kRegs])
+{
+    const uint4 *src = (const uint4 *)(m.bk + tid * kRegs);
+    u32 acc = 0u;
+#pragma unroll
+    for (int g = 0; g < kRegs / 4; g++) {
+        const uint4 q = src[g];
+        c[4 * g + 0] = acc; acc += q.x;
+        c[4 * g + 1] = acc; acc += q.y;
+        c[4 * g + 2] = acc; acc += q.z;
+        c[4 * g + 3] = acc; acc += q.w;
+    }
+    return acc;
+}
+
+// Per thread: bucket starts = prefix of earlier threads of the block (excl)
+// plus the local prefix.
+MF_HD void bucket_scan_store(const TileMem &m, int32_t tid, u32 excl, const u32 (&c)[kRegs])
+{
+    uint4 *dst = (uint4 *)(m.bk + tid * kRegs);
+#pragma unroll
+    for (int g = 0; g < kRegs / 4; g++) {
+        uint4 q;
+        q.x = excl + c[4 * g + 0];
+        q.y = excl + c[4 * g + 1];
+        q.z = excl + c[4 * g + 2];
+        q.w = excl + c[4 * g + 3];
+        dst[g] = q;
+    }
+}
+
+// Bucket [lo, hi) of key in block view V (key within the block's range).
+MF_HD void view_bucket(const Shape &s, const BlockView &V, u32 key, u32 &lo, u32 &hi)
+{
+    const u32 bk = (key - V.mn) >> V.sh;
+    lo = V.start[bk];
+    hi = (bk + 1u < (u32)s.S) ? V.start[bk + 1] : V.len;
+}
+
+// Per thread: place each item at bucket start + arrival number.
+MF_HD void bucket_scatter(const Shape &s, const Tile &T, const TileMem &m, int32_t tid,
+                          const u64 (&v)[kRegs], const u32 (&arr)[kRegs])
+{
+    const int32_t b = thread_block(s, T, tid);
+    if (b < 0) return;
+    const BlockView V = block_view(s, T, m, b);
+    u64 *row = m.srt + (b << s.logS);
+#pragma unroll
+    for (int j = 0; j < kRegs; j++)
+        if (sv_valid(v[j])) row[V.start[(sv_key(v[j]) - V.mn) >> V.sh] + arr[j]] = v[j];
+}
+
+// Per thread: final position = bucket start + rank among the bucket's items.
+// All of the thread's buckets are scanned together, one item per round,
+// with selects rather than branches.
+MF_HD void bucket_rank(const Shape &s, const Tile &T, const TileMem &m, int32_t tid,
+                       const u64 (&v)[kRegs], u32 (&fin)[kRegs])
+{
+    const int32_t b = thread_block(s, T, tid);
+    u32 x[kRegs], hi[kRegs];
+    BlockView V;
+    V.row = m.srt;
+    if (b >= 0) V = block_view(s, T, m, b);
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        x[j] = 0u;
+        hi[j] = 0u;
+        if (b >= 0 && sv_valid(v[j])) view_bucket(s, V, sv_key(v[j]), x[j], hi[j]);
+        fin[j] = x[j];
+    }
+    for (int round = 0; round < kBucketMax; round++) {
+        u32 more = 0u;
+#pragma unroll
+        for (int j = 0; j < kRegs; j++) {
+            const bool act = x[j] < hi[j];
+            const u64 o = V.row[act ? x[j] : 0u];
+            fin[j] += (act && o < v[j]) ? 1u : 0u;
+            x[j] += act ? 1u : 0u;
+            more |= (x[j] < hi[j]) ? 1u : 0u;
+        }
+        if (!more) break;
+    }
+}
+
+// Per thread: write the sorted blocks (after every rank has been read).
+MF_HD void bucket_place(const Shape &s, const TileMem &m, const u64 (&v)[kRegs], const u32 (&fin)[kRegs])
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; j++)
+        if (sv_valid(v[j])) m.srt[(sv_block(v[j]) << s.logS) + fin[j]] = v[j];
+}
+
+// Items of sorted block V with key < v (strict) or key <= v, for the
+// thread's items: range checks and bucket reads for all items first, then
+// the buckets are scanned together, one item per round, with selects.
+MF_HD void view_count_below(const Shape &s, const BlockView &V, const u64 (&v)[kRegs], bool strict,
+                            bool use, int32_t (&out)[kRegs])
+{
+    u32 lo[kRegs], hi[kRegs];
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        const u32 key = sv_key(v[j]);
+        lo[j] = 0u;
+        hi[j] = 0u;
+        if (use && sv_valid(v[j])) {
+            if (key > V.mx || (!strict && key == V.mx)) lo[j] = hi[j] = V.len;
+            else if (!(key < V.mn || (strict && key == V.mn))) view_bucket(s, V, key, lo[j], hi[j]);
+        }
+    }
+    for (int round = 0; round <= kBucketMax; round++) {
+        u32 more = 0u;
+#pragma unroll
+        for (int j = 0; j < kRegs; j++) {
+            const bool act = lo[j] < hi[j];
+            const u32 kx = sv_key(V.row[act ? lo[j] : 0u]);
+            const u32 key = sv_key(v[j]);
+            const bool below = strict ? (kx < key) : (kx <= key);
+            lo[j] += (act && below) ? 1u : 0u;
+            hi[j] = (act && !below) ? lo[j] : hi[j];
+            more |= (lo[j] < hi[j]) ? 1u : 0u;
+        }
+        if (!more) break;
+    }
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) out[j] = (use && sv_valid(v[j])) ? (int32_t)lo[j] : -1;
+}
+
+// Per thread: merged positions of the thread's items in the pair where
+// their block is A (pair b, B = block b+1: B's items with smaller key come
+// first) and in the pair where it is B (pair b-1: A's items with key <= the
+// item's key come first).  -1 where that pair is not in the tile.
+MF_HD void bucket_pair_positions(const Shape &s, const Tile &T, const TileMem &m, int32_t tid,
+                                 const u64 (&v)[kRegs], const u32 (&fin)[kRegs],
+                                 int32_t (&pa)[kRegs], int32_t (&pb)[kRegs])
+{
+    const int32_t b = thread_block(s, T, tid);
+    const bool hasA = b >= 0 && b < T.P, hasB = b >= 1;
+    BlockView VB, VA;
+    VB.row = VA.row = m.srt;
+    VB.len = VA.len = 0u;
+    VB.mn = VA.mn = VB.mx = VA.mx = VB.sh = VA.sh = 0u;
+    VB.start = VA.start = m.bk;
+    if (hasA) VB = block_view(s, T, m, b + 1);
+    if (hasB) VA = block_view(s, T, m, b - 1);
+    view_count_below(s, VB, v, true, hasA, pa);
+    view_count_below(s, VA, v, false, hasB, pb);
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        if (pa[j] >= 0) pa[j] += (int32_t)fin[j];
+        if (pb[j] >= 0) pb[j] += (int32_t)fin[j];
+    }
+}
+
+// Per thread: write M and the position maps (after every lookup is done).
+MF_HD void bucket_pair_write(const Shape &s, const TileMem &m, const u64 (&v)[kRegs],
+                             const int32_t (&pa)[kRegs], const int32_t (&pb)[kRegs])
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        if (sv_valid(v[j])) {
+            const int32_t b = sv_block(v[j]);
+            const u32 t = sv_t(v[j]);
+            if (pa[j] >= 0) {
+                m.M[b * s.Mstride + pa[j]] = (u16)t;
+                ((u16 *)(m.pos + b * s.Pstride + t))[0] = (u16)pa[j];
+            }
+            if (pb[j] >= 0) {
+                m.M[(b - 1) * s.Mstride + pb[j]] = (u16)(0x8000u | t);
+                ((u16 *)(m.pos + (b - 1) * s.Pstride + t))[1] = (u16)pb[j];
+            }
+        }
+    }
+}
+
+// Item = (pair p, position r >= k + len B): merged-order padding.
+MF_HD void pair_pad_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, int32_t r)
+{
+    if (r >= s.k + block_len(s, T, p + 1)) m.M[p * s.Mstride + r] = (u16)kMPad;
+}
+
+// ---------------------------------------------------------------- 3. pair merge
+
 
 static const int kMergeSeg = 32;   // merged outputs per pair-merge item
 
@@ -349,7 +705,7 @@ MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
     const u64 *A = m.srt + ((int32_t)p << s.logS);
     const u64 *B = m.srt + ((int32_t)(p + 1) << s.logS);
     u16 *Mp = m.M + p * s.Mstride;
-    u32 *pos = m.pos + p * s.k;
+    u32 *pos = m.pos + p * s.Pstride;
     const int32_t d = g * kMergeSeg;
     int32_t lo = d > lenB ? d - lenB : 0;
     int32_t hi = d < lenA ? d : lenA;
@@ -390,181 +746,234 @@ MF_HD int32_t pair_chunks(const Shape &s, const Tile &T, int32_t p)
     return ceil_div32(block_len(s, T, p + 1), s.L);
 }
 
-// Membership word of positions [64w, 64w+64) of pair p after step i
-// (i = -1: before the first step, when the window is all of A).
-MF_HD u64 member_word(const Shape &s, const u16 *Mp, int32_t w, int32_t i)
+// Count table of pair p: row c (chunk start c*L), column w (64-position
+// word): after the passes below, entry (c, w) is the number of members of
+// the window before step c*L among merged positions < 64w; column Wn holds
+// the total (k).  A position holding A's item t is a member before step cL
+// iff t >= cL, one holding B's item t iff t < cL.
+
+MF_HD u32 *cnt_row(const Shape &s, const TileMem &m, int32_t p, int32_t c)
 {
-    if (w < 0 || w >= s.Wn) return 0ull;
-    u64 word = 0ull;
-    const u16 *e = Mp + w * 64;
-    for (int q = 0; q < 64; q++) {
-        const int32_t v = e[q];
-        const int32_t t = v & 0x7FFF;
-        const bool mem = (v & 0x8000) ? (t <= i) : (t > i);
-        word |= (u64)mem << q;
-    }
-    return word;
+    return m.cnt + ((int64_t)p * s.C + c) * (s.Wn + 1);
 }
 
-// Item = (pair p, word w): chunk 0 gets the word before step 0, later
-// chunks start from zero (flips are XORed in, then prefix-XORed).
-MF_HD void table_init_item(const Shape &s, const TileMem &m, int32_t p, int32_t w)
-{
-    u64 *W = m.words + (int64_t)p * s.C * s.Wn;
-    W[w] = member_word(s, m.M + p * s.Mstride, w, -1);
-    for (int c = 1; c < s.C; c++) W[c * s.Wn + w] = 0ull;
-}
+// Item = entry e of the table of pair p: zero it.
+MF_HD void table_zero_item(const TileMem &m, int32_t e) { m.cnt[e] = 0u; }
 
 #if defined(__HIP_DEVICE_COMPILE__)
-#define MF_XOR64(ptr, v) atomicXor((unsigned long long *)(ptr), (unsigned long long)(v))
+#define MF_ADD32(ptr, v) atomicAdd((unsigned int *)(ptr), (unsigned int)(v))
 #else
-#define MF_XOR64(ptr, v) (*(ptr) ^= (v))
+#define MF_ADD32(ptr, v) (*(ptr) += (v))
 #endif
 
-// Item = (pair p, step i): the flips of step i reach every chunk starting
-// after it.  They are accumulated in chunk c = i/L + 1.
-MF_HD void table_flip_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, int32_t i)
+// Item = merged position r of pair p (r < k + len B): count its item in
+// bucket (min(t/L, chunks-1), r/64); A items in the low half, B items in the
+// high.  Lrcp = ceil(2^32 / L) makes t/L a high multiply (exact for t, L <
+// 2^16); Cp is the pair's chunk count.
+MF_HD void table_hist_item(const Shape &s, const TileMem &m, int32_t p, int32_t r, u32 Lrcp, int32_t Cp)
 {
-    const int32_t c = i / s.L + 1;
-    if (c >= pair_chunks(s, T, p)) return;
-    u64 *W = m.words + ((int64_t)p * s.C + c) * s.Wn;
-    const u32 pab = m.pos[p * s.k + i];
-    const u32 pa = pab & 0xFFFFu, pb = pab >> 16;
-    MF_XOR64(W + (pa >> 6), 1ull << (pa & 63));
-    MF_XOR64(W + (pb >> 6), 1ull << (pb & 63));
+    const u32 e = m.M[p * s.Mstride + r];
+    const u32 t = e & 0x7FFFu;
+#if defined(__HIP_DEVICE_COMPILE__)
+    int32_t b = (int32_t)__umulhi(t, Lrcp);
+#else
+    int32_t b = (int32_t)(((u64)t * Lrcp) >> 32);
+#endif
+    if (b > Cp - 1) b = Cp - 1;        // only A items reach past the last chunk
+    MF_ADD32(cnt_row(s, m, p, b) + (r >> 6), (e & 0x8000u) ? 0x10000u : 1u);
 }
 
-// Item = (pair p, word w): prefix XOR over the chunks.
-MF_HD void table_prefix_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, int32_t w)
+MF_HD u32 recip32(int32_t L) { return (u32)((0xFFFFFFFFull + (u64)L) / (u64)L); }
+
+// Item = (pair p, word w): members per word at every chunk start,
+// = (A items with bucket >= c) + (B items with bucket < c).  Rows are
+// visited eight at a time so that their loads are in flight together.
+MF_HD void table_column_item(const Shape &s, const TileMem &m, int32_t p, int32_t w, int32_t Cp)
 {
-    u64 *W = m.words + (int64_t)p * s.C * s.Wn;
-    const int32_t C = pair_chunks(s, T, p);
-    u64 acc = W[w];
-    for (int c = 1; c < C; c++) {
-        acc ^= W[c * s.Wn + w];
-        W[c * s.Wn + w] = acc;
+    const int32_t stride = s.Wn + 1;
+    u32 *col = cnt_row(s, m, p, 0) + w;
+    u32 sa = 0u;
+    for (int32_t c0 = ((Cp - 1) & ~7); c0 >= 0; c0 -= 8) {
+        u32 vals[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) vals[q] = (c0 + q < Cp) ? col[(c0 + q) * stride] : 0u;
+#pragma unroll
+        for (int q = 7; q >= 0; q--) {
+            sa += vals[q] & 0xFFFFu;
+            vals[q] = (vals[q] & 0xFFFF0000u) | sa;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; q++) if (c0 + q < Cp) col[(c0 + q) * stride] = vals[q];
+    }
+    u32 pb = 0u;
+    for (int32_t c0 = 0; c0 < Cp; c0 += 8) {
+        u32 vals[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) vals[q] = (c0 + q < Cp) ? col[(c0 + q) * stride] : 0u;
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const u32 v = vals[q];
+            vals[q] = (v & 0xFFFFu) + pb;
+            pb += v >> 16;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; q++) if (c0 + q < Cp) col[(c0 + q) * stride] = vals[q];
     }
 }
 
-// Item = (pair p, chunk c): prefix popcounts over the words.
-MF_HD void table_count_item(const Shape &s, const TileMem &m, int32_t p, int32_t c)
+// Item = (pair p, chunk c): exclusive prefix over the words.
+MF_HD void table_row_item(const Shape &s, const TileMem &m, int32_t p, int32_t c)
 {
-    const u64 *W = m.words + ((int64_t)p * s.C + c) * s.Wn;
-    u16 *pc = m.pc + ((int64_t)p * s.C + c) * (s.Wn + 1);
-    int32_t acc = 0;
-    for (int w = 0; w < s.Wn; w++) {
-        pc[w] = (u16)acc;
-        acc += popc64(W[w]);
+    u32 *row = cnt_row(s, m, p, c);
+    u32 acc = 0u;
+    for (int32_t w = 0; w < s.Wn; w++) {
+        const u32 v = row[w];
+        row[w] = acc;
+        acc += v;
     }
-    pc[s.Wn] = (u16)acc;
+    row[s.Wn] = acc;
 }
 
 // ---------------------------------------------------------------- 5. walk
 
-// Window of two membership words covering positions [64*wl, 64*wl + 128).
-struct Win {
-    int32_t wl;
-    u64 lo, hi;
-};
+// The walk keeps the membership of positions [32*wl, 32*wl + 96) in three
+// 32-bit registers w0, w1, w2 (dwords wl, wl+1, wl+2 of the merged order).
+// The helpers take the words by value (or update them one by one), so every
+// choice among them is a register select.
 
-MF_HD u64 win_word(const Shape &s, const u16 *Mp, const Win &W, int32_t wq, int32_t i)
+MF_HD int ctz32(u32 v) { return __builtin_ctz(v); }   // v != 0
+
+MF_HD int hibit32(u32 v)   // index of the highest set bit, v != 0
 {
-    if (wq == W.wl) return W.lo;
-    if (wq == W.wl + 1) return W.hi;
-    return member_word(s, Mp, wq, i);
+    return 31 - __builtin_clz(v);
 }
 
-// Keep r at least 16 positions inside the window; otherwise move the
-// window so that r sits in its middle half.
-MF_HD void win_center(const Shape &s, const u16 *Mp, Win &W, int32_t r, int32_t i)
+// Membership dword of positions [32w, 32w+32) after step i, read from M with
+// 16-byte loads (M rows are 128-byte aligned).  Used when the window moves.
+MF_HD u32 member_dword(const Shape &s, const u16 *Mp, int32_t w, int32_t i)
 {
-    const int32_t d = r - W.wl * 64;
-    if (d >= 16 && d < 112) return;
-    const int32_t wr = r >> 6;
-    const int32_t wl = ((r & 63) >= 32) ? wr : wr - 1;
-    if (wl == W.wl) return;
-    const u64 nlo = win_word(s, Mp, W, wl, i);
-    const u64 nhi = win_word(s, Mp, W, wl + 1, i);
-    W.wl = wl;
-    W.lo = nlo;
-    W.hi = nhi;
+    if (w < 0 || w >= 2 * s.Wn) return 0u;
+    const uint4 *src = (const uint4 *)(Mp + w * 32);
+    u32 word = 0u;
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+        const uint4 v = src[g];
+#pragma unroll
+        for (int h = 0; h < 4; h++) {
+            const u32 pr = (h == 0) ? v.x : ((h == 1) ? v.y : ((h == 2) ? v.z : v.w));
+#pragma unroll
+            for (int e = 0; e < 2; e++) {
+                const int32_t ent = (int32_t)((pr >> (16 * e)) & 0xFFFFu);
+                const int32_t t = ent & 0x7FFF;
+                const bool mem = (ent & 0x8000) ? (t <= i) : (t > i);
+                word |= (u32)mem << (g * 8 + h * 2 + e);
+            }
+        }
+    }
+    return word;
 }
 
-MF_HD void win_flip(Win &W, int32_t p, bool set)
+// The walk keeps the membership of 64 consecutive merged positions
+// [base, base + 64) in one 64-bit register (base a multiple of 32, chosen so
+// that the median starts at least 16 positions from either end).  Steps
+// whose answer lies outside it take win_search_far, which reads membership
+// from M, and then re-centre the window.
+
+MF_HD u64 win_read(const Shape &s, const u16 *Mp, int32_t base, int32_t i)
 {
-    const int32_t d = p - W.wl * 64;
-    if (d < 0 || d >= 128) return;
-    const u64 bit = 1ull << (d & 63);
-    if (d < 64) W.lo = set ? (W.lo | bit) : (W.lo & ~bit);
-    else        W.hi = set ? (W.hi | bit) : (W.hi & ~bit);
+    const int32_t d = base >> 5;
+    return (u64)member_dword(s, Mp, d, i) | ((u64)member_dword(s, Mp, d + 1, i) << 32);
 }
 
-// Walk of chunk c of pair p: steps [c*L, min((c+1)*L, len B)).
-// Returns 0, or -1 if a search ran off the merged order (cannot happen
-// for a correct table; the bound keeps the loop finite).
+// Window base for median position r: r - base in [16, 48).
+MF_HD int32_t win_base_for(int32_t r) { return ((r - 16) >> 5) << 5; }
+
+// Next member strictly above r (dir > 0) or below r (dir < 0), searched
+// dword by dword through M at step i (window bits are not needed: a dword
+// of M read at step i already reflects every step).
+MF_HD int32_t win_search_far(const Shape &s, const u16 *Mp, int32_t r, int32_t dir, int32_t i)
+{
+    int32_t q = r + dir;
+    int32_t wq = q >> 5;
+    u32 word = member_dword(s, Mp, wq, i);
+    word &= (dir > 0) ? (0xFFFFFFFFu << (q & 31)) : (0xFFFFFFFFu >> (31 - (q & 31)));
+#pragma unroll 1
+    for (int32_t guard = 0; guard <= 2 * s.Wn + 1; guard++) {
+        if (word) return wq * 32 + (dir > 0 ? ctz32(word) : hibit32(word));
+        wq += dir;
+        if (wq < 0 || wq >= 2 * s.Wn) return -1;
+        word = member_dword(s, Mp, wq, i);
+    }
+    return -1;
+}
+
+// Walk of chunk c of pair p: steps [c*L, min((c+1)*L, len B)).  Returns 0,
+// or -1 if a search ran off the merged order (cannot happen for a correct
+// table; the bound keeps the loop finite).
 MF_HD int walk_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, int32_t c)
 {
     const int32_t lenB = block_len(s, T, p + 1);
     const int32_t i0 = c * s.L;
     const int32_t i1 = (i0 + s.L < lenB) ? i0 + s.L : lenB;
     const u16 *Mp = m.M + p * s.Mstride;
-    const u64 *Wc = m.words + ((int64_t)p * s.C + c) * s.Wn;
-    const u16 *pc = m.pc + ((int64_t)p * s.C + c) * (s.Wn + 1);
-    const u32 *pos = m.pos + p * s.k;
+    const u32 *pc = cnt_row(s, m, p, c);
+    const u32 *pos = m.pos + p * s.Pstride;
     u16 *stage = m.stage + p * s.k;
     const int32_t h = s.h;
 
-    // rank-h member before step i0: largest w with pc[w] <= h
+    // the window before step i0 has pc[w] members below word w; the
+    // rank-h member lies in the largest word w with pc[w] <= h
     int32_t lo = 0, hi = s.Wn;
     while (hi - lo > 1) {
         const int32_t mid = (lo + hi) >> 1;
         if ((int32_t)pc[mid] <= h) lo = mid;
         else hi = mid;
     }
-    int32_t r = lo * 64 + select64(Wc[lo], h - (int32_t)pc[lo]);
+    const u32 dlo = member_dword(s, Mp, 2 * lo, i0 - 1);
+    const u32 dhi = member_dword(s, Mp, 2 * lo + 1, i0 - 1);
+    const u64 word = (u64)dlo | ((u64)dhi << 32);
+    int32_t r = lo * 64 + select64(word, h - (int32_t)pc[lo]);
 
-    Win W;
-    W.wl = ((r & 63) >= 32) ? (r >> 6) : (r >> 6) - 1;
-    W.lo = (W.wl >= 0) ? Wc[W.wl] : 0ull;
-    W.hi = (W.wl + 1 < s.Wn) ? Wc[W.wl + 1] : 0ull;
+    int32_t base = win_base_for(r);
+    u64 W;
+    if (base == lo * 64) W = word;
+    else if (base < lo * 64) W = (u64)member_dword(s, Mp, 2 * lo - 1, i0 - 1) | ((u64)dlo << 32);
+    else W = (u64)dhi | ((u64)member_dword(s, Mp, 2 * lo + 2, i0 - 1) << 32);
 
-    const int32_t maxw = s.Wn + 2;
-    int32_t i = i0;
     int bad = 0;
-    for (; i < i1 && !bad; i++) {
-        const u32 pab = pos[i];
-        const int32_t pa = (int32_t)(pab & 0xFFFFu), pb = (int32_t)(pab >> 16);
-        win_flip(W, pa, false);
-        win_flip(W, pb, true);
-        int32_t dir;
-        if (pa == r) dir = (pb < r) ? -1 : 1;
-        else dir = (int32_t)(pa < r) - (int32_t)(pb < r);
-        if (dir > 0) {
-            int32_t q = r + 1;
-            for (int32_t guard = 0;; guard++) {
-                const int32_t wq = q >> 6;
-                if (guard > maxw || wq >= s.Wn) { bad = 1; break; }
-                const u64 word = win_word(s, Mp, W, wq, i) & (~0ull << (q & 63));
-                if (word) { r = wq * 64 + ctz64(word); break; }
-                q = (wq + 1) * 64;
+    u32 nxt = pos[i0];
+#pragma unroll 1
+    for (int32_t i = i0; i < i1; i++) {
+        const u32 q = nxt;
+        if (i + 1 < i1) nxt = pos[i + 1];
+        const int32_t pa = (int32_t)(q & 0xFFFFu), pb = (int32_t)(q >> 16);
+        // A[i] leaves (its bit is set), B[i] joins (its bit is clear)
+        const int32_t da = pa - base, db = pb - base;
+        W ^= ((u32)da < 64u) ? (1ull << (da & 63)) : 0ull;
+        W ^= ((u32)db < 64u) ? (1ull << (db & 63)) : 0ull;
+        const int32_t dir = (pa == r) ? ((pb < r) ? -1 : 1)
+                                      : ((int32_t)(pa < r) - (int32_t)(pb < r));
+        const int32_t rel = r - base;
+        const u64 up = W & (~1ull << rel);
+        const u64 dn = W & ((1ull << rel) - 1ull);
+        int32_t nr = r;
+        if (dir > 0) nr = up ? base + ctz64(up) : -1;
+        if (dir < 0) nr = dn ? base + hibit64(dn) : -1;
+        if (nr < 0) {
+            nr = win_search_far(s, Mp, r, dir, i);
+            if (nr < 0) {
+                bad = 1;
+                nr = 0;
+            } else {
+                base = win_base_for(nr);
+                W = win_read(s, Mp, base, i);
             }
-            if (!bad) win_center(s, Mp, W, r, i);
-        } else if (dir < 0) {
-            int32_t q = r - 1;
-            for (int32_t guard = 0;; guard++) {
-                if (guard > maxw || q < 0) { bad = 1; break; }
-                const int32_t wq = q >> 6;
-                const u64 mask = ((q & 63) == 63) ? ~0ull : ((2ull << (q & 63)) - 1ull);
-                const u64 word = win_word(s, Mp, W, wq, i) & mask;
-                if (word) { r = wq * 64 + hibit64(word); break; }
-                q = wq * 64 - 1;
-            }
-            if (!bad) win_center(s, Mp, W, r, i);
         }
-        stage[i] = (u16)(bad ? 0 : r);
+        r = nr;
+        stage[i] = (u16)r;
     }
-    // after a failed search the rest of the chunk gets a valid placeholder
-    for (; i < i1; i++) stage[i] = 0;
+    if (bad)   // a failed search leaves a valid placeholder for the whole chunk
+        for (int32_t q = i0; q < i1; q++) stage[q] = 0;
     return bad ? -1 : 0;
 }
 
@@ -579,17 +988,15 @@ MF_HD int64_t tile_outputs(const Shape &s, const Tile &T)
     return cnt;
 }
 
-// Item = u-th output of the pairs (o = o0 + u).
-MF_HD void output_item(const Shape &s, const Tile &T, const TileMem &m, int64_t u,
+// Item = step i of pair p: output o = o0 + p*k + i.
+MF_HD void output_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, int32_t i,
                        u32 *y, int32_t *argmed)
 {
-    const int32_t p = (int32_t)(u / s.k);
-    const int32_t i = (int32_t)(u - (int64_t)p * s.k);
     const int32_t r = m.stage[p * s.k + i];
     const u32 e = m.M[p * s.Mstride + r];
     const int32_t b = p + (int32_t)(e >> 15);
     const int32_t t = (int32_t)(e & 0x7FFFu);
-    const int64_t o = T.o0 + u;
+    const int64_t o = T.o0 + (int64_t)p * s.k + i;
     y[o] = m.xv[(b << s.logS) + t];
     if (argmed) argmed[o] = (int32_t)(T.e0 + (int64_t)b * s.k + t);
 }

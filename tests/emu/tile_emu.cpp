@@ -13,6 +13,12 @@
 
 using namespace mf;
 
+static int g_force_merge = 0;
+static long g_fast_tiles = 0, g_slow_tiles = 0;
+extern "C" void emu_set_force_merge(int v) { g_force_merge = v; }
+extern "C" long emu_fast_tiles(void) { return g_fast_tiles; }
+extern "C" long emu_slow_tiles(void) { return g_slow_tiles; }
+
 template <bool F32>
 static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
                     const u32 *x, u32 *y, int32_t *argmed, std::vector<unsigned char> &lds)
@@ -22,52 +28,124 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
     memset(lds.data(), 0xA5, lds.size());
     TileMem m = tile_mem(lds.data(), l);
 
-    for (int b = 0; b < T.NB; b++)
-        for (int u = 0; u < block_len(s, T, b); u++) load_item(s, T, m, x, b, u);
-
     std::vector<u64> regs((size_t)threads * kRegs), tmp((size_t)threads * kRegs);
     for (int q = 0; q < threads; q++) {
         u64 v[kRegs];
-        for (int j = 0; j < kRegs; j++) v[j] = sort_value<F32>(s, T, m, q * kRegs + j);
-        sort_regs(v);
+        load_sort_values<F32>(s, T, m, x, q, v);
         for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
     }
-    for (int w = kRegs; w < s.S; w *= 2) {
-        memcpy(m.srt, regs.data(), sizeof(u64) * regs.size());
+    // bucket path
+    for (int e = 0; e < s.cap; e++) bucket_zero_item(m, e);
+    for (int b = 0; b < l.nbmax; b++) bucket_info_init(m, b);
+    bool fast = s.S >= kRegs && !g_force_merge;
+    auto V = [&](int q, u64 (&v)[kRegs]) { for (int j = 0; j < kRegs; j++) v[j] = regs[(size_t)q * kRegs + j]; };
+    std::vector<u32> arr((size_t)threads * kRegs), fin((size_t)threads * kRegs);
+    std::vector<int32_t> pa((size_t)threads * kRegs), pb((size_t)threads * kRegs);
+    if (fast) {
+        for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); bucket_minmax(m, v); }
+        for (int b = 0; b < T.NB; b++) bucket_shift_item(s, m, b);
         for (int q = 0; q < threads; q++) {
-            u64 out[kRegs];
-            merge_level(m.srt, w, q, out);
-            for (int j = 0; j < kRegs; j++) tmp[(size_t)q * kRegs + j] = out[j];
+            u64 v[kRegs]; V(q, v); u32 a[kRegs];
+            bucket_count(s, T, m, q, v, a);
+            for (int j = 0; j < kRegs; j++) arr[(size_t)q * kRegs + j] = a[j];
         }
-        regs.swap(tmp);
+        fast = m.flag[0] == 0u;
     }
-    memcpy(m.srt, regs.data(), sizeof(u64) * regs.size());
-
-    // sortedness check of every block
-    for (int b = 0; b < T.NB; b++) {
-        const int len = block_len(s, T, b);
-        for (int u = 1; u < len; u++)
-            if (m.srt[(b << s.logS) + u - 1] >= m.srt[(b << s.logS) + u]) return -10;
+    if (fast) {
+        const int G = s.S / kRegs;
+        std::vector<u32> tot(threads);
+        std::vector<std::vector<u32>> cl(threads, std::vector<u32>(kRegs));
+        for (int q = 0; q < threads; q++) {
+            u32 c[kRegs];
+            tot[q] = bucket_scan_local(m, q, c);
+            for (int j = 0; j < kRegs; j++) cl[q][j] = c[j];
+        }
+        for (int q = 0; q < threads; q++) {
+            u32 excl = 0;
+            for (int r = q & ~(G - 1); r < q; r++) excl += tot[r];
+            u32 c[kRegs];
+            for (int j = 0; j < kRegs; j++) c[j] = cl[q][j];
+            bucket_scan_store(m, q, excl, c);
+        }
+        for (int q = 0; q < threads; q++) {
+            u64 v[kRegs]; V(q, v); u32 a[kRegs];
+            for (int j = 0; j < kRegs; j++) a[j] = arr[(size_t)q * kRegs + j];
+            bucket_scatter(s, T, m, q, v, a);
+        }
+        for (int q = 0; q < threads; q++) {
+            u64 v[kRegs]; V(q, v); u32 f[kRegs];
+            bucket_rank(s, T, m, q, v, f);
+            for (int j = 0; j < kRegs; j++) fin[(size_t)q * kRegs + j] = f[j];
+        }
+        for (int q = 0; q < threads; q++) {
+            u64 v[kRegs]; V(q, v); u32 f[kRegs];
+            for (int j = 0; j < kRegs; j++) f[j] = fin[(size_t)q * kRegs + j];
+            bucket_place(s, m, v, f);
+        }
+        for (int b = 0; b < T.NB; b++) {
+            const int len = block_len(s, T, b);
+            for (int u = 1; u < len; u++)
+                if (m.srt[(b << s.logS) + u - 1] >= m.srt[(b << s.logS) + u]) return -12;
+        }
+        if (T.j0 == 1) output_first(s, T, m, y, argmed);
+        for (int q = 0; q < threads; q++) {
+            u64 v[kRegs]; V(q, v); u32 f[kRegs]; int32_t a[kRegs], b2[kRegs];
+            for (int j = 0; j < kRegs; j++) f[j] = fin[(size_t)q * kRegs + j];
+            bucket_pair_positions(s, T, m, q, v, f, a, b2);
+            for (int j = 0; j < kRegs; j++) { pa[(size_t)q * kRegs + j] = a[j]; pb[(size_t)q * kRegs + j] = b2[j]; }
+        }
+        // the pair orders overwrite the bucket scratch: poison it first
+        memset(m.M, 0xA5, (size_t)(l.pos - l.M) + 4 * (size_t)s.Pmax * s.Pstride);
+        for (int q = 0; q < threads; q++) {
+            u64 v[kRegs]; V(q, v); int32_t a[kRegs], b2[kRegs];
+            for (int j = 0; j < kRegs; j++) { a[j] = pa[(size_t)q * kRegs + j]; b2[j] = pb[(size_t)q * kRegs + j]; }
+            bucket_pair_write(s, m, v, a, b2);
+        }
+        for (int p = 0; p < T.P; p++)
+            for (int r = s.k; r < s.Mstride; r++) pair_pad_item(s, T, m, p, r);
+        g_fast_tiles++;
+    } else {
+        for (int q = 0; q < threads; q++) {
+            u64 v[kRegs]; V(q, v);
+            sort_regs(v);
+            for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
+        }
+        for (int w = kRegs; w < s.S; w *= 2) {
+            memcpy(m.srt, regs.data(), sizeof(u64) * regs.size());
+            for (int q = 0; q < threads; q++) {
+                u64 out[kRegs];
+                merge_level(m.srt, w, q, out);
+                for (int j = 0; j < kRegs; j++) tmp[(size_t)q * kRegs + j] = out[j];
+            }
+            regs.swap(tmp);
+        }
+        memcpy(m.srt, regs.data(), sizeof(u64) * regs.size());
+        for (int b = 0; b < T.NB; b++) {
+            const int len = block_len(s, T, b);
+            for (int u = 1; u < len; u++)
+                if (m.srt[(b << s.logS) + u - 1] >= m.srt[(b << s.logS) + u]) return -10;
+        }
+        const int ipp = merge_items_per_pair(s);
+        for (int p = 0; p < T.P; p++)
+            for (int g = 0; g < ipp; g++) pair_merge_item(s, T, m, p, g);
+        if (T.j0 == 1) output_first(s, T, m, y, argmed);
+        g_slow_tiles++;
     }
 
-    const int ipp = merge_items_per_pair(s);
+    for (int e = 0; e < T.P * s.C * (s.Wn + 1); e++) table_zero_item(m, e);
+    for (int p = 0; p < T.P; p++) {
+        const int lenB = block_len(s, T, p + 1), Cp = ceil_div32(lenB, s.L);
+        for (int r = 0; r < s.k + lenB; r++) table_hist_item(s, m, p, r, recip32(s.L), Cp);
+    }
     for (int p = 0; p < T.P; p++)
-        for (int g = 0; g < ipp; g++) pair_merge_item(s, T, m, p, g);
-    if (T.j0 == 1) output_first(s, T, m, y, argmed);
-
+        for (int w = 0; w < s.Wn; w++) table_column_item(s, m, p, w, pair_chunks(s, T, p));
     for (int p = 0; p < T.P; p++)
-        for (int w = 0; w < s.Wn; w++) table_init_item(s, m, p, w);
-    for (int p = 0; p < T.P; p++)
-        for (int i = 0; i < block_len(s, T, p + 1); i++) table_flip_item(s, T, m, p, i);
-    for (int p = 0; p < T.P; p++)
-        for (int w = 0; w < s.Wn; w++) table_prefix_item(s, T, m, p, w);
-    for (int p = 0; p < T.P; p++)
-        for (int c = 0; c < pair_chunks(s, T, p); c++) table_count_item(s, m, p, c);
+        for (int c = 0; c < pair_chunks(s, T, p); c++) table_row_item(s, m, p, c);
     for (int p = 0; p < T.P; p++)
         for (int c = 0; c < pair_chunks(s, T, p); c++)
             if (walk_item(s, T, m, p, c) != 0) return -11;
-    const int64_t no = tile_outputs(s, T);
-    for (int64_t u = 0; u < no; u++) output_item(s, T, m, u, y, argmed);
+    for (int p = 0; p < T.P; p++)
+        for (int i = 0; i < block_len(s, T, p + 1); i++) output_item(s, T, m, p, i, y, argmed);
     return 0;
 }
 
