@@ -1,0 +1,97 @@
+"""GPU ragged batch: every signal of a packed batch must match the oracle
+run on that signal alone (medians bitwise, argmedians local to the signal),
+through the cached-plan entry point and through explicit plans, including
+graph replays with new data and the backward of the batch."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1406_1717_amd as mf
+from paper_1406_1717_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def small_batch(seed, num=40, max_len=60_000, max_k=4001):
+    x, off, ks = workloads.ragged_impulse(num, seed, min_len=1000, max_len=max_len, max_k=max_k)
+    return x, off, ks
+
+
+def check_batch(x, off, ks, y, am):
+    yo = mf.output_offsets(off, ks)
+    for s in range(len(ks)):
+        xs = x[off[s]:off[s + 1]]
+        ys, ams = oracle.sortmedian(xs, int(ks[s]))
+        a = am[yo[s]:yo[s + 1]]
+        assert np.array_equal(a, ams), "signal %d (n=%d, k=%d)" % (s, len(xs), ks[s])
+        assert np.array_equal(y[yo[s]:yo[s + 1]].view(np.uint32), ys.view(np.uint32))
+
+
+def test_batched_small():
+    x, off, ks = small_batch(11)
+    y, am = mf.median_filter_batched(torch.from_numpy(x).to(DEV), off, ks)
+    torch.cuda.synchronize()
+    mf.lib.mf_check_device_error()
+    check_batch(x, off, ks, y.cpu().numpy(), am.cpu().numpy())
+
+
+def test_batched_mixed_paths_and_edges():
+    """k = 1, k = length (one output), windows above 4096 (global-memory
+    path) and tiny signals in one batch."""
+    rng = np.random.default_rng(12)
+    lens = [1, 5, 7, 1000, 4097, 9000, 20_000, 3, 33, 70_000]
+    ks = [1, 5, 3, 1, 4097, 5001, 4001, 3, 33, 101]
+    off = np.zeros(len(lens) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lens)
+    x = rng.standard_normal(int(off[-1])).astype(np.float32)
+    x[rng.random(x.size) < 0.1] = 0.5
+    y, am = mf.median_filter_batched(torch.from_numpy(x).to(DEV), off, np.array(ks, np.int32))
+    torch.cuda.synchronize()
+    check_batch(x, off, np.array(ks), y.cpu().numpy(), am.cpu().numpy())
+
+
+def test_plan_graph_replay_new_data():
+    """The plan's graph is replayed with other data in the same buffers, and
+    re-captured for other buffers."""
+    x, off, ks = small_batch(13, num=25)
+    plan = mf.Plan(off, ks)
+    nout = plan.output_length
+    xt = torch.from_numpy(x).to(DEV)
+    y = torch.empty(nout, device=DEV)
+    am = torch.empty(nout, dtype=torch.int32, device=DEV)
+    for rep in range(3):
+        x2 = (x * (rep + 1) + rep).astype(np.float32)
+        xt.copy_(torch.from_numpy(x2))
+        plan.execute(xt, y, am)
+        torch.cuda.synchronize()
+        check_batch(x2, off, ks, y.cpu().numpy(), am.cpu().numpy())
+    y2 = torch.empty_like(y)
+    am2 = torch.empty_like(am)
+    plan.execute(xt, y2, am2)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y2) and torch.equal(am, am2)
+    plan.close()
+
+
+def test_batched_backward():
+    x, off, ks = small_batch(14, num=20)
+    xt = torch.from_numpy(x).to(DEV)
+    y, am = mf.median_filter_batched(xt, off, ks)
+    yo = mf.output_offsets(off, ks)
+    g = workloads.normal_f32(int(yo[-1]), 15)
+    gx = mf.median_filter_backward_batched(torch.from_numpy(g).to(DEV), am, off, ks).cpu().numpy()
+    amh = am.cpu().numpy()
+    for s in range(len(ks)):
+        n = int(off[s + 1] - off[s])
+        g32, _ = oracle.backward(g[yo[s]:yo[s + 1]], amh[yo[s]:yo[s + 1]], n, int(ks[s]))
+        assert np.array_equal(gx[off[s]:off[s + 1]], g32)
+
+
+def test_batched_invalid_is_rejected():
+    off = np.array([0, 10, 12], dtype=np.int64)
+    ks = np.array([3, 5], dtype=np.int32)           # 5 > length 2
+    with pytest.raises(mf.MFError):
+        mf.median_filter_batched(torch.zeros(12, device=DEV), off, ks)
