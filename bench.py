@@ -169,7 +169,7 @@ def main():
                    "seed": workloads.SEEDS[WORKLOAD], "outputs_per_step": nout},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_tile_lds<256,int32>", "kernel_ms": kern_s * 1e3,
+                     "kernel": "k_tile_lds<512,int32>", "kernel_ms": kern_s * 1e3,
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
     if not args.no_cpu:
@@ -231,6 +231,29 @@ def extras(torch, mf, lib, workloads, args):
     tfb, _ = timed_steps(fb, 10, 2, torch)
     out["distinct_normal_256"] = {"fwd_ms": tf / 10 * 1e3, "fwd_bwd_ms": tfb / 10 * 1e3,
                                   "ratio": tfb / tf}
+    del xs, g, ys, ams, gx
+    # ragged batch: one plan (graph) launch vs one plain launch per signal
+    x, off, ks = workloads.ragged_impulse(10_000, workloads.SEEDS["ragged_impulse_10k"])
+    xt = torch.from_numpy(x).to(dev)
+    yo = mf.output_offsets(off, ks)
+    y = torch.empty(int(yo[-1]), device=dev)
+    am = torch.empty(int(yo[-1]), dtype=torch.int32, device=dev)
+    plan = mf.Plan(off, ks)
+    tb, _ = timed_steps(lambda: plan.execute(xt, y, am), 3, 1, torch)
+    n_sig = len(ks)
+    xs_v = [xt[off[s]:off[s + 1]] for s in range(n_sig)]
+    ys_v = [y[yo[s]:yo[s + 1]] for s in range(n_sig)]
+    as_v = [am[yo[s]:yo[s + 1]] for s in range(n_sig)]
+
+    def per_signal():
+        for s in range(n_sig):
+            lib.mf_median_filter(xs_v[s], off[s + 1] - off[s], ks[s], ys_v[s], as_v[s])
+    tp, _ = timed_steps(per_signal, 2, 1, torch)
+    out["ragged_impulse_10k"] = {"items": int(off[-1]), "outputs": int(yo[-1]),
+                                 "batched_ms": tb / 3 * 1e3, "per_signal_ms": tp / 2 * 1e3,
+                                 "speedup": (tp / 2) / (tb / 3),
+                                 "batched_outputs_per_s": int(yo[-1]) / (tb / 3)}
+    plan.close()
     return out
 
 

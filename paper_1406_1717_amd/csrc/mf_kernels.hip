@@ -101,34 +101,23 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
         __syncthreads();
     }
 
-    const int ncnt = T.P * s.C * (s.Wn + 1);
-    for (int it = tid; it < ncnt; it += NT) table_zero_item(m, it);
+    // the median before each pair's first step is A's median: remember its
+    // merged position (before the count tables reuse the sort buffer)
+    tail_first_medians(s, T, m, tid, NT);
     __syncthreads();
-    for (int p = 0; p < T.P; p++) {
-        const int lenB = block_len(s, T, p + 1), Cp = ceil_div32(lenB, s.L);
-        const u32 Lr = recip32(s.L);
-        for (int r = tid; r < s.k + lenB; r += NT) table_hist_item(s, m, p, r, Lr, Cp);
+    if (s.C > 1) {
+        tail_table_zero(s, T, m, tid, NT);
+        __syncthreads();
+        tail_table_hist(s, T, m, tid, NT);
+        __syncthreads();
+        tail_table_columns(s, T, m, tid, NT);
+        __syncthreads();
+        tail_table_rows(s, T, m, tid, NT);
+        __syncthreads();
     }
+    if (tail_walk(s, T, m, tid, NT)) atomicOr(err, 1);
     __syncthreads();
-    for (int it = tid; it < T.P * s.Wn; it += NT) { const int p = it / s.Wn; table_column_item(s, m, p, it - p * s.Wn, pair_chunks(s, T, p)); }
-    __syncthreads();
-    for (int it = tid; it < T.P * s.C; it += NT) {
-        const int p = it / s.C, c = it - p * s.C;
-        if (c < pair_chunks(s, T, p)) table_row_item(s, m, p, c);
-    }
-    __syncthreads();
-
-    for (int it = tid; it < T.P * s.C; it += NT) {
-        const int p = it / s.C, c = it - p * s.C;
-        if (c < pair_chunks(s, T, p))
-            if (walk_item(s, T, m, p, c) != 0) atomicOr(err, 1);
-    }
-    __syncthreads();
-
-    for (int p = 0; p < T.P; p++) {
-        const int lenB = block_len(s, T, p + 1);
-        for (int i = tid; i < lenB; i += NT) output_item(s, T, m, p, i, (u32 *)d.y, d.argmed);
-    }
+    tail_output(s, T, m, tid, NT, (u32 *)d.y, d.argmed);
 }
 
 // ------------------------------------------------------------------ LDS path
@@ -187,8 +176,7 @@ __global__ __launch_bounds__(NT) void k_tile_lds(Launch L, int *err)
         bucket_pair_positions(s, T, m, tid, v, fin, pa, pb);
         __syncthreads();
         bucket_pair_write(s, m, v, pa, pb);
-        for (int p = 0; p < T.P; p++)
-            for (int r = s.k + tid; r < s.Mstride; r += NT) pair_pad_item(s, T, m, p, r);
+        tail_pad(s, T, m, tid, NT);
         __syncthreads();
     } else {
         sort_regs(v);

@@ -783,7 +783,19 @@ MF_HD void table_hist_item(const Shape &s, const TileMem &m, int32_t p, int32_t 
     MF_ADD32(cnt_row(s, m, p, b) + (r >> 6), (e & 0x8000u) ? 0x10000u : 1u);
 }
 
-MF_HD u32 recip32(int32_t L) { return (u32)((0xFFFFFFFFull + (u64)L) / (u64)L); }
+// ceil(2^32 / d) for 2 <= d < 2^16; 0 stands for d = 1.
+MF_HD u32 recip32(int32_t d) { return d <= 1 ? 0u : (u32)((0xFFFFFFFFull + (u64)d) / (u64)d); }
+
+// a / d for a, d < 2^16 with dr = recip32(d): a high multiply, exact.
+MF_HD u32 udiv16(u32 a, u32 dr)
+{
+    if (dr == 0u) return a;
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umulhi(a, dr);
+#else
+    return (u32)(((u64)a * dr) >> 32);
+#endif
+}
 
 // Item = (pair p, word w): members per word at every chunk start,
 // = (A items with bucket >= c) + (B items with bucket < c).  Rows are
@@ -832,6 +844,16 @@ MF_HD void table_row_item(const Shape &s, const TileMem &m, int32_t p, int32_t c
         acc += v;
     }
     row[s.Wn] = acc;
+}
+
+// Item = pair p: the window before step 0 is all of A, whose median is A's
+// item of sorted rank h; its merged position is stored in the spare entry
+// pos[k] of the pair (k is odd, so the row has at least one spare entry).
+MF_HD void pair_first_median(const Shape &s, const TileMem &m, int32_t p)
+{
+    const u32 t = sv_t(m.srt[(p << s.logS) + s.h]);
+    const u32 *pos = m.pos + p * s.Pstride;
+    m.pos[p * s.Pstride + s.k] = pos[t] & 0xFFFFu;
 }
 
 // ---------------------------------------------------------------- 5. walk
@@ -921,18 +943,29 @@ MF_HD int walk_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, 
     u16 *stage = m.stage + p * s.k;
     const int32_t h = s.h;
 
-    // the window before step i0 has pc[w] members below word w; the
-    // rank-h member lies in the largest word w with pc[w] <= h
-    int32_t lo = 0, hi = s.Wn;
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if ((int32_t)pc[mid] <= h) lo = mid;
-        else hi = mid;
+    // chunk 0 starts from A's median (pair_first_median); later chunks find
+    // the rank-h member of the window before step i0 from the count table:
+    // it lies in the largest word w with pc[w] <= h
+    int32_t lo, r;
+    u32 dlo, dhi;
+    if (c == 0) {
+        r = (int32_t)pos[s.k];
+        lo = r >> 6;
+        dlo = member_dword(s, Mp, 2 * lo, -1);
+        dhi = member_dword(s, Mp, 2 * lo + 1, -1);
+    } else {
+        lo = 0;
+        int32_t hi = s.Wn;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if ((int32_t)pc[mid] <= h) lo = mid;
+            else hi = mid;
+        }
+        dlo = member_dword(s, Mp, 2 * lo, i0 - 1);
+        dhi = member_dword(s, Mp, 2 * lo + 1, i0 - 1);
+        r = lo * 64 + select64((u64)dlo | ((u64)dhi << 32), h - (int32_t)pc[lo]);
     }
-    const u32 dlo = member_dword(s, Mp, 2 * lo, i0 - 1);
-    const u32 dhi = member_dword(s, Mp, 2 * lo + 1, i0 - 1);
     const u64 word = (u64)dlo | ((u64)dhi << 32);
-    int32_t r = lo * 64 + select64(word, h - (int32_t)pc[lo]);
 
     int32_t base = win_base_for(r);
     u64 W;
@@ -977,6 +1010,65 @@ MF_HD int walk_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, 
     return bad ? -1 : 0;
 }
 
+// ---------------------------------------------------------------- tail phases
+//
+// Thread tid's share (of NT threads) of each phase after the pair orders
+// exist; the kernel separates consecutive phases with barriers, the host
+// check runs each phase for every tid in turn.
+
+MF_HD void tail_first_medians(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
+{
+    for (int32_t p = tid; p < T.P; p += NT) pair_first_median(s, m, p);
+}
+
+MF_HD void tail_table_zero(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
+{
+    const int32_t ncnt = T.P * s.C * (s.Wn + 1);
+    for (int32_t it = tid; it < ncnt; it += NT) table_zero_item(m, it);
+}
+
+MF_HD void tail_table_hist(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
+{
+    const u32 Lr = recip32(s.L);
+    const int32_t per = 2 * s.k;
+    const u32 perr = recip32(per);
+    for (int32_t it = tid; it < T.P * per; it += NT) {
+        const int32_t p = (int32_t)udiv16((u32)it, perr), r = it - p * per;
+        const int32_t lenB = block_len(s, T, p + 1);
+        if (r < s.k + lenB) table_hist_item(s, m, p, r, Lr, ceil_div32(lenB, s.L));
+    }
+}
+
+MF_HD void tail_table_columns(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
+{
+    const u32 Wr = recip32(s.Wn);
+    for (int32_t it = tid; it < T.P * s.Wn; it += NT) {
+        const int32_t p = (int32_t)udiv16((u32)it, Wr);
+        table_column_item(s, m, p, it - p * s.Wn, pair_chunks(s, T, p));
+    }
+}
+
+MF_HD void tail_table_rows(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
+{
+    const u32 Cr = recip32(s.C);
+    for (int32_t it = tid; it < T.P * s.C; it += NT) {
+        const int32_t p = (int32_t)udiv16((u32)it, Cr), c = it - p * s.C;
+        if (c < pair_chunks(s, T, p)) table_row_item(s, m, p, c);
+    }
+}
+
+// Returns nonzero if a walk reported an inconsistency.
+MF_HD int tail_walk(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
+{
+    int bad = 0;
+    const u32 Cr = recip32(s.C);
+    for (int32_t it = tid; it < T.P * s.C; it += NT) {
+        const int32_t p = (int32_t)udiv16((u32)it, Cr), c = it - p * s.C;
+        if (c < pair_chunks(s, T, p)) bad |= walk_item(s, T, m, p, c) != 0;
+    }
+    return bad;
+}
+
 // ---------------------------------------------------------------- 6. output
 
 // Number of outputs written by a tile: sum of len(B) over its pairs, plus
@@ -999,6 +1091,27 @@ MF_HD void output_item(const Shape &s, const Tile &T, const TileMem &m, int32_t 
     const int64_t o = T.o0 + (int64_t)p * s.k + i;
     y[o] = m.xv[(b << s.logS) + t];
     if (argmed) argmed[o] = (int32_t)(T.e0 + (int64_t)b * s.k + t);
+}
+
+MF_HD void tail_output(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT,
+                       u32 *y, int32_t *argmed)
+{
+    const u32 kr = recip32(s.k);
+    for (int32_t it = tid; it < T.P * s.k; it += NT) {
+        const int32_t p = (int32_t)udiv16((u32)it, kr), i = it - p * s.k;
+        if (i < block_len(s, T, p + 1)) output_item(s, T, m, p, i, y, argmed);
+    }
+}
+
+// Thread tid's share of the merged-order padding (after the bucket path).
+MF_HD void tail_pad(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
+{
+    const int32_t npad = s.Mstride - s.k;
+    const u32 padr = recip32(npad);
+    for (int32_t it = tid; it < T.P * npad; it += NT) {
+        const int32_t p = (int32_t)udiv16((u32)it, padr);
+        pair_pad_item(s, T, m, p, s.k + it - p * npad);
+    }
 }
 
 // Output 0: the median of block 0 (Section 3: Y_0's only element).

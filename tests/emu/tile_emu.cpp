@@ -101,8 +101,7 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
             for (int j = 0; j < kRegs; j++) { a[j] = pa[(size_t)q * kRegs + j]; b2[j] = pb[(size_t)q * kRegs + j]; }
             bucket_pair_write(s, m, v, a, b2);
         }
-        for (int p = 0; p < T.P; p++)
-            for (int r = s.k; r < s.Mstride; r++) pair_pad_item(s, T, m, p, r);
+        for (int q = 0; q < threads; q++) tail_pad(s, T, m, q, threads);
         g_fast_tiles++;
     } else {
         for (int q = 0; q < threads; q++) {
@@ -132,20 +131,16 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         g_slow_tiles++;
     }
 
-    for (int e = 0; e < T.P * s.C * (s.Wn + 1); e++) table_zero_item(m, e);
-    for (int p = 0; p < T.P; p++) {
-        const int lenB = block_len(s, T, p + 1), Cp = ceil_div32(lenB, s.L);
-        for (int r = 0; r < s.k + lenB; r++) table_hist_item(s, m, p, r, recip32(s.L), Cp);
+    for (int q = 0; q < threads; q++) tail_first_medians(s, T, m, q, threads);
+    if (s.C > 1) {
+        for (int q = 0; q < threads; q++) tail_table_zero(s, T, m, q, threads);
+        for (int q = 0; q < threads; q++) tail_table_hist(s, T, m, q, threads);
+        for (int q = 0; q < threads; q++) tail_table_columns(s, T, m, q, threads);
+        for (int q = 0; q < threads; q++) tail_table_rows(s, T, m, q, threads);
     }
-    for (int p = 0; p < T.P; p++)
-        for (int w = 0; w < s.Wn; w++) table_column_item(s, m, p, w, pair_chunks(s, T, p));
-    for (int p = 0; p < T.P; p++)
-        for (int c = 0; c < pair_chunks(s, T, p); c++) table_row_item(s, m, p, c);
-    for (int p = 0; p < T.P; p++)
-        for (int c = 0; c < pair_chunks(s, T, p); c++)
-            if (walk_item(s, T, m, p, c) != 0) return -11;
-    for (int p = 0; p < T.P; p++)
-        for (int i = 0; i < block_len(s, T, p + 1); i++) output_item(s, T, m, p, i, y, argmed);
+    for (int q = 0; q < threads; q++)
+        if (tail_walk(s, T, m, q, threads)) return -11;
+    for (int q = 0; q < threads; q++) tail_output(s, T, m, q, threads, y, argmed);
     return 0;
 }
 
