@@ -87,6 +87,21 @@ def cpu_baseline(x, k, budget_s=10.0):
                       % (m, done_out, spent)}
 
 
+def sampled_windows_ok(x, k, y, am, samples=2000, seed=0):
+    h = (k - 1) // 2
+    outs = np.random.default_rng(seed).integers(0, len(am), samples)
+    for o in outs:
+        a = int(am[o])
+        if not (o <= a <= o + k - 1) or y[o] != x[a]:
+            return False
+        w = x[o:o + k]
+        idx = np.arange(o, o + k)
+        below = np.count_nonzero((w < x[a]) | ((w == x[a]) & (idx < a)))
+        if below != h:
+            return False
+    return True
+
+
 def load_traffic():
     try:
         with open(TRAFFIC_FILE) as f:
@@ -137,14 +152,11 @@ def main():
     alg_bytes = 4.0 * n + 8.0 * nout
     achieved = alg_bytes / kern_s / 1e9
 
-    # spot check of the timed output against the definition oracle
-    import oracle
-    rng = np.random.default_rng(0)
-    outs = np.sort(rng.integers(0, nout, 2000))
-    ref = oracle.window_median(x_host, k, outs)
-    got = am.cpu().numpy()[outs]
-    if not np.array_equal(ref, got):
-        print("bench.py: sampled argmedians differ from the oracle", file=sys.stderr)
+    # spot check of the timed output: on sampled windows the argmedian lies
+    # in the window, y is its value, and exactly h window items order below
+    # it by (value, index)
+    if not sampled_windows_ok(x_host, k, y.cpu().numpy(), am.cpu().numpy()):
+        print("bench.py: sampled windows fail the median property", file=sys.stderr)
         sys.exit(3)
 
     traffic = None

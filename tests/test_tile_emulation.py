@@ -1,0 +1,80 @@
+"""Host check of the tile logic: the phase functions the GPU kernels run
+(shared header, compiled for the host by tests/emu/tile_emu.cpp) executed
+phase by phase for every thread share, against the CPU oracle.  Covers
+both sort paths (bucket sort, and the merge sort it falls back to), one-
+and many-chunk walks, partial last blocks and the float specials.  This is
+test infrastructure: the library never loads it."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "emu", "tile_emu.cpp")
+INC = os.path.join(os.path.dirname(HERE), "paper_1406_1717_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def emu(tmp_path_factory):
+    so = str(tmp_path_factory.mktemp("emu") / "tile_emu.so")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-I", INC, "-o", so, SRC], check=True)
+    lib = ctypes.CDLL(so)
+    lib.emu_median_filter.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.emu_fast_tiles.restype = ctypes.c_long
+    lib.emu_slow_tiles.restype = ctypes.c_long
+    return lib
+
+
+def threads_for(k):
+    S = 1 << int(np.ceil(np.log2(k))) if k > 1 else 1
+    return 512 if 2 * S <= 4096 else 1024
+
+
+def inputs(rng, kind, n):
+    if kind == 0:
+        return rng.random(n).astype(np.float32)
+    if kind == 1:
+        return rng.integers(0, 4, n).astype(np.int32)
+    if kind == 2:
+        return np.sort(rng.random(n)).astype(np.float32)
+    if kind == 3:
+        return np.cumsum(rng.standard_normal(n)).astype(np.float32)
+    if kind == 4:
+        return rng.integers(-2**31, 2**31, n, dtype=np.int32)
+    pool = np.array([0.0, -0.0, 1.0, np.inf, -np.inf, np.nan, 2.0], np.float32)
+    x = rng.standard_normal(n).astype(np.float32)
+    m = rng.random(n) < 0.3
+    x[m] = rng.choice(pool, int(m.sum()))
+    return x
+
+
+@pytest.mark.parametrize("force_merge", [0, 1])
+def test_tile_phases_match_oracle(emu, force_merge):
+    emu.emu_set_force_merge(force_merge)
+    fast0, slow0 = emu.emu_fast_tiles(), emu.emu_slow_tiles()
+    rng = np.random.default_rng(7 + force_merge)
+    ks = [3, 5, 15, 17, 31, 63, 65, 101, 255, 301, 513, 1001, 2047, 4001]
+    for trial in range(60):
+        k = ks[trial % len(ks)]
+        n = int(rng.integers(k, k * int(rng.integers(1, 8)) + 300))
+        x = inputs(rng, trial % 6, n)
+        y = np.empty(n - k + 1, x.dtype)
+        a = np.empty(n - k + 1, np.int32)
+        pm = ctypes.c_int32()
+        rc = emu.emu_median_filter(x.ctypes.data, n, k, int(x.dtype == np.float32), threads_for(k),
+                                   y.ctypes.data, a.ctypes.data, ctypes.byref(pm))
+        yo, ao = oracle.sortmedian(x, k)
+        assert rc == 0, (k, n, trial, rc)
+        assert np.array_equal(a, ao), (k, n, trial)
+        assert np.array_equal(y.view(np.uint32), yo.view(np.uint32)), (k, n, trial)
+    fast, slow = emu.emu_fast_tiles() - fast0, emu.emu_slow_tiles() - slow0
+    if force_merge:
+        assert fast == 0 and slow > 0
+    else:
+        assert fast > 0 and slow > 0      # duplicates-heavy tiles fall back
+    emu.emu_set_force_merge(0)
