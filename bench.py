@@ -251,6 +251,9 @@ def extras(torch, mf, lib, workloads, args):
     y = torch.empty(int(yo[-1]), device=dev)
     am = torch.empty(int(yo[-1]), dtype=torch.int32, device=dev)
     plan = mf.Plan(off, ks)
+    t0 = time.perf_counter()
+    tune = plan.autotune(xt, y, am, reps=2)
+    tune_s = time.perf_counter() - t0
     tb, _ = timed_steps(lambda: plan.execute(xt, y, am), 3, 1, torch)
     n_sig = len(ks)
     xs_v = [xt[off[s]:off[s + 1]] for s in range(n_sig)]
@@ -264,7 +267,9 @@ def extras(torch, mf, lib, workloads, args):
     out["ragged_impulse_10k"] = {"items": int(off[-1]), "outputs": int(yo[-1]),
                                  "batched_ms": tb / 3 * 1e3, "per_signal_ms": tp / 2 * 1e3,
                                  "speedup": (tp / 2) / (tb / 3),
-                                 "batched_outputs_per_s": int(yo[-1]) / (tb / 3)}
+                                 "batched_outputs_per_s": int(yo[-1]) / (tb / 3),
+                                 "launch_config": tune["config"], "tuned_ms_per_config": tune["tuned_ms"],
+                                 "autotune_s": tune_s}
     plan.close()
     return out
 

@@ -91,11 +91,19 @@ mf_status mf_median_filter_backward_batched(const float *grad_y, const int32_t *
                                             const int64_t *x_offsets, const int32_t *ks,
                                             int32_t num_signals, float *grad_x, void *stream);
 
-/* Explicit plans for the ragged batch: mf_plan_create_batched validates the
- * host arrays, builds the device work list and picks tile shapes (timing
- * candidates once per window class when tuning is enabled);
- * mf_plan_execute enqueues the whole batch as one graph launch on `stream`.
- * The plan owns device memory until mf_plan_destroy. */
+/* Explicit plans for the ragged batch (x_offsets, ks: host arrays as for
+ * mf_median_filter_batched, read only during the call).
+ *
+ * mf_plan_create_batched validates every signal (any invalid signal
+ * rejects the whole batch with its status), assigns each signal a tile
+ * family by its window, and uploads device work lists of (signal, tile)
+ * units ordered by window, largest first.  mf_plan_execute enqueues the
+ * whole forward batch on `stream` as one graph launch; the graph is
+ * captured on first use and again whenever x, y, argmed or the launch
+ * configuration change.  One plan must not be executed from two host
+ * threads or on two streams at once: its persistent launches share one
+ * work counter per launch.  The plan owns its device memory until
+ * mf_plan_destroy (which synchronizes the device). */
 typedef struct mf_plan mf_plan;
 mf_status mf_plan_create_batched(const int64_t *x_offsets, const int32_t *ks,
                                  int32_t num_signals, mf_plan **out);
@@ -105,6 +113,29 @@ mf_status mf_plan_execute_backward(mf_plan *plan, const float *grad_y, const int
                                    float *grad_x, void *stream);
 int64_t   mf_plan_output_length(const mf_plan *plan);
 void      mf_plan_destroy(mf_plan *plan);
+
+/* Launch configurations of a plan's forward.  Windows above 4096 (global
+ * workspace tiles) and k = 1 always have launches of their own. */
+typedef enum {
+    MF_LAUNCH_PER_FAMILY = 0,     /* one launch per tile family, one workgroup per tile */
+    MF_LAUNCH_PERSISTENT = 1,     /* one persistent launch per tile family (default) */
+    MF_LAUNCH_PERSISTENT_ONE = 2  /* one persistent launch for every LDS tile (k <= 4096),
+                                     all as 1024-thread tiles */
+} mf_launch_config;
+
+/* Times every launch configuration on these buffers (`reps` timed executes
+ * each, 1..100, after one warm-up) and keeps the fastest for later
+ * executes.  Writes y and argmed (the batch's outputs, as mf_plan_execute),
+ * and synchronizes `stream`; MF_ERR_UNSUPPORTED while `stream` is being
+ * captured.  On failure the configuration is left as it was. */
+mf_status mf_plan_autotune(mf_plan *plan, const float *x, float *y, int32_t *argmed,
+                           int32_t reps, void *stream);
+/* Forces a configuration (an mf_launch_config value). */
+mf_status mf_plan_set_config(mf_plan *plan, int32_t config);
+/* The configuration in use, and (if tuned_ms is not null) the mean time
+ * per execute of each configuration from the last mf_plan_autotune, in
+ * milliseconds, -1 where not timed: tuned_ms has 3 entries. */
+mf_status mf_plan_get_config(const mf_plan *plan, int32_t *config, float *tuned_ms);
 
 /* n-k+1 for a valid (n, k), else -1.  Host only. */
 int64_t mf_output_length(int64_t n, int32_t k);

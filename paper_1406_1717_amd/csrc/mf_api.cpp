@@ -189,6 +189,8 @@ mf_status backward_rows(const float *gy, const int32_t *argmed, int64_t rows, in
 
 struct PathGroup {
     Path path;
+    bool persistent = false;     // resident grid over a work counter
+    bool owns = true;            // d_units belongs to this group
     int64_t nunits = 0;
     SigDesc *d_sigs = nullptr;   // all signals of the plan
     Unit *d_units = nullptr;
@@ -196,22 +198,29 @@ struct PathGroup {
     int64_t ws_stride = 0;
 };
 
+const int kConfigs = 3;              // mf_launch_config values
+const int kDefaultConfig = MF_LAUNCH_PERSISTENT;
+
 struct mf_plan {
     int32_t num_signals = 0;
     int64_t total_in = 0, total_out = 0;
     std::vector<int64_t> offsets;
     std::vector<int32_t> ks;
     SigDesc *d_sigs = nullptr;
-    std::vector<PathGroup> groups;
+    std::vector<PathGroup> groups[kConfigs];   // forward launches per configuration
+    int32_t config = kDefaultConfig;
+    float tuned_ms[kConfigs] = {-1.f, -1.f, -1.f};
+    uint32_t *d_next = nullptr;                // work counters, one per group
     // backward work list
     Unit *d_bunits = nullptr;
     int64_t nbunits = 0;
-    // captured forward graph and the pointers it was captured with
+    // captured forward graph and what it was captured with
     hipGraphExec_t gexec = nullptr;
     const void *gx = nullptr;
     void *gy = nullptr;
     int32_t *gam = nullptr;
     unsigned char *gws = nullptr;
+    int32_t gconfig = -1;
     int64_t ws_need = 0;
 };
 
@@ -219,11 +228,37 @@ static void plan_free(mf_plan *p)
 {
     if (!p) return;
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
-    for (auto &g : p->groups)
-        if (g.d_units) (void)hipFree(g.d_units);
+    for (auto &gs : p->groups)
+        for (auto &g : gs)
+            if (g.owns && g.d_units) (void)hipFree(g.d_units);
     if (p->d_sigs) (void)hipFree(p->d_sigs);
+    if (p->d_next) (void)hipFree(p->d_next);
     if (p->d_bunits) (void)hipFree(p->d_bunits);
     delete p;
+}
+
+// Uploads a work list as a new group of configuration `cfg`.
+static mf_status plan_add_group(mf_plan *p, int cfg, Path f, bool persistent, const std::vector<Unit> &units,
+                                size_t lds, int64_t ws_stride)
+{
+    if (f != PATH_IDENTITY && f != PATH_GLOBAL && units.size() > 0x7FFFFFFFull)
+        return fail(MF_ERR_UNSUPPORTED, "too many tiles in one batch");
+    PathGroup g;
+    g.path = f;
+    g.persistent = persistent;
+    g.nunits = (int64_t)units.size();
+    g.lds = lds;
+    g.ws_stride = ws_stride;
+    g.d_sigs = p->d_sigs;
+    hipError_t e = hipMalloc(&g.d_units, sizeof(Unit) * units.size());
+    if (e == hipSuccess) e = hipMemcpy(g.d_units, units.data(), sizeof(Unit) * units.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (g.d_units) (void)hipFree(g.d_units);
+        return hip_fail(e, "plan work list");
+    }
+    if (f == PATH_GLOBAL) p->ws_need = std::max(p->ws_need, ws_stride * std::min<int64_t>(kWsSlots, g.nunits));
+    p->groups[cfg].push_back(g);
+    return MF_OK;
 }
 
 extern "C" mf_status mf_plan_create_batched(const int64_t *x_offsets, const int32_t *ks,
@@ -258,15 +293,35 @@ extern "C" mf_status mf_plan_create_batched(const int64_t *x_offsets, const int3
     p->offsets.assign(x_offsets, x_offsets + num_signals + 1);
     p->ks.assign(ks, ks + num_signals);
 
+    hipError_t e = hipMalloc(&p->d_sigs, sizeof(SigDesc) * sigs.size());
+    if (e == hipSuccess) e = hipMemcpy(p->d_sigs, sigs.data(), sizeof(SigDesc) * sigs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&p->d_next, sizeof(uint32_t) * 8);
+    if (e != hipSuccess) { plan_free(p); return hip_fail(e, "plan signal table"); }
+
     // forward work lists, one per kernel family; within a family the
-    // longest windows go first so that the heaviest tiles start early
+    // longest windows go first so that the heaviest tiles start early.
+    // MF_LAUNCH_PER_FAMILY and MF_LAUNCH_PERSISTENT share these lists;
+    // MF_LAUNCH_PERSISTENT_ONE puts every LDS tile into one list of
+    // 1024-thread tiles, launched first.
     const Path fams[4] = {PATH_LDS_LARGE, PATH_LDS_SMALL, PATH_GLOBAL, PATH_IDENTITY};
     std::vector<int32_t> order((size_t)num_signals);
     for (int32_t s = 0; s < num_signals; s++) order[s] = s;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ks[a] > ks[b]; });
-    hipError_t e = hipMalloc(&p->d_sigs, sizeof(SigDesc) * sigs.size());
-    if (e == hipSuccess) e = hipMemcpy(p->d_sigs, sigs.data(), sizeof(SigDesc) * sigs.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) { plan_free(p); return hip_fail(e, "plan signal table"); }
+    {
+        std::vector<Unit> units;
+        size_t lds = 0;
+        for (int32_t s : order) {
+            const Path f = path_for(ks[s]);
+            if (f != PATH_LDS_SMALL && f != PATH_LDS_LARGE) continue;
+            const int64_t nt = tiles_for(PATH_LDS_LARGE, sigs[s].n, ks[s]);
+            for (int64_t t = 0; t < nt; t++) units.push_back(Unit{s, 0, t});
+            lds = std::max(lds, (size_t)lds_bytes_for(PATH_LDS_LARGE, ks[s]));
+        }
+        if (!units.empty()) {
+            st = plan_add_group(p, MF_LAUNCH_PERSISTENT_ONE, PATH_LDS_LARGE, true, units, lds, 0);
+            if (st != MF_OK) { plan_free(p); return st; }
+        }
+    }
     for (Path f : fams) {
         std::vector<Unit> units;
         size_t lds = 0;
@@ -279,21 +334,16 @@ extern "C" mf_status mf_plan_create_batched(const int64_t *x_offsets, const int3
             if (f == PATH_GLOBAL) ws_stride = std::max(ws_stride, global_ws_stride(ks[s]));
         }
         if (units.empty()) continue;
-        if (f != PATH_IDENTITY && f != PATH_GLOBAL && units.size() > 0x7FFFFFFFull) {
-            plan_free(p);
-            return fail(MF_ERR_UNSUPPORTED, "too many tiles in one batch");
+        st = plan_add_group(p, MF_LAUNCH_PER_FAMILY, f, false, units, lds, ws_stride);
+        if (st != MF_OK) { plan_free(p); return st; }
+        PathGroup shared = p->groups[MF_LAUNCH_PER_FAMILY].back();
+        shared.owns = false;
+        shared.persistent = (f == PATH_LDS_SMALL || f == PATH_LDS_LARGE);
+        p->groups[MF_LAUNCH_PERSISTENT].push_back(shared);
+        if (f == PATH_GLOBAL || f == PATH_IDENTITY) {
+            shared.persistent = false;
+            p->groups[MF_LAUNCH_PERSISTENT_ONE].push_back(shared);
         }
-        PathGroup g;
-        g.path = f;
-        g.nunits = (int64_t)units.size();
-        g.lds = lds;
-        g.ws_stride = ws_stride;
-        g.d_sigs = p->d_sigs;
-        e = hipMalloc(&g.d_units, sizeof(Unit) * units.size());
-        if (e == hipSuccess) e = hipMemcpy(g.d_units, units.data(), sizeof(Unit) * units.size(), hipMemcpyHostToDevice);
-        if (e != hipSuccess) { if (g.d_units) (void)hipFree(g.d_units); plan_free(p); return hip_fail(e, "plan work list"); }
-        if (f == PATH_GLOBAL) p->ws_need = std::max(p->ws_need, ws_stride * std::min<int64_t>(kWsSlots, g.nunits));
-        p->groups.push_back(g);
     }
     // backward work list
     {
@@ -314,7 +364,9 @@ extern "C" mf_status mf_plan_create_batched(const int64_t *x_offsets, const int3
 static mf_status plan_enqueue(mf_plan *p, Device &D, const void *x, void *y, int32_t *argmed,
                               unsigned char *ws, hipStream_t st)
 {
-    for (const PathGroup &g : p->groups) {
+    const std::vector<PathGroup> &gs = p->groups[p->config];
+    for (size_t gi = 0; gi < gs.size(); gi++) {
+        const PathGroup &g = gs[gi];
         Launch L;
         memset(&L, 0, sizeof L);
         L.x = x;
@@ -323,6 +375,11 @@ static mf_status plan_enqueue(mf_plan *p, Device &D, const void *x, void *y, int
         L.sigs = g.d_sigs;
         L.units = g.d_units;
         L.nunits = g.nunits;
+        if (g.persistent) {
+            MF_HIP(launch_forward_persistent(g.path, L, g.lds, p->d_next + gi, D.d_err, st),
+                   "batched persistent launch");
+            continue;
+        }
         const int64_t slots = std::min<int64_t>(kWsSlots, g.nunits);
         MF_HIP(launch_forward(g.path, true, L, g.lds, ws, g.ws_stride, slots, D.d_err, st), "batched launch");
     }
@@ -341,7 +398,7 @@ extern "C" mf_status mf_plan_execute(mf_plan *p, const float *x, float *y, int32
     if (p->ws_need > 0 && (s = acquire_ws(*D, p->ws_need, st, &ws)) != MF_OK) return s;
     // the graph bakes in the data and workspace pointers; capture again
     // when any of them changed
-    if (!p->gexec || p->gx != x || p->gy != y || p->gam != argmed || p->gws != ws) {
+    if (!p->gexec || p->gx != x || p->gy != y || p->gam != argmed || p->gws != ws || p->gconfig != p->config) {
         if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
         hipStream_t cs;
         MF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate(capture)");
@@ -359,6 +416,7 @@ extern "C" mf_status mf_plan_execute(mf_plan *p, const float *x, float *y, int32
         p->gy = y;
         p->gam = argmed;
         p->gws = ws;
+        p->gconfig = p->config;
     }
     MF_HIP(hipGraphLaunch(p->gexec, st), "hipGraphLaunch");
     if (p->ws_need > 0) return release_ws(*D, st);
@@ -383,6 +441,69 @@ extern "C" mf_status mf_plan_execute_backward(mf_plan *p, const float *grad_y, c
 }
 
 extern "C" int64_t mf_plan_output_length(const mf_plan *p) { return p ? p->total_out : -1; }
+
+extern "C" mf_status mf_plan_set_config(mf_plan *p, int32_t config)
+{
+    if (!p) return fail(MF_ERR_INVALID_VALUE, "plan must not be null");
+    if (config < 0 || config >= kConfigs)
+        return fail(MF_ERR_INVALID_VALUE, "config = %d is not a launch configuration", config);
+    p->config = config;
+    return MF_OK;
+}
+
+extern "C" mf_status mf_plan_get_config(const mf_plan *p, int32_t *config, float *tuned_ms)
+{
+    if (!p || !config) return fail(MF_ERR_INVALID_VALUE, "plan and config must not be null");
+    *config = p->config;
+    if (tuned_ms)
+        for (int c = 0; c < kConfigs; c++) tuned_ms[c] = p->tuned_ms[c];
+    return MF_OK;
+}
+
+extern "C" mf_status mf_plan_autotune(mf_plan *p, const float *x, float *y, int32_t *argmed, int32_t reps,
+                                      void *stream)
+{
+    if (!p) return fail(MF_ERR_INVALID_VALUE, "plan must not be null");
+    if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
+    if (reps < 1 || reps > 100) return fail(MF_ERR_INVALID_VALUE, "reps = %d must be in 1..100", reps);
+    hipStream_t st = (hipStream_t)stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    MF_HIP(hipStreamIsCapturing(st, &cs), "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) return fail(MF_ERR_UNSUPPORTED, "cannot tune on a capturing stream");
+    hipEvent_t a = nullptr, b = nullptr;
+    MF_HIP(hipEventCreate(&a), "hipEventCreate");
+    hipError_t e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hip_fail(e, "hipEventCreate");
+    }
+    const int32_t before = p->config;
+    mf_status s = MF_OK;
+    int best = -1;
+    for (int c = 0; c < kConfigs && s == MF_OK; c++) {
+        p->config = c;
+        s = mf_plan_execute(p, x, y, argmed, stream);   // warm-up (and capture)
+        if (s != MF_OK) break;
+        e = hipEventRecord(a, st);
+        for (int r = 0; r < reps && s == MF_OK && e == hipSuccess; r++) s = mf_plan_execute(p, x, y, argmed, stream);
+        if (s != MF_OK) break;
+        if (e == hipSuccess) e = hipEventRecord(b, st);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e != hipSuccess) {
+            s = hip_fail(e, "autotune timing");
+            break;
+        }
+        p->tuned_ms[c] = ms / (float)reps;
+        if (best < 0 || p->tuned_ms[c] < p->tuned_ms[best]) best = c;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    p->config = (s == MF_OK && best >= 0) ? best : before;
+    return s;
+}
+
 
 extern "C" void mf_plan_destroy(mf_plan *p)
 {

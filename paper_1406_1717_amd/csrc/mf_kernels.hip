@@ -4,6 +4,8 @@
 //   k_tile_lds<NT>   k <= 4096: one workgroup per tile, every tile buffer
 //                    in LDS (NT = 512 threads for blocks up to 2048 slots,
 //                    1024 above).
+//   k_tile_lds_persistent  the same tiles for ragged batches: a resident
+//                    grid taking units from a work counter.
 //   k_tile_global    4096 < k <= 32767: one pair per tile, the first sort
 //                    levels in LDS and the tile buffers in a per-workgroup
 //                    global workspace; workgroups loop over tiles.
@@ -122,11 +124,10 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
 
 // ------------------------------------------------------------------ LDS path
 
+// One tile of the LDS path, every buffer in the workgroup's LDS.
 template <int NT, bool F32>
-__global__ __launch_bounds__(NT) void k_tile_lds(Launch L, int *err)
+__device__ __forceinline__ void lds_tile(const Resolved &d, unsigned char *lds, int *err)
 {
-    extern __shared__ __align__(16) unsigned char lds[];
-    const Resolved d = unit_of(L, blockIdx.x);
     const int64_t tile = d.tile;
     const int tid = threadIdx.x;
 
@@ -191,6 +192,38 @@ __global__ __launch_bounds__(NT) void k_tile_lds(Launch L, int *err)
     }
 
     tile_tail<NT>(s, T, m, d, err, fast);
+}
+
+// One workgroup per work unit.
+template <int NT, bool F32>
+__global__ __launch_bounds__(NT) void k_tile_lds(Launch L, int *err)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    lds_tile<NT, F32>(unit_of(L, blockIdx.x), lds, err);
+}
+
+// Persistent form: a grid sized to the resident workgroups takes units in
+// work-list order from the counter *next (zero at launch) until the list
+// is exhausted; every workgroup leaves the loop on the same condition.
+template <int NT, bool F32>
+__global__ __launch_bounds__(NT) void k_tile_lds_persistent(Launch L, u32 *next, int *err)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ u32 cur;
+    for (;;) {
+        __syncthreads();   // the previous tile is done with LDS and with cur
+        if (threadIdx.x == 0) cur = atomicAdd(next, 1u);
+        __syncthreads();
+        const u32 u = cur;
+        if ((int64_t)u >= L.nunits) break;
+        lds_tile<NT, F32>(unit_of(L, u), lds, err);
+    }
+}
+
+__global__ void k_zero_counters(u32 *c, int n)
+{
+    const int i = threadIdx.x;
+    if (i < n) c[i] = 0u;
 }
 
 // ------------------------------------------------------------------ global path
@@ -462,6 +495,8 @@ hipError_t prepare_kernels()
     MF_ATTR((k_tile_lds<kLdsSmall, false>))
     MF_ATTR((k_tile_lds<kLdsLarge, true>))
     MF_ATTR((k_tile_lds<kLdsLarge, false>))
+    MF_ATTR((k_tile_lds_persistent<kLdsSmall, true>))
+    MF_ATTR((k_tile_lds_persistent<kLdsLarge, true>))
     MF_ATTR((k_tile_global<true>))
     MF_ATTR((k_tile_global<false>))
 #undef MF_ATTR
@@ -496,6 +531,30 @@ hipError_t launch_forward(Path p, bool f32, const Launch &L, size_t lds_bytes,
     default:
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_persistent(Path p, const Launch &L, size_t lds_bytes, u32 *next,
+                                    int *d_err, hipStream_t st)
+{
+    if (L.nunits <= 0) return hipSuccess;
+    if (p != PATH_LDS_SMALL && p != PATH_LDS_LARGE) return hipErrorInvalidValue;
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int nt = p == PATH_LDS_SMALL ? kLdsSmall : kLdsLarge;
+    const void *kern = p == PATH_LDS_SMALL ? (const void *)k_tile_lds_persistent<kLdsSmall, true>
+                                           : (const void *)k_tile_lds_persistent<kLdsLarge, true>;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, lds_bytes);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    int64_t grid = (int64_t)cus * per_cu;
+    if (grid > L.nunits) grid = L.nunits;
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, next, 1);
+    if (p == PATH_LDS_SMALL)
+        hipLaunchKernelGGL((k_tile_lds_persistent<kLdsSmall, true>), dim3((unsigned)grid), dim3(kLdsSmall), lds_bytes, st, L, next, d_err);
+    else
+        hipLaunchKernelGGL((k_tile_lds_persistent<kLdsLarge, true>), dim3((unsigned)grid), dim3(kLdsLarge), lds_bytes, st, L, next, d_err);
     return hipGetLastError();
 }
 

@@ -43,6 +43,9 @@ def load():
         "mf_plan_create_batched": [P, P, I32, P],
         "mf_plan_execute": [P, P, P, P, P],
         "mf_plan_execute_backward": [P, P, P, P, P],
+        "mf_plan_autotune": [P, P, P, P, I32, P],
+        "mf_plan_set_config": [P, I32],
+        "mf_plan_get_config": [P, P, P],
         "mf_check_device_error": [P],
     }
     for name, args in sig.items():
@@ -165,6 +168,21 @@ class Plan:
     def execute_backward(self, grad_y, argmed, grad_x, stream=None):
         _check(load().mf_plan_execute_backward(self._h, _ptr(grad_y), _ptr(argmed), _ptr(grad_x),
                                                _stream(stream)))
+
+    def autotune(self, x, y, argmed, reps=2, stream=None):
+        """Times each launch configuration on these buffers and keeps the
+        fastest.  Returns {"config": c, "tuned_ms": [ms per configuration]}."""
+        _check(load().mf_plan_autotune(self._h, _ptr(x), _ptr(y), _ptr(argmed), int(reps), _stream(stream)))
+        return self.config_info()
+
+    def set_config(self, config):
+        _check(load().mf_plan_set_config(self._h, int(config)))
+
+    def config_info(self):
+        c = ctypes.c_int32()
+        ms = (ctypes.c_float * 3)()
+        _check(load().mf_plan_get_config(self._h, ctypes.byref(c), ms))
+        return {"config": int(c.value), "tuned_ms": [float(v) for v in ms]}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

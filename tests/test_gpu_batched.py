@@ -51,6 +51,16 @@ def test_batched_mixed_paths_and_edges():
     y, am = mf.median_filter_batched(torch.from_numpy(x).to(DEV), off, np.array(ks, np.int32))
     torch.cuda.synchronize()
     check_batch(x, off, np.array(ks), y.cpu().numpy(), am.cpu().numpy())
+    plan = mf.Plan(off, np.array(ks, np.int32))
+    xt = torch.from_numpy(x).to(DEV)
+    for config in (0, 1, 2):
+        plan.set_config(config)
+        y2 = torch.full_like(y, -1.0)
+        am2 = torch.full_like(am, -1)
+        plan.execute(xt, y2, am2)
+        torch.cuda.synchronize()
+        assert torch.equal(am2, am) and torch.equal(y2.view(torch.int32), y.view(torch.int32)), config
+    plan.close()
 
 
 def test_plan_graph_replay_new_data():
@@ -73,6 +83,44 @@ def test_plan_graph_replay_new_data():
     plan.execute(xt, y2, am2)
     torch.cuda.synchronize()
     assert torch.equal(y, y2) and torch.equal(am, am2)
+    plan.close()
+
+
+@pytest.mark.parametrize("config", [0, 1, 2])
+def test_plan_each_launch_config(config):
+    """Every launch configuration (per family, persistent per family, one
+    persistent launch) gives the oracle's result; replayed twice."""
+    x, off, ks = small_batch(16 + config, num=30)
+    plan = mf.Plan(off, ks)
+    plan.set_config(config)
+    assert plan.config_info()["config"] == config
+    xt = torch.from_numpy(x).to(DEV)
+    y = torch.empty(plan.output_length, device=DEV)
+    am = torch.empty(plan.output_length, dtype=torch.int32, device=DEV)
+    for rep in range(2):
+        y.fill_(-1.0)
+        am.fill_(-1)
+        plan.execute(xt, y, am)
+        torch.cuda.synchronize()
+        mf.lib.mf_check_device_error()
+        check_batch(x, off, ks, y.cpu().numpy(), am.cpu().numpy())
+    plan.close()
+
+
+def test_plan_autotune_picks_a_config():
+    x, off, ks = small_batch(19, num=30)
+    plan = mf.Plan(off, ks)
+    xt = torch.from_numpy(x).to(DEV)
+    y = torch.empty(plan.output_length, device=DEV)
+    am = torch.empty(plan.output_length, dtype=torch.int32, device=DEV)
+    info = plan.autotune(xt, y, am, reps=2)
+    assert all(t > 0 for t in info["tuned_ms"]), info
+    assert info["tuned_ms"][info["config"]] == min(info["tuned_ms"])
+    y.zero_()
+    am.zero_()
+    plan.execute(xt, y, am)
+    torch.cuda.synchronize()
+    check_batch(x, off, ks, y.cpu().numpy(), am.cpu().numpy())
     plan.close()
 
 

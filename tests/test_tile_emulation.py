@@ -53,8 +53,10 @@ def inputs(rng, kind, n):
     return x
 
 
-@pytest.mark.parametrize("force_merge", [0, 1])
-def test_tile_phases_match_oracle(emu, force_merge):
+@pytest.mark.parametrize("force_merge,wide", [(0, False), (1, False), (0, True)])
+def test_tile_phases_match_oracle(emu, force_merge, wide):
+    """wide: every tile with 1024 threads (the one-launch batch configuration
+    also runs small windows as 1024-thread tiles)."""
     emu.emu_set_force_merge(force_merge)
     fast0, slow0 = emu.emu_fast_tiles(), emu.emu_slow_tiles()
     rng = np.random.default_rng(7 + force_merge)
@@ -66,7 +68,8 @@ def test_tile_phases_match_oracle(emu, force_merge):
         y = np.empty(n - k + 1, x.dtype)
         a = np.empty(n - k + 1, np.int32)
         pm = ctypes.c_int32()
-        rc = emu.emu_median_filter(x.ctypes.data, n, k, int(x.dtype == np.float32), threads_for(k),
+        threads = 1024 if wide else threads_for(k)
+        rc = emu.emu_median_filter(x.ctypes.data, n, k, int(x.dtype == np.float32), threads,
                                    y.ctypes.data, a.ctypes.data, ctypes.byref(pm))
         yo, ao = oracle.sortmedian(x, k)
         assert rc == 0, (k, n, trial, rc)
