@@ -93,15 +93,11 @@ __device__ __forceinline__ Resolved unit_of(const Launch &L, int64_t uidx)
 // filled m.xv and m.srt.  NT threads, barriers between phases.
 template <int NT>
 __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
-                          int *err, bool merged)
+                                          int *err)
 {
     const int tid = threadIdx.x;
-    if (!merged) {
-        const int ipp = merge_items_per_pair(s);
-        for (int it = tid; it < T.P * ipp; it += NT) pair_merge_item(s, T, m, it / ipp, it % ipp);
-        if (T.j0 == 1 && tid == 0) output_first(s, T, m, (u32 *)d.y, d.argmed);
-        __syncthreads();
-    }
+    tail_pair_merge(s, T, m, tid, NT, (u32 *)d.y, d.argmed);
+    __syncthreads();
 
     // the median before each pair's first step is A's median: remember its
     // merged position (before the count tables reuse the sort buffer)
@@ -112,7 +108,9 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
         __syncthreads();
         tail_table_hist(s, T, m, tid, NT);
         __syncthreads();
-        tail_table_columns(s, T, m, tid, NT);
+        tail_table_colsums(s, T, m, tid, NT);
+        __syncthreads();
+        tail_table_colapply(s, T, m, tid, NT);
         __syncthreads();
         tail_table_rows(s, T, m, tid, NT);
         __syncthreads();
@@ -152,12 +150,23 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, unsigned char *lds, 
     bool fast = s.S >= kRegs;
     if (fast) bucket_minmax(m, v);
     __syncthreads();
-    if (fast && tid < T.NB) bucket_shift_item(s, m, tid);
+    if (fast && tid < T.NB) bucket_shift_item<F32>(s, m, tid, 0);
     __syncthreads();
     u32 arr[kRegs];
-    if (fast) bucket_count(s, T, m, tid, v, arr);
+    if (fast) bucket_count<F32>(s, T, m, tid, v, arr);
     __syncthreads();
-    fast = fast && (m.flag[0] == 0u);
+    if (fast && m.flag[0] != 0u) {
+        // crowded buckets: count again with the map linear in the float bit
+        // pattern (the flag is the same for every thread)
+        __syncthreads();
+        for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
+        if (tid < T.NB) bucket_shift_item<F32>(s, m, tid, 1);
+        if (tid == 0) m.flag[0] = 0u;
+        __syncthreads();
+        bucket_count<F32>(s, T, m, tid, v, arr);
+        __syncthreads();
+    }
+    fast = fast && (m.flag[0] & 1u) == 0u;
     if (fast) {
         __shared__ u32 wave_tot[NT / 64];
         u32 c[kRegs];
@@ -165,19 +174,12 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, unsigned char *lds, 
         const u32 excl = seg_excl_scan<NT>(tot, s.S / kRegs, wave_tot);
         bucket_scan_store(m, tid, excl, c);
         __syncthreads();
-        bucket_scatter(s, T, m, tid, v, arr);
+        bucket_scatter<F32>(s, T, m, tid, v, arr);
         __syncthreads();
         u32 fin[kRegs];
-        bucket_rank(s, T, m, tid, v, fin);
+        bucket_rank<F32>(s, T, m, tid, v, fin);
         __syncthreads();
         bucket_place(s, m, v, fin);
-        __syncthreads();
-        if (T.j0 == 1 && tid == 0) output_first(s, T, m, (u32 *)d.y, d.argmed);
-        int32_t pa[kRegs], pb[kRegs];
-        bucket_pair_positions(s, T, m, tid, v, fin, pa, pb);
-        __syncthreads();
-        bucket_pair_write(s, m, v, pa, pb);
-        tail_pad(s, T, m, tid, NT);
         __syncthreads();
     } else {
         sort_regs(v);
@@ -191,7 +193,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, unsigned char *lds, 
         __syncthreads();
     }
 
-    tile_tail<NT>(s, T, m, d, err, fast);
+    tile_tail<NT>(s, T, m, d, err);
 }
 
 // One workgroup per work unit.
@@ -229,7 +231,7 @@ __global__ void k_zero_counters(u32 *c, int n)
 // ------------------------------------------------------------------ global path
 
 struct GLayout {
-    int64_t xv, srt, srt2, M, pos, cnt, stage, total;
+    int64_t xv, srt, srt2, M, pos, cnt, ctot, stage, total;
 };
 
 __host__ __device__ inline void make_glayout(const Shape &s, GLayout *g)
@@ -240,11 +242,13 @@ __host__ __device__ inline void make_glayout(const Shape &s, GLayout *g)
     g->srt2 = off; off += 8ll * s.cap;
     g->M = off;    off += 2ll * s.Pmax * s.Mstride;
     off = (off + 255) & ~255ll;
-    g->pos = off;  off += 4ll * s.Pmax * s.k;
+    g->pos = off;  off += 4ll * s.Pmax * s.Pstride;
     off = (off + 255) & ~255ll;
     g->total = off;
     int64_t a = g->srt2;
     g->cnt = a;    a += 4ll * s.Pmax * s.C * (s.Wn + 1);
+    a = (a + 15) & ~15ll;
+    g->ctot = a;   a += 4ll * s.Pmax * s.Wn * kColGroups;
     a = (a + 15) & ~15ll;
     g->stage = a;
 }
@@ -273,12 +277,13 @@ __global__ __launch_bounds__(kGlobalThreads) void k_tile_global(Launch L, unsign
         global_shape(d.n, d.k, &s);
         GLayout g;
         make_glayout(s, &g);
-        TileMem m;
+        TileMem m = {};
         m.xv = (u32 *)(base + g.xv);
         m.srt = (u64 *)(base + g.srt);
         m.M = (u16 *)(base + g.M);
         m.pos = (u32 *)(base + g.pos);
         m.cnt = (u32 *)(base + g.cnt);
+        m.ctot = (u32 *)(base + g.ctot);
         m.stage = (u16 *)(base + g.stage);
         u64 *srt2 = (u64 *)(base + g.srt2);
         const Tile T = make_tile(s, tile);
@@ -327,7 +332,7 @@ __global__ __launch_bounds__(kGlobalThreads) void k_tile_global(Launch L, unsign
             __syncthreads();
         }
         (void)bufs;
-        tile_tail<kGlobalThreads>(s, T, m, d, err, false);
+        tile_tail<kGlobalThreads>(s, T, m, d, err);
     }
 }
 

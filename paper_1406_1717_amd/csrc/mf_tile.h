@@ -57,6 +57,7 @@ static const u64 kPadAll = ~0ull;          // slot beyond the tile's blocks
 static const u32 kMPad = 0xFFFFu;          // merged-order padding: never a member
 static const int kRegs = 8;                // sort values per thread
 static const int32_t kPairBudget = 48 * 1024; // bytes of M + pos per tile
+static const int kColGroups = 8;           // row groups per count-table column
 
 // ---------------------------------------------------------------- keys
 
@@ -130,7 +131,7 @@ struct Shape {
     int64_t nblocks; // ceil(n / k)
     int64_t npairs;  // nblocks - 1
     int64_t ntiles;  // tiles covering all pairs (1 when there is no pair)
-    int32_t L;       // walk chunk length (multiple of 4)
+    int32_t L;       // walk chunk length (odd)
     int32_t C;       // chunks of a full pair, ceil(k / L)
     int32_t Wn;      // 64-position words of a pair's merged order, ceil(2k/64)
     int32_t Mstride; // u16 entries per pair in M (= Wn * 64)
@@ -144,8 +145,9 @@ struct Layout {
     int32_t M;       // u16[Pmax * Mstride]
     int32_t pos;     // u32[Pmax * k]     posA | posB << 16
     int32_t cnt;     // u32[Pmax * C * (Wn + 1)]   (aliases srt)
+    int32_t ctot;    // u32[Pmax * Wn * kColGroups] (aliases srt)
     int32_t bk;      // u32[cap] bucket counters   (aliases M, pos)
-    int32_t info;    // u32[3 * nbmax + 1]         (aliases M, pos)
+    int32_t info;    // u32[7 * nbmax + 1]         (aliases M, pos)
     int32_t nbmax;   // blocks of a full tile
     int32_t stage;   // u16[Pmax * k]              (aliases srt)
     int32_t total;   // bytes
@@ -176,17 +178,19 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
     if (P * per_pair > kPairBudget) P = kPairBudget / per_pair;
     if (P < 1) P = 1;
     s->Pmax = P;
-    // chunk length: a multiple of 4, at least 16, large enough that the
-    // tile has no more chunks than threads and that the count tables and
-    // the staged medians of all pairs fit in the sort buffer they reuse
-    int32_t L = 16;
+    // chunk length: odd (lanes walking neighbouring chunks then read the
+    // position maps on distinct LDS banks), at least 17, large enough that
+    // the tile has no more chunks than threads and that the count tables,
+    // their column-group totals and the staged medians of all pairs fit in
+    // the sort buffer they reuse
+    int32_t L = 17;
     const int32_t per_thread = (int32_t)(((int64_t)P * k + threads - 1) / threads);
-    if (L < per_thread) L = (per_thread + 3) & ~3;
+    if (L < per_thread) L = per_thread | 1;
     for (;;) {
         const int64_t C = (k + L - 1) / L;
-        const int64_t need = (int64_t)P * (4 * C * (s->Wn + 1) + 2 * (int64_t)k + 32);
+        const int64_t need = (int64_t)P * (4 * C * (s->Wn + 1) + 4 * kColGroups * s->Wn + 2 * (int64_t)k + 48);
         if (need <= 8ll * s->cap || L >= k) break;
-        L += 4;
+        L += 2;
     }
     s->L = L;
     s->C = ceil_div32(k, L);
@@ -209,11 +213,13 @@ MF_HD void make_layout(const Shape &s, Layout *l)
     l->bk = l->M;
     l->info = l->bk + 4 * s.cap;
     l->nbmax = s.Pmax + 1;
-    const int32_t bend = l->info + 4 * (3 * (s.Pmax + 1) + 1);
+    const int32_t bend = l->info + 4 * (7 * (s.Pmax + 1) + 1);
     if (off < bend) off = (bend + 15) & ~15;
     l->total = off;
     int32_t a = l->srt;
     l->cnt = a;      a += 4 * s.Pmax * s.C * (s.Wn + 1);
+    a = (a + 15) & ~15;
+    l->ctot = a;     a += 4 * s.Pmax * s.Wn * kColGroups;
     a = (a + 15) & ~15;
     l->stage = a;    a += 2 * s.Pmax * s.k;
     if (a > l->srt + 8 * s.cap) l->total = -1;   // aliased region overflows
@@ -253,13 +259,18 @@ struct TileMem {
     u32 *bk;         // bucket counters / starts, slot-indexed like srt
     u32 *bmin;       // per block: smallest key
     u32 *bmax;       // per block: largest key
-    u32 *bshift;     // per block: key -> bucket shift
-    u32 *flag;       // set when a bucket overflows
+    u32 *bshift;     // per block: bucket shift (key and integer-log maps)
+    u32 *bmode;      // per block: bucket map (BK_KEY, BK_FLIN, BK_ILOG)
+    u32 *blo;        // per block: mapped value of the block minimum
+    u32 *bfmin;      // per block: float minimum (BK_FLIN), as bits
+    u32 *bscale;     // per block: buckets per unit value (BK_FLIN), as bits
+    u32 *flag;       // bit 0: a bucket passed kBucketMax; bit 1: kBucketSoft
     u32 *xv;
     u64 *srt;
     u16 *M;
     u32 *pos;
     u32 *cnt;
+    u32 *ctot;
     u16 *stage;
 };
 
@@ -270,12 +281,17 @@ MF_HD TileMem tile_mem(unsigned char *base, const Layout &l)
     m.bmin = (u32 *)(base + l.info);
     m.bmax = m.bmin + l.nbmax;
     m.bshift = m.bmax + l.nbmax;
-    m.flag = m.bshift + l.nbmax;
+    m.bmode = m.bshift + l.nbmax;
+    m.blo = m.bmode + l.nbmax;
+    m.bfmin = m.blo + l.nbmax;
+    m.bscale = m.bfmin + l.nbmax;
+    m.flag = m.bscale + l.nbmax;
     m.xv = (u32 *)(base + l.xv);
     m.srt = (u64 *)(base + l.srt);
     m.M = (u16 *)(base + l.M);
     m.pos = (u32 *)(base + l.pos);
     m.cnt = (u32 *)(base + l.cnt);
+    m.ctot = (u32 *)(base + l.ctot);
     m.stage = (u16 *)(base + l.stage);
     return m;
 }
@@ -398,14 +414,61 @@ MF_HD u32 sv_t(u64 v) { return (u32)(v & 0xFFFFu); }
 //
 // The common path of phase 2 (any sort may serve as the piecewise sort,
 // Section 1 "Contribution"): each block's keys are spread over S buckets by
-// (key - min) >> shift; an item's arrival number in its bucket, the bucket
-// starts (a scan of the counts) and its rank among the bucket's items by
-// the full (key, t) value give its sorted position.  A tile whose buckets
-// hold more than kBucketMax items (heavy ties, narrow clusters) takes the
-// merge sort above instead.  Needs S >= 16, so that the kRegs slots of a
-// thread lie in one block.
+// a monotone map of the value onto [0, S); an item's arrival number in its
+// bucket, the bucket starts (a scan of the counts) and its rank among the
+// bucket's items by the full (key, t) value give its sorted position.
+//
+// Maps: the first count uses one linear in the value (integers: the key;
+// floats with a finite range: (v - min) * S / (max - min)).  If a bucket
+// then holds kBucketSoft or more items (values clustered against the
+// block's range, as with rare outliers), the tile counts again with a map
+// linear in the float bit pattern of the value (for floats the key itself,
+// for integers the key of the converted float), which spreads values
+// evenly over orders of magnitude.  A tile whose buckets still hold more
+// than kBucketMax items (heavy ties) takes the merge sort above instead.
+// Needs S >= kRegs, so that the kRegs slots of a thread lie in one block.
 
 static const int kBucketMax = 32;
+static const int kBucketSoft = 12;
+enum { BK_KEY = 0, BK_FLIN = 1, BK_ILOG = 2 };
+
+MF_HD u32 f32_bits(float f)
+{
+    union { float f; u32 u; } c;
+    c.f = f;
+    return c.u;
+}
+
+MF_HD float bits_f32(u32 u)
+{
+    union { float f; u32 u; } c;
+    c.u = u;
+    return c.f;
+}
+
+// Float value of a float key (finite keys; -0.0 comes back as +0.0).
+MF_HD float f32_of_key(u32 key) { return bits_f32((key & 0x80000000u) ? (key & 0x7FFFFFFFu) : ~key); }
+
+// Key of the float nearest to the integer of an integer key (monotone).
+MF_HD u32 ilog_key(u32 key) { return key_of_f32(f32_bits((float)(int32_t)(key ^ 0x80000000u))); }
+
+// A block's bucket map.
+struct BucketFn {
+    u32 mode, lo, sh;
+    float fmin, scale;
+    u32 top;   // S - 1
+};
+
+template <bool F32>
+MF_HD u32 bucket_of(const BucketFn &f, u32 key)
+{
+    if (F32 && f.mode == BK_FLIN) {
+        const u32 q = (u32)((f32_of_key(key) - f.fmin) * f.scale);
+        return q < f.top ? q : f.top;
+    }
+    const u32 mk = (!F32 && f.mode == BK_ILOG) ? ilog_key(key) : key;
+    return (mk - f.lo) >> f.sh;
+}
 
 MF_HD bool sv_valid(u64 v) { return (v & 0xFFFFu) != 0xFFFFu; }
 MF_HD int32_t sv_block(u64 v) { return (int32_t)(v >> 48); }
@@ -423,7 +486,9 @@ MF_HD void bucket_info_init(const TileMem &m, int32_t b)
 #define MF_MIN32(ptr, v) atomicMin((unsigned int *)(ptr), (unsigned int)(v))
 #define MF_MAX32(ptr, v) atomicMax((unsigned int *)(ptr), (unsigned int)(v))
 #define MF_ADDRTN32(ptr, v) atomicAdd((unsigned int *)(ptr), (unsigned int)(v))
+#define MF_OR32(ptr, v) atomicOr((unsigned int *)(ptr), (unsigned int)(v))
 #else
+#define MF_OR32(ptr, v) (*(ptr) |= (v))
 #define MF_MIN32(ptr, v) (*(ptr) = (*(ptr) < (v) ? *(ptr) : (v)))
 #define MF_MAX32(ptr, v) (*(ptr) = (*(ptr) > (v) ? *(ptr) : (v)))
 static inline u32 mf_addrtn32(u32 *p, u32 v) { u32 o = *p; *p += v; return o; }
@@ -450,18 +515,56 @@ MF_HD void bucket_minmax(const TileMem &m, const u64 (&v)[kRegs])
     }
 }
 
-// Item = block b: bucket = (key - min) >> shift lands in [0, S).
-MF_HD void bucket_shift_item(const Shape &s, const TileMem &m, int32_t b)
+// Item = block b: the bucket map of `pass` (0: linear in the value, 1:
+// linear in the float bit pattern), landing in [0, S) over the block's range.
+template <bool F32>
+MF_HD void bucket_shift_item(const Shape &s, const TileMem &m, int32_t b, int pass)
 {
-    const u32 range = m.bmax[b] - m.bmin[b];
+    const u32 mn = m.bmin[b], mx = m.bmax[b];
+    u32 mode = BK_KEY, lo = mn, hi = mx;
+    float fmin = 0.f, scale = 0.f;
+    if (F32 && pass == 0 && mn > 0x007FFFFFu && mx < 0xFF800000u) {   // finite range
+        const float a = f32_of_key(mn), r = f32_of_key(mx) - a;
+        if (r > 0.f && r <= 3.0e38f) {
+            const float sc = (float)s.S / r;
+            if (sc <= 3.0e38f) {
+                mode = BK_FLIN;
+                fmin = a;
+                scale = sc;
+            }
+        }
+    }
+    if (!F32 && pass == 1) {
+        mode = BK_ILOG;
+        lo = ilog_key(mn);
+        hi = ilog_key(mx);
+    }
+    const u32 range = hi - lo;
     int32_t bits = 0;
     while (bits < 32 && (range >> bits) != 0u) bits++;
     m.bshift[b] = (u32)(bits > s.logS ? bits - s.logS : 0);
+    m.bmode[b] = mode;
+    m.blo[b] = lo;
+    m.bfmin[b] = f32_bits(fmin);
+    m.bscale[b] = f32_bits(scale);
+}
+
+MF_HD BucketFn bucket_fn(const Shape &s, const TileMem &m, int32_t b)
+{
+    BucketFn f;
+    f.mode = m.bmode[b];
+    f.lo = m.blo[b];
+    f.sh = m.bshift[b];
+    f.fmin = bits_f32(m.bfmin[b]);
+    f.scale = bits_f32(m.bscale[b]);
+    f.top = (u32)s.S - 1u;
+    return f;
 }
 
 // A block's bucket parameters, read once per thread.
 struct BlockView {
-    u32 mn, mx, sh, len;
+    u32 mn, mx, len;
+    BucketFn f;
     const u32 *start;      // bucket starts (after the scan)
     const u64 *row;        // the block's sort buffer
 };
@@ -471,7 +574,7 @@ MF_HD BlockView block_view(const Shape &s, const Tile &T, const TileMem &m, int3
     BlockView V;
     V.mn = m.bmin[b];
     V.mx = m.bmax[b];
-    V.sh = m.bshift[b];
+    V.f = bucket_fn(s, m, b);
     V.len = (u32)block_len(s, T, b);
     V.start = m.bk + (b << s.logS);
     V.row = m.srt + (b << s.logS);
@@ -487,22 +590,28 @@ MF_HD int32_t thread_block(const Shape &s, const Tile &T, int32_t tid)
 
 // Per thread: count each item in its bucket; the old count is its arrival
 // number.  Sets the flag when a bucket passes kBucketMax.
+template <bool F32>
 MF_HD void bucket_count(const Shape &s, const Tile &T, const TileMem &m, int32_t tid,
                         const u64 (&v)[kRegs], u32 (&arr)[kRegs])
 {
     const int32_t b = thread_block(s, T, tid);
-    const u32 mn = b >= 0 ? m.bmin[b] : 0u, sh = b >= 0 ? m.bshift[b] : 0u;
+    BucketFn f;
+    f.mode = BK_KEY;
+    f.lo = f.sh = 0u;
+    f.fmin = f.scale = 0.f;
+    f.top = 0u;
+    if (b >= 0) f = bucket_fn(s, m, b);
     u32 *cnt = m.bk + (b >= 0 ? (b << s.logS) : 0);
-    bool over = false;
+    u32 mx = 0u;
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         arr[j] = 0u;
         if (sv_valid(v[j])) {
-            arr[j] = MF_ADDRTN32(cnt + ((sv_key(v[j]) - mn) >> sh), 1u);
-            over = over || (arr[j] >= (u32)kBucketMax);
+            arr[j] = MF_ADDRTN32(cnt + bucket_of<F32>(f, sv_key(v[j])), 1u);
+            mx = arr[j] > mx ? arr[j] : mx;
         }
     }
-    if (over) m.flag[0] = 1u;
+    if (mx >= (u32)kBucketSoft) MF_OR32(m.flag, mx >= (u32)kBucketMax ? 3u : 2u);
 }
 
 // Per thread: the local part of the bucket scan.  Thread tid owns counters
@@ -540,14 +649,16 @@ MF_HD void bucket_scan_store(const TileMem &m, int32_t tid, u32 excl, const u32 
 }
 
 // Bucket [lo, hi) of key in block view V (key within the block's range).
+template <bool F32>
 MF_HD void view_bucket(const Shape &s, const BlockView &V, u32 key, u32 &lo, u32 &hi)
 {
-    const u32 bk = (key - V.mn) >> V.sh;
+    const u32 bk = bucket_of<F32>(V.f, key);
     lo = V.start[bk];
     hi = (bk + 1u < (u32)s.S) ? V.start[bk + 1] : V.len;
 }
 
 // Per thread: place each item at bucket start + arrival number.
+template <bool F32>
 MF_HD void bucket_scatter(const Shape &s, const Tile &T, const TileMem &m, int32_t tid,
                           const u64 (&v)[kRegs], const u32 (&arr)[kRegs])
 {
@@ -557,12 +668,13 @@ MF_HD void bucket_scatter(const Shape &s, const Tile &T, const TileMem &m, int32
     u64 *row = m.srt + (b << s.logS);
 #pragma unroll
     for (int j = 0; j < kRegs; j++)
-        if (sv_valid(v[j])) row[V.start[(sv_key(v[j]) - V.mn) >> V.sh] + arr[j]] = v[j];
+        if (sv_valid(v[j])) row[V.start[bucket_of<F32>(V.f, sv_key(v[j]))] + arr[j]] = v[j];
 }
 
 // Per thread: final position = bucket start + rank among the bucket's items.
 // All of the thread's buckets are scanned together, one item per round,
 // with selects rather than branches.
+template <bool F32>
 MF_HD void bucket_rank(const Shape &s, const Tile &T, const TileMem &m, int32_t tid,
                        const u64 (&v)[kRegs], u32 (&fin)[kRegs])
 {
@@ -575,7 +687,7 @@ MF_HD void bucket_rank(const Shape &s, const Tile &T, const TileMem &m, int32_t 
     for (int j = 0; j < kRegs; j++) {
         x[j] = 0u;
         hi[j] = 0u;
-        if (b >= 0 && sv_valid(v[j])) view_bucket(s, V, sv_key(v[j]), x[j], hi[j]);
+        if (b >= 0 && sv_valid(v[j])) view_bucket<F32>(s, V, sv_key(v[j]), x[j], hi[j]);
         fin[j] = x[j];
     }
     for (int round = 0; round < kBucketMax; round++) {
@@ -600,102 +712,18 @@ MF_HD void bucket_place(const Shape &s, const TileMem &m, const u64 (&v)[kRegs],
         if (sv_valid(v[j])) m.srt[(sv_block(v[j]) << s.logS) + fin[j]] = v[j];
 }
 
-// Items of sorted block V with key < v (strict) or key <= v, for the
-// thread's items: range checks and bucket reads for all items first, then
-// the buckets are scanned together, one item per round, with selects.
-MF_HD void view_count_below(const Shape &s, const BlockView &V, const u64 (&v)[kRegs], bool strict,
-                            bool use, int32_t (&out)[kRegs])
-{
-    u32 lo[kRegs], hi[kRegs];
-#pragma unroll
-    for (int j = 0; j < kRegs; j++) {
-        const u32 key = sv_key(v[j]);
-        lo[j] = 0u;
-        hi[j] = 0u;
-        if (use && sv_valid(v[j])) {
-            if (key > V.mx || (!strict && key == V.mx)) lo[j] = hi[j] = V.len;
-            else if (!(key < V.mn || (strict && key == V.mn))) view_bucket(s, V, key, lo[j], hi[j]);
-        }
-    }
-    for (int round = 0; round <= kBucketMax; round++) {
-        u32 more = 0u;
-#pragma unroll
-        for (int j = 0; j < kRegs; j++) {
-            const bool act = lo[j] < hi[j];
-            const u32 kx = sv_key(V.row[act ? lo[j] : 0u]);
-            const u32 key = sv_key(v[j]);
-            const bool below = strict ? (kx < key) : (kx <= key);
-            lo[j] += (act && below) ? 1u : 0u;
-            hi[j] = (act && !below) ? lo[j] : hi[j];
-            more |= (lo[j] < hi[j]) ? 1u : 0u;
-        }
-        if (!more) break;
-    }
-#pragma unroll
-    for (int j = 0; j < kRegs; j++) out[j] = (use && sv_valid(v[j])) ? (int32_t)lo[j] : -1;
-}
-
-// Per thread: merged positions of the thread's items in the pair where
-// their block is A (pair b, B = block b+1: B's items with smaller key come
-// first) and in the pair where it is B (pair b-1: A's items with key <= the
-// item's key come first).  -1 where that pair is not in the tile.
-MF_HD void bucket_pair_positions(const Shape &s, const Tile &T, const TileMem &m, int32_t tid,
-                                 const u64 (&v)[kRegs], const u32 (&fin)[kRegs],
-                                 int32_t (&pa)[kRegs], int32_t (&pb)[kRegs])
-{
-    const int32_t b = thread_block(s, T, tid);
-    const bool hasA = b >= 0 && b < T.P, hasB = b >= 1;
-    BlockView VB, VA;
-    VB.row = VA.row = m.srt;
-    VB.len = VA.len = 0u;
-    VB.mn = VA.mn = VB.mx = VA.mx = VB.sh = VA.sh = 0u;
-    VB.start = VA.start = m.bk;
-    if (hasA) VB = block_view(s, T, m, b + 1);
-    if (hasB) VA = block_view(s, T, m, b - 1);
-    view_count_below(s, VB, v, true, hasA, pa);
-    view_count_below(s, VA, v, false, hasB, pb);
-#pragma unroll
-    for (int j = 0; j < kRegs; j++) {
-        if (pa[j] >= 0) pa[j] += (int32_t)fin[j];
-        if (pb[j] >= 0) pb[j] += (int32_t)fin[j];
-    }
-}
-
-// Per thread: write M and the position maps (after every lookup is done).
-MF_HD void bucket_pair_write(const Shape &s, const TileMem &m, const u64 (&v)[kRegs],
-                             const int32_t (&pa)[kRegs], const int32_t (&pb)[kRegs])
-{
-#pragma unroll
-    for (int j = 0; j < kRegs; j++) {
-        if (sv_valid(v[j])) {
-            const int32_t b = sv_block(v[j]);
-            const u32 t = sv_t(v[j]);
-            if (pa[j] >= 0) {
-                m.M[b * s.Mstride + pa[j]] = (u16)t;
-                ((u16 *)(m.pos + b * s.Pstride + t))[0] = (u16)pa[j];
-            }
-            if (pb[j] >= 0) {
-                m.M[(b - 1) * s.Mstride + pb[j]] = (u16)(0x8000u | t);
-                ((u16 *)(m.pos + (b - 1) * s.Pstride + t))[1] = (u16)pb[j];
-            }
-        }
-    }
-}
-
-// Item = (pair p, position r >= k + len B): merged-order padding.
-MF_HD void pair_pad_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, int32_t r)
-{
-    if (r >= s.k + block_len(s, T, p + 1)) m.M[p * s.Mstride + r] = (u16)kMPad;
-}
-
 // ---------------------------------------------------------------- 3. pair merge
 
 
-static const int kMergeSeg = 32;   // merged outputs per pair-merge item
+// Merged outputs per pair-merge item: odd, so that the lanes of a wave,
+// which take consecutive segments, read LDS words on distinct banks.
+static const int kMergeSeg = 9;
 
-MF_HD int32_t merge_items_per_pair(const Shape &s) { return s.Mstride / kMergeSeg; }
+MF_HD int32_t merge_items_per_pair(const Shape &s) { return (s.Mstride + kMergeSeg - 1) / kMergeSeg; }
 
-// Item = (pair p, segment g): merged positions [g*32, g*32 + 32) of pair p.
+// Item = (pair p, segment g): merged positions [9g, 9g + 9) of pair p, by
+// merge path over the sorted blocks A = p and B = p + 1 (A first on equal
+// keys), writing M and the position maps.
 MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
                            int32_t p, int32_t g)
 {
@@ -705,14 +733,15 @@ MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
     const u64 *A = m.srt + ((int32_t)p << s.logS);
     const u64 *B = m.srt + ((int32_t)(p + 1) << s.logS);
     u16 *Mp = m.M + p * s.Mstride;
-    u32 *pos = m.pos + p * s.Pstride;
+    u16 *pos = (u16 *)(m.pos + p * s.Pstride);
     const int32_t d = g * kMergeSeg;
-    int32_t lo = d > lenB ? d - lenB : 0;
-    int32_t hi = d < lenA ? d : lenA;
     if (d >= mlen) {   // padding of the merged order
-        for (int q = 0; q < kMergeSeg; q++) Mp[d + q] = (u16)kMPad;
+        for (int q = 0; q < kMergeSeg; q++)
+            if (d + q < s.Mstride) Mp[d + q] = (u16)kMPad;
         return;
     }
+    int32_t lo = d > lenB ? d - lenB : 0;
+    int32_t hi = d < lenA ? d : lenA;
     while (lo < hi) {
         const int32_t mid = (lo + hi) >> 1;
         // A[mid] precedes B[d-1-mid] iff keyA <= keyB (A first on ties)
@@ -720,22 +749,25 @@ MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
         else hi = mid;
     }
     int32_t a = lo, b = d - lo;
+    u64 va = a < lenA ? A[a] : 0ull, vb = b < lenB ? B[b] : 0ull;
+#pragma unroll
     for (int q = 0; q < kMergeSeg; q++) {
         const int32_t r = d + q;
-        if (r >= mlen) { Mp[r] = (u16)kMPad; continue; }
-        bool takeA;
-        if (a >= lenA) takeA = false;
-        else if (b >= lenB) takeA = true;
-        else takeA = sv_key(A[a]) <= sv_key(B[b]);
-        if (takeA) {
-            const u32 t = sv_t(A[a++]);
-            Mp[r] = (u16)t;
-            ((u16 *)(pos + t))[0] = (u16)r;          // posA (low half)
-        } else {
-            const u32 t = sv_t(B[b++]);
-            Mp[r] = (u16)(0x8000u | t);
-            ((u16 *)(pos + t))[1] = (u16)r;          // posB (high half)
+        if (r >= mlen) {
+            if (r < s.Mstride) Mp[r] = (u16)kMPad;
+            continue;
         }
+        const bool takeA = a < lenA && (b >= lenB || sv_key(va) <= sv_key(vb));
+        const u32 t = sv_t(takeA ? va : vb);
+        Mp[r] = (u16)(takeA ? t : (0x8000u | t));
+        pos[2 * t + (takeA ? 0 : 1)] = (u16)r;   // posA low half, posB high half
+        a += takeA ? 1 : 0;
+        b += takeA ? 0 : 1;
+        const int32_t ni = takeA ? a : b;
+        const bool more = takeA ? (a < lenA) : (b < lenB);
+        const u64 nv = more ? (takeA ? A : B)[ni] : 0ull;
+        va = takeA ? nv : va;
+        vb = takeA ? vb : nv;
     }
 }
 
@@ -797,39 +829,50 @@ MF_HD u32 udiv16(u32 a, u32 dr)
 #endif
 }
 
-// Item = (pair p, word w): members per word at every chunk start,
-// = (A items with bucket >= c) + (B items with bucket < c).  Rows are
-// visited eight at a time so that their loads are in flight together.
-MF_HD void table_column_item(const Shape &s, const TileMem &m, int32_t p, int32_t w, int32_t Cp)
+// Column pass (two phases): entry (c, w) becomes the members of word w at
+// chunk start c, (A items with bucket >= c) + (B items with bucket < c).
+// Each column's rows are cut into kColGroups groups of R = ceil(C / 8)
+// consecutive rows; an item is (pair p, word w, group g).
+
+MF_HD int32_t col_rows(const Shape &s) { return (s.C + kColGroups - 1) / kColGroups; }
+
+// Phase one: the group's A and B totals (low and high halves) into ctot.
+MF_HD void table_colsum_item(const Shape &s, const TileMem &m, int32_t p, int32_t w, int32_t g, int32_t Cp)
 {
-    const int32_t stride = s.Wn + 1;
+    const int32_t stride = s.Wn + 1, R = col_rows(s);
+    const u32 *col = cnt_row(s, m, p, 0) + w;
+    const int32_t c0 = g * R, c1 = (c0 + R < Cp) ? c0 + R : Cp;
+    u32 tot = 0u;
+    for (int32_t c = c0; c < c1; c++) tot += col[c * stride];
+    m.ctot[(p * s.Wn + w) * kColGroups + g] = tot;
+}
+
+// Phase two: A suffix sums and B exclusive prefix sums down the group,
+// starting from the totals of the other groups.
+MF_HD void table_colapply_item(const Shape &s, const TileMem &m, int32_t p, int32_t w, int32_t g, int32_t Cp)
+{
+    const int32_t stride = s.Wn + 1, R = col_rows(s);
     u32 *col = cnt_row(s, m, p, 0) + w;
-    u32 sa = 0u;
-    for (int32_t c0 = ((Cp - 1) & ~7); c0 >= 0; c0 -= 8) {
-        u32 vals[8];
+    const int32_t c0 = g * R, c1 = (c0 + R < Cp) ? c0 + R : Cp;
+    if (c0 >= c1) return;
+    const u32 *gt = m.ctot + (p * s.Wn + w) * kColGroups;
+    u32 sa = 0u, pb = 0u;
 #pragma unroll
-        for (int q = 0; q < 8; q++) vals[q] = (c0 + q < Cp) ? col[(c0 + q) * stride] : 0u;
-#pragma unroll
-        for (int q = 7; q >= 0; q--) {
-            sa += vals[q] & 0xFFFFu;
-            vals[q] = (vals[q] & 0xFFFF0000u) | sa;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; q++) if (c0 + q < Cp) col[(c0 + q) * stride] = vals[q];
+    for (int q = 0; q < kColGroups; q++) {
+        const u32 v = gt[q];
+        sa += (q > g) ? (v & 0xFFFFu) : 0u;
+        pb += (q < g) ? (v >> 16) : 0u;
     }
-    u32 pb = 0u;
-    for (int32_t c0 = 0; c0 < Cp; c0 += 8) {
-        u32 vals[8];
-#pragma unroll
-        for (int q = 0; q < 8; q++) vals[q] = (c0 + q < Cp) ? col[(c0 + q) * stride] : 0u;
-#pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const u32 v = vals[q];
-            vals[q] = (v & 0xFFFFu) + pb;
-            pb += v >> 16;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; q++) if (c0 + q < Cp) col[(c0 + q) * stride] = vals[q];
+    // A: suffix over the group's rows, visited from the last
+    for (int32_t c = c1 - 1; c >= c0; c--) {
+        const u32 v = col[c * stride];
+        sa += v & 0xFFFFu;
+        col[c * stride] = (v & 0xFFFF0000u) | sa;
+    }
+    for (int32_t c = c0; c < c1; c++) {
+        const u32 v = col[c * stride];
+        col[c * stride] = (v & 0xFFFFu) + pb;
+        pb += v >> 16;
     }
 }
 
@@ -1012,9 +1055,10 @@ MF_HD int walk_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, 
 
 // ---------------------------------------------------------------- tail phases
 //
-// Thread tid's share (of NT threads) of each phase after the pair orders
-// exist; the kernel separates consecutive phases with barriers, the host
+// Thread tid's share (of NT threads) of each phase after the blocks are
+// sorted; the kernel separates consecutive phases with barriers, the host
 // check runs each phase for every tid in turn.
+
 
 MF_HD void tail_first_medians(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
 {
@@ -1039,12 +1083,23 @@ MF_HD void tail_table_hist(const Shape &s, const Tile &T, const TileMem &m, int3
     }
 }
 
-MF_HD void tail_table_columns(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
+MF_HD void tail_table_colsums(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
 {
     const u32 Wr = recip32(s.Wn);
-    for (int32_t it = tid; it < T.P * s.Wn; it += NT) {
-        const int32_t p = (int32_t)udiv16((u32)it, Wr);
-        table_column_item(s, m, p, it - p * s.Wn, pair_chunks(s, T, p));
+    for (int32_t it = tid; it < T.P * s.Wn * kColGroups; it += NT) {
+        const int32_t pw = it / kColGroups, g = it % kColGroups;
+        const int32_t p = (int32_t)udiv16((u32)pw, Wr);
+        table_colsum_item(s, m, p, pw - p * s.Wn, g, pair_chunks(s, T, p));
+    }
+}
+
+MF_HD void tail_table_colapply(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
+{
+    const u32 Wr = recip32(s.Wn);
+    for (int32_t it = tid; it < T.P * s.Wn * kColGroups; it += NT) {
+        const int32_t pw = it / kColGroups, g = it % kColGroups;
+        const int32_t p = (int32_t)udiv16((u32)pw, Wr);
+        table_colapply_item(s, m, p, pw - p * s.Wn, g, pair_chunks(s, T, p));
     }
 }
 
@@ -1103,23 +1158,25 @@ MF_HD void tail_output(const Shape &s, const Tile &T, const TileMem &m, int32_t 
     }
 }
 
-// Thread tid's share of the merged-order padding (after the bucket path).
-MF_HD void tail_pad(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
-{
-    const int32_t npad = s.Mstride - s.k;
-    const u32 padr = recip32(npad);
-    for (int32_t it = tid; it < T.P * npad; it += NT) {
-        const int32_t p = (int32_t)udiv16((u32)it, padr);
-        pair_pad_item(s, T, m, p, s.k + it - p * npad);
-    }
-}
-
 // Output 0: the median of block 0 (Section 3: Y_0's only element).
 MF_HD void output_first(const Shape &s, const Tile &T, const TileMem &m, u32 *y, int32_t *argmed)
 {
     const int32_t t = (int32_t)sv_t(m.srt[s.h]);
     y[0] = m.xv[t];
     if (argmed) argmed[0] = t;
+}
+
+// Thread tid's share of the pair orders (phase 3) and output 0.
+MF_HD void tail_pair_merge(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT,
+                           u32 *y, int32_t *argmed)
+{
+    const int32_t ipp = merge_items_per_pair(s);
+    const u32 ir = recip32(ipp);
+    for (int32_t it = tid; it < T.P * ipp; it += NT) {
+        const int32_t p = (int32_t)udiv16((u32)it, ir);
+        pair_merge_item(s, T, m, p, it - p * ipp);
+    }
+    if (T.j0 == 1 && tid == 0) output_first(s, T, m, y, argmed);
 }
 
 }  // namespace mf

@@ -14,10 +14,11 @@
 using namespace mf;
 
 static int g_force_merge = 0;
-static long g_fast_tiles = 0, g_slow_tiles = 0;
+static long g_fast_tiles = 0, g_slow_tiles = 0, g_recount_tiles = 0;
 extern "C" void emu_set_force_merge(int v) { g_force_merge = v; }
 extern "C" long emu_fast_tiles(void) { return g_fast_tiles; }
 extern "C" long emu_slow_tiles(void) { return g_slow_tiles; }
+extern "C" long emu_recount_tiles(void) { return g_recount_tiles; }
 
 template <bool F32>
 static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
@@ -40,16 +41,26 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
     bool fast = s.S >= kRegs && !g_force_merge;
     auto V = [&](int q, u64 (&v)[kRegs]) { for (int j = 0; j < kRegs; j++) v[j] = regs[(size_t)q * kRegs + j]; };
     std::vector<u32> arr((size_t)threads * kRegs), fin((size_t)threads * kRegs);
-    std::vector<int32_t> pa((size_t)threads * kRegs), pb((size_t)threads * kRegs);
     if (fast) {
         for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); bucket_minmax(m, v); }
-        for (int b = 0; b < T.NB; b++) bucket_shift_item(s, m, b);
+        for (int b = 0; b < T.NB; b++) bucket_shift_item<F32>(s, m, b, 0);
         for (int q = 0; q < threads; q++) {
             u64 v[kRegs]; V(q, v); u32 a[kRegs];
-            bucket_count(s, T, m, q, v, a);
+            bucket_count<F32>(s, T, m, q, v, a);
             for (int j = 0; j < kRegs; j++) arr[(size_t)q * kRegs + j] = a[j];
         }
-        fast = m.flag[0] == 0u;
+        if (m.flag[0] != 0u) {
+            g_recount_tiles++;
+            for (int e = 0; e < s.cap; e++) bucket_zero_item(m, e);
+            for (int b = 0; b < T.NB; b++) bucket_shift_item<F32>(s, m, b, 1);
+            m.flag[0] = 0u;
+            for (int q = 0; q < threads; q++) {
+                u64 v[kRegs]; V(q, v); u32 a[kRegs];
+                bucket_count<F32>(s, T, m, q, v, a);
+                for (int j = 0; j < kRegs; j++) arr[(size_t)q * kRegs + j] = a[j];
+            }
+        }
+        fast = (m.flag[0] & 1u) == 0u;
     }
     if (fast) {
         const int G = s.S / kRegs;
@@ -70,11 +81,11 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         for (int q = 0; q < threads; q++) {
             u64 v[kRegs]; V(q, v); u32 a[kRegs];
             for (int j = 0; j < kRegs; j++) a[j] = arr[(size_t)q * kRegs + j];
-            bucket_scatter(s, T, m, q, v, a);
+            bucket_scatter<F32>(s, T, m, q, v, a);
         }
         for (int q = 0; q < threads; q++) {
             u64 v[kRegs]; V(q, v); u32 f[kRegs];
-            bucket_rank(s, T, m, q, v, f);
+            bucket_rank<F32>(s, T, m, q, v, f);
             for (int j = 0; j < kRegs; j++) fin[(size_t)q * kRegs + j] = f[j];
         }
         for (int q = 0; q < threads; q++) {
@@ -87,21 +98,6 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
             for (int u = 1; u < len; u++)
                 if (m.srt[(b << s.logS) + u - 1] >= m.srt[(b << s.logS) + u]) return -12;
         }
-        if (T.j0 == 1) output_first(s, T, m, y, argmed);
-        for (int q = 0; q < threads; q++) {
-            u64 v[kRegs]; V(q, v); u32 f[kRegs]; int32_t a[kRegs], b2[kRegs];
-            for (int j = 0; j < kRegs; j++) f[j] = fin[(size_t)q * kRegs + j];
-            bucket_pair_positions(s, T, m, q, v, f, a, b2);
-            for (int j = 0; j < kRegs; j++) { pa[(size_t)q * kRegs + j] = a[j]; pb[(size_t)q * kRegs + j] = b2[j]; }
-        }
-        // the pair orders overwrite the bucket scratch: poison it first
-        memset(m.M, 0xA5, (size_t)(l.pos - l.M) + 4 * (size_t)s.Pmax * s.Pstride);
-        for (int q = 0; q < threads; q++) {
-            u64 v[kRegs]; V(q, v); int32_t a[kRegs], b2[kRegs];
-            for (int j = 0; j < kRegs; j++) { a[j] = pa[(size_t)q * kRegs + j]; b2[j] = pb[(size_t)q * kRegs + j]; }
-            bucket_pair_write(s, m, v, a, b2);
-        }
-        for (int q = 0; q < threads; q++) tail_pad(s, T, m, q, threads);
         g_fast_tiles++;
     } else {
         for (int q = 0; q < threads; q++) {
@@ -124,18 +120,18 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
             for (int u = 1; u < len; u++)
                 if (m.srt[(b << s.logS) + u - 1] >= m.srt[(b << s.logS) + u]) return -10;
         }
-        const int ipp = merge_items_per_pair(s);
-        for (int p = 0; p < T.P; p++)
-            for (int g = 0; g < ipp; g++) pair_merge_item(s, T, m, p, g);
-        if (T.j0 == 1) output_first(s, T, m, y, argmed);
         g_slow_tiles++;
     }
+    // the pair orders overwrite the bucket scratch: poison it first
+    memset(m.M, 0xA5, (size_t)(l.pos - l.M) + 4 * (size_t)s.Pmax * s.Pstride);
+    for (int q = 0; q < threads; q++) tail_pair_merge(s, T, m, q, threads, y, argmed);
 
     for (int q = 0; q < threads; q++) tail_first_medians(s, T, m, q, threads);
     if (s.C > 1) {
         for (int q = 0; q < threads; q++) tail_table_zero(s, T, m, q, threads);
         for (int q = 0; q < threads; q++) tail_table_hist(s, T, m, q, threads);
-        for (int q = 0; q < threads; q++) tail_table_columns(s, T, m, q, threads);
+        for (int q = 0; q < threads; q++) tail_table_colsums(s, T, m, q, threads);
+        for (int q = 0; q < threads; q++) tail_table_colapply(s, T, m, q, threads);
         for (int q = 0; q < threads; q++) tail_table_rows(s, T, m, q, threads);
     }
     for (int q = 0; q < threads; q++)
