@@ -18,7 +18,8 @@
 //                Packing the local index t makes every value distinct, so
 //                the sort is stable in the sense of Section 5.2.
 //   3. pair merge  for each pair, the merged order of A and B by
-//                (key, A-before-B, t) -> M[r] = isB << 15 | t, and the
+//                (key, A-before-B, t) -> M[r] = isB << 15 | t (stored at
+//                mslot(r)), and the
 //                merged positions posA[t], posB[t].
 //   4. tables    for every walk chunk (steps c*L ..), the number of window
 //                members below each 64-position word of the merged order at
@@ -55,6 +56,23 @@ typedef uint16_t u16;
 
 static const u64 kPadAll = ~0ull;          // slot beyond the tile's blocks
 static const u32 kMPad = 0xFFFFu;          // merged-order padding: never a member
+
+// Slot of merged position r in a pair's M row: within each group of 32
+// positions, dword j holds positions j and j + 16, so that the membership
+// bits of a group come out of its 16 dwords in position order.
+MF_HD int32_t mslot(int32_t r) { return (r & ~31) | ((r & 15) << 1) | ((r >> 4) & 1); }
+
+// Lane-wise 16-bit difference a - b of two packed halves.
+MF_HD uint32_t psub16(uint32_t a, uint32_t b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef unsigned short v2u16 __attribute__((ext_vector_type(2)));
+    const v2u16 d = __builtin_bit_cast(v2u16, a) - __builtin_bit_cast(v2u16, b);
+    return __builtin_bit_cast(uint32_t, d);
+#else
+    return (((a & 0xFFFFu) - (b & 0xFFFFu)) & 0xFFFFu) | ((((a >> 16) - (b >> 16)) & 0xFFFFu) << 16);
+#endif
+}
 static const int kRegs = 8;                // sort values per thread
 static const int32_t kPairBudget = 48 * 1024; // bytes of M + pos per tile
 static const int kColGroups = 8;           // row groups per count-table column
@@ -737,7 +755,7 @@ MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
     const int32_t d = g * kMergeSeg;
     if (d >= mlen) {   // padding of the merged order
         for (int q = 0; q < kMergeSeg; q++)
-            if (d + q < s.Mstride) Mp[d + q] = (u16)kMPad;
+            if (d + q < s.Mstride) Mp[mslot(d + q)] = (u16)kMPad;
         return;
     }
     int32_t lo = d > lenB ? d - lenB : 0;
@@ -754,12 +772,12 @@ MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
     for (int q = 0; q < kMergeSeg; q++) {
         const int32_t r = d + q;
         if (r >= mlen) {
-            if (r < s.Mstride) Mp[r] = (u16)kMPad;
+            if (r < s.Mstride) Mp[mslot(r)] = (u16)kMPad;
             continue;
         }
         const bool takeA = a < lenA && (b >= lenB || sv_key(va) <= sv_key(vb));
         const u32 t = sv_t(takeA ? va : vb);
-        Mp[r] = (u16)(takeA ? t : (0x8000u | t));
+        Mp[mslot(r)] = (u16)(takeA ? t : (0x8000u | t));
         pos[2 * t + (takeA ? 0 : 1)] = (u16)r;   // posA low half, posB high half
         a += takeA ? 1 : 0;
         b += takeA ? 0 : 1;
@@ -804,7 +822,7 @@ MF_HD void table_zero_item(const TileMem &m, int32_t e) { m.cnt[e] = 0u; }
 // 2^16); Cp is the pair's chunk count.
 MF_HD void table_hist_item(const Shape &s, const TileMem &m, int32_t p, int32_t r, u32 Lrcp, int32_t Cp)
 {
-    const u32 e = m.M[p * s.Mstride + r];
+    const u32 e = m.M[p * s.Mstride + mslot(r)];
     const u32 t = e & 0x7FFFu;
 #if defined(__HIP_DEVICE_COMPILE__)
     int32_t b = (int32_t)__umulhi(t, Lrcp);
@@ -914,26 +932,23 @@ MF_HD int hibit32(u32 v)   // index of the highest set bit, v != 0
 }
 
 // Membership dword of positions [32w, 32w+32) after step i, read from M with
-// 16-byte loads (M rows are 128-byte aligned).  Used when the window moves.
+// 16-byte loads (M rows are 128-byte aligned).  For an entry e = isB << 15 | t
+// the 16-bit difference i - e has its sign bit set exactly when the item is a
+// member after step i (A: t > i; B: t <= i; padding: never; i = -1 is the
+// state before step 0), so one packed subtraction tests two positions.
 MF_HD u32 member_dword(const Shape &s, const u16 *Mp, int32_t w, int32_t i)
 {
     if (w < 0 || w >= 2 * s.Wn) return 0u;
     const uint4 *src = (const uint4 *)(Mp + w * 32);
+    const u32 ii = ((u32)i & 0xFFFFu) * 0x10001u;
     u32 word = 0u;
 #pragma unroll
     for (int g = 0; g < 4; g++) {
         const uint4 v = src[g];
-#pragma unroll
-        for (int h = 0; h < 4; h++) {
-            const u32 pr = (h == 0) ? v.x : ((h == 1) ? v.y : ((h == 2) ? v.z : v.w));
-#pragma unroll
-            for (int e = 0; e < 2; e++) {
-                const int32_t ent = (int32_t)((pr >> (16 * e)) & 0xFFFFu);
-                const int32_t t = ent & 0x7FFF;
-                const bool mem = (ent & 0x8000) ? (t <= i) : (t > i);
-                word |= (u32)mem << (g * 8 + h * 2 + e);
-            }
-        }
+        word |= (psub16(ii, v.x) & 0x80008000u) >> (15 - 4 * g);
+        word |= (psub16(ii, v.y) & 0x80008000u) >> (14 - 4 * g);
+        word |= (psub16(ii, v.z) & 0x80008000u) >> (13 - 4 * g);
+        word |= (psub16(ii, v.w) & 0x80008000u) >> (12 - 4 * g);
     }
     return word;
 }
@@ -1140,7 +1155,7 @@ MF_HD void output_item(const Shape &s, const Tile &T, const TileMem &m, int32_t 
                        u32 *y, int32_t *argmed)
 {
     const int32_t r = m.stage[p * s.k + i];
-    const u32 e = m.M[p * s.Mstride + r];
+    const u32 e = m.M[p * s.Mstride + mslot(r)];
     const int32_t b = p + (int32_t)(e >> 15);
     const int32_t t = (int32_t)(e & 0x7FFFu);
     const int64_t o = T.o0 + (int64_t)p * s.k + i;
