@@ -154,6 +154,7 @@ struct Shape {
     int32_t Wn;      // 64-position words of a pair's merged order, ceil(2k/64)
     int32_t Mstride; // u16 entries per pair in M (= Wn * 64)
     int32_t Pstride; // u32 entries per pair in pos (k rounded up to 4)
+    int32_t seg;     // merged outputs per pair-merge item (odd)
 };
 
 // LDS (or scratch) layout of a tile, in bytes from the base.
@@ -196,6 +197,12 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
     if (P * per_pair > kPairBudget) P = kPairBudget / per_pair;
     if (P < 1) P = 1;
     s->Pmax = P;
+    // pair-merge segments: odd (the lanes of a wave, which take consecutive
+    // segments, then read LDS words on distinct banks) and long enough that
+    // no thread has more than one, so that no lane runs two search chains
+    int32_t seg = (int32_t)(((int64_t)P * s->Mstride + threads - 1) / threads);
+    if (seg < 9) seg = 9;
+    s->seg = seg | 1;
     // chunk length: odd (lanes walking neighbouring chunks then read the
     // position maps on distinct LDS banks), at least 17, large enough that
     // the tile has no more chunks than threads and that the count tables,
@@ -733,13 +740,9 @@ MF_HD void bucket_place(const Shape &s, const TileMem &m, const u64 (&v)[kRegs],
 // ---------------------------------------------------------------- 3. pair merge
 
 
-// Merged outputs per pair-merge item: odd, so that the lanes of a wave,
-// which take consecutive segments, read LDS words on distinct banks.
-static const int kMergeSeg = 9;
+MF_HD int32_t merge_items_per_pair(const Shape &s) { return (s.Mstride + s.seg - 1) / s.seg; }
 
-MF_HD int32_t merge_items_per_pair(const Shape &s) { return (s.Mstride + kMergeSeg - 1) / kMergeSeg; }
-
-// Item = (pair p, segment g): merged positions [9g, 9g + 9) of pair p, by
+// Item = (pair p, segment g): merged positions [g*seg, (g+1)*seg) of pair p, by
 // merge path over the sorted blocks A = p and B = p + 1 (A first on equal
 // keys), writing M and the position maps.
 MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
@@ -752,9 +755,9 @@ MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
     const u64 *B = m.srt + ((int32_t)(p + 1) << s.logS);
     u16 *Mp = m.M + p * s.Mstride;
     u16 *pos = (u16 *)(m.pos + p * s.Pstride);
-    const int32_t d = g * kMergeSeg;
+    const int32_t d = g * s.seg;
     if (d >= mlen) {   // padding of the merged order
-        for (int q = 0; q < kMergeSeg; q++)
+        for (int q = 0; q < s.seg; q++)
             if (d + q < s.Mstride) Mp[mslot(d + q)] = (u16)kMPad;
         return;
     }
@@ -768,8 +771,7 @@ MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
     }
     int32_t a = lo, b = d - lo;
     u64 va = a < lenA ? A[a] : 0ull, vb = b < lenB ? B[b] : 0ull;
-#pragma unroll
-    for (int q = 0; q < kMergeSeg; q++) {
+    for (int q = 0; q < s.seg; q++) {
         const int32_t r = d + q;
         if (r >= mlen) {
             if (r < s.Mstride) Mp[mslot(r)] = (u16)kMPad;
