@@ -54,6 +54,24 @@ __device__ __forceinline__ u32 seg_excl_scan(u32 tot, int G, u32 *wave_tot)
     return incl - tot + add;
 }
 
+// Exclusive prefix of a 64-bit value over the workgroup (NT threads);
+// wave_tot holds NT/64 wave totals.
+template <int NT>
+__device__ __forceinline__ u64 excl_scan64(u64 c, u64 *wave_tot)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    u64 incl = c;
+    for (int d = 1; d < 64; d <<= 1) {
+        const u64 o = __shfl_up(incl, (unsigned)d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) wave_tot[wave] = incl;
+    __syncthreads();
+    u64 add = 0ull;
+    for (int w = 0; w < wave; w++) add += wave_tot[w];
+    return incl - c + add;
+}
+
 // Resolves work unit uidx of a launch into its signal and tile.
 struct Resolved {
     const u32 *x;
@@ -93,16 +111,17 @@ __device__ __forceinline__ Resolved unit_of(const Launch &L, int64_t uidx)
 // filled m.xv and m.srt.  NT threads, barriers between phases.
 template <int NT>
 __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
-                                          int *err)
+                                          int *err, bool merged)
 {
     const int tid = threadIdx.x;
-    tail_pair_merge(s, T, m, tid, NT, (u32 *)d.y, d.argmed);
-    __syncthreads();
-
-    // the median before each pair's first step is A's median: remember its
-    // merged position (before the count tables reuse the sort buffer)
-    tail_first_medians(s, T, m, tid, NT);
-    __syncthreads();
+    if (!merged) {
+        tail_pair_merge(s, T, m, tid, NT, (u32 *)d.y, d.argmed);
+        __syncthreads();
+        // the median before each pair's first step is A's median: remember
+        // its merged position (before the count tables reuse the sort buffer)
+        tail_first_medians(s, T, m, tid, NT);
+        __syncthreads();
+    }
     if (s.C > 1) {
         tail_table_zero(s, T, m, tid, NT);
         __syncthreads();
@@ -136,52 +155,111 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, unsigned char *lds, 
     const TileMem m = tile_mem(lds, l);
     const Tile T = make_tile(s, tile);
     const u32 *x = d.x;
+    __shared__ u32 wave_tot[NT / 64];
+    __shared__ u64 wave_tot64[NT / 64];
+
+    // tiles of at most four blocks sort in tile order (pair orders by a
+    // prefix count); others, and tile-order tiles whose buckets overflow
+    // (heavy ties across the tile), sort block by block and merge each pair
+    const Shape st = tile_order_shape(s);
+    bool tord = tile_order_ok(s);
 
     // 1. load into registers
     u64 v[kRegs];
-    load_sort_values<F32>(s, T, m, x, tid, v);
+    if (tord) load_tile_values<F32>(s, T, m, x, tid, v);
+    else load_sort_values<F32>(s, T, m, x, tid, v);
 
-    // 2. bucket sort of every block, and the pair orders by lookup in the
-    // neighbour block's buckets; tiles with an overfull bucket (or blocks
-    // under 16 slots) take the merge sort and merge path below
+    // 2. bucket sort; tiles with an overfull bucket (or blocks under kRegs
+    // slots) take the merge sort below.  Crowded buckets are counted again
+    // with the map linear in the float bit pattern (the flag is the same for
+    // every thread).
     for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
     for (int b = tid; b < l.nbmax; b += NT) bucket_info_init(m, b);
     __syncthreads();
     bool fast = s.S >= kRegs;
-    if (fast) bucket_minmax(m, v);
-    __syncthreads();
-    if (fast && tid < T.NB) bucket_shift_item<F32>(s, m, tid, 0);
-    __syncthreads();
     u32 arr[kRegs];
-    if (fast) bucket_count<F32>(s, T, m, tid, v, arr);
-    __syncthreads();
-    if (fast && m.flag[0] != 0u) {
-        // crowded buckets: count again with the map linear in the float bit
-        // pattern (the flag is the same for every thread)
+    if (tord) {
+        tile_minmax(m, v);
         __syncthreads();
-        for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
-        if (tid < T.NB) bucket_shift_item<F32>(s, m, tid, 1);
-        if (tid == 0) m.flag[0] = 0u;
+        if (tile_many_ties(m, tile_items(s, T))) {
+            __syncthreads();
+            tord = false;
+            tile_to_block_values(s, T, tid, v);
+            for (int b = tid; b < l.nbmax; b += NT) bucket_info_init(m, b);
+            __syncthreads();
+        }
+    }
+    if (tord) {
+        if (tid == 0) bucket_shift_item<F32>(st, m, 0, 0);
+        __syncthreads();
+        tile_count<F32>(st, m, v, arr);
+        __syncthreads();
+        if (m.flag[0] != 0u) {
+            __syncthreads();
+            for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
+            if (tid == 0) bucket_shift_item<F32>(st, m, 0, 1);
+            if (tid == 0) m.flag[0] = 0u;
+            __syncthreads();
+            tile_count<F32>(st, m, v, arr);
+            __syncthreads();
+        }
+        if ((m.flag[0] & 1u) != 0u) {
+            __syncthreads();
+            tord = false;
+            tile_to_block_values(s, T, tid, v);
+            for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
+            for (int b = tid; b < l.nbmax; b += NT) bucket_info_init(m, b);
+            __syncthreads();
+        }
+    }
+    if (fast && !tord) {
+        bucket_minmax(m, v);
+        __syncthreads();
+        if (tid < T.NB) bucket_shift_item<F32>(s, m, tid, 0);
         __syncthreads();
         bucket_count<F32>(s, T, m, tid, v, arr);
         __syncthreads();
+        if (m.flag[0] != 0u) {
+            __syncthreads();
+            for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
+            if (tid < T.NB) bucket_shift_item<F32>(s, m, tid, 1);
+            if (tid == 0) m.flag[0] = 0u;
+            __syncthreads();
+            bucket_count<F32>(s, T, m, tid, v, arr);
+            __syncthreads();
+        }
     }
     fast = fast && (m.flag[0] & 1u) == 0u;
     if (fast) {
-        __shared__ u32 wave_tot[NT / 64];
         u32 c[kRegs];
         const u32 tot = bucket_scan_local(m, tid, c);
-        const u32 excl = seg_excl_scan<NT>(tot, s.S / kRegs, wave_tot);
+        const u32 excl = seg_excl_scan<NT>(tot, (tord ? st.S : s.S) / kRegs, wave_tot);
         bucket_scan_store(m, tid, excl, c);
         __syncthreads();
-        bucket_scatter<F32>(s, T, m, tid, v, arr);
+        if (tord) tile_scatter<F32>(st, m, v, arr);
+        else bucket_scatter<F32>(s, T, m, tid, v, arr);
         __syncthreads();
         u32 fin[kRegs];
-        bucket_rank<F32>(s, T, m, tid, v, fin);
+        const int32_t N = tile_items(s, T);
+        if (tord) tile_rank<F32>(st, m, v, N, fin);
+        else bucket_rank<F32>(s, T, m, tid, v, fin);
         __syncthreads();
-        bucket_place(s, m, v, fin);
+        if (tord) tile_place(m, v, fin);
+        else bucket_place(s, m, v, fin);
         __syncthreads();
+        if (tord) {
+            // 3. pair orders from the per-block counts along the tile order
+            u64 w[kRegs];
+            const u64 cnt = tile_label_counts(m, tid, N, w);
+            const u64 ex = excl_scan64<NT>(cnt, wave_tot64);
+            tile_positions(s, T, m, ex, w, (u32 *)d.y, d.argmed);
+            tile_mpad(s, T, m, tid, NT);
+            __syncthreads();
+            tile_tail<NT>(s, T, m, d, err, true);
+            return;
+        }
     } else {
+        if (tord) tile_to_block_values(s, T, tid, v);
         sort_regs(v);
         for (int w = kRegs; w < s.S; w <<= 1) {
             store_regs(m.srt + tid * kRegs, v);
@@ -193,7 +271,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, unsigned char *lds, 
         __syncthreads();
     }
 
-    tile_tail<NT>(s, T, m, d, err);
+    tile_tail<NT>(s, T, m, d, err, false);
 }
 
 // One workgroup per work unit.
@@ -332,7 +410,7 @@ __global__ __launch_bounds__(kGlobalThreads) void k_tile_global(Launch L, unsign
             __syncthreads();
         }
         (void)bufs;
-        tile_tail<kGlobalThreads>(s, T, m, d, err);
+        tile_tail<kGlobalThreads>(s, T, m, d, err, false);
     }
 }
 

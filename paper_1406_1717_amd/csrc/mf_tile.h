@@ -174,6 +174,20 @@ struct Layout {
 
 MF_HD int32_t ceil_div32(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
 
+// ceil(2^32 / d) for 2 <= d < 2^16; 0 stands for d = 1.
+MF_HD u32 recip32(int32_t d) { return d <= 1 ? 0u : (u32)((0xFFFFFFFFull + (u64)d) / (u64)d); }
+
+// a / d for a, d < 2^16 with dr = recip32(d): a high multiply, exact.
+MF_HD u32 udiv16(u32 a, u32 dr)
+{
+    if (dr == 0u) return a;
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umulhi(a, dr);
+#else
+    return (u32)(((u64)a * dr) >> 32);
+#endif
+}
+
 // Fills s for window k over n items with `threads` threads per tile.
 // Returns 0, or -1 when k does not fit this capacity (two blocks needed).
 MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
@@ -285,9 +299,9 @@ struct TileMem {
     u32 *bmin;       // per block: smallest key
     u32 *bmax;       // per block: largest key
     u32 *bshift;     // per block: bucket shift (key and integer-log maps)
-    u32 *bmode;      // per block: bucket map (BK_KEY, BK_FLIN, BK_ILOG)
+    u32 *bmode;      // per block: bucket map (BK_KEY, BK_FLIN, BK_CLOG)
     u32 *blo;        // per block: mapped value of the block minimum
-    u32 *bfmin;      // per block: float minimum (BK_FLIN), as bits
+    u32 *bfmin;      // per block: float minimum (BK_FLIN, as bits) or floor (BK_CLOG)
     u32 *bscale;     // per block: buckets per unit value (BK_FLIN), as bits
     u32 *flag;       // bit 0: a bucket passed kBucketMax; bit 1: kBucketSoft
     u32 *xv;
@@ -446,16 +460,19 @@ MF_HD u32 sv_t(u64 v) { return (u32)(v & 0xFFFFu); }
 // Maps: the first count uses one linear in the value (integers: the key;
 // floats with a finite range: (v - min) * S / (max - min)).  If a bucket
 // then holds kBucketSoft or more items (values clustered against the
-// block's range, as with rare outliers), the tile counts again with a map
-// linear in the float bit pattern of the value (for floats the key itself,
-// for integers the key of the converted float), which spreads values
-// evenly over orders of magnitude.  A tile whose buckets still hold more
-// than kBucketMax items (heavy ties) takes the merge sort above instead.
+// block's range, as with rare outliers), the tile counts again with a
+// clamped logarithmic map: the float bit pattern of |v| (integers are
+// converted to float first), with magnitudes more than kLogSpan binades
+// below the block's largest collapsed to zero, signed back; it spreads
+// values evenly over orders of magnitude without spending buckets on the
+// tiny ones.  A tile whose buckets still hold more than kBucketMax items
+// (heavy ties) takes the merge sort above instead.
 // Needs S >= kRegs, so that the kRegs slots of a thread lie in one block.
 
 static const int kBucketMax = 32;
 static const int kBucketSoft = 12;
-enum { BK_KEY = 0, BK_FLIN = 1, BK_ILOG = 2 };
+static const u32 kLogSpan = 16;
+enum { BK_KEY = 0, BK_FLIN = 1, BK_CLOG = 2 };
 
 MF_HD u32 f32_bits(float f)
 {
@@ -477,11 +494,23 @@ MF_HD float f32_of_key(u32 key) { return bits_f32((key & 0x80000000u) ? (key & 0
 // Key of the float nearest to the integer of an integer key (monotone).
 MF_HD u32 ilog_key(u32 key) { return key_of_f32(f32_bits((float)(int32_t)(key ^ 0x80000000u))); }
 
+// Magnitude bits |v| of a float key.
+MF_HD u32 key_mag(u32 fk) { return (fk & 0x80000000u) ? (fk & 0x7FFFFFFFu) : (~fk & 0x7FFFFFFFu); }
+
+// Clamped logarithmic code of a float key: monotone in the key.
+MF_HD u32 clog_code(u32 fk, u32 floor_mag)
+{
+    const u32 mag = key_mag(fk);
+    const u32 c = mag > floor_mag ? mag - floor_mag : 0u;
+    return (fk & 0x80000000u) ? 0x40000000u + c : 0x40000000u - c;
+}
+
 // A block's bucket map.
 struct BucketFn {
     u32 mode, lo, sh;
-    float fmin, scale;
-    u32 top;   // S - 1
+    float fmin, scale;   // BK_FLIN
+    u32 floor_mag;       // BK_CLOG
+    u32 top;             // S - 1
 };
 
 template <bool F32>
@@ -491,8 +520,8 @@ MF_HD u32 bucket_of(const BucketFn &f, u32 key)
         const u32 q = (u32)((f32_of_key(key) - f.fmin) * f.scale);
         return q < f.top ? q : f.top;
     }
-    const u32 mk = (!F32 && f.mode == BK_ILOG) ? ilog_key(key) : key;
-    return (mk - f.lo) >> f.sh;
+    if (f.mode == BK_CLOG) return (clog_code(F32 ? key : ilog_key(key), f.floor_mag) - f.lo) >> f.sh;
+    return (key - f.lo) >> f.sh;
 }
 
 MF_HD bool sv_valid(u64 v) { return (v & 0xFFFFu) != 0xFFFFu; }
@@ -541,12 +570,12 @@ MF_HD void bucket_minmax(const TileMem &m, const u64 (&v)[kRegs])
 }
 
 // Item = block b: the bucket map of `pass` (0: linear in the value, 1:
-// linear in the float bit pattern), landing in [0, S) over the block's range.
+// clamped logarithmic), landing in [0, S) over the block's range.
 template <bool F32>
 MF_HD void bucket_shift_item(const Shape &s, const TileMem &m, int32_t b, int pass)
 {
     const u32 mn = m.bmin[b], mx = m.bmax[b];
-    u32 mode = BK_KEY, lo = mn, hi = mx;
+    u32 mode = BK_KEY, lo = mn, hi = mx, floor_mag = 0u;
     float fmin = 0.f, scale = 0.f;
     if (F32 && pass == 0 && mn > 0x007FFFFFu && mx < 0xFF800000u) {   // finite range
         const float a = f32_of_key(mn), r = f32_of_key(mx) - a;
@@ -559,10 +588,14 @@ MF_HD void bucket_shift_item(const Shape &s, const TileMem &m, int32_t b, int pa
             }
         }
     }
-    if (!F32 && pass == 1) {
-        mode = BK_ILOG;
-        lo = ilog_key(mn);
-        hi = ilog_key(mx);
+    if (pass == 1) {
+        const u32 a = F32 ? mn : ilog_key(mn), z = F32 ? mx : ilog_key(mx);
+        const u32 ma = key_mag(a), mz = key_mag(z);
+        const u32 top = ma > mz ? ma : mz, span = kLogSpan << 23;
+        mode = BK_CLOG;
+        floor_mag = top > span ? top - span : 0u;
+        lo = clog_code(a, floor_mag);
+        hi = clog_code(z, floor_mag);
     }
     const u32 range = hi - lo;
     int32_t bits = 0;
@@ -570,7 +603,7 @@ MF_HD void bucket_shift_item(const Shape &s, const TileMem &m, int32_t b, int pa
     m.bshift[b] = (u32)(bits > s.logS ? bits - s.logS : 0);
     m.bmode[b] = mode;
     m.blo[b] = lo;
-    m.bfmin[b] = f32_bits(fmin);
+    m.bfmin[b] = mode == BK_CLOG ? floor_mag : f32_bits(fmin);
     m.bscale[b] = f32_bits(scale);
 }
 
@@ -581,6 +614,7 @@ MF_HD BucketFn bucket_fn(const Shape &s, const TileMem &m, int32_t b)
     f.lo = m.blo[b];
     f.sh = m.bshift[b];
     f.fmin = bits_f32(m.bfmin[b]);
+    f.floor_mag = m.bfmin[b];
     f.scale = bits_f32(m.bscale[b]);
     f.top = (u32)s.S - 1u;
     return f;
@@ -624,7 +658,7 @@ MF_HD void bucket_count(const Shape &s, const Tile &T, const TileMem &m, int32_t
     f.mode = BK_KEY;
     f.lo = f.sh = 0u;
     f.fmin = f.scale = 0.f;
-    f.top = 0u;
+    f.floor_mag = f.top = 0u;
     if (b >= 0) f = bucket_fn(s, m, b);
     u32 *cnt = m.bk + (b >= 0 ? (b << s.logS) : 0);
     u32 mx = 0u;
@@ -737,6 +771,243 @@ MF_HD void bucket_place(const Shape &s, const TileMem &m, const u64 (&v)[kRegs],
         if (sv_valid(v[j])) m.srt[(sv_block(v[j]) << s.logS) + fin[j]] = v[j];
 }
 
+// ---------------------------------------------------------------- 2''. tile-order sort
+//
+// Tiles of at most four blocks sort all their items at once by (key, block,
+// t).  Restricted to blocks b and b + 1 that order is pair b's merged order
+// (on equal keys A = block b comes first, then t), so counting, along it,
+// the items of each block gives every item its merged position in both of
+// its pairs: phase 3 without a merge.  The counts of the four blocks are
+// packed in one 64-bit word (16 bits each), so the count is one prefix scan.
+// The sort is the bucket sort above over a single segment: cap buckets
+// spanning the tile's value range.  Values: key << 32 | block << 16 | t,
+// padding ~0 (t field 0xFFFF, so sv_valid and sv_t still apply).
+
+static const int kTileOrderBlocks = 4;
+
+MF_HD bool tile_order_ok(const Shape &s) { return s.Pmax + 1 <= kTileOrderBlocks && s.S >= kRegs; }
+
+MF_HD u32 tv_key(u64 v) { return (u32)(v >> 32); }
+MF_HD int32_t tv_block(u64 v) { return (int32_t)((v >> 16) & 0xFFFFu); }
+
+// The bucket sort's shape for the tile-wide segment.
+MF_HD Shape tile_order_shape(const Shape &s)
+{
+    Shape st = s;
+    st.S = s.cap;
+    int32_t l = 0;
+    while ((1 << l) < s.cap) l++;
+    st.logS = l;
+    return st;
+}
+
+// Valid items of the tile.
+MF_HD int32_t tile_items(const Shape &s, const Tile &T)
+{
+    int32_t N = 0;
+    for (int32_t b = 0; b < T.NB; b++) N += block_len(s, T, b);
+    return N;
+}
+
+// Phase 1 for tile order: as load_sort_values, with tile-order values.
+template <bool F32>
+MF_HD void load_tile_values(const Shape &s, const Tile &T, const TileMem &m, const u32 *x,
+                            int32_t tid, u64 (&v)[kRegs])
+{
+    u32 raw[kRegs];
+    int32_t len[kRegs];
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        const int32_t u = tid * kRegs + j;
+        const int32_t b = u >> s.logS;
+        const int32_t t = u & (s.S - 1);
+        len[j] = (b < T.NB) ? block_len(s, T, b) : 0;
+        raw[j] = (t < len[j]) ? x[T.e0 + (int64_t)b * s.k + t] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        const int32_t u = tid * kRegs + j;
+        const int32_t b = u >> s.logS;
+        const int32_t t = u & (s.S - 1);
+        if (t >= len[j]) { v[j] = kPadAll; continue; }
+        m.xv[u] = raw[j];
+        const u32 key = F32 ? key_of_f32(raw[j]) : key_of_i32(raw[j]);
+        v[j] = ((u64)key << 32) | ((u64)b << 16) | (u64)t;
+    }
+}
+
+// The same slots as block-first sort values (for the merge-sort fallback).
+MF_HD void tile_to_block_values(const Shape &s, const Tile &T, int32_t tid, u64 (&v)[kRegs])
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        const int32_t b = (tid * kRegs + j) >> s.logS;
+        if (sv_valid(v[j])) v[j] = ((u64)b << 48) | ((u64)tv_key(v[j]) << 16) | (u64)sv_t(v[j]);
+        else v[j] = (b >= T.NB) ? kPadAll : (((u64)b << 48) | 0x0000FFFFFFFFFFFFull);
+    }
+}
+
+// Per thread: the tile's key range into block info entry 0 (reduced over
+// the wave first, so that one lane per wave updates the shared words).
+MF_HD void tile_minmax(const TileMem &m, const u64 (&v)[kRegs])
+{
+    u32 mn = 0xFFFFFFFFu, mx = 0u;
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        if (sv_valid(v[j])) {
+            const u32 key = tv_key(v[j]);
+            mn = key < mn ? key : mn;
+            mx = key > mx ? key : mx;
+        }
+    }
+#if defined(__HIP_DEVICE_COMPILE__)
+    for (int d = 32; d >= 1; d >>= 1) {
+        const u32 omn = (u32)__shfl_xor((int)mn, d, 64), omx = (u32)__shfl_xor((int)mx, d, 64);
+        mn = omn < mn ? omn : mn;
+        mx = omx > mx ? omx : mx;
+    }
+    const bool lead = (threadIdx.x & 63) == 0;
+#else
+    const bool lead = true;
+#endif
+    if (lead && mn <= mx) {
+        MF_MIN32(m.bmin, mn);
+        MF_MAX32(m.bmax, mx);
+    }
+}
+
+// After tile_minmax: true when the tile's values are so few (range under a
+// quarter of the item count) that equal keys would crowd its buckets; such
+// tiles sort block by block.
+MF_HD bool tile_many_ties(const TileMem &m, int32_t N)
+{
+    const u32 range = m.bmax[0] - m.bmin[0];
+    return (u64)range * 4u < (u64)N;
+}
+
+// Per thread: arrival numbers in the tile's buckets (st = tile_order_shape).
+template <bool F32>
+MF_HD void tile_count(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], u32 (&arr)[kRegs])
+{
+    const BucketFn f = bucket_fn(st, m, 0);
+    u32 mx = 0u;
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        arr[j] = 0u;
+        if (sv_valid(v[j])) {
+            arr[j] = MF_ADDRTN32(m.bk + bucket_of<F32>(f, tv_key(v[j])), 1u);
+            mx = arr[j] > mx ? arr[j] : mx;
+        }
+    }
+    if (mx >= (u32)kBucketSoft) MF_OR32(m.flag, mx >= (u32)kBucketMax ? 3u : 2u);
+}
+
+template <bool F32>
+MF_HD void tile_scatter(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], const u32 (&arr)[kRegs])
+{
+    const BucketFn f = bucket_fn(st, m, 0);
+#pragma unroll
+    for (int j = 0; j < kRegs; j++)
+        if (sv_valid(v[j])) m.srt[m.bk[bucket_of<F32>(f, tv_key(v[j]))] + arr[j]] = v[j];
+}
+
+// Per thread: sorted position = bucket start + rank by the full value among
+// the bucket's items (rounds as in bucket_rank).  N: valid items.
+template <bool F32>
+MF_HD void tile_rank(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], int32_t N, u32 (&fin)[kRegs])
+{
+    const BucketFn f = bucket_fn(st, m, 0);
+    u32 x[kRegs], hi[kRegs];
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        x[j] = 0u;
+        hi[j] = 0u;
+        if (sv_valid(v[j])) {
+            const u32 bk = bucket_of<F32>(f, tv_key(v[j]));
+            x[j] = m.bk[bk];
+            hi[j] = (bk + 1u < (u32)st.S) ? m.bk[bk + 1] : (u32)N;
+        }
+        fin[j] = x[j];
+    }
+    for (int round = 0; round < kBucketMax; round++) {
+        u32 more = 0u;
+#pragma unroll
+        for (int j = 0; j < kRegs; j++) {
+            const bool act = x[j] < hi[j];
+            const u64 o = m.srt[act ? x[j] : 0u];
+            fin[j] += (act && o < v[j]) ? 1u : 0u;
+            x[j] += act ? 1u : 0u;
+            more |= (x[j] < hi[j]) ? 1u : 0u;
+        }
+        if (!more) break;
+    }
+}
+
+MF_HD void tile_place(const TileMem &m, const u64 (&v)[kRegs], const u32 (&fin)[kRegs])
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; j++)
+        if (sv_valid(v[j])) m.srt[fin[j]] = v[j];
+}
+
+// Per thread: its kRegs consecutive tile-order items (into w) and their
+// count per block, packed 16 bits per block.
+MF_HD u64 tile_label_counts(const TileMem &m, int32_t tid, int32_t N, u64 (&w)[kRegs])
+{
+    u64 c = 0ull;
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        const int32_t q = tid * kRegs + j;
+        w[j] = q < N ? m.srt[q] : kPadAll;
+        if (q < N) c += 1ull << (16 * tv_block(w[j]));
+    }
+    return c;
+}
+
+// Per thread: with excl = the packed counts of all earlier items, the
+// merged positions of its items in both of their pairs (M and the position
+// maps), each pair's first median (A's item of own rank h) and output 0.
+MF_HD void tile_positions(const Shape &s, const Tile &T, const TileMem &m, u64 excl, const u64 (&w)[kRegs],
+                          u32 *y, int32_t *argmed)
+{
+    u64 c = excl;
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        if (!sv_valid(w[j])) continue;
+        const int32_t b = tv_block(w[j]);
+        const u32 t = sv_t(w[j]);
+        const int32_t cb = (int32_t)((c >> (16 * b)) & 0xFFFFu);
+        if (b < T.P) {   // A of pair b: with B's earlier items
+            const int32_t r = cb + (int32_t)((c >> (16 * b + 16)) & 0xFFFFu);
+            m.M[b * s.Mstride + mslot(r)] = (u16)t;
+            ((u16 *)(m.pos + b * s.Pstride))[2 * t] = (u16)r;
+            if (cb == s.h) m.pos[b * s.Pstride + s.k] = (u32)r;
+        }
+        if (b >= 1) {    // B of pair b - 1: with A's earlier items
+            const int32_t r = cb + (int32_t)((c >> (16 * b - 16)) & 0xFFFFu);
+            m.M[(b - 1) * s.Mstride + mslot(r)] = (u16)(0x8000u | t);
+            ((u16 *)(m.pos + (b - 1) * s.Pstride))[2 * t + 1] = (u16)r;
+        }
+        if (b == 0 && cb == s.h && T.j0 == 1) {
+            y[0] = m.xv[t];
+            if (argmed) argmed[0] = (int32_t)t;
+        }
+        c += 1ull << (16 * b);
+    }
+}
+
+// Thread tid's share of the merged-order padding (tile order).
+MF_HD void tile_mpad(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
+{
+    const int32_t npad = s.Mstride - s.k;
+    const u32 padr = recip32(npad);
+    for (int32_t it = tid; it < T.P * npad; it += NT) {
+        const int32_t p = (int32_t)udiv16((u32)it, padr);
+        const int32_t r = s.k + it - p * npad;
+        if (r >= s.k + block_len(s, T, p + 1)) m.M[p * s.Mstride + mslot(r)] = (u16)kMPad;
+    }
+}
+
 // ---------------------------------------------------------------- 3. pair merge
 
 
@@ -835,19 +1106,6 @@ MF_HD void table_hist_item(const Shape &s, const TileMem &m, int32_t p, int32_t 
     MF_ADD32(cnt_row(s, m, p, b) + (r >> 6), (e & 0x8000u) ? 0x10000u : 1u);
 }
 
-// ceil(2^32 / d) for 2 <= d < 2^16; 0 stands for d = 1.
-MF_HD u32 recip32(int32_t d) { return d <= 1 ? 0u : (u32)((0xFFFFFFFFull + (u64)d) / (u64)d); }
-
-// a / d for a, d < 2^16 with dr = recip32(d): a high multiply, exact.
-MF_HD u32 udiv16(u32 a, u32 dr)
-{
-    if (dr == 0u) return a;
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __umulhi(a, dr);
-#else
-    return (u32)(((u64)a * dr) >> 32);
-#endif
-}
 
 // Column pass (two phases): entry (c, w) becomes the members of word w at
 // chunk start c, (A items with bucket >= c) + (B items with bucket < c).

@@ -14,11 +14,12 @@
 using namespace mf;
 
 static int g_force_merge = 0;
-static long g_fast_tiles = 0, g_slow_tiles = 0, g_recount_tiles = 0;
+static long g_fast_tiles = 0, g_slow_tiles = 0, g_recount_tiles = 0, g_tile_order_tiles = 0;
 extern "C" void emu_set_force_merge(int v) { g_force_merge = v; }
 extern "C" long emu_fast_tiles(void) { return g_fast_tiles; }
 extern "C" long emu_slow_tiles(void) { return g_slow_tiles; }
 extern "C" long emu_recount_tiles(void) { return g_recount_tiles; }
+extern "C" long emu_tile_order_tiles(void) { return g_tile_order_tiles; }
 
 template <bool F32>
 static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
@@ -28,42 +29,78 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
     // poison the tile memory so that reads of unwritten data show up
     memset(lds.data(), 0xA5, lds.size());
     TileMem m = tile_mem(lds.data(), l);
+    bool tord = tile_order_ok(s);
+    const Shape st = tile_order_shape(s);
 
     std::vector<u64> regs((size_t)threads * kRegs), tmp((size_t)threads * kRegs);
     for (int q = 0; q < threads; q++) {
         u64 v[kRegs];
-        load_sort_values<F32>(s, T, m, x, q, v);
+        if (tord) load_tile_values<F32>(s, T, m, x, q, v);
+        else load_sort_values<F32>(s, T, m, x, q, v);
         for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
     }
+    auto V = [&](int q, u64 (&v)[kRegs]) { for (int j = 0; j < kRegs; j++) v[j] = regs[(size_t)q * kRegs + j]; };
+    auto count = [&](std::vector<u32> &arr) {
+        for (int q = 0; q < threads; q++) {
+            u64 v[kRegs]; V(q, v); u32 a[kRegs];
+            if (tord) tile_count<F32>(st, m, v, a);
+            else bucket_count<F32>(s, T, m, q, v, a);
+            for (int j = 0; j < kRegs; j++) arr[(size_t)q * kRegs + j] = a[j];
+        }
+    };
+    auto shift = [&](int pass) {
+        if (tord) bucket_shift_item<F32>(st, m, 0, pass);
+        else for (int b = 0; b < T.NB; b++) bucket_shift_item<F32>(s, m, b, pass);
+    };
     // bucket path
     for (int e = 0; e < s.cap; e++) bucket_zero_item(m, e);
     for (int b = 0; b < l.nbmax; b++) bucket_info_init(m, b);
     bool fast = s.S >= kRegs && !g_force_merge;
-    auto V = [&](int q, u64 (&v)[kRegs]) { for (int j = 0; j < kRegs; j++) v[j] = regs[(size_t)q * kRegs + j]; };
     std::vector<u32> arr((size_t)threads * kRegs), fin((size_t)threads * kRegs);
-    if (fast) {
-        for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); bucket_minmax(m, v); }
-        for (int b = 0; b < T.NB; b++) bucket_shift_item<F32>(s, m, b, 0);
-        for (int q = 0; q < threads; q++) {
-            u64 v[kRegs]; V(q, v); u32 a[kRegs];
-            bucket_count<F32>(s, T, m, q, v, a);
-            for (int j = 0; j < kRegs; j++) arr[(size_t)q * kRegs + j] = a[j];
-        }
+    const int32_t N = tile_items(s, T);
+    auto attempt_counts = [&]() {
+        shift(0);
+        count(arr);
         if (m.flag[0] != 0u) {
             g_recount_tiles++;
             for (int e = 0; e < s.cap; e++) bucket_zero_item(m, e);
-            for (int b = 0; b < T.NB; b++) bucket_shift_item<F32>(s, m, b, 1);
+            shift(1);
             m.flag[0] = 0u;
-            for (int q = 0; q < threads; q++) {
-                u64 v[kRegs]; V(q, v); u32 a[kRegs];
-                bucket_count<F32>(s, T, m, q, v, a);
-                for (int j = 0; j < kRegs; j++) arr[(size_t)q * kRegs + j] = a[j];
-            }
+            count(arr);
         }
-        fast = (m.flag[0] & 1u) == 0u;
+    };
+    if (fast && tord) {
+        for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); tile_minmax(m, v); }
+        if (tile_many_ties(m, N)) {
+            tord = false;
+            for (int q = 0; q < threads; q++) {
+                u64 v[kRegs]; V(q, v);
+                tile_to_block_values(s, T, q, v);
+                for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
+            }
+            for (int b = 0; b < l.nbmax; b++) bucket_info_init(m, b);
+        }
     }
+    if (fast && tord) {
+        attempt_counts();
+        if ((m.flag[0] & 1u) != 0u) {
+            tord = false;
+            for (int q = 0; q < threads; q++) {
+                u64 v[kRegs]; V(q, v);
+                tile_to_block_values(s, T, q, v);
+                for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
+            }
+            for (int e = 0; e < s.cap; e++) bucket_zero_item(m, e);
+            for (int b = 0; b < l.nbmax; b++) bucket_info_init(m, b);
+        }
+    }
+    if (fast && !tord) {
+        for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); bucket_minmax(m, v); }
+        attempt_counts();
+    }
+    if (fast) fast = (m.flag[0] & 1u) == 0u;
     if (fast) {
-        const int G = s.S / kRegs;
+        const int G = (tord ? st.S : s.S) / kRegs;
         std::vector<u32> tot(threads);
         std::vector<std::vector<u32>> cl(threads, std::vector<u32>(kRegs));
         for (int q = 0; q < threads; q++) {
@@ -81,27 +118,36 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         for (int q = 0; q < threads; q++) {
             u64 v[kRegs]; V(q, v); u32 a[kRegs];
             for (int j = 0; j < kRegs; j++) a[j] = arr[(size_t)q * kRegs + j];
-            bucket_scatter<F32>(s, T, m, q, v, a);
+            if (tord) tile_scatter<F32>(st, m, v, a);
+            else bucket_scatter<F32>(s, T, m, q, v, a);
         }
         for (int q = 0; q < threads; q++) {
             u64 v[kRegs]; V(q, v); u32 f[kRegs];
-            bucket_rank<F32>(s, T, m, q, v, f);
+            if (tord) tile_rank<F32>(st, m, v, N, f);
+            else bucket_rank<F32>(s, T, m, q, v, f);
             for (int j = 0; j < kRegs; j++) fin[(size_t)q * kRegs + j] = f[j];
         }
         for (int q = 0; q < threads; q++) {
             u64 v[kRegs]; V(q, v); u32 f[kRegs];
             for (int j = 0; j < kRegs; j++) f[j] = fin[(size_t)q * kRegs + j];
-            bucket_place(s, m, v, f);
+            if (tord) tile_place(m, v, f);
+            else bucket_place(s, m, v, f);
         }
-        for (int b = 0; b < T.NB; b++) {
-            const int len = block_len(s, T, b);
-            for (int u = 1; u < len; u++)
-                if (m.srt[(b << s.logS) + u - 1] >= m.srt[(b << s.logS) + u]) return -12;
+        if (tord) {
+            for (int u = 1; u < N; u++)
+                if (m.srt[u - 1] >= m.srt[u]) return -13;
+        } else {
+            for (int b = 0; b < T.NB; b++) {
+                const int len = block_len(s, T, b);
+                for (int u = 1; u < len; u++)
+                    if (m.srt[(b << s.logS) + u - 1] >= m.srt[(b << s.logS) + u]) return -12;
+            }
         }
         g_fast_tiles++;
     } else {
         for (int q = 0; q < threads; q++) {
             u64 v[kRegs]; V(q, v);
+            if (tord) tile_to_block_values(s, T, q, v);
             sort_regs(v);
             for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
         }
@@ -124,9 +170,26 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
     }
     // the pair orders overwrite the bucket scratch: poison it first
     memset(m.M, 0xA5, (size_t)(l.pos - l.M) + 4 * (size_t)s.Pmax * s.Pstride);
-    for (int q = 0; q < threads; q++) tail_pair_merge(s, T, m, q, threads, y, argmed);
-
-    for (int q = 0; q < threads; q++) tail_first_medians(s, T, m, q, threads);
+    if (fast && tord) {
+        g_tile_order_tiles++;
+        std::vector<u64> w((size_t)threads * kRegs), cnt(threads);
+        for (int q = 0; q < threads; q++) {
+            u64 ww[kRegs];
+            cnt[q] = tile_label_counts(m, q, N, ww);
+            for (int j = 0; j < kRegs; j++) w[(size_t)q * kRegs + j] = ww[j];
+        }
+        u64 ex = 0;
+        for (int q = 0; q < threads; q++) {
+            u64 ww[kRegs];
+            for (int j = 0; j < kRegs; j++) ww[j] = w[(size_t)q * kRegs + j];
+            tile_positions(s, T, m, ex, ww, y, argmed);
+            ex += cnt[q];
+        }
+        for (int q = 0; q < threads; q++) tile_mpad(s, T, m, q, threads);
+    } else {
+        for (int q = 0; q < threads; q++) tail_pair_merge(s, T, m, q, threads, y, argmed);
+        for (int q = 0; q < threads; q++) tail_first_medians(s, T, m, q, threads);
+    }
     if (s.C > 1) {
         for (int q = 0; q < threads; q++) tail_table_zero(s, T, m, q, threads);
         for (int q = 0; q < threads; q++) tail_table_hist(s, T, m, q, threads);
