@@ -123,10 +123,12 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
         __syncthreads();
     }
     if (s.C > 1) {
-        tail_table_zero(s, T, m, tid, NT);
-        __syncthreads();
-        tail_table_hist(s, T, m, tid, NT);
-        __syncthreads();
+        if (!merged) {   // tile order counts its items with the pair orders
+            tail_table_zero(s, T, m, tid, NT);
+            __syncthreads();
+            tail_table_hist(s, T, m, tid, NT);
+            __syncthreads();
+        }
         tail_table_colsums(s, T, m, tid, NT);
         __syncthreads();
         tail_table_colapply(s, T, m, tid, NT);
@@ -252,6 +254,10 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, unsigned char *lds, 
             u64 w[kRegs];
             const u64 cnt = tile_label_counts(m, tid, N, w);
             const u64 ex = excl_scan64<NT>(cnt, wave_tot64);
+            if (s.C > 1) {   // the count tables reuse the sort buffer, read above
+                tail_table_zero(s, T, m, tid, NT);
+                __syncthreads();
+            }
             tile_positions(s, T, m, ex, w, (u32 *)d.y, d.argmed);
             tile_mpad(s, T, m, tid, NT);
             __syncthreads();

@@ -212,9 +212,12 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
     if (P < 1) P = 1;
     s->Pmax = P;
     // pair-merge segments: odd (the lanes of a wave, which take consecutive
-    // segments, then read LDS words on distinct banks) and long enough that
-    // no thread has more than one, so that no lane runs two search chains
+    // segments, then read LDS words on distinct banks), long enough that no
+    // thread has more than one search chain, but not much longer than the
+    // search itself (short blocks: many short segments)
     int32_t seg = (int32_t)(((int64_t)P * s->Mstride + threads - 1) / threads);
+    const int32_t seg_max = 2 * logS + 5;
+    if (seg > seg_max) seg = seg_max;
     if (seg < 9) seg = 9;
     s->seg = seg | 1;
     // chunk length: odd (lanes walking neighbouring chunks then read the
@@ -771,6 +774,23 @@ MF_HD void bucket_place(const Shape &s, const TileMem &m, const u64 (&v)[kRegs],
         if (sv_valid(v[j])) m.srt[(sv_block(v[j]) << s.logS) + fin[j]] = v[j];
 }
 
+// Walk chunks of pair p (phase 4), and row c of its count table.
+MF_HD int32_t pair_chunks(const Shape &s, const Tile &T, int32_t p)
+{
+    return ceil_div32(block_len(s, T, p + 1), s.L);
+}
+
+MF_HD u32 *cnt_row(const Shape &s, const TileMem &m, int32_t p, int32_t c)
+{
+    return m.cnt + ((int64_t)p * s.C + c) * (s.Wn + 1);
+}
+
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MF_ADD32(ptr, v) atomicAdd((unsigned int *)(ptr), (unsigned int)(v))
+#else
+#define MF_ADD32(ptr, v) (*(ptr) += (v))
+#endif
+
 // ---------------------------------------------------------------- 2''. tile-order sort
 //
 // Tiles of at most four blocks sort all their items at once by (key, block,
@@ -970,6 +990,10 @@ MF_HD u64 tile_label_counts(const TileMem &m, int32_t tid, int32_t N, u64 (&w)[k
 MF_HD void tile_positions(const Shape &s, const Tile &T, const TileMem &m, u64 excl, const u64 (&w)[kRegs],
                           u32 *y, int32_t *argmed)
 {
+    // with more than one walk chunk, also the count histogram of phase 4
+    // (table_hist_item for both merged positions of every item)
+    const bool hist = s.C > 1;
+    const u32 Lr = recip32(s.L);
     u64 c = excl;
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
@@ -982,11 +1006,18 @@ MF_HD void tile_positions(const Shape &s, const Tile &T, const TileMem &m, u64 e
             m.M[b * s.Mstride + mslot(r)] = (u16)t;
             ((u16 *)(m.pos + b * s.Pstride))[2 * t] = (u16)r;
             if (cb == s.h) m.pos[b * s.Pstride + s.k] = (u32)r;
+            if (hist) {
+                int32_t row = (int32_t)udiv16(t, Lr);
+                const int32_t Cp = pair_chunks(s, T, b);
+                row = row < Cp ? row : Cp - 1;
+                MF_ADD32(cnt_row(s, m, b, row) + (r >> 6), 1u);
+            }
         }
         if (b >= 1) {    // B of pair b - 1: with A's earlier items
             const int32_t r = cb + (int32_t)((c >> (16 * b - 16)) & 0xFFFFu);
             m.M[(b - 1) * s.Mstride + mslot(r)] = (u16)(0x8000u | t);
             ((u16 *)(m.pos + (b - 1) * s.Pstride))[2 * t + 1] = (u16)r;
+            if (hist) MF_ADD32(cnt_row(s, m, b - 1, (int32_t)udiv16(t, Lr)) + (r >> 6), 0x10000u);
         }
         if (b == 0 && cb == s.h && T.j0 == 1) {
             y[0] = m.xv[t];
@@ -1064,10 +1095,6 @@ MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
 
 // ---------------------------------------------------------------- 4. tables
 
-MF_HD int32_t pair_chunks(const Shape &s, const Tile &T, int32_t p)
-{
-    return ceil_div32(block_len(s, T, p + 1), s.L);
-}
 
 // Count table of pair p: row c (chunk start c*L), column w (64-position
 // word): after the passes below, entry (c, w) is the number of members of
@@ -1075,19 +1102,10 @@ MF_HD int32_t pair_chunks(const Shape &s, const Tile &T, int32_t p)
 // the total (k).  A position holding A's item t is a member before step cL
 // iff t >= cL, one holding B's item t iff t < cL.
 
-MF_HD u32 *cnt_row(const Shape &s, const TileMem &m, int32_t p, int32_t c)
-{
-    return m.cnt + ((int64_t)p * s.C + c) * (s.Wn + 1);
-}
 
 // Item = entry e of the table of pair p: zero it.
 MF_HD void table_zero_item(const TileMem &m, int32_t e) { m.cnt[e] = 0u; }
 
-#if defined(__HIP_DEVICE_COMPILE__)
-#define MF_ADD32(ptr, v) atomicAdd((unsigned int *)(ptr), (unsigned int)(v))
-#else
-#define MF_ADD32(ptr, v) (*(ptr) += (v))
-#endif
 
 // Item = merged position r of pair p (r < k + len B): count its item in
 // bucket (min(t/L, chunks-1), r/64); A items in the low half, B items in the
@@ -1138,18 +1156,15 @@ MF_HD void table_colapply_item(const Shape &s, const TileMem &m, int32_t p, int3
 #pragma unroll
     for (int q = 0; q < kColGroups; q++) {
         const u32 v = gt[q];
-        sa += (q > g) ? (v & 0xFFFFu) : 0u;
-        pb += (q < g) ? (v >> 16) : 0u;
+        sa += (q >= g) ? (v & 0xFFFFu) : 0u;   // A items of this and later groups
+        pb += (q < g) ? (v >> 16) : 0u;        // B items of earlier groups
     }
-    // A: suffix over the group's rows, visited from the last
-    for (int32_t c = c1 - 1; c >= c0; c--) {
-        const u32 v = col[c * stride];
-        sa += v & 0xFFFFu;
-        col[c * stride] = (v & 0xFFFF0000u) | sa;
-    }
+    // one pass down the group: the A suffix at row c is the A count from
+    // row c on, i.e. sa minus the A items of the group's earlier rows
     for (int32_t c = c0; c < c1; c++) {
         const u32 v = col[c * stride];
-        col[c * stride] = (v & 0xFFFFu) + pb;
+        col[c * stride] = sa + pb;
+        sa -= v & 0xFFFFu;
         pb += v >> 16;
     }
 }

@@ -178,6 +178,8 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
             cnt[q] = tile_label_counts(m, q, N, ww);
             for (int j = 0; j < kRegs; j++) w[(size_t)q * kRegs + j] = ww[j];
         }
+        if (s.C > 1)
+            for (int q = 0; q < threads; q++) tail_table_zero(s, T, m, q, threads);
         u64 ex = 0;
         for (int q = 0; q < threads; q++) {
             u64 ww[kRegs];
@@ -191,8 +193,10 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         for (int q = 0; q < threads; q++) tail_first_medians(s, T, m, q, threads);
     }
     if (s.C > 1) {
-        for (int q = 0; q < threads; q++) tail_table_zero(s, T, m, q, threads);
-        for (int q = 0; q < threads; q++) tail_table_hist(s, T, m, q, threads);
+        if (!(fast && tord)) {
+            for (int q = 0; q < threads; q++) tail_table_zero(s, T, m, q, threads);
+            for (int q = 0; q < threads; q++) tail_table_hist(s, T, m, q, threads);
+        }
         for (int q = 0; q < threads; q++) tail_table_colsums(s, T, m, q, threads);
         for (int q = 0; q < threads; q++) tail_table_colapply(s, T, m, q, threads);
         for (int q = 0; q < threads; q++) tail_table_rows(s, T, m, q, threads);
