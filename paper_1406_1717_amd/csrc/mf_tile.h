@@ -733,9 +733,8 @@ MF_HD void bucket_scatter(const Shape &s, const Tile &T, const TileMem &m, int32
         if (sv_valid(v[j])) row[V.start[bucket_of<F32>(V.f, sv_key(v[j]))] + arr[j]] = v[j];
 }
 
-// Per thread: final position = bucket start + rank among the bucket's items.
-// All of the thread's buckets are scanned together, one item per round,
-// with selects rather than branches.
+// Per thread: final position = bucket start + rank among the bucket's items
+// by the full value.
 template <bool F32>
 MF_HD void bucket_rank(const Shape &s, const Tile &T, const TileMem &m, int32_t tid,
                        const u64 (&v)[kRegs], u32 (&fin)[kRegs])
@@ -752,17 +751,13 @@ MF_HD void bucket_rank(const Shape &s, const Tile &T, const TileMem &m, int32_t 
         if (b >= 0 && sv_valid(v[j])) view_bucket<F32>(s, V, sv_key(v[j]), x[j], hi[j]);
         fin[j] = x[j];
     }
-    for (int round = 0; round < kBucketMax; round++) {
-        u32 more = 0u;
+    // one bucket scan per item: a wave pays, per item slot, for the largest
+    // of its lanes' buckets (rather than for the largest of all its items)
 #pragma unroll
-        for (int j = 0; j < kRegs; j++) {
-            const bool act = x[j] < hi[j];
-            const u64 o = V.row[act ? x[j] : 0u];
-            fin[j] += (act && o < v[j]) ? 1u : 0u;
-            x[j] += act ? 1u : 0u;
-            more |= (x[j] < hi[j]) ? 1u : 0u;
-        }
-        if (!more) break;
+    for (int j = 0; j < kRegs; j++) {
+        u32 f = fin[j];
+        for (u32 q = x[j]; q < hi[j]; q++) f += (V.row[q] < v[j]) ? 1u : 0u;
+        fin[j] = f;
     }
 }
 
@@ -782,7 +777,7 @@ MF_HD int32_t pair_chunks(const Shape &s, const Tile &T, int32_t p)
 
 MF_HD u32 *cnt_row(const Shape &s, const TileMem &m, int32_t p, int32_t c)
 {
-    return m.cnt + ((int64_t)p * s.C + c) * (s.Wn + 1);
+    return m.cnt + (p * s.C + c) * (s.Wn + 1);
 }
 
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -932,7 +927,7 @@ MF_HD void tile_scatter(const Shape &st, const TileMem &m, const u64 (&v)[kRegs]
 }
 
 // Per thread: sorted position = bucket start + rank by the full value among
-// the bucket's items (rounds as in bucket_rank).  N: valid items.
+// the bucket's items (as in bucket_rank).  N: valid items.
 template <bool F32>
 MF_HD void tile_rank(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], int32_t N, u32 (&fin)[kRegs])
 {
@@ -949,17 +944,11 @@ MF_HD void tile_rank(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], i
         }
         fin[j] = x[j];
     }
-    for (int round = 0; round < kBucketMax; round++) {
-        u32 more = 0u;
 #pragma unroll
-        for (int j = 0; j < kRegs; j++) {
-            const bool act = x[j] < hi[j];
-            const u64 o = m.srt[act ? x[j] : 0u];
-            fin[j] += (act && o < v[j]) ? 1u : 0u;
-            x[j] += act ? 1u : 0u;
-            more |= (x[j] < hi[j]) ? 1u : 0u;
-        }
-        if (!more) break;
+    for (int j = 0; j < kRegs; j++) {
+        u32 f = fin[j];
+        for (u32 q = x[j]; q < hi[j]; q++) f += (m.srt[q] < v[j]) ? 1u : 0u;
+        fin[j] = f;
     }
 }
 
@@ -1317,14 +1306,15 @@ MF_HD int walk_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, 
         const int32_t da = pa - base, db = pb - base;
         W ^= ((u32)da < 64u) ? (1ull << (da & 63)) : 0ull;
         W ^= ((u32)db < 64u) ? (1ull << (db & 63)) : 0ull;
-        const int32_t dir = (pa == r) ? ((pb < r) ? -1 : 1)
-                                      : ((int32_t)(pa < r) - (int32_t)(pb < r));
+        const int32_t ltA = (int32_t)(pa < r), ltB = (int32_t)(pb < r);
+        const int32_t dir = (pa == r) ? 1 - 2 * ltB : ltA - ltB;
         const int32_t rel = r - base;
         const u64 up = W & (~1ull << rel);
         const u64 dn = W & ((1ull << rel) - 1ull);
-        int32_t nr = r;
-        if (dir > 0) nr = up ? base + ctz64(up) : -1;
-        if (dir < 0) nr = dn ? base + hibit64(dn) : -1;
+        const int32_t nup = up ? base + ctz64(up) : -1;
+        const int32_t ndn = dn ? base + hibit64(dn) : -1;
+        const int32_t nr0 = dir > 0 ? nup : ndn;
+        int32_t nr = dir == 0 ? r : nr0;
         if (nr < 0) {
             nr = win_search_far(s, Mp, r, dir, i);
             if (nr < 0) {
