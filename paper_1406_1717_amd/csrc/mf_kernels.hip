@@ -14,6 +14,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <vector>
+
 #include "mf_tile.h"
 #include "mf_launch.h"
 
@@ -143,20 +146,24 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
 
 // ------------------------------------------------------------------ LDS path
 
-// One tile of the LDS path, every buffer in the workgroup's LDS.
-template <int NT, bool F32>
-__device__ __forceinline__ void lds_tile(const Resolved &d, unsigned char *lds, int *err)
+// Shape and tile of a work unit for NT-thread tiles.
+template <int NT>
+__device__ __forceinline__ void unit_shape(const Resolved &d, Shape &s, Tile &T)
 {
-    const int64_t tile = d.tile;
-    const int tid = threadIdx.x;
-
-    Shape s;
     make_shape(d.n, d.k, NT, &s);
+    T = make_tile(s, d.tile);
+}
+
+// One tile of the LDS path, every buffer in the workgroup's LDS; raw holds
+// the thread's inputs (load_raw).
+template <int NT, bool F32>
+__device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, const Tile &T,
+                                         const u32 (&raw)[kRegs], unsigned char *lds, int *err)
+{
+    const int tid = threadIdx.x;
     Layout l;
     make_layout(s, &l);
     const TileMem m = tile_mem(lds, l);
-    const Tile T = make_tile(s, tile);
-    const u32 *x = d.x;
     __shared__ u32 wave_tot[NT / 64];
     __shared__ u64 wave_tot64[NT / 64];
 
@@ -168,8 +175,8 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, unsigned char *lds, 
 
     // 1. load into registers
     u64 v[kRegs];
-    if (tord) load_tile_values<F32>(s, T, m, x, tid, v);
-    else load_sort_values<F32>(s, T, m, x, tid, v);
+    if (tord) load_tile_values<F32>(s, T, m, raw, tid, v);
+    else load_sort_values<F32>(s, T, m, raw, tid, v);
 
     // 2. bucket sort; tiles with an overfull bucket (or blocks under kRegs
     // slots) take the merge sort below.  Crowded buckets are counted again
@@ -179,6 +186,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, unsigned char *lds, 
     for (int b = tid; b < l.nbmax; b += NT) bucket_info_init(m, b);
     __syncthreads();
     bool fast = s.S >= kRegs;
+    int pass = 0;   // bucket map: 0 linear, 1 clamped logarithmic
     u32 arr[kRegs];
     if (tord) {
         tile_minmax(m, v);
@@ -192,22 +200,21 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, unsigned char *lds, 
         }
     }
     if (tord) {
-        if (tid == 0) bucket_shift_item<F32>(st, m, 0, 0);
-        __syncthreads();
-        tile_count<F32>(st, m, v, arr);
+        tile_count<F32>(st, m, v, arr, pass);
         __syncthreads();
         if (m.flag[0] != 0u) {
             __syncthreads();
+            pass = 1;
             for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
-            if (tid == 0) bucket_shift_item<F32>(st, m, 0, 1);
             if (tid == 0) m.flag[0] = 0u;
             __syncthreads();
-            tile_count<F32>(st, m, v, arr);
+            tile_count<F32>(st, m, v, arr, pass);
             __syncthreads();
         }
         if ((m.flag[0] & 1u) != 0u) {
             __syncthreads();
             tord = false;
+            pass = 0;
             tile_to_block_values(s, T, tid, v);
             for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
             for (int b = tid; b < l.nbmax; b += NT) bucket_info_init(m, b);
@@ -217,17 +224,15 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, unsigned char *lds, 
     if (fast && !tord) {
         bucket_minmax(m, v);
         __syncthreads();
-        if (tid < T.NB) bucket_shift_item<F32>(s, m, tid, 0);
-        __syncthreads();
-        bucket_count<F32>(s, T, m, tid, v, arr);
+        bucket_count<F32>(s, T, m, tid, v, arr, pass);
         __syncthreads();
         if (m.flag[0] != 0u) {
             __syncthreads();
+            pass = 1;
             for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
-            if (tid < T.NB) bucket_shift_item<F32>(s, m, tid, 1);
             if (tid == 0) m.flag[0] = 0u;
             __syncthreads();
-            bucket_count<F32>(s, T, m, tid, v, arr);
+            bucket_count<F32>(s, T, m, tid, v, arr, pass);
             __syncthreads();
         }
     }
@@ -238,13 +243,13 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, unsigned char *lds, 
         const u32 excl = seg_excl_scan<NT>(tot, (tord ? st.S : s.S) / kRegs, wave_tot);
         bucket_scan_store(m, tid, excl, c);
         __syncthreads();
-        if (tord) tile_scatter<F32>(st, m, v, arr);
-        else bucket_scatter<F32>(s, T, m, tid, v, arr);
+        if (tord) tile_scatter<F32>(st, m, v, arr, pass);
+        else bucket_scatter<F32>(s, T, m, tid, v, arr, pass);
         __syncthreads();
         u32 fin[kRegs];
         const int32_t N = tile_items(s, T);
-        if (tord) tile_rank<F32>(st, m, v, N, fin);
-        else bucket_rank<F32>(s, T, m, tid, v, fin);
+        if (tord) tile_rank<F32>(st, m, v, N, fin, pass);
+        else bucket_rank<F32>(s, T, m, tid, v, fin, pass);
         __syncthreads();
         if (tord) tile_place(m, v, fin);
         else bucket_place(s, m, v, fin);
@@ -285,24 +290,60 @@ template <int NT, bool F32>
 __global__ __launch_bounds__(NT) void k_tile_lds(Launch L, int *err)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    lds_tile<NT, F32>(unit_of(L, blockIdx.x), lds, err);
+    const Resolved d = unit_of(L, blockIdx.x);
+    Shape s;
+    Tile T;
+    unit_shape<NT>(d, s, T);
+    u32 raw[kRegs];
+    load_raw(s, T, d.x, threadIdx.x, raw);
+    lds_tile<NT, F32>(d, s, T, raw, lds, err);
 }
 
-// Persistent form: a grid sized to the resident workgroups takes units in
-// work-list order from the counter *next (zero at launch) until the list
-// is exhausted; every workgroup leaves the loop on the same condition.
+// Persistent form for ragged work lists: a grid sized to the resident
+// workgroups takes units in work-list order from the counter *next (zero
+// at launch) until the list is exhausted, fetching each next unit (and
+// issuing its loads) before working on the current one; every workgroup
+// leaves the loop on the same condition.
 template <int NT, bool F32>
-__global__ __launch_bounds__(NT) void k_tile_lds_persistent(Launch L, u32 *next, int *err)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_tile_lds_persistent(Launch L, u32 *next, int *err)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ u32 cur;
+    if (threadIdx.x == 0) cur = atomicAdd(next, 1u);
+    __syncthreads();
+    u32 u = cur;
+    if ((int64_t)u >= L.nunits) return;
+    Resolved d = unit_of(L, u);
+    u32 raw[kRegs];
+    {
+        Shape s;
+        Tile T;
+        unit_shape<NT>(d, s, T);
+        load_raw(s, T, d.x, threadIdx.x, raw);
+    }
     for (;;) {
-        __syncthreads();   // the previous tile is done with LDS and with cur
+        __syncthreads();   // every thread has read cur; the last tile is done with LDS
         if (threadIdx.x == 0) cur = atomicAdd(next, 1u);
         __syncthreads();
-        const u32 u = cur;
-        if ((int64_t)u >= L.nunits) break;
-        lds_tile<NT, F32>(unit_of(L, u), lds, err);
+        const u32 un = cur;
+        const bool more = (int64_t)un < L.nunits;
+        Resolved dn = d;
+        u32 rawn[kRegs];
+        if (more) {
+            dn = unit_of(L, un);
+            Shape sn;
+            Tile Tn;
+            unit_shape<NT>(dn, sn, Tn);
+            load_raw(sn, Tn, dn.x, threadIdx.x, rawn);
+        }
+        Shape s;
+        Tile T;
+        unit_shape<NT>(d, s, T);
+        lds_tile<NT, F32>(d, s, T, raw, lds, err);
+        if (!more) break;
+        d = dn;
+#pragma unroll
+        for (int j = 0; j < kRegs; j++) raw[j] = rawn[j];
     }
 }
 
@@ -592,6 +633,41 @@ hipError_t prepare_kernels()
     return e;
 }
 
+// Workgroups of `kern` (nt threads, lds bytes of dynamic LDS) resident on
+// the current device at once; cached per (kernel, lds) on each device.
+static hipError_t resident_workgroups(const void *kern, int nt, size_t lds, int64_t *out)
+{
+    struct Entry {
+        int dev;
+        const void *kern;
+        size_t lds;
+        int64_t n;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const Entry &c : cache)
+            if (c.dev == dev && c.kern == kern && c.lds == lds) {
+                *out = c.n;
+                return hipSuccess;
+            }
+    }
+    int cus = 0, per_cu = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    const int64_t n = (int64_t)cus * per_cu;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cache.size() < 256) cache.push_back(Entry{dev, kern, lds, n});
+    *out = n;
+    return hipSuccess;
+}
+
 hipError_t launch_forward(Path p, bool f32, const Launch &L, size_t lds_bytes,
                           unsigned char *ws, int64_t ws_stride, int64_t ws_slots,
                           int *d_err, hipStream_t st)
@@ -604,13 +680,18 @@ hipError_t launch_forward(Path p, bool f32, const Launch &L, size_t lds_bytes,
         break;
     }
     case PATH_LDS_SMALL:
-        if (f32) hipLaunchKernelGGL((k_tile_lds<kLdsSmall, true>), dim3((unsigned)L.nunits), dim3(kLdsSmall), lds_bytes, st, L, d_err);
-        else     hipLaunchKernelGGL((k_tile_lds<kLdsSmall, false>), dim3((unsigned)L.nunits), dim3(kLdsSmall), lds_bytes, st, L, d_err);
+    case PATH_LDS_LARGE: {
+        const int nt = p == PATH_LDS_SMALL ? kLdsSmall : kLdsLarge;
+        const dim3 g((unsigned)L.nunits), b((unsigned)nt);
+        if (p == PATH_LDS_SMALL) {
+            if (f32) hipLaunchKernelGGL((k_tile_lds<kLdsSmall, true>), g, b, lds_bytes, st, L, d_err);
+            else     hipLaunchKernelGGL((k_tile_lds<kLdsSmall, false>), g, b, lds_bytes, st, L, d_err);
+        } else {
+            if (f32) hipLaunchKernelGGL((k_tile_lds<kLdsLarge, true>), g, b, lds_bytes, st, L, d_err);
+            else     hipLaunchKernelGGL((k_tile_lds<kLdsLarge, false>), g, b, lds_bytes, st, L, d_err);
+        }
         break;
-    case PATH_LDS_LARGE:
-        if (f32) hipLaunchKernelGGL((k_tile_lds<kLdsLarge, true>), dim3((unsigned)L.nunits), dim3(kLdsLarge), lds_bytes, st, L, d_err);
-        else     hipLaunchKernelGGL((k_tile_lds<kLdsLarge, false>), dim3((unsigned)L.nunits), dim3(kLdsLarge), lds_bytes, st, L, d_err);
-        break;
+    }
     case PATH_GLOBAL: {
         const int64_t grid = L.nunits < ws_slots ? L.nunits : ws_slots;
         if (f32) hipLaunchKernelGGL((k_tile_global<true>), dim3((unsigned)grid), dim3(kGlobalThreads), lds_bytes, st, L, ws, ws_stride, d_err);
@@ -628,16 +709,12 @@ hipError_t launch_forward_persistent(Path p, const Launch &L, size_t lds_bytes, 
 {
     if (L.nunits <= 0) return hipSuccess;
     if (p != PATH_LDS_SMALL && p != PATH_LDS_LARGE) return hipErrorInvalidValue;
-    int dev = 0, cus = 0, per_cu = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int nt = p == PATH_LDS_SMALL ? kLdsSmall : kLdsLarge;
     const void *kern = p == PATH_LDS_SMALL ? (const void *)k_tile_lds_persistent<kLdsSmall, true>
                                            : (const void *)k_tile_lds_persistent<kLdsLarge, true>;
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, lds_bytes);
+    int64_t grid = 0;
+    hipError_t e = resident_workgroups(kern, nt, lds_bytes, &grid);
     if (e != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
-    int64_t grid = (int64_t)cus * per_cu;
     if (grid > L.nunits) grid = L.nunits;
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, next, 1);
     if (p == PATH_LDS_SMALL)

@@ -117,6 +117,16 @@ MF_HD int hibit64(u64 v)   // index of the highest set bit, v != 0
 #endif
 }
 
+// Number of significant bits of v (0 for v = 0).
+MF_HD int32_t bitlen32(u32 v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return v ? 32 - __clz((int)v) : 0;
+#else
+    return v ? 32 - __builtin_clz(v) : 0;
+#endif
+}
+
 // Position of the q-th (0-based) set bit of w; w must have more than q bits.
 MF_HD int select64(u64 w, int q)
 {
@@ -166,7 +176,7 @@ struct Layout {
     int32_t cnt;     // u32[Pmax * C * (Wn + 1)]   (aliases srt)
     int32_t ctot;    // u32[Pmax * Wn * kColGroups] (aliases srt)
     int32_t bk;      // u32[cap] bucket counters   (aliases M, pos)
-    int32_t info;    // u32[7 * nbmax + 1]         (aliases M, pos)
+    int32_t info;    // u32[2 * nbmax + 1]         (aliases M, pos)
     int32_t nbmax;   // blocks of a full tile
     int32_t stage;   // u16[Pmax * k]              (aliases srt)
     int32_t total;   // bytes
@@ -255,7 +265,7 @@ MF_HD void make_layout(const Shape &s, Layout *l)
     l->bk = l->M;
     l->info = l->bk + 4 * s.cap;
     l->nbmax = s.Pmax + 1;
-    const int32_t bend = l->info + 4 * (7 * (s.Pmax + 1) + 1);
+    const int32_t bend = l->info + 4 * (2 * (s.Pmax + 1) + 1);
     if (off < bend) off = (bend + 15) & ~15;
     l->total = off;
     int32_t a = l->srt;
@@ -301,11 +311,6 @@ struct TileMem {
     u32 *bk;         // bucket counters / starts, slot-indexed like srt
     u32 *bmin;       // per block: smallest key
     u32 *bmax;       // per block: largest key
-    u32 *bshift;     // per block: bucket shift (key and integer-log maps)
-    u32 *bmode;      // per block: bucket map (BK_KEY, BK_FLIN, BK_CLOG)
-    u32 *blo;        // per block: mapped value of the block minimum
-    u32 *bfmin;      // per block: float minimum (BK_FLIN, as bits) or floor (BK_CLOG)
-    u32 *bscale;     // per block: buckets per unit value (BK_FLIN), as bits
     u32 *flag;       // bit 0: a bucket passed kBucketMax; bit 1: kBucketSoft
     u32 *xv;
     u64 *srt;
@@ -322,12 +327,7 @@ MF_HD TileMem tile_mem(unsigned char *base, const Layout &l)
     m.bk = (u32 *)(base + l.bk);
     m.bmin = (u32 *)(base + l.info);
     m.bmax = m.bmin + l.nbmax;
-    m.bshift = m.bmax + l.nbmax;
-    m.bmode = m.bshift + l.nbmax;
-    m.blo = m.bmode + l.nbmax;
-    m.bfmin = m.blo + l.nbmax;
-    m.bscale = m.bfmin + l.nbmax;
-    m.flag = m.bscale + l.nbmax;
+    m.flag = m.bmax + l.nbmax;
     m.xv = (u32 *)(base + l.xv);
     m.srt = (u64 *)(base + l.srt);
     m.M = (u16 *)(base + l.M);
@@ -363,23 +363,28 @@ MF_HD u64 sort_value(const Shape &s, const Tile &T, const TileMem &m, int32_t u)
     return hb | ((u64)key << 16) | (u64)t;
 }
 
-// Phases 1 and 2 together: thread `tid` loads the inputs of its kRegs slots
-// straight into registers (all loads in flight at once), keeps the raw
-// patterns in xv for the output phase and returns the packed sort values.
-template <bool F32>
-MF_HD void load_sort_values(const Shape &s, const Tile &T, const TileMem &m, const u32 *x,
-                            int32_t tid, u64 (&v)[kRegs])
+// Phase 1, global part: thread `tid` loads the inputs of its kRegs slots
+// (block b = slot >> logS, t = slot & (S-1); 0 past a block's end) into
+// registers, all loads in flight at once.  Separate from the rest of the
+// tile so that a workgroup can issue the next tile's loads early.
+MF_HD void load_raw(const Shape &s, const Tile &T, const u32 *x, int32_t tid, u32 (&raw)[kRegs])
 {
-    u32 raw[kRegs];
-    int32_t len[kRegs];
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         const int32_t u = tid * kRegs + j;
         const int32_t b = u >> s.logS;
         const int32_t t = u & (s.S - 1);
-        len[j] = (b < T.NB) ? block_len(s, T, b) : 0;
-        raw[j] = (t < len[j]) ? x[T.e0 + (int64_t)b * s.k + t] : 0u;
+        const int32_t len = (b < T.NB) ? block_len(s, T, b) : 0;
+        raw[j] = (t < len) ? x[T.e0 + (int64_t)b * s.k + t] : 0u;
     }
+}
+
+// Phases 1 and 2 together: keeps the raw patterns in xv for the output
+// phase and returns the packed sort values of the thread's slots.
+template <bool F32>
+MF_HD void load_sort_values(const Shape &s, const Tile &T, const TileMem &m, const u32 (&raw)[kRegs],
+                            int32_t tid, u64 (&v)[kRegs])
+{
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         const int32_t u = tid * kRegs + j;
@@ -387,7 +392,7 @@ MF_HD void load_sort_values(const Shape &s, const Tile &T, const TileMem &m, con
         const int32_t t = u & (s.S - 1);
         if (b >= T.NB) { v[j] = kPadAll; continue; }
         const u64 hb = (u64)b << 48;
-        if (t >= len[j]) { v[j] = hb | 0x0000FFFFFFFFFFFFull; continue; }
+        if (t >= block_len(s, T, b)) { v[j] = hb | 0x0000FFFFFFFFFFFFull; continue; }
         m.xv[u] = raw[j];
         const u32 key = F32 ? key_of_f32(raw[j]) : key_of_i32(raw[j]);
         v[j] = hb | ((u64)key << 16) | (u64)t;
@@ -572,22 +577,28 @@ MF_HD void bucket_minmax(const TileMem &m, const u64 (&v)[kRegs])
     }
 }
 
-// Item = block b: the bucket map of `pass` (0: linear in the value, 1:
-// clamped logarithmic), landing in [0, S) over the block's range.
+// The bucket map of `pass` (0: linear in the value, 1: clamped
+// logarithmic) for keys in [mn, mx], landing in [0, S).  Every thread that
+// needs a block's map builds it from the block's key range (the same
+// arithmetic everywhere, so the same map).
 template <bool F32>
-MF_HD void bucket_shift_item(const Shape &s, const TileMem &m, int32_t b, int pass)
+MF_HD BucketFn make_bucket_fn(int32_t S, int32_t logS, u32 mn, u32 mx, int pass)
 {
-    const u32 mn = m.bmin[b], mx = m.bmax[b];
-    u32 mode = BK_KEY, lo = mn, hi = mx, floor_mag = 0u;
-    float fmin = 0.f, scale = 0.f;
+    BucketFn f;
+    f.mode = BK_KEY;
+    f.lo = mn;
+    f.fmin = f.scale = 0.f;
+    f.floor_mag = 0u;
+    f.top = (u32)S - 1u;
+    u32 hi = mx;
     if (F32 && pass == 0 && mn > 0x007FFFFFu && mx < 0xFF800000u) {   // finite range
         const float a = f32_of_key(mn), r = f32_of_key(mx) - a;
         if (r > 0.f && r <= 3.0e38f) {
-            const float sc = (float)s.S / r;
+            const float sc = (float)S / r;
             if (sc <= 3.0e38f) {
-                mode = BK_FLIN;
-                fmin = a;
-                scale = sc;
+                f.mode = BK_FLIN;
+                f.fmin = a;
+                f.scale = sc;
             }
         }
     }
@@ -595,32 +606,20 @@ MF_HD void bucket_shift_item(const Shape &s, const TileMem &m, int32_t b, int pa
         const u32 a = F32 ? mn : ilog_key(mn), z = F32 ? mx : ilog_key(mx);
         const u32 ma = key_mag(a), mz = key_mag(z);
         const u32 top = ma > mz ? ma : mz, span = kLogSpan << 23;
-        mode = BK_CLOG;
-        floor_mag = top > span ? top - span : 0u;
-        lo = clog_code(a, floor_mag);
-        hi = clog_code(z, floor_mag);
+        f.mode = BK_CLOG;
+        f.floor_mag = top > span ? top - span : 0u;
+        f.lo = clog_code(a, f.floor_mag);
+        hi = clog_code(z, f.floor_mag);
     }
-    const u32 range = hi - lo;
-    int32_t bits = 0;
-    while (bits < 32 && (range >> bits) != 0u) bits++;
-    m.bshift[b] = (u32)(bits > s.logS ? bits - s.logS : 0);
-    m.bmode[b] = mode;
-    m.blo[b] = lo;
-    m.bfmin[b] = mode == BK_CLOG ? floor_mag : f32_bits(fmin);
-    m.bscale[b] = f32_bits(scale);
+    const int32_t bits = bitlen32(hi - f.lo);
+    f.sh = (u32)(bits > logS ? bits - logS : 0);
+    return f;
 }
 
-MF_HD BucketFn bucket_fn(const Shape &s, const TileMem &m, int32_t b)
+template <bool F32>
+MF_HD BucketFn bucket_fn(const Shape &s, const TileMem &m, int32_t b, int pass)
 {
-    BucketFn f;
-    f.mode = m.bmode[b];
-    f.lo = m.blo[b];
-    f.sh = m.bshift[b];
-    f.fmin = bits_f32(m.bfmin[b]);
-    f.floor_mag = m.bfmin[b];
-    f.scale = bits_f32(m.bscale[b]);
-    f.top = (u32)s.S - 1u;
-    return f;
+    return make_bucket_fn<F32>(s.S, s.logS, m.bmin[b], m.bmax[b], pass);
 }
 
 // A block's bucket parameters, read once per thread.
@@ -631,12 +630,13 @@ struct BlockView {
     const u64 *row;        // the block's sort buffer
 };
 
-MF_HD BlockView block_view(const Shape &s, const Tile &T, const TileMem &m, int32_t b)
+template <bool F32>
+MF_HD BlockView block_view(const Shape &s, const Tile &T, const TileMem &m, int32_t b, int pass)
 {
     BlockView V;
     V.mn = m.bmin[b];
     V.mx = m.bmax[b];
-    V.f = bucket_fn(s, m, b);
+    V.f = bucket_fn<F32>(s, m, b, pass);
     V.len = (u32)block_len(s, T, b);
     V.start = m.bk + (b << s.logS);
     V.row = m.srt + (b << s.logS);
@@ -654,7 +654,7 @@ MF_HD int32_t thread_block(const Shape &s, const Tile &T, int32_t tid)
 // number.  Sets the flag when a bucket passes kBucketMax.
 template <bool F32>
 MF_HD void bucket_count(const Shape &s, const Tile &T, const TileMem &m, int32_t tid,
-                        const u64 (&v)[kRegs], u32 (&arr)[kRegs])
+                        const u64 (&v)[kRegs], u32 (&arr)[kRegs], int pass)
 {
     const int32_t b = thread_block(s, T, tid);
     BucketFn f;
@@ -662,7 +662,7 @@ MF_HD void bucket_count(const Shape &s, const Tile &T, const TileMem &m, int32_t
     f.lo = f.sh = 0u;
     f.fmin = f.scale = 0.f;
     f.floor_mag = f.top = 0u;
-    if (b >= 0) f = bucket_fn(s, m, b);
+    if (b >= 0) f = bucket_fn<F32>(s, m, b, pass);
     u32 *cnt = m.bk + (b >= 0 ? (b << s.logS) : 0);
     u32 mx = 0u;
 #pragma unroll
@@ -722,11 +722,11 @@ MF_HD void view_bucket(const Shape &s, const BlockView &V, u32 key, u32 &lo, u32
 // Per thread: place each item at bucket start + arrival number.
 template <bool F32>
 MF_HD void bucket_scatter(const Shape &s, const Tile &T, const TileMem &m, int32_t tid,
-                          const u64 (&v)[kRegs], const u32 (&arr)[kRegs])
+                          const u64 (&v)[kRegs], const u32 (&arr)[kRegs], int pass)
 {
     const int32_t b = thread_block(s, T, tid);
     if (b < 0) return;
-    const BlockView V = block_view(s, T, m, b);
+    const BlockView V = block_view<F32>(s, T, m, b, pass);
     u64 *row = m.srt + (b << s.logS);
 #pragma unroll
     for (int j = 0; j < kRegs; j++)
@@ -737,13 +737,13 @@ MF_HD void bucket_scatter(const Shape &s, const Tile &T, const TileMem &m, int32
 // by the full value.
 template <bool F32>
 MF_HD void bucket_rank(const Shape &s, const Tile &T, const TileMem &m, int32_t tid,
-                       const u64 (&v)[kRegs], u32 (&fin)[kRegs])
+                       const u64 (&v)[kRegs], u32 (&fin)[kRegs], int pass)
 {
     const int32_t b = thread_block(s, T, tid);
     u32 x[kRegs], hi[kRegs];
     BlockView V;
     V.row = m.srt;
-    if (b >= 0) V = block_view(s, T, m, b);
+    if (b >= 0) V = block_view<F32>(s, T, m, b, pass);
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         x[j] = 0u;
@@ -826,25 +826,15 @@ MF_HD int32_t tile_items(const Shape &s, const Tile &T)
 
 // Phase 1 for tile order: as load_sort_values, with tile-order values.
 template <bool F32>
-MF_HD void load_tile_values(const Shape &s, const Tile &T, const TileMem &m, const u32 *x,
+MF_HD void load_tile_values(const Shape &s, const Tile &T, const TileMem &m, const u32 (&raw)[kRegs],
                             int32_t tid, u64 (&v)[kRegs])
 {
-    u32 raw[kRegs];
-    int32_t len[kRegs];
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         const int32_t u = tid * kRegs + j;
         const int32_t b = u >> s.logS;
         const int32_t t = u & (s.S - 1);
-        len[j] = (b < T.NB) ? block_len(s, T, b) : 0;
-        raw[j] = (t < len[j]) ? x[T.e0 + (int64_t)b * s.k + t] : 0u;
-    }
-#pragma unroll
-    for (int j = 0; j < kRegs; j++) {
-        const int32_t u = tid * kRegs + j;
-        const int32_t b = u >> s.logS;
-        const int32_t t = u & (s.S - 1);
-        if (t >= len[j]) { v[j] = kPadAll; continue; }
+        if (b >= T.NB || t >= block_len(s, T, b)) { v[j] = kPadAll; continue; }
         m.xv[u] = raw[j];
         const u32 key = F32 ? key_of_f32(raw[j]) : key_of_i32(raw[j]);
         v[j] = ((u64)key << 32) | ((u64)b << 16) | (u64)t;
@@ -902,9 +892,9 @@ MF_HD bool tile_many_ties(const TileMem &m, int32_t N)
 
 // Per thread: arrival numbers in the tile's buckets (st = tile_order_shape).
 template <bool F32>
-MF_HD void tile_count(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], u32 (&arr)[kRegs])
+MF_HD void tile_count(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], u32 (&arr)[kRegs], int pass)
 {
-    const BucketFn f = bucket_fn(st, m, 0);
+    const BucketFn f = bucket_fn<F32>(st, m, 0, pass);
     u32 mx = 0u;
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
@@ -918,9 +908,10 @@ MF_HD void tile_count(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], 
 }
 
 template <bool F32>
-MF_HD void tile_scatter(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], const u32 (&arr)[kRegs])
+MF_HD void tile_scatter(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], const u32 (&arr)[kRegs],
+                        int pass)
 {
-    const BucketFn f = bucket_fn(st, m, 0);
+    const BucketFn f = bucket_fn<F32>(st, m, 0, pass);
 #pragma unroll
     for (int j = 0; j < kRegs; j++)
         if (sv_valid(v[j])) m.srt[m.bk[bucket_of<F32>(f, tv_key(v[j]))] + arr[j]] = v[j];
@@ -929,9 +920,10 @@ MF_HD void tile_scatter(const Shape &st, const TileMem &m, const u64 (&v)[kRegs]
 // Per thread: sorted position = bucket start + rank by the full value among
 // the bucket's items (as in bucket_rank).  N: valid items.
 template <bool F32>
-MF_HD void tile_rank(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], int32_t N, u32 (&fin)[kRegs])
+MF_HD void tile_rank(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], int32_t N, u32 (&fin)[kRegs],
+                     int pass)
 {
-    const BucketFn f = bucket_fn(st, m, 0);
+    const BucketFn f = bucket_fn<F32>(st, m, 0, pass);
     u32 x[kRegs], hi[kRegs];
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {

@@ -35,22 +35,21 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
     std::vector<u64> regs((size_t)threads * kRegs), tmp((size_t)threads * kRegs);
     for (int q = 0; q < threads; q++) {
         u64 v[kRegs];
-        if (tord) load_tile_values<F32>(s, T, m, x, q, v);
-        else load_sort_values<F32>(s, T, m, x, q, v);
+        u32 raw[kRegs];
+        load_raw(s, T, x, q, raw);
+        if (tord) load_tile_values<F32>(s, T, m, raw, q, v);
+        else load_sort_values<F32>(s, T, m, raw, q, v);
         for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
     }
     auto V = [&](int q, u64 (&v)[kRegs]) { for (int j = 0; j < kRegs; j++) v[j] = regs[(size_t)q * kRegs + j]; };
+    int pass = 0;
     auto count = [&](std::vector<u32> &arr) {
         for (int q = 0; q < threads; q++) {
             u64 v[kRegs]; V(q, v); u32 a[kRegs];
-            if (tord) tile_count<F32>(st, m, v, a);
-            else bucket_count<F32>(s, T, m, q, v, a);
+            if (tord) tile_count<F32>(st, m, v, a, pass);
+            else bucket_count<F32>(s, T, m, q, v, a, pass);
             for (int j = 0; j < kRegs; j++) arr[(size_t)q * kRegs + j] = a[j];
         }
-    };
-    auto shift = [&](int pass) {
-        if (tord) bucket_shift_item<F32>(st, m, 0, pass);
-        else for (int b = 0; b < T.NB; b++) bucket_shift_item<F32>(s, m, b, pass);
     };
     // bucket path
     for (int e = 0; e < s.cap; e++) bucket_zero_item(m, e);
@@ -59,12 +58,12 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
     std::vector<u32> arr((size_t)threads * kRegs), fin((size_t)threads * kRegs);
     const int32_t N = tile_items(s, T);
     auto attempt_counts = [&]() {
-        shift(0);
+        pass = 0;
         count(arr);
         if (m.flag[0] != 0u) {
             g_recount_tiles++;
             for (int e = 0; e < s.cap; e++) bucket_zero_item(m, e);
-            shift(1);
+            pass = 1;
             m.flag[0] = 0u;
             count(arr);
         }
@@ -85,6 +84,7 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         attempt_counts();
         if ((m.flag[0] & 1u) != 0u) {
             tord = false;
+            pass = 0;
             for (int q = 0; q < threads; q++) {
                 u64 v[kRegs]; V(q, v);
                 tile_to_block_values(s, T, q, v);
@@ -118,13 +118,13 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         for (int q = 0; q < threads; q++) {
             u64 v[kRegs]; V(q, v); u32 a[kRegs];
             for (int j = 0; j < kRegs; j++) a[j] = arr[(size_t)q * kRegs + j];
-            if (tord) tile_scatter<F32>(st, m, v, a);
-            else bucket_scatter<F32>(s, T, m, q, v, a);
+            if (tord) tile_scatter<F32>(st, m, v, a, pass);
+            else bucket_scatter<F32>(s, T, m, q, v, a, pass);
         }
         for (int q = 0; q < threads; q++) {
             u64 v[kRegs]; V(q, v); u32 f[kRegs];
-            if (tord) tile_rank<F32>(st, m, v, N, f);
-            else bucket_rank<F32>(s, T, m, q, v, f);
+            if (tord) tile_rank<F32>(st, m, v, N, f, pass);
+            else bucket_rank<F32>(s, T, m, q, v, f, pass);
             for (int j = 0; j < kRegs; j++) fin[(size_t)q * kRegs + j] = f[j];
         }
         for (int q = 0; q < threads; q++) {
