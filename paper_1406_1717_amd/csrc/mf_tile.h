@@ -11,31 +11,35 @@
 // so the same functions also run on the host, one item after another, for
 // checking the tile logic without a GPU.
 //
-//   1. load      x -> xv (raw 32-bit patterns), block b at slot b*S.
-//   2. sort      each block sorted by (key, t): packed u64 values
-//                (block << 48 | key << 16 | t), bitonic-16 in registers,
-//                then merge-path levels of run length 16, 32, .., S/2.
-//                Packing the local index t makes every value distinct, so
-//                the sort is stable in the sense of Section 5.2.
-//   3. pair merge  for each pair, the merged order of A and B by
+//   1. load      x -> registers (8 slots per thread; block b at slot b*S)
+//                and the raw patterns into xv for the output.
+//   2. sort      bucket sort (a monotone map of the key onto buckets, LDS
+//                atomic counts, scan, scatter, rank within the bucket by
+//                the full value).  Tiles of at most four blocks sort all
+//                their items at once by (key, block, t) ("tile order");
+//                others sort each block by (key, t).  Packing the index
+//                into the value makes every value distinct, so the sort is
+//                stable in the sense of Section 5.2.  Heavy ties fall back
+//                to a merge sort (bitonic in registers, merge-path levels).
+//   3. pair orders  for each pair, the merged order of A and B by
 //                (key, A-before-B, t) -> M[r] = isB << 15 | t (stored at
-//                mslot(r)), and the
-//                merged positions posA[t], posB[t].
+//                mslot(r)), and the merged positions posA[t], posB[t]:
+//                from a prefix count of each block's items along the tile
+//                order, or by merge path.
 //   4. tables    for every walk chunk (steps c*L ..), the number of window
 //                members below each 64-position word of the merged order at
-//                the chunk's start: one packed histogram over (time bucket
-//                t/L, word) of A and B items, then prefix sums.
+//                the chunk's start: a packed histogram over (t/L, word) of
+//                A and B items, then prefix sums.
 //   5. walk      one lane per chunk of L steps (short chunks, so that many
 //                lanes walk at once): the window of step i is
-//                A[i+1..] u B[..i] (Section 3 "Postprocessing").  In merged
-//                order, position r is a member after step i iff
-//                (isA and t > i) or (isB and t <= i).  Step i removes
-//                A[i] and adds B[i]; the rank-h member then moves to the
-//                next or previous member, or stays: this is the block
-//                structures' cursor update (Section 5.3) and rebalancing
-//                (Section 6.2) with both cursors folded into one position
-//                of the merged order.  A 128-bit register window of
-//                membership bits around the median is kept up to date.
+//                A[i+1..] u B[..i] (Section 3, postprocessing).  In merged order,
+//                position r is a member after step i iff (isA and t > i) or (isB and
+//                t <= i).  Step i removes A[i] and adds B[i]; the rank-h
+//                member then moves to the next or previous member, or stays:
+//                this is the block structures' cursor update (Section 5.3)
+//                and rebalancing (Section 6.2) with both cursors folded into
+//                one position of the merged order.  A 64-bit register window
+//                of membership bits around the median is kept up to date.
 //   6. output    y[o] = x[argmed[o]] (bit copy), argmed[o] global index.
 #pragma once
 #include <stdint.h>
@@ -1174,11 +1178,6 @@ MF_HD void pair_first_median(const Shape &s, const TileMem &m, int32_t p)
 }
 
 // ---------------------------------------------------------------- 5. walk
-
-// The walk keeps the membership of positions [32*wl, 32*wl + 96) in three
-// 32-bit registers w0, w1, w2 (dwords wl, wl+1, wl+2 of the merged order).
-// The helpers take the words by value (or update them one by one), so every
-// choice among them is a register select.
 
 MF_HD int ctz32(u32 v) { return __builtin_ctz(v); }   // v != 0
 
