@@ -192,11 +192,17 @@ def main():
 
 
 def kernel_source_sha():
+    """Hash of the kernel sources with comments and blank space removed
+    (the HBM counters stay valid across comment edits)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("mf_tile.h", "mf_kernels.hip"):
-        with open(os.path.join(ROOT, "paper_1406_1717_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1406_1717_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update(re.sub(r"\s+", "", text).encode())
     return h.hexdigest()[:16]
 
 
