@@ -111,14 +111,14 @@ __device__ __forceinline__ Resolved unit_of(const Launch &L, int64_t uidx)
 }
 
 // Phases 3-6 of a tile (pair merge, tables, walk, output); phases 1-2 have
-// filled m.xv and m.srt.  NT threads, barriers between phases.
+// filled m.srt.  NT threads, barriers between phases.
 template <int NT>
 __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
                                           int *err, bool merged)
 {
     const int tid = threadIdx.x;
     if (!merged) {
-        tail_pair_merge(s, T, m, tid, NT, (u32 *)d.y, d.argmed);
+        tail_pair_merge(s, T, m, tid, NT, d.x, (u32 *)d.y, d.argmed);
         __syncthreads();
         // the median before each pair's first step is A's median: remember
         // its merged position (before the count tables reuse the sort buffer)
@@ -141,7 +141,7 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
     }
     if (tail_walk(s, T, m, tid, NT)) atomicOr(err, 1);
     __syncthreads();
-    tail_output(s, T, m, tid, NT, (u32 *)d.y, d.argmed);
+    tail_output(s, T, m, tid, NT, d.x, (u32 *)d.y, d.argmed);
 }
 
 // ------------------------------------------------------------------ LDS path
@@ -256,29 +256,33 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
         __syncthreads();
         if (tord) {
             // 3. pair orders from the per-block counts along the tile order
-            u64 w[kRegs];
-            const u64 cnt = tile_label_counts(m, tid, N, w);
+            u32 w[kRegs];
+            const u64 cnt = tile_label_counts(s, m, tid, N, w);
             const u64 ex = excl_scan64<NT>(cnt, wave_tot64);
             if (s.C > 1) {   // the count tables reuse the sort buffer, read above
                 tail_table_zero(s, T, m, tid, NT);
                 __syncthreads();
             }
-            tile_positions(s, T, m, ex, w, (u32 *)d.y, d.argmed);
+            tile_positions(s, T, m, ex, w, d.x, (u32 *)d.y, d.argmed);
             tile_mpad(s, T, m, tid, NT);
             __syncthreads();
             tile_tail<NT>(s, T, m, d, err, true);
             return;
         }
     } else {
+        // merge sort through the 64-bit buffer (free during the sort), then
+        // the sorted blocks into the key and slot arrays
         if (tord) tile_to_block_values(s, T, tid, v);
         sort_regs(v);
         for (int w = kRegs; w < s.S; w <<= 1) {
-            store_regs(m.srt + tid * kRegs, v);
+            store_regs(m.mbuf + tid * kRegs, v);
             __syncthreads();
-            merge_level(m.srt, w, tid, v);
+            merge_level(m.mbuf, w, tid, v);
             __syncthreads();
         }
-        store_regs(m.srt + tid * kRegs, v);
+#pragma unroll
+        for (int j = 0; j < kRegs; j++)
+            if (sv_valid(v[j])) put_block_value(s, m, tid * kRegs + j, v[j]);
         __syncthreads();
     }
 
@@ -358,6 +362,9 @@ __global__ void k_zero_counters(u32 *c, int n)
 struct GLayout {
     int64_t xv, srt, srt2, M, pos, cnt, ctot, stage, total;
 };
+// After the sort, the sorted keys take the xv region and the slots the
+// start of srt2 (the tables overwrite them only after the pair orders and
+// first medians are done).
 
 __host__ __device__ inline void make_glayout(const Shape &s, GLayout *g)
 {
@@ -371,7 +378,7 @@ __host__ __device__ inline void make_glayout(const Shape &s, GLayout *g)
     off = (off + 255) & ~255ll;
     g->total = off;
     int64_t a = g->srt2;
-    g->cnt = a;    a += 4ll * s.Pmax * s.C * (s.Wn + 1);
+    g->cnt = a;    a += 2ll * s.Pmax * s.C * (s.Wn + 1);
     a = (a + 15) & ~15ll;
     g->ctot = a;   a += 4ll * s.Pmax * s.Wn * kColGroups;
     a = (a + 15) & ~15ll;
@@ -404,10 +411,10 @@ __global__ __launch_bounds__(kGlobalThreads) void k_tile_global(Launch L, unsign
         make_glayout(s, &g);
         TileMem m = {};
         m.xv = (u32 *)(base + g.xv);
-        m.srt = (u64 *)(base + g.srt);
+        u64 *srt = (u64 *)(base + g.srt);
         m.M = (u16 *)(base + g.M);
         m.pos = (u32 *)(base + g.pos);
-        m.cnt = (u32 *)(base + g.cnt);
+        m.cnt = (u16 *)(base + g.cnt);
         m.ctot = (u32 *)(base + g.ctot);
         m.stage = (u16 *)(base + g.stage);
         u64 *srt2 = (u64 *)(base + g.srt2);
@@ -426,7 +433,7 @@ __global__ __launch_bounds__(kGlobalThreads) void k_tile_global(Launch L, unsign
         // srt2 and srt so that the last one lands in srt
         int nlev = 0;
         for (int w = chunk; w < s.S; w <<= 1) nlev++;
-        u64 *bufs[2] = {m.srt, srt2};
+        u64 *bufs[2] = {srt, srt2};
         int cur = nlev & 1;                 // buffer the LDS pass writes
         const int wmax = s.S < chunk ? s.S : chunk;
         for (int z = 0; z < s.cap / chunk; z++) {
@@ -441,12 +448,12 @@ __global__ __launch_bounds__(kGlobalThreads) void k_tile_global(Launch L, unsign
                 merge_level(sbuf, w, tid, v);
                 __syncthreads();
             }
-            store_regs((cur ? srt2 : m.srt) + (int64_t)vt * kRegs, v);
+            store_regs((cur ? srt2 : srt) + (int64_t)vt * kRegs, v);
         }
         __syncthreads();
         for (int w = chunk; w < s.S; w <<= 1) {
-            const u64 *src = cur ? srt2 : m.srt;
-            u64 *dst = cur ? m.srt : srt2;
+            const u64 *src = cur ? srt2 : srt;
+            u64 *dst = cur ? srt : srt2;
             const int vthreads = s.cap / kRegs;
             for (int vt = tid; vt < vthreads; vt += kGlobalThreads) {
                 u64 v[kRegs];
@@ -457,6 +464,13 @@ __global__ __launch_bounds__(kGlobalThreads) void k_tile_global(Launch L, unsign
             __syncthreads();
         }
         (void)bufs;
+        m.skey = (u32 *)(base + g.xv);
+        m.sslot = (u16 *)(base + g.srt2);
+        for (int u = tid; u < s.cap; u += kGlobalThreads) {
+            const u64 v = srt[u];
+            if (sv_valid(v)) put_block_value(s, m, u, v);
+        }
+        __syncthreads();
         tile_tail<kGlobalThreads>(s, T, m, d, err, false);
     }
 }

@@ -11,8 +11,7 @@
 // so the same functions also run on the host, one item after another, for
 // checking the tile logic without a GPU.
 //
-//   1. load      x -> registers (8 slots per thread; block b at slot b*S)
-//                and the raw patterns into xv for the output.
+//   1. load      x -> registers (8 slots per thread; block b at slot b*S).
 //   2. sort      bucket sort (a monotone map of the key onto buckets, LDS
 //                atomic counts, scan, scatter, rank within the bucket by
 //                the full value).  Tiles of at most four blocks sort all
@@ -40,7 +39,8 @@
 //                and rebalancing (Section 6.2) with both cursors folded into
 //                one position of the merged order.  A 64-bit register window
 //                of membership bits around the median is kept up to date.
-//   6. output    y[o] = x[argmed[o]] (bit copy), argmed[o] global index.
+//   6. output    y[o] = x[argmed[o]] (bit copy, gathered from x, which the
+//                tile has just read), argmed[o] global index.
 #pragma once
 #include <stdint.h>
 
@@ -171,18 +171,21 @@ struct Shape {
     int32_t seg;     // merged outputs per pair-merge item (odd)
 };
 
-// LDS (or scratch) layout of a tile, in bytes from the base.
+// LDS (or scratch) layout of a tile, in bytes from the base.  The sorted
+// blocks are kept as keys and slot indices in two arrays (6 bytes per slot).
 struct Layout {
-    int32_t xv;      // u32[cap]
-    int32_t srt;     // u64[cap]
+    int32_t xv;      // unused in LDS (-1): the output gathers from x
+    int32_t skey;    // u32[cap]  sorted keys
+    int32_t sslot;   // u16[cap]  their slots (block << logS | t)
+    int32_t mbuf;    // u64[cap]  merge-sort buffer (aliases skey, sslot, M)
     int32_t M;       // u16[Pmax * Mstride]
     int32_t pos;     // u32[Pmax * k]     posA | posB << 16
-    int32_t cnt;     // u32[Pmax * C * (Wn + 1)]   (aliases srt)
-    int32_t ctot;    // u32[Pmax * Wn * kColGroups] (aliases srt)
+    int32_t cnt;     // u16[Pmax * C * (Wn + 1)]   (aliases skey, sslot)
+    int32_t ctot;    // u32[Pmax * Wn * kColGroups] (aliases skey, sslot)
     int32_t bk;      // u32[cap] bucket counters   (aliases M, pos)
     int32_t info;    // u32[2 * nbmax + 1]         (aliases M, pos)
     int32_t nbmax;   // blocks of a full tile
-    int32_t stage;   // u16[Pmax * k]              (aliases srt)
+    int32_t stage;   // u16[Pmax * k]              (aliases skey, sslot)
     int32_t total;   // bytes
 };
 
@@ -244,8 +247,8 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
     if (L < per_thread) L = per_thread | 1;
     for (;;) {
         const int64_t C = (k + L - 1) / L;
-        const int64_t need = (int64_t)P * (4 * C * (s->Wn + 1) + 4 * kColGroups * s->Wn + 2 * (int64_t)k + 48);
-        if (need <= 8ll * s->cap || L >= k) break;
+        const int64_t need = (int64_t)P * (2 * C * (s->Wn + 1) + 4 * kColGroups * s->Wn + 2 * (int64_t)k + 48);
+        if (need <= 6ll * s->cap || L >= k) break;
         L += 2;
     }
     s->L = L;
@@ -259,8 +262,11 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
 MF_HD void make_layout(const Shape &s, Layout *l)
 {
     int32_t off = 0;
-    l->xv = off;     off += 4 * s.cap;
-    l->srt = off;    off += 8 * s.cap;
+    l->xv = -1;
+    l->skey = off;   off += 4 * s.cap;
+    l->sslot = off;  off += 2 * s.cap;
+    off = (off + 15) & ~15;
+    l->mbuf = 0;
     l->M = off;      off += 2 * s.Pmax * s.Mstride;
     off = (off + 15) & ~15;
     l->pos = off;    off += 4 * s.Pmax * s.Pstride;
@@ -271,14 +277,15 @@ MF_HD void make_layout(const Shape &s, Layout *l)
     l->nbmax = s.Pmax + 1;
     const int32_t bend = l->info + 4 * (2 * (s.Pmax + 1) + 1);
     if (off < bend) off = (bend + 15) & ~15;
+    if (off < 8 * s.cap) off = 8 * s.cap;
     l->total = off;
-    int32_t a = l->srt;
-    l->cnt = a;      a += 4 * s.Pmax * s.C * (s.Wn + 1);
+    int32_t a = 0;
+    l->cnt = a;      a += 2 * s.Pmax * s.C * (s.Wn + 1);
     a = (a + 15) & ~15;
     l->ctot = a;     a += 4 * s.Pmax * s.Wn * kColGroups;
     a = (a + 15) & ~15;
     l->stage = a;    a += 2 * s.Pmax * s.k;
-    if (a > l->srt + 8 * s.cap) l->total = -1;   // aliased region overflows
+    if (a > l->M) l->total = -1;   // aliased region overflows
 }
 
 // The tile of pairs [j0, j0 + P).
@@ -312,15 +319,17 @@ MF_HD int32_t block_len(const Shape &s, const Tile &T, int32_t b)
 // ---------------------------------------------------------------- views
 
 struct TileMem {
-    u32 *bk;         // bucket counters / starts, slot-indexed like srt
+    u32 *bk;         // bucket counters / starts, slot-indexed like skey
     u32 *bmin;       // per block: smallest key
     u32 *bmax;       // per block: largest key
     u32 *flag;       // bit 0: a bucket passed kBucketMax; bit 1: kBucketSoft
     u32 *xv;
-    u64 *srt;
+    u32 *skey;
+    u16 *sslot;
+    u64 *mbuf;
     u16 *M;
     u32 *pos;
-    u32 *cnt;
+    u16 *cnt;
     u32 *ctot;
     u16 *stage;
 };
@@ -332,11 +341,13 @@ MF_HD TileMem tile_mem(unsigned char *base, const Layout &l)
     m.bmin = (u32 *)(base + l.info);
     m.bmax = m.bmin + l.nbmax;
     m.flag = m.bmax + l.nbmax;
-    m.xv = (u32 *)(base + l.xv);
-    m.srt = (u64 *)(base + l.srt);
+    m.xv = nullptr;
+    m.skey = (u32 *)(base + l.skey);
+    m.sslot = (u16 *)(base + l.sslot);
+    m.mbuf = (u64 *)(base + l.mbuf);
     m.M = (u16 *)(base + l.M);
     m.pos = (u32 *)(base + l.pos);
-    m.cnt = (u32 *)(base + l.cnt);
+    m.cnt = (u16 *)(base + l.cnt);
     m.ctot = (u32 *)(base + l.ctot);
     m.stage = (u16 *)(base + l.stage);
     return m;
@@ -383,8 +394,7 @@ MF_HD void load_raw(const Shape &s, const Tile &T, const u32 *x, int32_t tid, u3
     }
 }
 
-// Phases 1 and 2 together: keeps the raw patterns in xv for the output
-// phase and returns the packed sort values of the thread's slots.
+// Phases 1 and 2 together: the packed sort values of the thread's slots.
 template <bool F32>
 MF_HD void load_sort_values(const Shape &s, const Tile &T, const TileMem &m, const u32 (&raw)[kRegs],
                             int32_t tid, u64 (&v)[kRegs])
@@ -397,7 +407,6 @@ MF_HD void load_sort_values(const Shape &s, const Tile &T, const TileMem &m, con
         if (b >= T.NB) { v[j] = kPadAll; continue; }
         const u64 hb = (u64)b << 48;
         if (t >= block_len(s, T, b)) { v[j] = hb | 0x0000FFFFFFFFFFFFull; continue; }
-        m.xv[u] = raw[j];
         const u32 key = F32 ? key_of_f32(raw[j]) : key_of_i32(raw[j]);
         v[j] = hb | ((u64)key << 16) | (u64)t;
     }
@@ -539,6 +548,25 @@ MF_HD u32 bucket_of(const BucketFn &f, u32 key)
 MF_HD bool sv_valid(u64 v) { return (v & 0xFFFFu) != 0xFFFFu; }
 MF_HD int32_t sv_block(u64 v) { return (int32_t)(v >> 48); }
 
+// Sorted item at slot q: key and slot index (block << logS | t).
+MF_HD void put_sorted(const TileMem &m, int32_t q, u32 key, u32 slot)
+{
+    m.skey[q] = key;
+    m.sslot[q] = (u16)slot;
+}
+
+// The sorted item at q as a block-order value of block 0 (key << 16 | t),
+// for comparisons within a block and for merge path.
+MF_HD u64 sorted_kt(const Shape &s, const TileMem &m, int32_t q)
+{
+    return ((u64)m.skey[q] << 16) | (u64)(m.sslot[q] & (u32)(s.S - 1));
+}
+
+MF_HD void put_block_value(const Shape &s, const TileMem &m, int32_t q, u64 v)
+{
+    put_sorted(m, q, sv_key(v), ((u32)sv_block(v) << s.logS) | sv_t(v));
+}
+
 // Item = one of the tile's cap counters, or block info entry b < nbmax.
 MF_HD void bucket_zero_item(const TileMem &m, int32_t e) { m.bk[e] = 0u; }
 MF_HD void bucket_info_init(const TileMem &m, int32_t b)
@@ -631,7 +659,7 @@ struct BlockView {
     u32 mn, mx, len;
     BucketFn f;
     const u32 *start;      // bucket starts (after the scan)
-    const u64 *row;        // the block's sort buffer
+    int32_t base;          // the block's first slot
 };
 
 template <bool F32>
@@ -643,7 +671,7 @@ MF_HD BlockView block_view(const Shape &s, const Tile &T, const TileMem &m, int3
     V.f = bucket_fn<F32>(s, m, b, pass);
     V.len = (u32)block_len(s, T, b);
     V.start = m.bk + (b << s.logS);
-    V.row = m.srt + (b << s.logS);
+    V.base = b << s.logS;
     return V;
 }
 
@@ -731,10 +759,9 @@ MF_HD void bucket_scatter(const Shape &s, const Tile &T, const TileMem &m, int32
     const int32_t b = thread_block(s, T, tid);
     if (b < 0) return;
     const BlockView V = block_view<F32>(s, T, m, b, pass);
-    u64 *row = m.srt + (b << s.logS);
 #pragma unroll
     for (int j = 0; j < kRegs; j++)
-        if (sv_valid(v[j])) row[V.start[bucket_of<F32>(V.f, sv_key(v[j]))] + arr[j]] = v[j];
+        if (sv_valid(v[j])) put_block_value(s, m, V.base + (int32_t)(V.start[bucket_of<F32>(V.f, sv_key(v[j]))] + arr[j]), v[j]);
 }
 
 // Per thread: final position = bucket start + rank among the bucket's items
@@ -746,7 +773,7 @@ MF_HD void bucket_rank(const Shape &s, const Tile &T, const TileMem &m, int32_t 
     const int32_t b = thread_block(s, T, tid);
     u32 x[kRegs], hi[kRegs];
     BlockView V;
-    V.row = m.srt;
+    V.base = 0;
     if (b >= 0) V = block_view<F32>(s, T, m, b, pass);
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
@@ -760,7 +787,8 @@ MF_HD void bucket_rank(const Shape &s, const Tile &T, const TileMem &m, int32_t 
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         u32 f = fin[j];
-        for (u32 q = x[j]; q < hi[j]; q++) f += (V.row[q] < v[j]) ? 1u : 0u;
+        const u64 vk = v[j] & 0x0000FFFFFFFFFFFFull;   // (key, t) within the block
+        for (u32 q = x[j]; q < hi[j]; q++) f += (sorted_kt(s, m, V.base + (int32_t)q) < vk) ? 1u : 0u;
         fin[j] = f;
     }
 }
@@ -770,7 +798,7 @@ MF_HD void bucket_place(const Shape &s, const TileMem &m, const u64 (&v)[kRegs],
 {
 #pragma unroll
     for (int j = 0; j < kRegs; j++)
-        if (sv_valid(v[j])) m.srt[(sv_block(v[j]) << s.logS) + fin[j]] = v[j];
+        if (sv_valid(v[j])) put_block_value(s, m, (sv_block(v[j]) << s.logS) + (int32_t)fin[j], v[j]);
 }
 
 // Walk chunks of pair p (phase 4), and row c of its count table.
@@ -779,16 +807,29 @@ MF_HD int32_t pair_chunks(const Shape &s, const Tile &T, int32_t p)
     return ceil_div32(block_len(s, T, p + 1), s.L);
 }
 
-MF_HD u32 *cnt_row(const Shape &s, const TileMem &m, int32_t p, int32_t c)
-{
-    return m.cnt + (p * s.C + c) * (s.Wn + 1);
-}
-
 #if defined(__HIP_DEVICE_COMPILE__)
 #define MF_ADD32(ptr, v) atomicAdd((unsigned int *)(ptr), (unsigned int)(v))
 #else
 #define MF_ADD32(ptr, v) (*(ptr) += (v))
 #endif
+
+// Row c of pair p's count table: 16-bit cells.  While the histogram is
+// built, a cell holds its word's A items in the low byte and B items in the
+// high byte (each at most 64); after the column pass, a member count.
+MF_HD int32_t cnt_row_idx(const Shape &s, int32_t p, int32_t c) { return (p * s.C + c) * (s.Wn + 1); }
+
+MF_HD u16 *cnt_row(const Shape &s, const TileMem &m, int32_t p, int32_t c)
+{
+    return m.cnt + cnt_row_idx(s, p, c);
+}
+
+// Adds v (1 for an A item, 0x100 for a B item) to cell e, through an atomic
+// add on the 32-bit word that holds it (the other cell's bytes never carry).
+MF_HD void cnt_add(const TileMem &m, int32_t e, u32 v)
+{
+    MF_ADD32((u32 *)m.cnt + (e >> 1), v << (16 * (e & 1)));
+}
+
 
 // ---------------------------------------------------------------- 2''. tile-order sort
 //
@@ -799,15 +840,16 @@ MF_HD u32 *cnt_row(const Shape &s, const TileMem &m, int32_t p, int32_t c)
 // its pairs: phase 3 without a merge.  The counts of the four blocks are
 // packed in one 64-bit word (16 bits each), so the count is one prefix scan.
 // The sort is the bucket sort above over a single segment: cap buckets
-// spanning the tile's value range.  Values: key << 32 | block << 16 | t,
-// padding ~0 (t field 0xFFFF, so sv_valid and sv_t still apply).
+// spanning the tile's value range.  Values: key << 32 | slot, where the
+// slot (block << logS | t) orders like (block, t); padding ~0 (slot field
+// 0xFFFF, so sv_valid still applies).
 
 static const int kTileOrderBlocks = 4;
 
 MF_HD bool tile_order_ok(const Shape &s) { return s.Pmax + 1 <= kTileOrderBlocks && s.S >= kRegs; }
 
 MF_HD u32 tv_key(u64 v) { return (u32)(v >> 32); }
-MF_HD int32_t tv_block(u64 v) { return (int32_t)((v >> 16) & 0xFFFFu); }
+MF_HD u32 tv_slot(u64 v) { return (u32)(v & 0xFFFFu); }
 
 // The bucket sort's shape for the tile-wide segment.
 MF_HD Shape tile_order_shape(const Shape &s)
@@ -839,9 +881,8 @@ MF_HD void load_tile_values(const Shape &s, const Tile &T, const TileMem &m, con
         const int32_t b = u >> s.logS;
         const int32_t t = u & (s.S - 1);
         if (b >= T.NB || t >= block_len(s, T, b)) { v[j] = kPadAll; continue; }
-        m.xv[u] = raw[j];
         const u32 key = F32 ? key_of_f32(raw[j]) : key_of_i32(raw[j]);
-        v[j] = ((u64)key << 32) | ((u64)b << 16) | (u64)t;
+        v[j] = ((u64)key << 32) | (u64)u;
     }
 }
 
@@ -851,7 +892,7 @@ MF_HD void tile_to_block_values(const Shape &s, const Tile &T, int32_t tid, u64 
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         const int32_t b = (tid * kRegs + j) >> s.logS;
-        if (sv_valid(v[j])) v[j] = ((u64)b << 48) | ((u64)tv_key(v[j]) << 16) | (u64)sv_t(v[j]);
+        if (sv_valid(v[j])) v[j] = ((u64)b << 48) | ((u64)tv_key(v[j]) << 16) | (u64)(tv_slot(v[j]) & (u32)(s.S - 1));
         else v[j] = (b >= T.NB) ? kPadAll : (((u64)b << 48) | 0x0000FFFFFFFFFFFFull);
     }
 }
@@ -918,7 +959,7 @@ MF_HD void tile_scatter(const Shape &st, const TileMem &m, const u64 (&v)[kRegs]
     const BucketFn f = bucket_fn<F32>(st, m, 0, pass);
 #pragma unroll
     for (int j = 0; j < kRegs; j++)
-        if (sv_valid(v[j])) m.srt[m.bk[bucket_of<F32>(f, tv_key(v[j]))] + arr[j]] = v[j];
+        if (sv_valid(v[j])) put_sorted(m, (int32_t)(m.bk[bucket_of<F32>(f, tv_key(v[j]))] + arr[j]), tv_key(v[j]), tv_slot(v[j]));
 }
 
 // Per thread: sorted position = bucket start + rank by the full value among
@@ -943,7 +984,7 @@ MF_HD void tile_rank(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], i
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         u32 f = fin[j];
-        for (u32 q = x[j]; q < hi[j]; q++) f += (m.srt[q] < v[j]) ? 1u : 0u;
+        for (u32 q = x[j]; q < hi[j]; q++) f += ((((u64)m.skey[q]) << 32 | m.sslot[q]) < v[j]) ? 1u : 0u;
         fin[j] = f;
     }
 }
@@ -952,19 +993,19 @@ MF_HD void tile_place(const TileMem &m, const u64 (&v)[kRegs], const u32 (&fin)[
 {
 #pragma unroll
     for (int j = 0; j < kRegs; j++)
-        if (sv_valid(v[j])) m.srt[fin[j]] = v[j];
+        if (sv_valid(v[j])) put_sorted(m, (int32_t)fin[j], tv_key(v[j]), tv_slot(v[j]));
 }
 
-// Per thread: its kRegs consecutive tile-order items (into w) and their
-// count per block, packed 16 bits per block.
-MF_HD u64 tile_label_counts(const TileMem &m, int32_t tid, int32_t N, u64 (&w)[kRegs])
+// Per thread: the slots of its kRegs consecutive tile-order items (into w,
+// 0xFFFF past the end) and their count per block, packed 16 bits per block.
+MF_HD u64 tile_label_counts(const Shape &s, const TileMem &m, int32_t tid, int32_t N, u32 (&w)[kRegs])
 {
     u64 c = 0ull;
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         const int32_t q = tid * kRegs + j;
-        w[j] = q < N ? m.srt[q] : kPadAll;
-        if (q < N) c += 1ull << (16 * tv_block(w[j]));
+        w[j] = q < N ? (u32)m.sslot[q] : 0xFFFFu;
+        if (q < N) c += 1ull << (16 * (int32_t)(w[j] >> s.logS));
     }
     return c;
 }
@@ -972,8 +1013,8 @@ MF_HD u64 tile_label_counts(const TileMem &m, int32_t tid, int32_t N, u64 (&w)[k
 // Per thread: with excl = the packed counts of all earlier items, the
 // merged positions of its items in both of their pairs (M and the position
 // maps), each pair's first median (A's item of own rank h) and output 0.
-MF_HD void tile_positions(const Shape &s, const Tile &T, const TileMem &m, u64 excl, const u64 (&w)[kRegs],
-                          u32 *y, int32_t *argmed)
+MF_HD void tile_positions(const Shape &s, const Tile &T, const TileMem &m, u64 excl, const u32 (&w)[kRegs],
+                          const u32 *x, u32 *y, int32_t *argmed)
 {
     // with more than one walk chunk, also the count histogram of phase 4
     // (table_hist_item for both merged positions of every item)
@@ -982,9 +1023,9 @@ MF_HD void tile_positions(const Shape &s, const Tile &T, const TileMem &m, u64 e
     u64 c = excl;
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
-        if (!sv_valid(w[j])) continue;
-        const int32_t b = tv_block(w[j]);
-        const u32 t = sv_t(w[j]);
+        if (w[j] == 0xFFFFu) continue;
+        const int32_t b = (int32_t)(w[j] >> s.logS);
+        const u32 t = w[j] & (u32)(s.S - 1);
         const int32_t cb = (int32_t)((c >> (16 * b)) & 0xFFFFu);
         if (b < T.P) {   // A of pair b: with B's earlier items
             const int32_t r = cb + (int32_t)((c >> (16 * b + 16)) & 0xFFFFu);
@@ -995,17 +1036,17 @@ MF_HD void tile_positions(const Shape &s, const Tile &T, const TileMem &m, u64 e
                 int32_t row = (int32_t)udiv16(t, Lr);
                 const int32_t Cp = pair_chunks(s, T, b);
                 row = row < Cp ? row : Cp - 1;
-                MF_ADD32(cnt_row(s, m, b, row) + (r >> 6), 1u);
+                cnt_add(m, cnt_row_idx(s, b, row) + (r >> 6), 1u);
             }
         }
         if (b >= 1) {    // B of pair b - 1: with A's earlier items
             const int32_t r = cb + (int32_t)((c >> (16 * b - 16)) & 0xFFFFu);
             m.M[(b - 1) * s.Mstride + mslot(r)] = (u16)(0x8000u | t);
             ((u16 *)(m.pos + (b - 1) * s.Pstride))[2 * t + 1] = (u16)r;
-            if (hist) MF_ADD32(cnt_row(s, m, b - 1, (int32_t)udiv16(t, Lr)) + (r >> 6), 0x10000u);
+            if (hist) cnt_add(m, cnt_row_idx(s, b - 1, (int32_t)udiv16(t, Lr)) + (r >> 6), 0x100u);
         }
         if (b == 0 && cb == s.h && T.j0 == 1) {
-            y[0] = m.xv[t];
+            y[0] = x[t];
             if (argmed) argmed[0] = (int32_t)t;
         }
         c += 1ull << (16 * b);
@@ -1038,8 +1079,7 @@ MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
     const int32_t lenA = s.k;
     const int32_t lenB = block_len(s, T, p + 1);
     const int32_t mlen = lenA + lenB;
-    const u64 *A = m.srt + ((int32_t)p << s.logS);
-    const u64 *B = m.srt + ((int32_t)(p + 1) << s.logS);
+    const int32_t A = (int32_t)p << s.logS, B = (int32_t)(p + 1) << s.logS;   // first slots
     u16 *Mp = m.M + p * s.Mstride;
     u16 *pos = (u16 *)(m.pos + p * s.Pstride);
     const int32_t d = g * s.seg;
@@ -1053,11 +1093,11 @@ MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
     while (lo < hi) {
         const int32_t mid = (lo + hi) >> 1;
         // A[mid] precedes B[d-1-mid] iff keyA <= keyB (A first on ties)
-        if (sv_key(A[mid]) <= sv_key(B[d - 1 - mid])) lo = mid + 1;
+        if (m.skey[A + mid] <= m.skey[B + d - 1 - mid]) lo = mid + 1;
         else hi = mid;
     }
     int32_t a = lo, b = d - lo;
-    u64 va = a < lenA ? A[a] : 0ull, vb = b < lenB ? B[b] : 0ull;
+    u64 va = a < lenA ? sorted_kt(s, m, A + a) : 0ull, vb = b < lenB ? sorted_kt(s, m, B + b) : 0ull;
     for (int q = 0; q < s.seg; q++) {
         const int32_t r = d + q;
         if (r >= mlen) {
@@ -1072,7 +1112,7 @@ MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
         b += takeA ? 0 : 1;
         const int32_t ni = takeA ? a : b;
         const bool more = takeA ? (a < lenA) : (b < lenB);
-        const u64 nv = more ? (takeA ? A : B)[ni] : 0ull;
+        const u64 nv = more ? sorted_kt(s, m, (takeA ? A : B) + ni) : 0ull;
         va = takeA ? nv : va;
         vb = takeA ? vb : nv;
     }
@@ -1088,8 +1128,8 @@ MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
 // iff t >= cL, one holding B's item t iff t < cL.
 
 
-// Item = entry e of the table of pair p: zero it.
-MF_HD void table_zero_item(const TileMem &m, int32_t e) { m.cnt[e] = 0u; }
+// Item = 32-bit word e of the tables (two cells): zero it.
+MF_HD void table_zero_item(const TileMem &m, int32_t e) { ((u32 *)m.cnt)[e] = 0u; }
 
 
 // Item = merged position r of pair p (r < k + len B): count its item in
@@ -1106,7 +1146,7 @@ MF_HD void table_hist_item(const Shape &s, const TileMem &m, int32_t p, int32_t 
     int32_t b = (int32_t)(((u64)t * Lrcp) >> 32);
 #endif
     if (b > Cp - 1) b = Cp - 1;        // only A items reach past the last chunk
-    MF_ADD32(cnt_row(s, m, p, b) + (r >> 6), (e & 0x8000u) ? 0x10000u : 1u);
+    cnt_add(m, cnt_row_idx(s, p, b) + (r >> 6), (e & 0x8000u) ? 0x100u : 1u);
 }
 
 
@@ -1121,10 +1161,13 @@ MF_HD int32_t col_rows(const Shape &s) { return (s.C + kColGroups - 1) / kColGro
 MF_HD void table_colsum_item(const Shape &s, const TileMem &m, int32_t p, int32_t w, int32_t g, int32_t Cp)
 {
     const int32_t stride = s.Wn + 1, R = col_rows(s);
-    const u32 *col = cnt_row(s, m, p, 0) + w;
+    const u16 *col = cnt_row(s, m, p, 0) + w;
     const int32_t c0 = g * R, c1 = (c0 + R < Cp) ? c0 + R : Cp;
     u32 tot = 0u;
-    for (int32_t c = c0; c < c1; c++) tot += col[c * stride];
+    for (int32_t c = c0; c < c1; c++) {
+        const u32 v = col[c * stride];
+        tot += (v & 0xFFu) | ((v >> 8) << 16);
+    }
     m.ctot[(p * s.Wn + w) * kColGroups + g] = tot;
 }
 
@@ -1133,7 +1176,7 @@ MF_HD void table_colsum_item(const Shape &s, const TileMem &m, int32_t p, int32_
 MF_HD void table_colapply_item(const Shape &s, const TileMem &m, int32_t p, int32_t w, int32_t g, int32_t Cp)
 {
     const int32_t stride = s.Wn + 1, R = col_rows(s);
-    u32 *col = cnt_row(s, m, p, 0) + w;
+    u16 *col = cnt_row(s, m, p, 0) + w;
     const int32_t c0 = g * R, c1 = (c0 + R < Cp) ? c0 + R : Cp;
     if (c0 >= c1) return;
     const u32 *gt = m.ctot + (p * s.Wn + w) * kColGroups;
@@ -1148,23 +1191,23 @@ MF_HD void table_colapply_item(const Shape &s, const TileMem &m, int32_t p, int3
     // row c on, i.e. sa minus the A items of the group's earlier rows
     for (int32_t c = c0; c < c1; c++) {
         const u32 v = col[c * stride];
-        col[c * stride] = sa + pb;
-        sa -= v & 0xFFFFu;
-        pb += v >> 16;
+        col[c * stride] = (u16)(sa + pb);
+        sa -= v & 0xFFu;
+        pb += v >> 8;
     }
 }
 
 // Item = (pair p, chunk c): exclusive prefix over the words.
 MF_HD void table_row_item(const Shape &s, const TileMem &m, int32_t p, int32_t c)
 {
-    u32 *row = cnt_row(s, m, p, c);
+    u16 *row = cnt_row(s, m, p, c);
     u32 acc = 0u;
     for (int32_t w = 0; w < s.Wn; w++) {
         const u32 v = row[w];
-        row[w] = acc;
+        row[w] = (u16)acc;
         acc += v;
     }
-    row[s.Wn] = acc;
+    row[s.Wn] = (u16)acc;
 }
 
 // Item = pair p: the window before step 0 is all of A, whose median is A's
@@ -1172,7 +1215,7 @@ MF_HD void table_row_item(const Shape &s, const TileMem &m, int32_t p, int32_t c
 // pos[k] of the pair (k is odd, so the row has at least one spare entry).
 MF_HD void pair_first_median(const Shape &s, const TileMem &m, int32_t p)
 {
-    const u32 t = sv_t(m.srt[(p << s.logS) + s.h]);
+    const u32 t = m.sslot[(p << s.logS) + s.h] & (u32)(s.S - 1);
     const u32 *pos = m.pos + p * s.Pstride;
     m.pos[p * s.Pstride + s.k] = pos[t] & 0xFFFFu;
 }
@@ -1251,7 +1294,7 @@ MF_HD int walk_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, 
     const int32_t i0 = c * s.L;
     const int32_t i1 = (i0 + s.L < lenB) ? i0 + s.L : lenB;
     const u16 *Mp = m.M + p * s.Mstride;
-    const u32 *pc = cnt_row(s, m, p, c);
+    const u16 *pc = cnt_row(s, m, p, c);
     const u32 *pos = m.pos + p * s.Pstride;
     u16 *stage = m.stage + p * s.k;
     const int32_t h = s.h;
@@ -1338,8 +1381,8 @@ MF_HD void tail_first_medians(const Shape &s, const Tile &T, const TileMem &m, i
 
 MF_HD void tail_table_zero(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
 {
-    const int32_t ncnt = T.P * s.C * (s.Wn + 1);
-    for (int32_t it = tid; it < ncnt; it += NT) table_zero_item(m, it);
+    const int32_t nwords = (T.P * s.C * (s.Wn + 1) + 1) / 2;
+    for (int32_t it = tid; it < nwords; it += NT) table_zero_item(m, it);
 }
 
 MF_HD void tail_table_hist(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
@@ -1408,38 +1451,38 @@ MF_HD int64_t tile_outputs(const Shape &s, const Tile &T)
 
 // Item = step i of pair p: output o = o0 + p*k + i.
 MF_HD void output_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, int32_t i,
-                       u32 *y, int32_t *argmed)
+                       const u32 *x, u32 *y, int32_t *argmed)
 {
     const int32_t r = m.stage[p * s.k + i];
     const u32 e = m.M[p * s.Mstride + mslot(r)];
     const int32_t b = p + (int32_t)(e >> 15);
     const int32_t t = (int32_t)(e & 0x7FFFu);
     const int64_t o = T.o0 + (int64_t)p * s.k + i;
-    y[o] = m.xv[(b << s.logS) + t];
+    y[o] = x[T.e0 + (int64_t)b * s.k + t];
     if (argmed) argmed[o] = (int32_t)(T.e0 + (int64_t)b * s.k + t);
 }
 
 MF_HD void tail_output(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT,
-                       u32 *y, int32_t *argmed)
+                       const u32 *x, u32 *y, int32_t *argmed)
 {
     const u32 kr = recip32(s.k);
     for (int32_t it = tid; it < T.P * s.k; it += NT) {
         const int32_t p = (int32_t)udiv16((u32)it, kr), i = it - p * s.k;
-        if (i < block_len(s, T, p + 1)) output_item(s, T, m, p, i, y, argmed);
+        if (i < block_len(s, T, p + 1)) output_item(s, T, m, p, i, x, y, argmed);
     }
 }
 
 // Output 0: the median of block 0 (Section 3: Y_0's only element).
-MF_HD void output_first(const Shape &s, const Tile &T, const TileMem &m, u32 *y, int32_t *argmed)
+MF_HD void output_first(const Shape &s, const Tile &T, const TileMem &m, const u32 *x, u32 *y, int32_t *argmed)
 {
-    const int32_t t = (int32_t)sv_t(m.srt[s.h]);
-    y[0] = m.xv[t];
+    const int32_t t = (int32_t)(m.sslot[s.h] & (u32)(s.S - 1));
+    y[0] = x[t];
     if (argmed) argmed[0] = t;
 }
 
 // Thread tid's share of the pair orders (phase 3) and output 0.
 MF_HD void tail_pair_merge(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT,
-                           u32 *y, int32_t *argmed)
+                           const u32 *x, u32 *y, int32_t *argmed)
 {
     const int32_t ipp = merge_items_per_pair(s);
     const u32 ir = recip32(ipp);
@@ -1447,7 +1490,7 @@ MF_HD void tail_pair_merge(const Shape &s, const Tile &T, const TileMem &m, int3
         const int32_t p = (int32_t)udiv16((u32)it, ir);
         pair_merge_item(s, T, m, p, it - p * ipp);
     }
-    if (T.j0 == 1 && tid == 0) output_first(s, T, m, y, argmed);
+    if (T.j0 == 1 && tid == 0) output_first(s, T, m, x, y, argmed);
 }
 
 }  // namespace mf

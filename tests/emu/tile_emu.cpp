@@ -133,14 +133,15 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
             if (tord) tile_place(m, v, f);
             else bucket_place(s, m, v, f);
         }
+        auto tkey = [&](int u) { return ((u64)m.skey[u] << 32) | m.sslot[u]; };
         if (tord) {
             for (int u = 1; u < N; u++)
-                if (m.srt[u - 1] >= m.srt[u]) return -13;
+                if (tkey(u - 1) >= tkey(u)) return -13;
         } else {
             for (int b = 0; b < T.NB; b++) {
                 const int len = block_len(s, T, b);
                 for (int u = 1; u < len; u++)
-                    if (m.srt[(b << s.logS) + u - 1] >= m.srt[(b << s.logS) + u]) return -12;
+                    if (tkey((b << s.logS) + u - 1) >= tkey((b << s.logS) + u)) return -12;
             }
         }
         g_fast_tiles++;
@@ -152,44 +153,46 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
             for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
         }
         for (int w = kRegs; w < s.S; w *= 2) {
-            memcpy(m.srt, regs.data(), sizeof(u64) * regs.size());
+            memcpy(m.mbuf, regs.data(), sizeof(u64) * regs.size());
             for (int q = 0; q < threads; q++) {
                 u64 out[kRegs];
-                merge_level(m.srt, w, q, out);
+                merge_level(m.mbuf, w, q, out);
                 for (int j = 0; j < kRegs; j++) tmp[(size_t)q * kRegs + j] = out[j];
             }
             regs.swap(tmp);
         }
-        memcpy(m.srt, regs.data(), sizeof(u64) * regs.size());
         for (int b = 0; b < T.NB; b++) {
             const int len = block_len(s, T, b);
             for (int u = 1; u < len; u++)
-                if (m.srt[(b << s.logS) + u - 1] >= m.srt[(b << s.logS) + u]) return -10;
+                if (regs[(b << s.logS) + u - 1] >= regs[(b << s.logS) + u]) return -10;
         }
+        for (int u = 0; u < (int)regs.size(); u++)
+            if (sv_valid(regs[u])) put_block_value(s, m, u, regs[u]);
         g_slow_tiles++;
     }
     // the pair orders overwrite the bucket scratch: poison it first
     memset(m.M, 0xA5, (size_t)(l.pos - l.M) + 4 * (size_t)s.Pmax * s.Pstride);
     if (fast && tord) {
         g_tile_order_tiles++;
-        std::vector<u64> w((size_t)threads * kRegs), cnt(threads);
+        std::vector<u32> w((size_t)threads * kRegs);
+        std::vector<u64> cnt(threads);
         for (int q = 0; q < threads; q++) {
-            u64 ww[kRegs];
-            cnt[q] = tile_label_counts(m, q, N, ww);
+            u32 ww[kRegs];
+            cnt[q] = tile_label_counts(s, m, q, N, ww);
             for (int j = 0; j < kRegs; j++) w[(size_t)q * kRegs + j] = ww[j];
         }
         if (s.C > 1)
             for (int q = 0; q < threads; q++) tail_table_zero(s, T, m, q, threads);
         u64 ex = 0;
         for (int q = 0; q < threads; q++) {
-            u64 ww[kRegs];
+            u32 ww[kRegs];
             for (int j = 0; j < kRegs; j++) ww[j] = w[(size_t)q * kRegs + j];
-            tile_positions(s, T, m, ex, ww, y, argmed);
+            tile_positions(s, T, m, ex, ww, x, y, argmed);
             ex += cnt[q];
         }
         for (int q = 0; q < threads; q++) tile_mpad(s, T, m, q, threads);
     } else {
-        for (int q = 0; q < threads; q++) tail_pair_merge(s, T, m, q, threads, y, argmed);
+        for (int q = 0; q < threads; q++) tail_pair_merge(s, T, m, q, threads, x, y, argmed);
         for (int q = 0; q < threads; q++) tail_first_medians(s, T, m, q, threads);
     }
     if (s.C > 1) {
@@ -203,7 +206,7 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
     }
     for (int q = 0; q < threads; q++)
         if (tail_walk(s, T, m, q, threads)) return -11;
-    for (int q = 0; q < threads; q++) tail_output(s, T, m, q, threads, y, argmed);
+    for (int q = 0; q < threads; q++) tail_output(s, T, m, q, threads, x, y, argmed);
     return 0;
 }
 
