@@ -542,37 +542,46 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(BwdLaunch L)
             const int64_t olo = (j0 - d.k + 1) > 0 ? (j0 - d.k + 1) : 0;
             int64_t ohi = j0 + kBwdTargetsPerWave;
             if (ohi > nout) ohi = nout;
-            for (int64_t b0 = olo; b0 < ohi; b0 += 64) {
-                const int64_t o = b0 + lane;
-                int tgt = -1;
-                float g = 0.f;
-                if (o < ohi) {
-                    const int64_t j = d.argmed[o];
-                    if (j >= j0 && j < j0 + kBwdTargetsPerWave) {
-                        tgt = (int)(j - j0);
-                        g = d.grad_y[o];
-                    }
+            // candidates in groups of kBwdGroup batches of 64: the loads of
+            // a whole group are issued together, then the batches retire in
+            // order (increasing o), each lowest lane first per target
+            for (int64_t g0 = olo; g0 < ohi; g0 += 64 * kBwdGroup) {
+                int tgt[kBwdGroup];
+                float gv[kBwdGroup];
+#pragma unroll
+                for (int q = 0; q < kBwdGroup; q++) {
+                    const int64_t o = g0 + q * 64 + lane;
+                    const bool in = o < ohi;
+                    const int64_t oc = in ? o : ohi - 1;
+                    const int64_t j = d.argmed[oc];
+                    gv[q] = d.grad_y[oc];
+                    tgt[q] = (in && j >= j0 && j < j0 + kBwdTargetsPerWave) ? (int)(j - j0) : -1;
                 }
-                bool pend = tgt >= 0;
-                // each round retires the lowest pending lane of every target,
-                // so 64 rounds always suffice
-                for (int round = 0; round < 64 && __ballot(pend) != 0ull; round++) {
-                    if (pend) atomicMin(&own[tgt], lane);
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    const bool win = pend && (__atomic_load_n(&own[tgt], __ATOMIC_RELAXED) == lane);
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    if (win) {
-                        A[tgt] += (double)g;
-                        own[tgt] = 64;
-                        pend = false;
+#pragma unroll
+                for (int q = 0; q < kBwdGroup; q++) {
+                    const int t = tgt[q];
+                    const float g = gv[q];
+                    bool pend = t >= 0;
+                    // each round retires the lowest pending lane of every
+                    // target, so 64 rounds always suffice
+                    for (int round = 0; round < 64 && __ballot(pend) != 0ull; round++) {
+                        if (pend) atomicMin(&own[t], lane);
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        const bool win = pend && (__atomic_load_n(&own[t], __ATOMIC_RELAXED) == lane);
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        if (win) {
+                            A[t] += (double)g;
+                            own[t] = 64;
+                            pend = false;
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                     }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
             }
             for (int t = lane; t < kBwdTargetsPerWave; t += 64)
