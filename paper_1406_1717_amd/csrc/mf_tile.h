@@ -295,6 +295,8 @@ struct Tile {
     int32_t NB;      // blocks = P + 1
     int64_t e0;      // global index of the first element of the tile
     int64_t o0;      // first output index written by the pairs: (j0-1)k + 1
+    int32_t lenLast; // length of block NB-1 (every other block has k items)
+    int32_t Clast;   // walk chunks of pair P-1 (every other pair has C)
 };
 
 MF_HD Tile make_tile(const Shape &s, int64_t t)
@@ -306,14 +308,17 @@ MF_HD Tile make_tile(const Shape &s, int64_t t)
     T.NB = T.P + 1;
     T.e0 = (T.j0 - 1) * (int64_t)s.k;
     T.o0 = T.e0 + 1;
+    // only the signal's last block can be short, and it ends the last tile
+    const int64_t rem = s.n - (T.e0 + (int64_t)(T.NB - 1) * s.k);
+    T.lenLast = (int32_t)(rem < s.k ? rem : s.k);
+    T.Clast = (T.lenLast + s.L - 1) / s.L;
     return T;
 }
 
+// Items of block b of the tile (0 <= b < NB).
 MF_HD int32_t block_len(const Shape &s, const Tile &T, int32_t b)
 {
-    int64_t start = T.e0 + (int64_t)b * s.k;
-    int64_t rem = s.n - start;
-    return (int32_t)(rem < s.k ? rem : s.k);
+    return b == T.NB - 1 ? T.lenLast : s.k;
 }
 
 // ---------------------------------------------------------------- views
@@ -804,7 +809,7 @@ MF_HD void bucket_place(const Shape &s, const TileMem &m, const u64 (&v)[kRegs],
 // Walk chunks of pair p (phase 4), and row c of its count table.
 MF_HD int32_t pair_chunks(const Shape &s, const Tile &T, int32_t p)
 {
-    return ceil_div32(block_len(s, T, p + 1), s.L);
+    return p == T.P - 1 ? T.Clast : s.C;
 }
 
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -1393,7 +1398,7 @@ MF_HD void tail_table_hist(const Shape &s, const Tile &T, const TileMem &m, int3
     for (int32_t it = tid; it < T.P * per; it += NT) {
         const int32_t p = (int32_t)udiv16((u32)it, perr), r = it - p * per;
         const int32_t lenB = block_len(s, T, p + 1);
-        if (r < s.k + lenB) table_hist_item(s, m, p, r, Lr, ceil_div32(lenB, s.L));
+        if (r < s.k + lenB) table_hist_item(s, m, p, r, Lr, pair_chunks(s, T, p));
     }
 }
 
