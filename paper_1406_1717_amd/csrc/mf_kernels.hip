@@ -187,7 +187,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
     __syncthreads();
     bool fast = s.S >= kRegs;
     int pass = 0;   // bucket map: 0 linear, 1 clamped logarithmic
-    u32 arr[kRegs];
+    u32 arr[kRegs], bkt[kRegs];
     if (tord) {
         tile_minmax(m, v);
         __syncthreads();
@@ -200,7 +200,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
         }
     }
     if (tord) {
-        tile_count<F32>(st, m, v, arr, pass);
+        tile_count<F32>(st, m, v, arr, bkt, pass);
         __syncthreads();
         if (m.flag[0] != 0u) {
             __syncthreads();
@@ -208,7 +208,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
             for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
             if (tid == 0) m.flag[0] = 0u;
             __syncthreads();
-            tile_count<F32>(st, m, v, arr, pass);
+            tile_count<F32>(st, m, v, arr, bkt, pass);
             __syncthreads();
         }
         if ((m.flag[0] & 1u) != 0u) {
@@ -243,12 +243,12 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
         const u32 excl = seg_excl_scan<NT>(tot, (tord ? st.S : s.S) / kRegs, wave_tot);
         bucket_scan_store(m, tid, excl, c);
         __syncthreads();
-        if (tord) tile_scatter<F32>(st, m, v, arr, pass);
+        if (tord) tile_scatter(m, v, arr, bkt);
         else bucket_scatter<F32>(s, T, m, tid, v, arr, pass);
         __syncthreads();
         u32 fin[kRegs];
         const int32_t N = tile_items(s, T);
-        if (tord) tile_rank<F32>(st, m, v, N, fin, pass);
+        if (tord) tile_rank(st, m, v, N, fin, bkt);
         else bucket_rank<F32>(s, T, m, tid, v, fin, pass);
         __syncthreads();
         if (tord) tile_place(m, v, fin);

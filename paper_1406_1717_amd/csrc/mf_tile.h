@@ -192,7 +192,7 @@ struct Layout {
 MF_HD int32_t ceil_div32(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
 
 // ceil(2^32 / d) for 2 <= d < 2^16; 0 stands for d = 1.
-MF_HD u32 recip32(int32_t d) { return d <= 1 ? 0u : (u32)((0xFFFFFFFFull + (u64)d) / (u64)d); }
+MF_HD u32 recip32(int32_t d) { return d <= 1 ? 0u : 0xFFFFFFFFu / (u32)d + 1u; }
 
 // a / d for a, d < 2^16 with dr = recip32(d): a high multiply, exact.
 MF_HD u32 udiv16(u32 a, u32 dr)
@@ -940,47 +940,46 @@ MF_HD bool tile_many_ties(const TileMem &m, int32_t N)
     return (u64)range * 4u < (u64)N;
 }
 
-// Per thread: arrival numbers in the tile's buckets (st = tile_order_shape).
+// Per thread: arrival numbers in the tile's buckets (st = tile_order_shape),
+// and the buckets themselves (for scatter and rank).
 template <bool F32>
-MF_HD void tile_count(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], u32 (&arr)[kRegs], int pass)
+MF_HD void tile_count(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], u32 (&arr)[kRegs],
+                      u32 (&bkt)[kRegs], int pass)
 {
     const BucketFn f = bucket_fn<F32>(st, m, 0, pass);
     u32 mx = 0u;
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         arr[j] = 0u;
+        bkt[j] = 0u;
         if (sv_valid(v[j])) {
-            arr[j] = MF_ADDRTN32(m.bk + bucket_of<F32>(f, tv_key(v[j])), 1u);
+            bkt[j] = bucket_of<F32>(f, tv_key(v[j]));
+            arr[j] = MF_ADDRTN32(m.bk + bkt[j], 1u);
             mx = arr[j] > mx ? arr[j] : mx;
         }
     }
     if (mx >= (u32)kBucketSoft) MF_OR32(m.flag, mx >= (u32)kBucketMax ? 3u : 2u);
 }
 
-template <bool F32>
-MF_HD void tile_scatter(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], const u32 (&arr)[kRegs],
-                        int pass)
+MF_HD void tile_scatter(const TileMem &m, const u64 (&v)[kRegs], const u32 (&arr)[kRegs], const u32 (&bkt)[kRegs])
 {
-    const BucketFn f = bucket_fn<F32>(st, m, 0, pass);
 #pragma unroll
     for (int j = 0; j < kRegs; j++)
-        if (sv_valid(v[j])) put_sorted(m, (int32_t)(m.bk[bucket_of<F32>(f, tv_key(v[j]))] + arr[j]), tv_key(v[j]), tv_slot(v[j]));
+        if (sv_valid(v[j])) put_sorted(m, (int32_t)(m.bk[bkt[j]] + arr[j]), tv_key(v[j]), tv_slot(v[j]));
 }
 
 // Per thread: sorted position = bucket start + rank by the full value among
 // the bucket's items (as in bucket_rank).  N: valid items.
-template <bool F32>
 MF_HD void tile_rank(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], int32_t N, u32 (&fin)[kRegs],
-                     int pass)
+                     const u32 (&bkt)[kRegs])
 {
-    const BucketFn f = bucket_fn<F32>(st, m, 0, pass);
     u32 x[kRegs], hi[kRegs];
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         x[j] = 0u;
         hi[j] = 0u;
         if (sv_valid(v[j])) {
-            const u32 bk = bucket_of<F32>(f, tv_key(v[j]));
+            const u32 bk = bkt[j];
             x[j] = m.bk[bk];
             hi[j] = (bk + 1u < (u32)st.S) ? m.bk[bk + 1] : (u32)N;
         }

@@ -43,12 +43,13 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
     }
     auto V = [&](int q, u64 (&v)[kRegs]) { for (int j = 0; j < kRegs; j++) v[j] = regs[(size_t)q * kRegs + j]; };
     int pass = 0;
+    std::vector<u32> bkts((size_t)threads * kRegs);
     auto count = [&](std::vector<u32> &arr) {
         for (int q = 0; q < threads; q++) {
-            u64 v[kRegs]; V(q, v); u32 a[kRegs];
-            if (tord) tile_count<F32>(st, m, v, a, pass);
-            else bucket_count<F32>(s, T, m, q, v, a, pass);
-            for (int j = 0; j < kRegs; j++) arr[(size_t)q * kRegs + j] = a[j];
+            u64 v[kRegs]; V(q, v); u32 a[kRegs], bk[kRegs];
+            if (tord) tile_count<F32>(st, m, v, a, bk, pass);
+            else { bucket_count<F32>(s, T, m, q, v, a, pass); for (int j = 0; j < kRegs; j++) bk[j] = 0; }
+            for (int j = 0; j < kRegs; j++) { arr[(size_t)q * kRegs + j] = a[j]; bkts[(size_t)q * kRegs + j] = bk[j]; }
         }
     };
     // bucket path
@@ -118,12 +119,16 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         for (int q = 0; q < threads; q++) {
             u64 v[kRegs]; V(q, v); u32 a[kRegs];
             for (int j = 0; j < kRegs; j++) a[j] = arr[(size_t)q * kRegs + j];
-            if (tord) tile_scatter<F32>(st, m, v, a, pass);
+            u32 bk[kRegs];
+            for (int j = 0; j < kRegs; j++) bk[j] = bkts[(size_t)q * kRegs + j];
+            if (tord) tile_scatter(m, v, a, bk);
             else bucket_scatter<F32>(s, T, m, q, v, a, pass);
         }
         for (int q = 0; q < threads; q++) {
             u64 v[kRegs]; V(q, v); u32 f[kRegs];
-            if (tord) tile_rank<F32>(st, m, v, N, f, pass);
+            u32 bk[kRegs];
+            for (int j = 0; j < kRegs; j++) bk[j] = bkts[(size_t)q * kRegs + j];
+            if (tord) tile_rank(st, m, v, N, f, bk);
             else bucket_rank<F32>(s, T, m, q, v, f, pass);
             for (int j = 0; j < kRegs; j++) fin[(size_t)q * kRegs + j] = f[j];
         }
