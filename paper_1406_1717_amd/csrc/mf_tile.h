@@ -207,32 +207,34 @@ MF_HD u32 udiv16(u32 a, u32 dr)
 
 // Fills s for window k over n items with `threads` threads per tile.
 // Returns 0, or -1 when k does not fit this capacity (two blocks needed).
+// All arithmetic is 32-bit (n < 2^31): the kernels evaluate this per tile.
 MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
 {
+    const u32 uk = (u32)k, ut = (u32)threads;
     s->n = n;
     s->k = k;
-    s->h = (k - 1) / 2;
+    s->h = (k - 1) >> 1;
     int32_t S = 1, logS = 0;
     while (S < k) { S <<= 1; logS++; }
     s->S = S;
     s->logS = logS;
     s->cap = threads * kRegs;
     if (2 * S > s->cap) return -1;
-    s->Wn = ceil_div32(2 * (int64_t)k, 64);
+    s->Wn = (int32_t)((2u * uk + 63u) >> 6);
     s->Mstride = s->Wn * 64;
     s->Pstride = (k + 3) & ~3;
     // pairs per tile: as many blocks as the sort holds, but the merged
     // orders and position maps of all pairs stay within kPairBudget bytes
-    int32_t P = s->cap / S - 1;
+    int32_t P = (s->cap >> logS) - 1;
     const int32_t per_pair = 2 * s->Mstride + 4 * s->Pstride + 16;
-    if (P * per_pair > kPairBudget) P = kPairBudget / per_pair;
+    if (P * per_pair > kPairBudget) P = (int32_t)((u32)kPairBudget / (u32)per_pair);
     if (P < 1) P = 1;
     s->Pmax = P;
     // pair-merge segments: odd (the lanes of a wave, which take consecutive
     // segments, then read LDS words on distinct banks), long enough that no
     // thread has more than one search chain, but not much longer than the
     // search itself (short blocks: many short segments)
-    int32_t seg = (int32_t)(((int64_t)P * s->Mstride + threads - 1) / threads);
+    int32_t seg = (int32_t)(((u32)P * (u32)s->Mstride + ut - 1u) / ut);
     const int32_t seg_max = 2 * logS + 5;
     if (seg > seg_max) seg = seg_max;
     if (seg < 9) seg = 9;
@@ -243,19 +245,20 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
     // their column-group totals and the staged medians of all pairs fit in
     // the sort buffer they reuse
     int32_t L = 17;
-    const int32_t per_thread = (int32_t)(((int64_t)P * k + threads - 1) / threads);
+    const int32_t per_thread = (int32_t)(((u32)P * uk + ut - 1u) / ut);
     if (L < per_thread) L = per_thread | 1;
+    u32 C = (uk + (u32)L - 1u) / (u32)L;
     for (;;) {
-        const int64_t C = (k + L - 1) / L;
-        const int64_t need = (int64_t)P * (2 * C * (s->Wn + 1) + 4 * kColGroups * s->Wn + 2 * (int64_t)k + 48);
-        if (need <= 6ll * s->cap || L >= k) break;
+        const u32 need = (u32)P * (2u * C * (u32)(s->Wn + 1) + 4u * kColGroups * (u32)s->Wn + 2u * uk + 48u);
+        if (need <= 6u * (u32)s->cap || L >= k) break;
         L += 2;
+        C = (uk + (u32)L - 1u) / (u32)L;
     }
     s->L = L;
-    s->C = ceil_div32(k, L);
-    s->nblocks = (n + k - 1) / k;
+    s->C = (int32_t)C;
+    s->nblocks = (int64_t)(((u32)n + uk - 1u) / uk);
     s->npairs = s->nblocks - 1;
-    s->ntiles = s->npairs > 0 ? (s->npairs + s->Pmax - 1) / s->Pmax : 1;
+    s->ntiles = s->npairs > 0 ? (int64_t)(((u32)s->npairs + (u32)P - 1u) / (u32)P) : 1;
     return 0;
 }
 
