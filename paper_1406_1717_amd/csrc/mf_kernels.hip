@@ -237,6 +237,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
         }
     }
     fast = fast && (m.flag[0] & 1u) == 0u;
+    bool merged = false;   // pair orders already written (tile order)
     if (fast) {
         u32 c[kRegs];
         const u32 tot = bucket_scan_local(m, tid, c);
@@ -266,8 +267,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
             tile_positions(s, T, m, ex, w, d.x, (u32 *)d.y, d.argmed);
             tile_mpad(s, T, m, tid, NT);
             __syncthreads();
-            tile_tail<NT>(s, T, m, d, err, true);
-            return;
+            merged = true;
         }
     } else {
         // merge sort through the 64-bit buffer (free during the sort), then
@@ -286,7 +286,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
         __syncthreads();
     }
 
-    tile_tail<NT>(s, T, m, d, err, false);
+    tile_tail<NT>(s, T, m, d, err, merged);
 }
 
 // One workgroup per work unit.
