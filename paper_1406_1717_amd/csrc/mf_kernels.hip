@@ -182,27 +182,34 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
     // slots) take the merge sort below.  Crowded buckets are counted again
     // with the map linear in the float bit pattern (the flag is the same for
     // every thread).
+    // Presorted tiles (flag bit 2 clear after the key-range pass) skip the
+    // bucket sort.
     for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
     for (int b = tid; b < l.nbmax; b += NT) bucket_info_init(m, b);
+    presort_note(m, tid, v);
     __syncthreads();
     bool fast = s.S >= kRegs;
-    int pass = 0;   // bucket map: 0 linear, 1 clamped logarithmic
+    bool direct = false;   // items already in sort order
+    int pass = 0;          // bucket map: 0 linear, 1 clamped logarithmic
     u32 arr[kRegs], bkt[kRegs];
     if (tord) {
         tile_minmax(m, v);
+        presort_check(s, T, m, tid, NT, v, true);
         __syncthreads();
-        if (tile_many_ties(m, tile_items(s, T))) {
+        direct = (m.flag[0] & 4u) == 0u;
+        if (!direct && tile_many_ties(m, tile_items(s, T))) {
             __syncthreads();
             tord = false;
             tile_to_block_values(s, T, tid, v);
             for (int b = tid; b < l.nbmax; b += NT) bucket_info_init(m, b);
+            presort_note(m, tid, v);
             __syncthreads();
         }
     }
-    if (tord) {
+    if (tord && !direct) {
         tile_count<F32>(st, m, v, arr, bkt, pass);
         __syncthreads();
-        if (m.flag[0] != 0u) {
+        if ((m.flag[0] & 3u) != 0u) {
             __syncthreads();
             pass = 1;
             for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
@@ -218,43 +225,53 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
             tile_to_block_values(s, T, tid, v);
             for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
             for (int b = tid; b < l.nbmax; b += NT) bucket_info_init(m, b);
+            presort_note(m, tid, v);
             __syncthreads();
         }
     }
     if (fast && !tord) {
         bucket_minmax(m, v);
+        presort_check(s, T, m, tid, NT, v, false);
         __syncthreads();
-        bucket_count<F32>(s, T, m, tid, v, arr, pass);
-        __syncthreads();
-        if (m.flag[0] != 0u) {
-            __syncthreads();
-            pass = 1;
-            for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
-            if (tid == 0) m.flag[0] = 0u;
-            __syncthreads();
+        direct = (m.flag[0] & 4u) == 0u;
+        if (!direct) {
             bucket_count<F32>(s, T, m, tid, v, arr, pass);
             __syncthreads();
+            if ((m.flag[0] & 3u) != 0u) {
+                __syncthreads();
+                pass = 1;
+                for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
+                if (tid == 0) m.flag[0] = 0u;
+                __syncthreads();
+                bucket_count<F32>(s, T, m, tid, v, arr, pass);
+                __syncthreads();
+            }
         }
     }
     fast = fast && (m.flag[0] & 1u) == 0u;
     bool merged = false;   // pair orders already written (tile order)
     if (fast) {
-        u32 c[kRegs];
-        const u32 tot = bucket_scan_local(m, tid, c);
-        const u32 excl = seg_excl_scan<NT>(tot, (tord ? st.S : s.S) / kRegs, wave_tot);
-        bucket_scan_store(m, tid, excl, c);
-        __syncthreads();
-        if (tord) tile_scatter(m, v, arr, bkt);
-        else bucket_scatter<F32>(s, T, m, tid, v, arr, pass);
-        __syncthreads();
-        u32 fin[kRegs];
         const int32_t N = tile_items(s, T);
-        if (tord) tile_rank(st, m, v, N, fin, bkt);
-        else bucket_rank<F32>(s, T, m, tid, v, fin, pass);
-        __syncthreads();
-        if (tord) tile_place(m, v, fin);
-        else bucket_place(s, m, v, fin);
-        __syncthreads();
+        if (direct) {
+            presort_place(s, m, v, tord);
+            __syncthreads();
+        } else {
+            u32 c[kRegs];
+            const u32 tot = bucket_scan_local(m, tid, c);
+            const u32 excl = seg_excl_scan<NT>(tot, (tord ? st.S : s.S) / kRegs, wave_tot);
+            bucket_scan_store(m, tid, excl, c);
+            __syncthreads();
+            if (tord) tile_scatter(m, v, arr, bkt);
+            else bucket_scatter<F32>(s, T, m, tid, v, arr, pass);
+            __syncthreads();
+            u32 fin[kRegs];
+            if (tord) tile_rank(st, m, v, N, fin, bkt);
+            else bucket_rank<F32>(s, T, m, tid, v, fin, pass);
+            __syncthreads();
+            if (tord) tile_place(m, v, fin);
+            else bucket_place(s, m, v, fin);
+            __syncthreads();
+        }
         if (tord) {
             // 3. pair orders from the per-block counts along the tile order
             u32 w[kRegs];
@@ -289,9 +306,10 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
     tile_tail<NT>(s, T, m, d, err, merged);
 }
 
-// One workgroup per work unit.
+// One workgroup per work unit.  512-thread tiles of at most 53 KB run three
+// workgroups per CU, which needs at most 80 VGPRs (six waves per SIMD).
 template <int NT, bool F32>
-__global__ __launch_bounds__(NT) void k_tile_lds(Launch L, int *err)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 6 : 4))) void k_tile_lds(Launch L, int *err)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const Resolved d = unit_of(L, blockIdx.x);

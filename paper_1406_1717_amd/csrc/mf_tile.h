@@ -330,7 +330,8 @@ struct TileMem {
     u32 *bk;         // bucket counters / starts, slot-indexed like skey
     u32 *bmin;       // per block: smallest key
     u32 *bmax;       // per block: largest key
-    u32 *flag;       // bit 0: a bucket passed kBucketMax; bit 1: kBucketSoft
+    u32 *flag;       // bit 0: a bucket passed kBucketMax; bit 1: kBucketSoft;
+                     // bit 2: the items are not already in sort order
     u32 *xv;
     u32 *skey;
     u16 *sslot;
@@ -1069,6 +1070,80 @@ MF_HD void tile_mpad(const Shape &s, const Tile &T, const TileMem &m, int32_t ti
         const int32_t p = (int32_t)udiv16((u32)it, padr);
         const int32_t r = s.k + it - p * npad;
         if (r >= s.k + block_len(s, T, p + 1)) m.M[p * s.Mstride + mslot(r)] = (u16)kMPad;
+    }
+}
+
+// ---------------------------------------------------------------- 2+. presorted tiles
+//
+// A tile whose items already stand in sort order (the benign inputs of the
+// paper's experiments, Section 7: ascending or nearly ascending data) needs
+// no sort: the bucket sort is skipped and every item goes straight to its
+// sorted position.  The check rides on the passes that find the key range:
+// each thread notes its first value before their barrier (presort_note),
+// then checks its own items and the step to the next item (presort_check),
+// setting flag bit 2 on any descent.  In tile order the whole tile must be
+// in (key, slot) order; in block order each block in (key, t) order.
+
+MF_HD u64 first_value(const u64 (&v)[kRegs])
+{
+    u64 f = kPadAll;
+#pragma unroll
+    for (int j = kRegs - 1; j >= 0; j--)
+        if (sv_valid(v[j])) f = v[j];
+    return f;
+}
+
+// Before the barrier (the scratch is the merge-sort buffer, free here).
+MF_HD void presort_note(const TileMem &m, int32_t tid, const u64 (&v)[kRegs])
+{
+    m.mbuf[tid] = first_value(v);
+}
+
+// After the barrier; tile: tile-order values (else block order).
+MF_HD void presort_check(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT,
+                         const u64 (&v)[kRegs], bool tile)
+{
+    bool ok = true, any = false;
+    u64 last = 0ull;
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        if (sv_valid(v[j])) {
+            ok = ok && (!any || last < v[j]);
+            last = v[j];
+            any = true;
+        }
+    }
+    if (any) {
+        // the item after the thread's last: the next thread's first, or, when
+        // the last ends its block, the first of the next block (tile order)
+        const u32 u = tile ? tv_slot(last) : (((u32)sv_block(last) << s.logS) | sv_t(last));
+        const int32_t b = (int32_t)(u >> s.logS), t = (int32_t)(u & (u32)(s.S - 1));
+        u64 next = kPadAll;
+        if (t == block_len(s, T, b) - 1) {
+            if (tile && b + 1 < T.NB) next = m.mbuf[((b + 1) << s.logS) / kRegs];
+        } else if (tid + 1 < NT) {
+            next = m.mbuf[tid + 1];
+        }
+        ok = ok && (next == kPadAll || last < next);
+    }
+    if (!ok) MF_OR32(m.flag, 4u);
+}
+
+// Sorted positions of a presorted tile: in tile order the rank of block b's
+// item t is b*k + t (every block before the last is full); in block order
+// an item stays at its slot.
+MF_HD void presort_place(const Shape &s, const TileMem &m, const u64 (&v)[kRegs], bool tile)
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        if (!sv_valid(v[j])) continue;
+        if (tile) {
+            const u32 u = tv_slot(v[j]);
+            const int32_t b = (int32_t)(u >> s.logS), t = (int32_t)(u & (u32)(s.S - 1));
+            put_sorted(m, b * s.k + t, tv_key(v[j]), u);
+        } else {
+            put_block_value(s, m, (sv_block(v[j]) << s.logS) + (int32_t)sv_t(v[j]), v[j]);
+        }
     }
 }
 

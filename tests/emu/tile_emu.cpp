@@ -14,12 +14,13 @@
 using namespace mf;
 
 static int g_force_merge = 0;
-static long g_fast_tiles = 0, g_slow_tiles = 0, g_recount_tiles = 0, g_tile_order_tiles = 0;
+static long g_fast_tiles = 0, g_slow_tiles = 0, g_recount_tiles = 0, g_tile_order_tiles = 0, g_presorted_tiles = 0;
 extern "C" void emu_set_force_merge(int v) { g_force_merge = v; }
 extern "C" long emu_fast_tiles(void) { return g_fast_tiles; }
 extern "C" long emu_slow_tiles(void) { return g_slow_tiles; }
 extern "C" long emu_recount_tiles(void) { return g_recount_tiles; }
 extern "C" long emu_tile_order_tiles(void) { return g_tile_order_tiles; }
+extern "C" long emu_presorted_tiles(void) { return g_presorted_tiles; }
 
 template <bool F32>
 static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
@@ -55,13 +56,23 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
     // bucket path
     for (int e = 0; e < s.cap; e++) bucket_zero_item(m, e);
     for (int b = 0; b < l.nbmax; b++) bucket_info_init(m, b);
+    auto note = [&]() { for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); presort_note(m, q, v); } };
+    auto to_block = [&]() {
+        for (int q = 0; q < threads; q++) {
+            u64 v[kRegs]; V(q, v);
+            tile_to_block_values(s, T, q, v);
+            for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
+        }
+    };
+    note();
     bool fast = s.S >= kRegs && !g_force_merge;
+    bool direct = false;
     std::vector<u32> arr((size_t)threads * kRegs), fin((size_t)threads * kRegs);
     const int32_t N = tile_items(s, T);
     auto attempt_counts = [&]() {
         pass = 0;
         count(arr);
-        if (m.flag[0] != 0u) {
+        if ((m.flag[0] & 3u) != 0u) {
             g_recount_tiles++;
             for (int e = 0; e < s.cap; e++) bucket_zero_item(m, e);
             pass = 1;
@@ -71,36 +82,54 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
     };
     if (fast && tord) {
         for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); tile_minmax(m, v); }
-        if (tile_many_ties(m, N)) {
+        for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); presort_check(s, T, m, q, threads, v, true); }
+        direct = (m.flag[0] & 4u) == 0u;
+        if (!direct && tile_many_ties(m, N)) {
             tord = false;
-            for (int q = 0; q < threads; q++) {
-                u64 v[kRegs]; V(q, v);
-                tile_to_block_values(s, T, q, v);
-                for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
-            }
+            to_block();
             for (int b = 0; b < l.nbmax; b++) bucket_info_init(m, b);
+            note();
         }
     }
-    if (fast && tord) {
+    if (fast && tord && !direct) {
         attempt_counts();
         if ((m.flag[0] & 1u) != 0u) {
             tord = false;
             pass = 0;
-            for (int q = 0; q < threads; q++) {
-                u64 v[kRegs]; V(q, v);
-                tile_to_block_values(s, T, q, v);
-                for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
-            }
+            to_block();
             for (int e = 0; e < s.cap; e++) bucket_zero_item(m, e);
             for (int b = 0; b < l.nbmax; b++) bucket_info_init(m, b);
+            note();
         }
     }
     if (fast && !tord) {
         for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); bucket_minmax(m, v); }
-        attempt_counts();
+        for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); presort_check(s, T, m, q, threads, v, false); }
+        direct = (m.flag[0] & 4u) == 0u;
+        if (!direct) attempt_counts();
     }
     if (fast) fast = (m.flag[0] & 1u) == 0u;
-    if (fast) {
+    auto tkey = [&](int u) { return ((u64)m.skey[u] << 32) | m.sslot[u]; };  // (key, slot) order
+    auto check_sorted = [&]() {
+        if (tord) {
+            for (int u = 1; u < N; u++)
+                if (tkey(u - 1) >= tkey(u)) return -13;
+        } else {
+            for (int b = 0; b < T.NB; b++) {
+                const int len = block_len(s, T, b);
+                for (int u = 1; u < len; u++)
+                    if (tkey((b << s.logS) + u - 1) >= tkey((b << s.logS) + u)) return -12;
+            }
+        }
+        return 0;
+    };
+    if (fast && direct) {
+        g_presorted_tiles++;
+        for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); presort_place(s, m, v, tord); }
+        const int rc = check_sorted();
+        if (rc) return rc;
+        g_fast_tiles++;
+    } else if (fast) {
         const int G = (tord ? st.S : s.S) / kRegs;
         std::vector<u32> tot(threads);
         std::vector<std::vector<u32>> cl(threads, std::vector<u32>(kRegs));
@@ -138,17 +167,8 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
             if (tord) tile_place(m, v, f);
             else bucket_place(s, m, v, f);
         }
-        auto tkey = [&](int u) { return ((u64)m.skey[u] << 32) | m.sslot[u]; };
-        if (tord) {
-            for (int u = 1; u < N; u++)
-                if (tkey(u - 1) >= tkey(u)) return -13;
-        } else {
-            for (int b = 0; b < T.NB; b++) {
-                const int len = block_len(s, T, b);
-                for (int u = 1; u < len; u++)
-                    if (tkey((b << s.logS) + u - 1) >= tkey((b << s.logS) + u)) return -12;
-            }
-        }
+        const int rc = check_sorted();
+        if (rc) return rc;
         g_fast_tiles++;
     } else {
         for (int q = 0; q < threads; q++) {

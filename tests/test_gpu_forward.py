@@ -129,3 +129,25 @@ def test_without_argmed():
     assert am is None
     yo, _ = oracle.sortmedian(x, 101)
     assert np.array_equal(y.cpu().numpy(), yo)
+
+
+@pytest.mark.parametrize("k", [5, 101, 1001, 3001])
+def test_presorted_inputs(k):
+    """Ascending data (the presorted path), with ties, and with one descent
+    that must send its tile through the sort."""
+    rng = np.random.default_rng(900 + k)
+    n = 40 * k + 17
+    cases = [np.sort(rng.random(n)).astype(np.float32),
+             np.sort(rng.integers(0, 40, n)).astype(np.int32),
+             (np.arange(n, dtype=np.int32) // 3)]
+    bump = np.sort(rng.random(n)).astype(np.float32)
+    bump[n // 2] = -1.0
+    cases.append(bump)
+    for x in cases:
+        xt = torch.from_numpy(x).to(DEV)
+        y, am = mf.median_filter(xt, k)
+        torch.cuda.synchronize()
+        mf.lib.mf_check_device_error()
+        yo, ao = oracle.sortmedian(x, k)
+        assert np.array_equal(am.cpu().numpy(), ao), (k, x.dtype)
+        assert np.array_equal(y.cpu().numpy().view(np.uint32), yo.view(np.uint32))

@@ -81,3 +81,33 @@ def test_tile_phases_match_oracle(emu, force_merge, wide):
     else:
         assert fast > 0 and slow > 0      # duplicates-heavy tiles fall back
     emu.emu_set_force_merge(0)
+
+
+def test_presorted_tiles(emu):
+    """Ascending inputs (with ties) skip the bucket sort; a single descent
+    anywhere in a tile must send that tile through the sort."""
+    emu.emu_presorted_tiles.restype = ctypes.c_long
+    before = emu.emu_presorted_tiles()
+    rng = np.random.default_rng(31)
+    for trial in range(48):
+        k = [5, 33, 101, 513, 1001, 3001][trial % 6]
+        n = int(rng.integers(k, 6 * k + 200))
+        kind = (trial // 6) % 4
+        if kind == 0:
+            x = np.sort(rng.random(n)).astype(np.float32)
+        elif kind == 1:
+            x = np.sort(rng.integers(0, 50, n)).astype(np.int32)
+        elif kind == 2:
+            x = np.sort(rng.random(n)).astype(np.float32)
+            x[rng.integers(0, n)] = -1.0
+        else:
+            x = (np.arange(n, dtype=np.int32) // 3)
+        y = np.empty(n - k + 1, x.dtype)
+        a = np.empty(n - k + 1, np.int32)
+        pm = ctypes.c_int32()
+        rc = emu.emu_median_filter(x.ctypes.data, n, k, int(x.dtype == np.float32), threads_for(k),
+                                   y.ctypes.data, a.ctypes.data, ctypes.byref(pm))
+        yo, ao = oracle.sortmedian(x, k)
+        assert rc == 0 and np.array_equal(a, ao), (k, n, kind, rc)
+        assert np.array_equal(y.view(np.uint32), yo.view(np.uint32))
+    assert emu.emu_presorted_tiles() > before
