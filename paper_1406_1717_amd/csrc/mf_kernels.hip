@@ -514,17 +514,21 @@ __global__ void k_identity(Launch L)
 // grad_x[j] = sum over o with argmed[o] == j of grad_y[o], float64, in
 // increasing o.  Each wave owns kBwdTargetsPerWave consecutive targets and
 // visits the outputs that can select them (o in [j-k+1, j]) 64 at a time in
-// increasing order; lanes that hit the same target take turns in lane
-// order (lowest lane first, settled by an LDS atomic minimum), so every
-// accumulator receives its terms in increasing o.
+// increasing order.  Within a batch, every lane finds the lanes holding its
+// target (ten ballots, one per bit of the target); the lowest of them adds
+// the batch's terms of that target to its accumulator, lane by lane in
+// increasing lane (= increasing o) order, so every accumulator receives its
+// terms in increasing o.
+__device__ __forceinline__ u64 wave_ballot(bool p) { return (u64)__ballot(p); }
+
 __global__ __launch_bounds__(kBwdThreads) void k_backward(BwdLaunch L)
 {
     __shared__ double acc[kBwdThreads / 64][kBwdTargetsPerWave];
-    __shared__ int owner[kBwdThreads / 64][kBwdTargetsPerWave];
+    __shared__ float gstage[kBwdThreads / 64][64];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     double *A = acc[wave];
-    int *own = owner[wave];
+    float *G = gstage[wave];
 
     for (int64_t uidx = blockIdx.x; uidx < L.nunits; uidx += gridDim.x) {
         SigDesc sd;
@@ -549,10 +553,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(BwdLaunch L)
         } d = {L.grad_y + sd.y_off, L.argmed + sd.y_off, L.grad_x + sd.x_off, sd.n, sd.k};
         const int64_t nout = d.n - d.k + 1;
         const int64_t j0 = tile * kBwdTargetsPerBlock + (int64_t)wave * kBwdTargetsPerWave;
-        for (int t = lane; t < kBwdTargetsPerWave; t += 64) {
-            A[t] = 0.0;
-            own[t] = 64;
-        }
+        for (int t = lane; t < kBwdTargetsPerWave; t += 64) A[t] = 0.0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -562,7 +563,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(BwdLaunch L)
             if (ohi > nout) ohi = nout;
             // candidates in groups of kBwdGroup batches of 64: the loads of
             // a whole group are issued together, then the batches retire in
-            // order (increasing o), each lowest lane first per target
+            // order (increasing o)
             for (int64_t g0 = olo; g0 < ohi; g0 += 64 * kBwdGroup) {
                 int tgt[kBwdGroup];
                 float gv[kBwdGroup];
@@ -578,28 +579,31 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(BwdLaunch L)
 #pragma unroll
                 for (int q = 0; q < kBwdGroup; q++) {
                     const int t = tgt[q];
-                    const float g = gv[q];
-                    bool pend = t >= 0;
-                    // each round retires the lowest pending lane of every
-                    // target, so 64 rounds always suffice
-                    for (int round = 0; round < 64 && __ballot(pend) != 0ull; round++) {
-                        if (pend) atomicMin(&own[t], lane);
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                        const bool win = pend && (__atomic_load_n(&own[t], __ATOMIC_RELAXED) == lane);
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                        if (win) {
-                            A[t] += (double)g;
-                            own[t] = 64;
-                            pend = false;
-                        }
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    const bool valid = t >= 0;
+                    // lanes of the batch holding the same target as this lane
+                    u64 same = wave_ballot(valid);
+#pragma unroll
+                    for (int bit = 0; bit < 10; bit++) {
+                        const u64 ones = wave_ballot(valid && ((t >> bit) & 1));
+                        same &= ((t >> bit) & 1) ? ones : ~ones;
                     }
+                    G[lane] = gv[q];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    // the lowest lane of each target adds the target's terms
+                    if (valid && ((same & ((1ull << lane) - 1ull)) == 0ull)) {
+                        double a = A[t];
+                        u64 rem = same;
+                        while (rem) {
+                            a += (double)G[__ffsll((unsigned long long)rem) - 1];
+                            rem &= rem - 1ull;
+                        }
+                        A[t] = a;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
             }
             for (int t = lane; t < kBwdTargetsPerWave; t += 64)
