@@ -18,7 +18,8 @@ before the timed region.  Prints one JSON line:
 
 Flags: --gpus N (only 1 is supported: the method shards trivially, but this
 build runs on one GPU), --steps K, --warmup W, --extras (also time the
-duplicates-heavy input, the row batch with backward, and the ragged batch;
+duplicates-heavy input, the random-walk window sweep, the row batch with
+backward, the ragged batch, and the paper's generator families over h;
 minutes of host-side data generation).
 """
 import argparse
@@ -277,7 +278,32 @@ def extras(torch, mf, lib, workloads, args):
                                  "launch_config": tune["config"], "tuned_ms_per_config": tune["tuned_ms"],
                                  "autotune_s": tune_s}
     plan.close()
+    out["paper_generators"] = paper_sweep(torch, lib, workloads)
     return out
+
+
+def paper_sweep(torch, lib, workloads, bh=10**7, hs=(1, 10, 100, 1000, 10000)):
+    """The paper's generator families (Section 7.3) with b*h fixed and the
+    half-window h varied (n = (2h+1) b, k = 2h+1), int32: median outputs/s
+    of the forward, each output spot-checked by the median property."""
+    dev = torch.device("cuda:0")
+    res = {}
+    for fam in ("asc", "desc", "r-asc", "r-desc", "r-large", "r-small", "r-block"):
+        row = {}
+        for h in hs:
+            b = bh // h
+            k = 2 * h + 1
+            n = b * k
+            x_host = workloads.paper_family(fam, n, 700 + h)
+            x = torch.from_numpy(x_host).to(dev)
+            y = torch.empty(n - k + 1, dtype=torch.int32, device=dev)
+            a = torch.empty(n - k + 1, dtype=torch.int32, device=dev)
+            total, _ = timed_steps(lambda: lib.mf_median_filter_i32(x, n, k, y, a), 3, 1, torch)
+            ok = sampled_windows_ok(x_host, k, y.cpu().numpy(), a.cpu().numpy(), samples=200)
+            row[str(h)] = {"n": n, "k": k, "outputs_per_s": (n - k + 1) * 3 / total, "checked": ok}
+            del x, y, a
+        res[fam] = row
+    return res
 
 
 if __name__ == "__main__":

@@ -72,6 +72,10 @@ mf_status mf_median_filter_rows(const float *x, int64_t rows, int64_t n, int32_t
 mf_status mf_median_filter_batched(const float *x, const int64_t *x_offsets,
                                    const int32_t *ks, int32_t num_signals,
                                    float *y, int32_t *argmed, void *stream);
+/* The same for int32 signals. */
+mf_status mf_median_filter_batched_i32(const int32_t *x, const int64_t *x_offsets,
+                                       const int32_t *ks, int32_t num_signals,
+                                       int32_t *y, int32_t *argmed, void *stream);
 
 /* Backward of y = x[argmed]: grad_x[j] = sum of grad_y[o] over the outputs
  * o with argmed[o] == j, accumulated in float64 in increasing o and rounded
@@ -109,6 +113,9 @@ mf_status mf_plan_create_batched(const int64_t *x_offsets, const int32_t *ks,
                                  int32_t num_signals, mf_plan **out);
 mf_status mf_plan_execute(mf_plan *plan, const float *x, float *y, int32_t *argmed,
                           void *stream);
+/* mf_plan_execute for int32 signals (the plan does not depend on the type). */
+mf_status mf_plan_execute_i32(mf_plan *plan, const int32_t *x, int32_t *y, int32_t *argmed,
+                              void *stream);
 mf_status mf_plan_execute_backward(mf_plan *plan, const float *grad_y, const int32_t *argmed,
                                    float *grad_x, void *stream);
 int64_t   mf_plan_output_length(const mf_plan *plan);
@@ -124,8 +131,8 @@ typedef enum {
 } mf_launch_config;
 
 /* Times every launch configuration on these buffers (`reps` timed executes
- * each, 1..100, after one warm-up) and keeps the fastest for later
- * executes.  Writes y and argmed (the batch's outputs, as mf_plan_execute),
+ * each, 1..100, after one warm-up, with the float kernels; the choice holds
+ * for int32 executes too) and keeps the fastest for later executes.  Writes y and argmed (the batch's outputs, as mf_plan_execute),
  * and synchronizes `stream`; MF_ERR_UNSUPPORTED while `stream` is being
  * captured.  On failure the configuration is left as it was. */
 mf_status mf_plan_autotune(mf_plan *plan, const float *x, float *y, int32_t *argmed,

@@ -67,12 +67,15 @@ def output_offsets(x_offsets, ks):
 def median_filter_batched(x, x_offsets, ks, with_argmed=True):
     """Ragged batch: signal s = x[x_offsets[s]:x_offsets[s+1]], window ks[s]."""
     _require_gpu(x, "x")
-    if x.dtype != torch.float32:
-        raise TypeError("batched signals must be float32")
+    if x.dtype not in (torch.float32, torch.int32):
+        raise TypeError("batched signals must be float32 or int32")
     yo = output_offsets(x_offsets, ks)
-    y = torch.empty(int(yo[-1]), dtype=torch.float32, device=x.device)
+    y = torch.empty(int(yo[-1]), dtype=x.dtype, device=x.device)
     am = torch.empty(int(yo[-1]), dtype=torch.int32, device=x.device) if with_argmed else None
-    lib.mf_median_filter_batched(x, x_offsets, ks, len(ks), y, am)
+    if x.dtype == torch.int32:
+        lib.mf_median_filter_batched_i32(x, x_offsets, ks, len(ks), y, am)
+    else:
+        lib.mf_median_filter_batched(x, x_offsets, ks, len(ks), y, am)
     return y, am
 
 

@@ -221,6 +221,7 @@ struct mf_plan {
     int32_t *gam = nullptr;
     unsigned char *gws = nullptr;
     int32_t gconfig = -1;
+    bool gf32 = true;
     int64_t ws_need = 0;
 };
 
@@ -362,7 +363,7 @@ extern "C" mf_status mf_plan_create_batched(const int64_t *x_offsets, const int3
 }
 
 static mf_status plan_enqueue(mf_plan *p, Device &D, const void *x, void *y, int32_t *argmed,
-                              unsigned char *ws, hipStream_t st)
+                              unsigned char *ws, bool f32, hipStream_t st)
 {
     const std::vector<PathGroup> &gs = p->groups[p->config];
     for (size_t gi = 0; gi < gs.size(); gi++) {
@@ -376,17 +377,17 @@ static mf_status plan_enqueue(mf_plan *p, Device &D, const void *x, void *y, int
         L.units = g.d_units;
         L.nunits = g.nunits;
         if (g.persistent) {
-            MF_HIP(launch_forward_persistent(g.path, L, g.lds, p->d_next + gi, D.d_err, st),
+            MF_HIP(launch_forward_persistent(g.path, f32, L, g.lds, p->d_next + gi, D.d_err, st),
                    "batched persistent launch");
             continue;
         }
         const int64_t slots = std::min<int64_t>(kWsSlots, g.nunits);
-        MF_HIP(launch_forward(g.path, true, L, g.lds, ws, g.ws_stride, slots, D.d_err, st), "batched launch");
+        MF_HIP(launch_forward(g.path, f32, L, g.lds, ws, g.ws_stride, slots, D.d_err, st), "batched launch");
     }
     return MF_OK;
 }
 
-extern "C" mf_status mf_plan_execute(mf_plan *p, const float *x, float *y, int32_t *argmed, void *stream)
+static mf_status plan_execute(mf_plan *p, const void *x, void *y, int32_t *argmed, bool f32, void *stream)
 {
     if (!p) return fail(MF_ERR_INVALID_VALUE, "plan must not be null");
     if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
@@ -398,14 +399,15 @@ extern "C" mf_status mf_plan_execute(mf_plan *p, const float *x, float *y, int32
     if (p->ws_need > 0 && (s = acquire_ws(*D, p->ws_need, st, &ws)) != MF_OK) return s;
     // the graph bakes in the data and workspace pointers; capture again
     // when any of them changed
-    if (!p->gexec || p->gx != x || p->gy != y || p->gam != argmed || p->gws != ws || p->gconfig != p->config) {
+    if (!p->gexec || p->gx != x || p->gy != y || p->gam != argmed || p->gws != ws || p->gconfig != p->config ||
+        p->gf32 != f32) {
         if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
         hipStream_t cs;
         MF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate(capture)");
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         mf_status es = MF_OK;
-        if (e == hipSuccess) es = plan_enqueue(p, *D, x, y, argmed, ws, cs);
+        if (e == hipSuccess) es = plan_enqueue(p, *D, x, y, argmed, ws, f32, cs);
         hipError_t e2 = (e == hipSuccess) ? hipStreamEndCapture(cs, &graph) : e;
         if (e2 == hipSuccess && es == MF_OK) e2 = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
         if (graph) (void)hipGraphDestroy(graph);
@@ -417,10 +419,21 @@ extern "C" mf_status mf_plan_execute(mf_plan *p, const float *x, float *y, int32
         p->gam = argmed;
         p->gws = ws;
         p->gconfig = p->config;
+        p->gf32 = f32;
     }
     MF_HIP(hipGraphLaunch(p->gexec, st), "hipGraphLaunch");
     if (p->ws_need > 0) return release_ws(*D, st);
     return MF_OK;
+}
+
+extern "C" mf_status mf_plan_execute(mf_plan *p, const float *x, float *y, int32_t *argmed, void *stream)
+{
+    return plan_execute(p, x, y, argmed, true, stream);
+}
+
+extern "C" mf_status mf_plan_execute_i32(mf_plan *p, const int32_t *x, int32_t *y, int32_t *argmed, void *stream)
+{
+    return plan_execute(p, x, y, argmed, false, stream);
 }
 
 extern "C" mf_status mf_plan_execute_backward(mf_plan *p, const float *grad_y, const int32_t *argmed,
@@ -574,7 +587,17 @@ extern "C" mf_status mf_median_filter_batched(const float *x, const int64_t *x_o
     mf_plan *p = nullptr;
     mf_status s = cached_plan(x_offsets, ks, num_signals, &p);
     if (s != MF_OK) return s;
-    return mf_plan_execute(p, x, y, argmed, stream);
+    return plan_execute(p, x, y, argmed, true, stream);
+}
+
+extern "C" mf_status mf_median_filter_batched_i32(const int32_t *x, const int64_t *x_offsets, const int32_t *ks,
+                                                  int32_t num_signals, int32_t *y, int32_t *argmed, void *stream)
+{
+    if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
+    mf_plan *p = nullptr;
+    mf_status s = cached_plan(x_offsets, ks, num_signals, &p);
+    if (s != MF_OK) return s;
+    return plan_execute(p, x, y, argmed, false, stream);
 }
 
 extern "C" mf_status mf_median_filter_backward(const float *grad_y, const int32_t *argmed, int64_t n,

@@ -672,6 +672,8 @@ hipError_t prepare_kernels()
     MF_ATTR((k_tile_lds<kLdsLarge, false>))
     MF_ATTR((k_tile_lds_persistent<kLdsSmall, true>))
     MF_ATTR((k_tile_lds_persistent<kLdsLarge, true>))
+    MF_ATTR((k_tile_lds_persistent<kLdsSmall, false>))
+    MF_ATTR((k_tile_lds_persistent<kLdsLarge, false>))
     MF_ATTR((k_tile_global<true>))
     MF_ATTR((k_tile_global<false>))
 #undef MF_ATTR
@@ -749,23 +751,28 @@ hipError_t launch_forward(Path p, bool f32, const Launch &L, size_t lds_bytes,
     return hipGetLastError();
 }
 
-hipError_t launch_forward_persistent(Path p, const Launch &L, size_t lds_bytes, u32 *next,
+hipError_t launch_forward_persistent(Path p, bool f32, const Launch &L, size_t lds_bytes, u32 *next,
                                     int *d_err, hipStream_t st)
 {
     if (L.nunits <= 0) return hipSuccess;
     if (p != PATH_LDS_SMALL && p != PATH_LDS_LARGE) return hipErrorInvalidValue;
     const int nt = p == PATH_LDS_SMALL ? kLdsSmall : kLdsLarge;
-    const void *kern = p == PATH_LDS_SMALL ? (const void *)k_tile_lds_persistent<kLdsSmall, true>
-                                           : (const void *)k_tile_lds_persistent<kLdsLarge, true>;
+    const void *kern = p == PATH_LDS_SMALL
+                           ? (f32 ? (const void *)k_tile_lds_persistent<kLdsSmall, true> : (const void *)k_tile_lds_persistent<kLdsSmall, false>)
+                           : (f32 ? (const void *)k_tile_lds_persistent<kLdsLarge, true> : (const void *)k_tile_lds_persistent<kLdsLarge, false>);
     int64_t grid = 0;
     hipError_t e = resident_workgroups(kern, nt, lds_bytes, &grid);
     if (e != hipSuccess) return e;
     if (grid > L.nunits) grid = L.nunits;
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, next, 1);
-    if (p == PATH_LDS_SMALL)
-        hipLaunchKernelGGL((k_tile_lds_persistent<kLdsSmall, true>), dim3((unsigned)grid), dim3(kLdsSmall), lds_bytes, st, L, next, d_err);
-    else
-        hipLaunchKernelGGL((k_tile_lds_persistent<kLdsLarge, true>), dim3((unsigned)grid), dim3(kLdsLarge), lds_bytes, st, L, next, d_err);
+    const dim3 g((unsigned)grid);
+    if (p == PATH_LDS_SMALL) {
+        if (f32) hipLaunchKernelGGL((k_tile_lds_persistent<kLdsSmall, true>), g, dim3(kLdsSmall), lds_bytes, st, L, next, d_err);
+        else     hipLaunchKernelGGL((k_tile_lds_persistent<kLdsSmall, false>), g, dim3(kLdsSmall), lds_bytes, st, L, next, d_err);
+    } else {
+        if (f32) hipLaunchKernelGGL((k_tile_lds_persistent<kLdsLarge, true>), g, dim3(kLdsLarge), lds_bytes, st, L, next, d_err);
+        else     hipLaunchKernelGGL((k_tile_lds_persistent<kLdsLarge, false>), g, dim3(kLdsLarge), lds_bytes, st, L, next, d_err);
+    }
     return hipGetLastError();
 }
 

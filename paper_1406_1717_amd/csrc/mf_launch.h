@@ -76,9 +76,9 @@ hipError_t launch_forward(Path p, bool f32, const Launch &L, size_t lds_bytes,
                           unsigned char *ws, int64_t ws_stride, int64_t ws_slots,
                           int *d_err, hipStream_t st);
 
-// Float LDS tiles of a work list as one persistent launch: a resident grid
-// takes units from the counter *next, which is cleared on `st` first.
-hipError_t launch_forward_persistent(Path p, const Launch &L, size_t lds_bytes, uint32_t *next,
+// LDS tiles of a work list as one persistent launch: a resident grid takes
+// units from the counter *next, which is cleared on `st` first.
+hipError_t launch_forward_persistent(Path p, bool f32, const Launch &L, size_t lds_bytes, uint32_t *next,
                                     int *d_err, hipStream_t st);
 
 hipError_t launch_backward(const BwdLaunch &L, hipStream_t st);

@@ -37,11 +37,13 @@ def load():
         "mf_median_filter_i32": [P, I64, I32, P, P, P],
         "mf_median_filter_rows": [P, I64, I64, I32, P, P, P],
         "mf_median_filter_batched": [P, P, P, I32, P, P, P],
+        "mf_median_filter_batched_i32": [P, P, P, I32, P, P, P],
         "mf_median_filter_backward": [P, P, I64, I32, P, P],
         "mf_median_filter_backward_rows": [P, P, I64, I64, I32, P, P],
         "mf_median_filter_backward_batched": [P, P, P, P, I32, P, P],
         "mf_plan_create_batched": [P, P, I32, P],
         "mf_plan_execute": [P, P, P, P, P],
+        "mf_plan_execute_i32": [P, P, P, P, P],
         "mf_plan_execute_backward": [P, P, P, P, P],
         "mf_plan_autotune": [P, P, P, P, I32, P],
         "mf_plan_set_config": [P, I32],
@@ -123,6 +125,13 @@ def mf_median_filter_batched(x, x_offsets, ks, num_signals, y, argmed, stream=No
                                            _stream(stream)))
 
 
+def mf_median_filter_batched_i32(x, x_offsets, ks, num_signals, y, argmed, stream=None):
+    off, offp = _host_i64(x_offsets)
+    kk, kp = _host_i32(ks)
+    _check(load().mf_median_filter_batched_i32(_ptr(x), offp, kp, int(num_signals), _ptr(y), _ptr(argmed),
+                                               _stream(stream)))
+
+
 def mf_median_filter_backward(grad_y, argmed, n, k, grad_x, stream=None):
     _check(load().mf_median_filter_backward(_ptr(grad_y), _ptr(argmed), int(n), int(k), _ptr(grad_x),
                                             _stream(stream)))
@@ -148,6 +157,10 @@ def mf_check_device_error(stream=None):
     _check(load().mf_check_device_error(_stream(stream)))
 
 
+def _is_i32(t):
+    return str(getattr(t, "dtype", "")) in ("torch.int32", "int32")
+
+
 class Plan:
     """mf_plan_* for one ragged batch layout (host offsets and windows)."""
 
@@ -163,7 +176,8 @@ class Plan:
         return int(load().mf_plan_output_length(self._h))
 
     def execute(self, x, y, argmed, stream=None):
-        _check(load().mf_plan_execute(self._h, _ptr(x), _ptr(y), _ptr(argmed), _stream(stream)))
+        fn = load().mf_plan_execute_i32 if _is_i32(x) else load().mf_plan_execute
+        _check(fn(self._h, _ptr(x), _ptr(y), _ptr(argmed), _stream(stream)))
 
     def execute_backward(self, grad_y, argmed, grad_x, stream=None):
         _check(load().mf_plan_execute_backward(self._h, _ptr(grad_y), _ptr(argmed), _ptr(grad_x),

@@ -143,3 +143,25 @@ def test_batched_invalid_is_rejected():
     ks = np.array([3, 5], dtype=np.int32)           # 5 > length 2
     with pytest.raises(mf.MFError):
         mf.median_filter_batched(torch.zeros(12, device=DEV), off, ks)
+
+
+def test_batched_int32_and_plan():
+    """int32 ragged batch through the one-call entry and through a plan
+    (every launch configuration), against the oracle per signal."""
+    rng = np.random.default_rng(21)
+    _, off, ks = small_batch(22, num=24)
+    x = rng.integers(-2**31, 2**31, int(off[-1]), dtype=np.int32)
+    x[rng.random(x.size) < 0.2] = 7
+    y, am = mf.median_filter_batched(torch.from_numpy(x).to(DEV), off, ks)
+    torch.cuda.synchronize()
+    check_batch(x, off, ks, y.cpu().numpy(), am.cpu().numpy())
+    plan = mf.Plan(off, ks)
+    xt = torch.from_numpy(x).to(DEV)
+    for config in (0, 1, 2):
+        plan.set_config(config)
+        y2 = torch.full_like(y, -1)
+        am2 = torch.full_like(am, -1)
+        plan.execute(xt, y2, am2)
+        torch.cuda.synchronize()
+        assert torch.equal(am2, am) and torch.equal(y2, y), config
+    plan.close()
