@@ -184,9 +184,9 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
     // every thread).
     // Presorted tiles (flag bit 2 clear after the key-range pass) skip the
     // bucket sort.
-    for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
+    bucket_zero_thread(m, tid);
     for (int b = tid; b < l.nbmax; b += NT) bucket_info_init(m, b);
-    presort_note(m, tid, v);
+    presort_note(s, m, tid, v);
     __syncthreads();
     bool fast = s.S >= kRegs;
     bool direct = false;   // items already in sort order
@@ -202,7 +202,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
             tord = false;
             tile_to_block_values(s, T, tid, v);
             for (int b = tid; b < l.nbmax; b += NT) bucket_info_init(m, b);
-            presort_note(m, tid, v);
+            presort_note(s, m, tid, v);
             __syncthreads();
         }
     }
@@ -212,7 +212,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
         if ((m.flag[0] & 3u) != 0u) {
             __syncthreads();
             pass = 1;
-            for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
+            bucket_zero_thread(m, tid);
             if (tid == 0) m.flag[0] = 0u;
             __syncthreads();
             tile_count<F32>(st, m, v, arr, bkt, pass);
@@ -223,9 +223,9 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
             tord = false;
             pass = 0;
             tile_to_block_values(s, T, tid, v);
-            for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
+            bucket_zero_thread(m, tid);
             for (int b = tid; b < l.nbmax; b += NT) bucket_info_init(m, b);
-            presort_note(m, tid, v);
+            presort_note(s, m, tid, v);
             __syncthreads();
         }
     }
@@ -240,7 +240,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
             if ((m.flag[0] & 3u) != 0u) {
                 __syncthreads();
                 pass = 1;
-                for (int e = tid; e < s.cap; e += NT) bucket_zero_item(m, e);
+                bucket_zero_thread(m, tid);
                 if (tid == 0) m.flag[0] = 0u;
                 __syncthreads();
                 bucket_count<F32>(s, T, m, tid, v, arr, pass);
@@ -396,7 +396,7 @@ __host__ __device__ inline void make_glayout(const Shape &s, GLayout *g)
     off = (off + 255) & ~255ll;
     g->total = off;
     int64_t a = g->srt2;
-    g->cnt = a;    a += 2ll * s.Pmax * s.C * (s.Wn + 1);
+    g->cnt = a;    a += 2ll * s.Pmax * s.C * s.Wrow;
     a = (a + 15) & ~15ll;
     g->ctot = a;   a += 4ll * s.Pmax * s.Wn * kColGroups;
     a = (a + 15) & ~15ll;

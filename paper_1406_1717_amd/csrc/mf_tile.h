@@ -166,6 +166,7 @@ struct Shape {
     int32_t L;       // walk chunk length (odd)
     int32_t C;       // chunks of a full pair, ceil(k / L)
     int32_t Wn;      // 64-position words of a pair's merged order, ceil(2k/64)
+    int32_t Wrow;    // cells per count-table row: even, an odd number of dwords
     int32_t Mstride; // u16 entries per pair in M (= Wn * 64)
     int32_t Pstride; // u32 entries per pair in pos (k rounded up to 4)
     int32_t seg;     // merged outputs per pair-merge item (odd)
@@ -177,17 +178,21 @@ struct Layout {
     int32_t xv;      // unused in LDS (-1): the output gathers from x
     int32_t skey;    // u32[cap]  sorted keys
     int32_t sslot;   // u16[cap]  their slots (block << logS | t)
-    int32_t mbuf;    // u64[cap]  merge-sort buffer (aliases skey, sslot, M)
+    int32_t mbuf;    // u64[cap]  merge-sort buffer, and the bucket sort's
+                     //           scattered values (aliases skey, sslot, M)
     int32_t M;       // u16[Pmax * Mstride]
     int32_t pos;     // u32[Pmax * k]     posA | posB << 16
-    int32_t cnt;     // u16[Pmax * C * (Wn + 1)]   (aliases skey, sslot)
+    int32_t cnt;     // u16[Pmax * C * Wrow]       (aliases skey, sslot)
     int32_t ctot;    // u32[Pmax * Wn * kColGroups] (aliases skey, sslot)
-    int32_t bk;      // u32[cap] bucket counters   (aliases M, pos)
+    int32_t bk;      // u32[cap] bucket counters, after mbuf (aliases M, pos)
     int32_t info;    // u32[2 * nbmax + 1]         (aliases M, pos)
     int32_t nbmax;   // blocks of a full tile
     int32_t stage;   // u16[Pmax * k]              (aliases skey, sslot)
     int32_t total;   // bytes
 };
+
+// Largest window walked as a single chunk per pair (no count tables).
+static const int32_t kOneChunkMax = 31;
 
 MF_HD int32_t ceil_div32(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
 
@@ -202,6 +207,16 @@ MF_HD u32 udiv16(u32 a, u32 dr)
     return __umulhi(a, dr);
 #else
     return (u32)(((u64)a * dr) >> 32);
+#endif
+}
+
+// a * b for operands below 2^24 (one 24-bit multiply on the GPU).
+MF_HD u32 mul24(u32 a, u32 b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umul24(a, b);
+#else
+    return a * b;
 #endif
 }
 
@@ -221,6 +236,8 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
     s->cap = threads * kRegs;
     if (2 * S > s->cap) return -1;
     s->Wn = (int32_t)((2u * uk + 63u) >> 6);
+    // an odd dword stride spreads a column's cells over the LDS banks
+    s->Wrow = 2 * (((s->Wn + 1) >> 1) | 1);
     s->Mstride = s->Wn * 64;
     s->Pstride = (k + 3) & ~3;
     // pairs per tile: as many blocks as the sort holds, but the merged
@@ -243,13 +260,15 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
     // position maps on distinct LDS banks), at least 17, large enough that
     // the tile has no more chunks than threads and that the count tables,
     // their column-group totals and the staged medians of all pairs fit in
-    // the sort buffer they reuse
+    // the sort buffer they reuse.  Windows up to 31 walk a pair in one chunk:
+    // the count tables cost more than the longer walk saves.
     int32_t L = 17;
     const int32_t per_thread = (int32_t)(((u32)P * uk + ut - 1u) / ut);
     if (L < per_thread) L = per_thread | 1;
+    if (k <= kOneChunkMax) L = k;
     u32 C = (uk + (u32)L - 1u) / (u32)L;
     for (;;) {
-        const u32 need = (u32)P * (2u * C * (u32)(s->Wn + 1) + 4u * kColGroups * (u32)s->Wn + 2u * uk + 48u);
+        const u32 need = (u32)P * (2u * C * (u32)s->Wrow + 4u * kColGroups * (u32)s->Wn + 2u * uk + 48u);
         if (need <= 6u * (u32)s->cap || L >= k) break;
         L += 2;
         C = (uk + (u32)L - 1u) / (u32)L;
@@ -275,7 +294,7 @@ MF_HD void make_layout(const Shape &s, Layout *l)
     l->pos = off;    off += 4 * s.Pmax * s.Pstride;
     off = (off + 15) & ~15;
     // bucket sort scratch, used before the pair orders are written
-    l->bk = l->M;
+    l->bk = 8 * s.cap;
     l->info = l->bk + 4 * s.cap;
     l->nbmax = s.Pmax + 1;
     const int32_t bend = l->info + 4 * (2 * (s.Pmax + 1) + 1);
@@ -283,7 +302,7 @@ MF_HD void make_layout(const Shape &s, Layout *l)
     if (off < 8 * s.cap) off = 8 * s.cap;
     l->total = off;
     int32_t a = 0;
-    l->cnt = a;      a += 2 * s.Pmax * s.C * (s.Wn + 1);
+    l->cnt = a;      a += 2 * s.Pmax * s.C * s.Wrow;
     a = (a + 15) & ~15;
     l->ctot = a;     a += 4 * s.Pmax * s.Wn * kColGroups;
     a = (a + 15) & ~15;
@@ -393,6 +412,21 @@ MF_HD u64 sort_value(const Shape &s, const Tile &T, const TileMem &m, int32_t u)
 // tile so that a workgroup can issue the next tile's loads early.
 MF_HD void load_raw(const Shape &s, const Tile &T, const u32 *x, int32_t tid, u32 (&raw)[kRegs])
 {
+    if (s.S >= kRegs) {
+        // the thread's slots are consecutive items of one block
+        const int32_t u = tid * kRegs;
+        const int32_t b = u >> s.logS, t0 = u & (s.S - 1);
+        const int32_t len = b < T.NB ? block_len(s, T, b) : 0;
+        const u32 *src = x + T.e0 + (int64_t)b * s.k + t0;
+        if (t0 + kRegs <= len) {
+#pragma unroll
+            for (int j = 0; j < kRegs; j++) raw[j] = src[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < kRegs; j++) raw[j] = (t0 + j < len) ? src[j] : 0u;
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         const int32_t u = tid * kRegs + j;
@@ -408,6 +442,20 @@ template <bool F32>
 MF_HD void load_sort_values(const Shape &s, const Tile &T, const TileMem &m, const u32 (&raw)[kRegs],
                             int32_t tid, u64 (&v)[kRegs])
 {
+    if (s.S >= kRegs) {
+        const int32_t u = tid * kRegs;
+        const int32_t b = u >> s.logS, t0 = u & (s.S - 1);
+        const bool inb = b < T.NB;
+        const int32_t nv = inb ? block_len(s, T, b) - t0 : 0;
+        const u64 hb = (u64)b << 48;
+        const u64 pad = inb ? (hb | 0x0000FFFFFFFFFFFFull) : kPadAll;
+#pragma unroll
+        for (int j = 0; j < kRegs; j++) {
+            const u32 key = F32 ? key_of_f32(raw[j]) : key_of_i32(raw[j]);
+            v[j] = j < nv ? (hb | ((u64)key << 16) | (u64)(t0 + j)) : pad;
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         const int32_t u = tid * kRegs + j;
@@ -578,6 +626,15 @@ MF_HD void put_block_value(const Shape &s, const TileMem &m, int32_t q, u64 v)
 
 // Item = one of the tile's cap counters, or block info entry b < nbmax.
 MF_HD void bucket_zero_item(const TileMem &m, int32_t e) { m.bk[e] = 0u; }
+
+// The kRegs consecutive counters of thread tid (cap = threads * kRegs).
+MF_HD void bucket_zero_thread(const TileMem &m, int32_t tid)
+{
+    uint4 *p = (uint4 *)(m.bk + tid * kRegs);
+    const uint4 z = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int j = 0; j < kRegs / 4; j++) p[j] = z;
+}
 MF_HD void bucket_info_init(const TileMem &m, int32_t b)
 {
     m.bmin[b] = 0xFFFFFFFFu;
@@ -751,6 +808,22 @@ MF_HD void bucket_scan_store(const TileMem &m, int32_t tid, u32 excl, const u32 
     }
 }
 
+// Entries of the scattered bucket [x, hi) of buf below v.  The first four
+// are read by every lane without a loop (an entry past the bucket is read
+// at x and not counted); longer buckets loop over the rest.
+MF_HD u32 bucket_below(const u64 *buf, u32 x, u32 hi, u64 v)
+{
+    const u32 n = hi - x;
+    u32 f = 0u;
+#pragma unroll
+    for (u32 u = 0; u < 4u; u++) {
+        const u64 e = buf[x + (u < n ? u : 0u)];
+        f += (u < n && e < v) ? 1u : 0u;
+    }
+    for (u32 q = x + 4u; q < hi; q++) f += (buf[q] < v) ? 1u : 0u;
+    return f;
+}
+
 // Bucket [lo, hi) of key in block view V (key within the block's range).
 template <bool F32>
 MF_HD void view_bucket(const Shape &s, const BlockView &V, u32 key, u32 &lo, u32 &hi)
@@ -770,7 +843,7 @@ MF_HD void bucket_scatter(const Shape &s, const Tile &T, const TileMem &m, int32
     const BlockView V = block_view<F32>(s, T, m, b, pass);
 #pragma unroll
     for (int j = 0; j < kRegs; j++)
-        if (sv_valid(v[j])) put_block_value(s, m, V.base + (int32_t)(V.start[bucket_of<F32>(V.f, sv_key(v[j]))] + arr[j]), v[j]);
+        if (sv_valid(v[j])) m.mbuf[V.base + (int32_t)(V.start[bucket_of<F32>(V.f, sv_key(v[j]))] + arr[j])] = v[j];
 }
 
 // Per thread: final position = bucket start + rank among the bucket's items
@@ -794,12 +867,7 @@ MF_HD void bucket_rank(const Shape &s, const Tile &T, const TileMem &m, int32_t 
     // one bucket scan per item: a wave pays, per item slot, for the largest
     // of its lanes' buckets (rather than for the largest of all its items)
 #pragma unroll
-    for (int j = 0; j < kRegs; j++) {
-        u32 f = fin[j];
-        const u64 vk = v[j] & 0x0000FFFFFFFFFFFFull;   // (key, t) within the block
-        for (u32 q = x[j]; q < hi[j]; q++) f += (sorted_kt(s, m, V.base + (int32_t)q) < vk) ? 1u : 0u;
-        fin[j] = f;
-    }
+    for (int j = 0; j < kRegs; j++) fin[j] += bucket_below(m.mbuf + V.base, x[j], hi[j], v[j]);
 }
 
 // Per thread: write the sorted blocks (after every rank has been read).
@@ -825,7 +893,7 @@ MF_HD int32_t pair_chunks(const Shape &s, const Tile &T, int32_t p)
 // Row c of pair p's count table: 16-bit cells.  While the histogram is
 // built, a cell holds its word's A items in the low byte and B items in the
 // high byte (each at most 64); after the column pass, a member count.
-MF_HD int32_t cnt_row_idx(const Shape &s, int32_t p, int32_t c) { return (p * s.C + c) * (s.Wn + 1); }
+MF_HD int32_t cnt_row_idx(const Shape &s, int32_t p, int32_t c) { return (p * s.C + c) * s.Wrow; }
 
 MF_HD u16 *cnt_row(const Shape &s, const TileMem &m, int32_t p, int32_t c)
 {
@@ -884,6 +952,17 @@ template <bool F32>
 MF_HD void load_tile_values(const Shape &s, const Tile &T, const TileMem &m, const u32 (&raw)[kRegs],
                             int32_t tid, u64 (&v)[kRegs])
 {
+    if (s.S >= kRegs) {
+        const int32_t u = tid * kRegs;
+        const int32_t b = u >> s.logS, t0 = u & (s.S - 1);
+        const int32_t nv = b < T.NB ? block_len(s, T, b) - t0 : 0;
+#pragma unroll
+        for (int j = 0; j < kRegs; j++) {
+            const u32 key = F32 ? key_of_f32(raw[j]) : key_of_i32(raw[j]);
+            v[j] = j < nv ? (((u64)key << 32) | (u64)(u + j)) : kPadAll;
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         const int32_t u = tid * kRegs + j;
@@ -969,7 +1048,7 @@ MF_HD void tile_scatter(const TileMem &m, const u64 (&v)[kRegs], const u32 (&arr
 {
 #pragma unroll
     for (int j = 0; j < kRegs; j++)
-        if (sv_valid(v[j])) put_sorted(m, (int32_t)(m.bk[bkt[j]] + arr[j]), tv_key(v[j]), tv_slot(v[j]));
+        if (sv_valid(v[j])) m.mbuf[m.bk[bkt[j]] + arr[j]] = v[j];
 }
 
 // Per thread: sorted position = bucket start + rank by the full value among
@@ -990,18 +1069,15 @@ MF_HD void tile_rank(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], i
         fin[j] = x[j];
     }
 #pragma unroll
-    for (int j = 0; j < kRegs; j++) {
-        u32 f = fin[j];
-        for (u32 q = x[j]; q < hi[j]; q++) f += ((((u64)m.skey[q]) << 32 | m.sslot[q]) < v[j]) ? 1u : 0u;
-        fin[j] = f;
-    }
+    for (int j = 0; j < kRegs; j++) fin[j] += bucket_below(m.mbuf, x[j], hi[j], v[j]);
 }
 
+// The pair orders read only the slots of the tile order, not the keys.
 MF_HD void tile_place(const TileMem &m, const u64 (&v)[kRegs], const u32 (&fin)[kRegs])
 {
 #pragma unroll
     for (int j = 0; j < kRegs; j++)
-        if (sv_valid(v[j])) put_sorted(m, (int32_t)fin[j], tv_key(v[j]), tv_slot(v[j]));
+        if (sv_valid(v[j])) m.sslot[fin[j]] = (u16)tv_slot(v[j]);
 }
 
 // Per thread: the slots of its kRegs consecutive tile-order items (into w,
@@ -1028,36 +1104,42 @@ MF_HD void tile_positions(const Shape &s, const Tile &T, const TileMem &m, u64 e
     // (table_hist_item for both merged positions of every item)
     const bool hist = s.C > 1;
     const u32 Lr = recip32(s.L);
+    const u32 wn1 = (u32)s.Wrow;
     u64 c = excl;
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         if (w[j] == 0xFFFFu) continue;
-        const int32_t b = (int32_t)(w[j] >> s.logS);
+        const u32 b = w[j] >> s.logS;
         const u32 t = w[j] & (u32)(s.S - 1);
-        const int32_t cb = (int32_t)((c >> (16 * b)) & 0xFFFFu);
-        if (b < T.P) {   // A of pair b: with B's earlier items
-            const int32_t r = cb + (int32_t)((c >> (16 * b + 16)) & 0xFFFFu);
-            m.M[b * s.Mstride + mslot(r)] = (u16)t;
-            ((u16 *)(m.pos + b * s.Pstride))[2 * t] = (u16)r;
-            if (cb == s.h) m.pos[b * s.Pstride + s.k] = (u32)r;
+        const u32 sh = 16u * b;
+        // field q of R: earlier items of blocks q and q + 1 = rank in pair q
+        const u64 R = c + (c >> 16);
+        const u32 row = hist ? udiv16(t, Lr) : 0u;
+        const u32 cb = (u32)(c >> sh) & 0xFFFFu;
+        if ((int32_t)b < T.P) {   // A of pair b
+            const u32 r = (u32)(R >> sh) & 0xFFFFu;
+            m.M[mul24(b, (u32)s.Mstride) + mslot((int32_t)r)] = (u16)t;
+            const u32 pb = mul24(b, (u32)s.Pstride);
+            ((u16 *)(m.pos + pb))[2u * t] = (u16)r;
+            if (cb == (u32)s.h) m.pos[pb + (u32)s.k] = r;
             if (hist) {
-                int32_t row = (int32_t)udiv16(t, Lr);
-                const int32_t Cp = pair_chunks(s, T, b);
-                row = row < Cp ? row : Cp - 1;
-                cnt_add(m, cnt_row_idx(s, b, row) + (r >> 6), 1u);
+                const u32 Cp = (u32)pair_chunks(s, T, (int32_t)b);
+                const u32 ra = row < Cp ? row : Cp - 1u;
+                cnt_add(m, (int32_t)(mul24(mul24(b, (u32)s.C) + ra, wn1) + (r >> 6)), 1u);
             }
         }
-        if (b >= 1) {    // B of pair b - 1: with A's earlier items
-            const int32_t r = cb + (int32_t)((c >> (16 * b - 16)) & 0xFFFFu);
-            m.M[(b - 1) * s.Mstride + mslot(r)] = (u16)(0x8000u | t);
-            ((u16 *)(m.pos + (b - 1) * s.Pstride))[2 * t + 1] = (u16)r;
-            if (hist) cnt_add(m, cnt_row_idx(s, b - 1, (int32_t)udiv16(t, Lr)) + (r >> 6), 0x100u);
+        if (b >= 1u) {    // B of pair b - 1
+            const u32 r = (u32)(R >> (sh - 16u)) & 0xFFFFu;
+            const u32 q = b - 1u;
+            m.M[mul24(q, (u32)s.Mstride) + mslot((int32_t)r)] = (u16)(0x8000u | t);
+            ((u16 *)(m.pos + mul24(q, (u32)s.Pstride)))[2u * t + 1u] = (u16)r;
+            if (hist) cnt_add(m, (int32_t)(mul24(mul24(q, (u32)s.C) + row, wn1) + (r >> 6)), 0x100u);
         }
-        if (b == 0 && cb == s.h && T.j0 == 1) {
+        if (b == 0u && cb == (u32)s.h && T.j0 == 1) {   // output 0: the median of block 0
             y[0] = x[t];
             if (argmed) argmed[0] = (int32_t)t;
         }
-        c += 1ull << (16 * b);
+        c += 1ull << sh;
     }
 }
 
@@ -1094,9 +1176,10 @@ MF_HD u64 first_value(const u64 (&v)[kRegs])
 }
 
 // Before the barrier (the scratch is the merge-sort buffer, free here).
-MF_HD void presort_note(const TileMem &m, int32_t tid, const u64 (&v)[kRegs])
+MF_HD void presort_note(const Shape &s, const TileMem &m, int32_t tid, const u64 (&v)[kRegs])
 {
-    m.mbuf[tid] = first_value(v);
+    // with S >= kRegs a thread's valid items are a prefix of its slots
+    m.mbuf[tid] = s.S >= kRegs ? (sv_valid(v[0]) ? v[0] : kPadAll) : first_value(v);
 }
 
 // After the barrier; tile: tile-order values (else block order).
@@ -1140,7 +1223,7 @@ MF_HD void presort_place(const Shape &s, const TileMem &m, const u64 (&v)[kRegs]
         if (tile) {
             const u32 u = tv_slot(v[j]);
             const int32_t b = (int32_t)(u >> s.logS), t = (int32_t)(u & (u32)(s.S - 1));
-            put_sorted(m, b * s.k + t, tv_key(v[j]), u);
+            m.sslot[b * s.k + t] = (u16)u;
         } else {
             put_block_value(s, m, (sv_block(v[j]) << s.logS) + (int32_t)sv_t(v[j]), v[j]);
         }
@@ -1242,7 +1325,7 @@ MF_HD int32_t col_rows(const Shape &s) { return (s.C + kColGroups - 1) / kColGro
 // Phase one: the group's A and B totals (low and high halves) into ctot.
 MF_HD void table_colsum_item(const Shape &s, const TileMem &m, int32_t p, int32_t w, int32_t g, int32_t Cp)
 {
-    const int32_t stride = s.Wn + 1, R = col_rows(s);
+    const int32_t stride = s.Wrow, R = col_rows(s);
     const u16 *col = cnt_row(s, m, p, 0) + w;
     const int32_t c0 = g * R, c1 = (c0 + R < Cp) ? c0 + R : Cp;
     u32 tot = 0u;
@@ -1250,22 +1333,22 @@ MF_HD void table_colsum_item(const Shape &s, const TileMem &m, int32_t p, int32_
         const u32 v = col[c * stride];
         tot += (v & 0xFFu) | ((v >> 8) << 16);
     }
-    m.ctot[(p * s.Wn + w) * kColGroups + g] = tot;
+    m.ctot[(p * kColGroups + g) * s.Wn + w] = tot;
 }
 
 // Phase two: A suffix sums and B exclusive prefix sums down the group,
 // starting from the totals of the other groups.
 MF_HD void table_colapply_item(const Shape &s, const TileMem &m, int32_t p, int32_t w, int32_t g, int32_t Cp)
 {
-    const int32_t stride = s.Wn + 1, R = col_rows(s);
+    const int32_t stride = s.Wrow, R = col_rows(s);
     u16 *col = cnt_row(s, m, p, 0) + w;
     const int32_t c0 = g * R, c1 = (c0 + R < Cp) ? c0 + R : Cp;
     if (c0 >= c1) return;
-    const u32 *gt = m.ctot + (p * s.Wn + w) * kColGroups;
+    const u32 *gt = m.ctot + p * kColGroups * s.Wn + w;
     u32 sa = 0u, pb = 0u;
 #pragma unroll
     for (int q = 0; q < kColGroups; q++) {
-        const u32 v = gt[q];
+        const u32 v = gt[q * s.Wn];
         sa += (q >= g) ? (v & 0xFFFFu) : 0u;   // A items of this and later groups
         pb += (q < g) ? (v >> 16) : 0u;        // B items of earlier groups
     }
@@ -1279,17 +1362,24 @@ MF_HD void table_colapply_item(const Shape &s, const TileMem &m, int32_t p, int3
     }
 }
 
-// Item = (pair p, chunk c): exclusive prefix over the words.
+// Item = (pair p, chunk c): exclusive prefix over the words, sixteen cells
+// (eight dwords, read before any is written) at a time.
 MF_HD void table_row_item(const Shape &s, const TileMem &m, int32_t p, int32_t c)
 {
-    u16 *row = cnt_row(s, m, p, c);
+    u32 *row = (u32 *)cnt_row(s, m, p, c);
+    const int32_t nd = s.Wrow / 2;
     u32 acc = 0u;
-    for (int32_t w = 0; w < s.Wn; w++) {
-        const u32 v = row[w];
-        row[w] = (u16)acc;
-        acc += v;
+    for (int32_t d0 = 0; d0 < nd; d0 += 8) {
+        u32 in[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) in[q] = d0 + q < nd ? row[d0 + q] : 0u;
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const u32 lo = acc, hi = acc + (in[q] & 0xFFFFu);
+            acc = hi + (in[q] >> 16);
+            if (d0 + q < nd) row[d0 + q] = (lo & 0xFFFFu) | (hi << 16);
+        }
     }
-    row[s.Wn] = (u16)acc;
 }
 
 // Item = pair p: the window before step 0 is all of A, whose median is A's
@@ -1463,7 +1553,7 @@ MF_HD void tail_first_medians(const Shape &s, const Tile &T, const TileMem &m, i
 
 MF_HD void tail_table_zero(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
 {
-    const int32_t nwords = (T.P * s.C * (s.Wn + 1) + 1) / 2;
+    const int32_t nwords = T.P * s.C * s.Wrow / 2;
     for (int32_t it = tid; it < nwords; it += NT) table_zero_item(m, it);
 }
 
@@ -1481,21 +1571,23 @@ MF_HD void tail_table_hist(const Shape &s, const Tile &T, const TileMem &m, int3
 
 MF_HD void tail_table_colsums(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
 {
+    // consecutive items take consecutive words of one row group
     const u32 Wr = recip32(s.Wn);
     for (int32_t it = tid; it < T.P * s.Wn * kColGroups; it += NT) {
-        const int32_t pw = it / kColGroups, g = it % kColGroups;
-        const int32_t p = (int32_t)udiv16((u32)pw, Wr);
-        table_colsum_item(s, m, p, pw - p * s.Wn, g, pair_chunks(s, T, p));
+        const int32_t pg = (int32_t)udiv16((u32)it, Wr), w = it - pg * s.Wn;
+        const int32_t p = pg / kColGroups, g = pg % kColGroups;
+        table_colsum_item(s, m, p, w, g, pair_chunks(s, T, p));
     }
 }
 
 MF_HD void tail_table_colapply(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
 {
+    // consecutive items take consecutive words of one row group
     const u32 Wr = recip32(s.Wn);
     for (int32_t it = tid; it < T.P * s.Wn * kColGroups; it += NT) {
-        const int32_t pw = it / kColGroups, g = it % kColGroups;
-        const int32_t p = (int32_t)udiv16((u32)pw, Wr);
-        table_colapply_item(s, m, p, pw - p * s.Wn, g, pair_chunks(s, T, p));
+        const int32_t pg = (int32_t)udiv16((u32)it, Wr), w = it - pg * s.Wn;
+        const int32_t p = pg / kColGroups, g = pg % kColGroups;
+        table_colapply_item(s, m, p, w, g, pair_chunks(s, T, p));
     }
 }
 
@@ -1531,26 +1623,41 @@ MF_HD int64_t tile_outputs(const Shape &s, const Tile &T)
     return cnt;
 }
 
-// Item = step i of pair p: output o = o0 + p*k + i.
-MF_HD void output_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, int32_t i,
-                       const u32 *x, u32 *y, int32_t *argmed)
-{
-    const int32_t r = m.stage[p * s.k + i];
-    const u32 e = m.M[p * s.Mstride + mslot(r)];
-    const int32_t b = p + (int32_t)(e >> 15);
-    const int32_t t = (int32_t)(e & 0x7FFFu);
-    const int64_t o = T.o0 + (int64_t)p * s.k + i;
-    y[o] = x[T.e0 + (int64_t)b * s.k + t];
-    if (argmed) argmed[o] = (int32_t)(T.e0 + (int64_t)b * s.k + t);
-}
-
 MF_HD void tail_output(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT,
                        const u32 *x, u32 *y, int32_t *argmed)
 {
+    // the tile's outputs are o0 + it for it = p*k + i, it < (P-1)k + len of
+    // the last block; every gather is issued before the first store
+    const u32 *xt = x + T.e0;
+    u32 *yt = y + T.o0;
+    int32_t *at = argmed ? argmed + T.o0 : nullptr;
+    const int32_t e0 = (int32_t)T.e0;
+    const int32_t nout = (T.P - 1) * s.k + T.lenLast;
     const u32 kr = recip32(s.k);
-    for (int32_t it = tid; it < T.P * s.k; it += NT) {
-        const int32_t p = (int32_t)udiv16((u32)it, kr), i = it - p * s.k;
-        if (i < block_len(s, T, p + 1)) output_item(s, T, m, p, i, x, y, argmed);
+    for (int32_t base = 0; base < nout; base += NT * kRegs) {
+        u32 v[kRegs];
+        int32_t g[kRegs];
+#pragma unroll
+        for (int j = 0; j < kRegs; j++) {
+            const int32_t it = base + j * NT + tid;
+            g[j] = 0;
+            v[j] = 0u;
+            if (it < nout) {
+                const int32_t p = (int32_t)udiv16((u32)it, kr);
+                const int32_t r = m.stage[it];
+                const u32 e = m.M[(int32_t)mul24((u32)p, (u32)s.Mstride) + mslot(r)];
+                g[j] = (int32_t)mul24((u32)p + (e >> 15), (u32)s.k) + (int32_t)(e & 0x7FFFu);
+                v[j] = xt[g[j]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kRegs; j++) {
+            const int32_t it = base + j * NT + tid;
+            if (it < nout) {
+                yt[it] = v[j];
+                if (at) at[it] = e0 + g[j];
+            }
+        }
     }
 }
 

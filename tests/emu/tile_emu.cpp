@@ -54,9 +54,9 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         }
     };
     // bucket path
-    for (int e = 0; e < s.cap; e++) bucket_zero_item(m, e);
+    for (int q = 0; q < threads; q++) bucket_zero_thread(m, q);
     for (int b = 0; b < l.nbmax; b++) bucket_info_init(m, b);
-    auto note = [&]() { for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); presort_note(m, q, v); } };
+    auto note = [&]() { for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); presort_note(s, m, q, v); } };
     auto to_block = [&]() {
         for (int q = 0; q < threads; q++) {
             u64 v[kRegs]; V(q, v);
@@ -74,7 +74,7 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         count(arr);
         if ((m.flag[0] & 3u) != 0u) {
             g_recount_tiles++;
-            for (int e = 0; e < s.cap; e++) bucket_zero_item(m, e);
+            for (int q = 0; q < threads; q++) bucket_zero_thread(m, q);
             pass = 1;
             m.flag[0] = 0u;
             count(arr);
@@ -97,7 +97,7 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
             tord = false;
             pass = 0;
             to_block();
-            for (int e = 0; e < s.cap; e++) bucket_zero_item(m, e);
+            for (int q = 0; q < threads; q++) bucket_zero_thread(m, q);
             for (int b = 0; b < l.nbmax; b++) bucket_info_init(m, b);
             note();
         }
@@ -109,9 +109,20 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         if (!direct) attempt_counts();
     }
     if (fast) fast = (m.flag[0] & 1u) == 0u;
-    auto tkey = [&](int u) { return ((u64)m.skey[u] << 32) | m.sslot[u]; };  // (key, slot) order
+    // (key, slot) order; tile-order placement writes only the slots, whose
+    // keys come from the loaded values
+    std::vector<u32> slotkey((size_t)s.cap, 0u);
+    auto tkey = [&](int u) {
+        if (tord) {
+            const u32 sl = m.sslot[u];
+            return ((u64)slotkey[sl] << 32) | sl;
+        }
+        return ((u64)m.skey[u] << 32) | m.sslot[u];
+    };
     auto check_sorted = [&]() {
         if (tord) {
+            for (size_t e = 0; e < regs.size(); e++)
+                if (sv_valid(regs[e])) slotkey[tv_slot(regs[e])] = tv_key(regs[e]);
             for (int u = 1; u < N; u++)
                 if (tkey(u - 1) >= tkey(u)) return -13;
         } else {
