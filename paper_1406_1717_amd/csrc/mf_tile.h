@@ -257,12 +257,12 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
     if (seg < 9) seg = 9;
     s->seg = seg | 1;
     // chunk length: odd (lanes walking neighbouring chunks then read the
-    // position maps on distinct LDS banks), at least 17, large enough that
+    // position maps on distinct LDS banks), at least 15, large enough that
     // the tile has no more chunks than threads and that the count tables,
     // their column-group totals and the staged medians of all pairs fit in
     // the sort buffer they reuse.  Windows up to 31 walk a pair in one chunk:
     // the count tables cost more than the longer walk saves.
-    int32_t L = 17;
+    int32_t L = 15;
     const int32_t per_thread = (int32_t)(((u32)P * uk + ut - 1u) / ut);
     if (L < per_thread) L = per_thread | 1;
     if (k <= kOneChunkMax) L = k;
