@@ -114,7 +114,7 @@ __device__ __forceinline__ Resolved unit_of(const Launch &L, int64_t uidx)
 // filled m.srt.  NT threads, barriers between phases.
 template <int NT>
 __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
-                                          int *err, bool merged)
+                                          int *err, bool merged, u32 *rowbuf = nullptr)
 {
     const int tid = threadIdx.x;
     if (!merged) {
@@ -126,7 +126,10 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
         __syncthreads();
     }
     if (s.C > 1) {
-        if (!merged) {   // tile order counts its items with the pair orders
+        if (rowbuf) {    // tables in global memory: whole rows from LDS row buffers
+            tail_table_hist_rows(s, T, m, rowbuf, tid & 63, tid >> 6, NT / 64, 64);
+            __syncthreads();
+        } else if (!merged) {   // tile order counts its items with the pair orders
             tail_table_zero(s, T, m, tid, NT);
             __syncthreads();
             tail_table_hist(s, T, m, tid, NT);
@@ -136,7 +139,8 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
         __syncthreads();
         tail_table_colapply(s, T, m, tid, NT);
         __syncthreads();
-        tail_table_rows(s, T, m, tid, NT);
+        if (rowbuf) tail_table_rows_waves(s, T, m, tid & 63, tid >> 6, NT / 64, 64);
+        else tail_table_rows(s, T, m, tid, NT);
         __syncthreads();
     }
     if (tail_walk(s, T, m, tid, NT)) atomicOr(err, 1);
@@ -489,7 +493,8 @@ __global__ __launch_bounds__(kGlobalThreads) void k_tile_global(Launch L, unsign
             if (sv_valid(v)) put_block_value(s, m, u, v);
         }
         __syncthreads();
-        tile_tail<kGlobalThreads>(s, T, m, d, err, false);
+        // the sort buffer is free: it holds the waves' histogram row buffers
+        tile_tail<kGlobalThreads>(s, T, m, d, err, false, (u32 *)lds);
     }
 }
 
