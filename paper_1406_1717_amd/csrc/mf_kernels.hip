@@ -143,6 +143,20 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
         else tail_table_rows(s, T, m, tid, NT);
         __syncthreads();
     }
+    if (rowbuf && T.P > 0) {
+        // tiles in global memory: the walk and the output read the merged
+        // orders from a copy in LDS (the row buffers are done)
+        TileMem ml = m;
+        ml.M = (u16 *)rowbuf;
+        const uint4 *src = (const uint4 *)m.M;
+        uint4 *dst = (uint4 *)rowbuf;
+        for (int e = tid; e < T.P * s.Mstride / 8; e += NT) dst[e] = src[e];
+        __syncthreads();
+        if (tail_walk(s, T, ml, tid, NT)) atomicOr(err, 1);
+        __syncthreads();
+        tail_output(s, T, ml, tid, NT, d.x, (u32 *)d.y, d.argmed);
+        return;
+    }
     if (tail_walk(s, T, m, tid, NT)) atomicOr(err, 1);
     __syncthreads();
     tail_output(s, T, m, tid, NT, d.x, (u32 *)d.y, d.argmed);
@@ -414,11 +428,208 @@ __host__ __device__ inline int global_shape(int64_t n, int32_t k, Shape *s)
     return make_shape(n, k, 2 * S / kRegs, s);
 }
 
+
+// Bucket sort of a one-pair tile in global memory (P = 1).  Blocks A and B
+// are sorted together by (key, block, t), which is the pair's merged order
+// (A before B on equal keys), so M and the position maps come straight out
+// of the sort.  Slot u = b << logS | t.  The counters (nbk 16-bit cells)
+// live in LDS, the arrival numbers and the scattered values in the
+// workspace.  Fills M (with its padding), the position maps, the pair's
+// first median (pos[k]) and output 0.  Returns false, having written only
+// scratch, if a bucket overflows even under the logarithmic map; the
+// caller then takes the merge sort.
+template <bool F32>
+__device__ bool global_pair_bucket(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
+                                   u64 *srt, u16 *arrv, u32 *lcnt, u32 *gsh, u32 *wave_tot)
+{
+    const int tid = threadIdx.x;
+    const int NT = kGlobalThreads;
+    const int32_t nbk = 2 * s.S;   // at most 65536 cells: 128 KB of LDS
+    int32_t lognbk = 0;
+    while ((1 << lognbk) < nbk) lognbk++;
+    const int32_t lenB = T.lenLast;
+    const int32_t N = s.k + lenB;
+    const int32_t nslots = 2 * s.S;   // a multiple of kGW * NT
+    const u32 *xt = d.x + T.e0;
+    // each pass below takes kGW slots per thread at a time, u = u0 + q * NT,
+    // with their loads in flight together
+    constexpr int kGW = 4;
+    auto load_group = [&](int u0, u32 (&raw)[kGW], bool (&ok)[kGW]) {
+#pragma unroll
+        for (int q = 0; q < kGW; q++) {
+            const int u = u0 + q * NT, b = u >> s.logS, tt = u & (s.S - 1);
+            ok[q] = tt < (b ? lenB : s.k);
+            raw[q] = ok[q] ? xt[b * s.k + tt] : 0u;
+        }
+    };
+    auto key_of = [&](u32 raw) { return F32 ? key_of_f32(raw) : key_of_i32(raw); };
+    auto cell = [&](u32 bk) { return (lcnt[bk >> 1] >> (16u * (bk & 1u))) & 0xFFFFu; };
+
+    for (int e = tid; e < nbk / 2; e += NT) lcnt[e] = 0u;
+    if (tid == 0) {
+        gsh[0] = 0xFFFFFFFFu;
+        gsh[1] = 0u;
+        gsh[2] = 0u;
+    }
+    __syncthreads();
+    // key range
+    {
+        u32 mn = 0xFFFFFFFFu, mx = 0u;
+        for (int u0 = tid; u0 < nslots; u0 += kGW * NT) {
+            u32 raw[kGW];
+            bool ok[kGW];
+            load_group(u0, raw, ok);
+#pragma unroll
+            for (int q = 0; q < kGW; q++) {
+                const u32 key = key_of(raw[q]);
+                mn = ok[q] && key < mn ? key : mn;
+                mx = ok[q] && key > mx ? key : mx;
+            }
+        }
+        for (int dd = 32; dd >= 1; dd >>= 1) {
+            const u32 omn = (u32)__shfl_xor((int)mn, dd, 64), omx = (u32)__shfl_xor((int)mx, dd, 64);
+            mn = omn < mn ? omn : mn;
+            mx = omx > mx ? omx : mx;
+        }
+        if ((tid & 63) == 0 && mn <= mx) {
+            atomicMin(gsh + 0, mn);
+            atomicMax(gsh + 1, mx);
+        }
+    }
+    __syncthreads();
+    // arrival numbers: a crowded linear map is counted again with the
+    // logarithmic one; if that overflows but the linear map only crowded,
+    // the linear map is counted a third time and kept
+    int pass = 0, round = 0;
+    u32 fl0 = 0u;
+    for (;; round++) {
+        const BucketFn f = make_bucket_fn<F32>(nbk, lognbk, gsh[0], gsh[1], pass);
+        u32 amax = 0u;
+        for (int u0 = tid; u0 < nslots; u0 += kGW * NT) {
+            u32 raw[kGW];
+            bool ok[kGW];
+            load_group(u0, raw, ok);
+#pragma unroll
+            for (int q = 0; q < kGW; q++) {
+                if (!ok[q]) continue;
+                const u32 bk = bucket_of<F32>(f, key_of(raw[q]));
+                const u32 sh = 16u * (bk & 1u);
+                const u32 a = (atomicAdd(lcnt + (bk >> 1), 1u << sh) >> sh) & 0xFFFFu;
+                arrv[u0 + q * NT] = (u16)a;
+                amax = a > amax ? a : amax;
+            }
+        }
+        if (amax >= (u32)kBucketSoft) atomicOr(gsh + 2, amax >= (u32)kBucketMax ? 3u : 2u);
+        __syncthreads();
+        const u32 fl = gsh[2];
+        if (round == 0) fl0 = fl;
+        if ((round == 0 && (fl & 3u) == 0u) || (round == 1 && (fl & 1u) == 0u) || round == 2) break;
+        if (round == 1 && (fl0 & 1u) != 0u) return false;
+        __syncthreads();   // every thread has read the flag
+        pass = round == 0 ? 1 : 0;
+        for (int e = tid; e < nbk / 2; e += NT) lcnt[e] = 0u;
+        if (tid == 0) gsh[2] = 0u;
+        __syncthreads();
+    }
+    const BucketFn f = make_bucket_fn<F32>(nbk, lognbk, gsh[0], gsh[1], pass);
+    // bucket starts: each thread's run of cells, then the runs' totals
+    {
+        const int32_t nd = nbk / 2 / NT;   // dwords per thread (8, 16 or 32)
+        uint4 *cells = (uint4 *)(lcnt + tid * nd);
+        u32 tot = 0u;
+        for (int q = 0; q < nd / 4; q++) {
+            const uint4 v = cells[q];
+            tot += (v.x & 0xFFFFu) + (v.x >> 16) + (v.y & 0xFFFFu) + (v.y >> 16) +
+                   (v.z & 0xFFFFu) + (v.z >> 16) + (v.w & 0xFFFFu) + (v.w >> 16);
+        }
+        u32 acc = seg_excl_scan<kGlobalThreads>(tot, NT, wave_tot);
+        for (int q = 0; q < nd / 4; q++) {
+            const uint4 v = cells[q];
+            const u32 in[4] = {v.x, v.y, v.z, v.w};
+            u32 out[4];
+#pragma unroll
+            for (int z = 0; z < 4; z++) {
+                const u32 lo = acc, hi = acc + (in[z] & 0xFFFFu);
+                acc = hi + (in[z] >> 16);
+                out[z] = (lo & 0xFFFFu) | (hi << 16);
+            }
+            cells[q] = make_uint4(out[0], out[1], out[2], out[3]);
+        }
+    }
+    __syncthreads();
+    // scatter
+    for (int u0 = tid; u0 < nslots; u0 += kGW * NT) {
+        u32 raw[kGW], a[kGW];
+        bool ok[kGW];
+        load_group(u0, raw, ok);
+#pragma unroll
+        for (int q = 0; q < kGW; q++) a[q] = ok[q] ? arrv[u0 + q * NT] : 0u;
+#pragma unroll
+        for (int q = 0; q < kGW; q++) {
+            if (!ok[q]) continue;
+            const u32 key = key_of(raw[q]);
+            srt[cell(bucket_of<F32>(f, key)) + a[q]] = ((u64)key << 32) | (u64)(u0 + q * NT);
+        }
+    }
+    __syncthreads();
+    // rank within the bucket, then the merged order and position maps; by
+    // position of the scattered array, so that the reads are coalesced and
+    // a bucket's other entries sit in the same cache lines
+    u16 *pos16 = (u16 *)m.pos;
+    for (int r0 = tid; r0 < N; r0 += kGW * NT) {
+        u64 v[kGW];
+#pragma unroll
+        for (int q = 0; q < kGW; q++) v[q] = r0 + q * NT < N ? srt[r0 + q * NT] : 0ull;
+#pragma unroll
+        for (int q = 0; q < kGW; q++) {
+            if (r0 + q * NT >= N) continue;
+            const u32 key = (u32)(v[q] >> 32), u = (u32)v[q] & 0xFFFFu;
+            const u32 b = u >> s.logS, tt = u & (u32)(s.S - 1);
+            const u32 bk = bucket_of<F32>(f, key);
+            const u32 x0 = cell(bk), hi = bk + 1u < (u32)nbk ? cell(bk + 1u) : (u32)N;
+            const u32 fin = x0 + bucket_below(srt, x0, hi, v[q]);
+            m.M[mslot((int32_t)fin)] = (u16)((b << 15) | tt);
+            pos16[2 * tt + b] = (u16)fin;
+        }
+    }
+    for (int r = N + tid; r < s.Mstride; r += NT) m.M[mslot(r)] = (u16)kMPad;
+    __syncthreads();
+    // the pair's first median: A's item of rank h among A's items in M
+    {
+        const int32_t per = (N + NT - 1) / NT;
+        const int32_t r0 = tid * per < N ? tid * per : N, r1 = r0 + per < N ? r0 + per : N;
+        u32 na = 0u;
+        for (int r = r0; r < r1; r++) na += (m.M[mslot(r)] & 0x8000u) ? 0u : 1u;
+        const u32 ex = seg_excl_scan<kGlobalThreads>(na, NT, wave_tot);
+        const u32 h = (u32)s.h;
+        if (ex <= h && h < ex + na) {
+            u32 c = ex;
+            for (int r = r0; r < r1; r++) {
+                const u32 e = m.M[mslot(r)];
+                if (e & 0x8000u) continue;
+                if (c == h) {
+                    m.pos[s.k] = (u32)r;
+                    if (T.j0 == 1) {   // output 0: the median of block 0
+                        d.y[0] = d.x[e];
+                        if (d.argmed) d.argmed[0] = (int32_t)e;
+                    }
+                    break;
+                }
+                c++;
+            }
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
 template <bool F32>
 __global__ __launch_bounds__(kGlobalThreads) void k_tile_global(Launch L, unsigned char *ws,
                                                                 int64_t ws_stride, int *err)
 {
     extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ u32 gsh[3];
+    __shared__ u32 wave_tot[kGlobalThreads / 64];
     u64 *sbuf = (u64 *)lds;   // kGlobalThreads * kRegs values
     const int tid = threadIdx.x;
     const int chunk = kGlobalThreads * kRegs;
@@ -444,6 +655,15 @@ __global__ __launch_bounds__(kGlobalThreads) void k_tile_global(Launch L, unsign
         const u32 *x = d.x;
 
         __syncthreads();   // the previous tile is done with the workspace
+        // one-pair tiles: bucket sort of the pair (the sort buffer holds the
+        // counters, then the waves' histogram row buffers)
+        if (T.P == 1 && s.S >= 8192 && global_pair_bucket<F32>(s, T, m, d, srt, (u16 *)srt2, (u32 *)lds, gsh, wave_tot)) {
+            tile_tail<kGlobalThreads>(s, T, m, d, err, true, (u32 *)lds);
+            continue;
+        }
+        // otherwise (a single block, or buckets that overflow on heavy ties):
+        // merge sort of each block, then merge path per pair
+        __syncthreads();
         for (int b = 0; b < T.NB; b++) {
             const int len = block_len(s, T, b);
             for (int t = tid; t < len; t += kGlobalThreads) load_item(s, T, m, x, b, t);
@@ -650,7 +870,7 @@ int64_t lds_bytes_for(Path p, int32_t k)
     switch (p) {
     case PATH_LDS_SMALL: make_shape(1ll << 20, k, kLdsSmall, &s); make_layout(s, &l); return l.total;
     case PATH_LDS_LARGE: make_shape(1ll << 20, k, kLdsLarge, &s); make_layout(s, &l); return l.total;
-    case PATH_GLOBAL: return 8ll * kGlobalThreads * kRegs;
+    case PATH_GLOBAL: return kGlobalLds;
     default: return 0;
     }
 }

@@ -59,6 +59,10 @@ static const int kLdsSmall = 512;
 static const int kLdsLarge = 1024;
 
 static const int kGlobalThreads = 1024;
+// Dynamic LDS of a global-memory tile: the sort buffer, then the bucket
+// counters (2S 16-bit cells), the histogram row buffers and the copy of the
+// merged order (2 Mstride bytes); at most 128 KB for k <= 32767.
+static const int kGlobalLds = 128 * 1024;
 static const int kBwdThreads = 256;
 static const int kBwdTargetsPerWave = 1024;
 static const int kBwdTargetsPerBlock = kBwdTargetsPerWave * (kBwdThreads / 64);

@@ -81,6 +81,23 @@ def test_float_specials(k):
     assert_same(x, k, y, am, "specials")
 
 
+@pytest.mark.parametrize("k", [4097, 5001, 9999, 20001])
+def test_global_tiles_crowded_maps(k):
+    """Global-memory tiles (k > 4096): N(0,1) with 5 % impulses of +-50 (the
+    linear bucket map crowds, the logarithmic one is used), values with
+    moderate ties (0..3999), and a second pair of windows per launch."""
+    rng = np.random.default_rng(6000 + k)
+    n = 3 * k + int(rng.integers(0, k))
+    x = rng.standard_normal(n).astype(np.float32)
+    m = rng.random(n) < 0.05
+    x[m] = rng.uniform(-50, 50, int(m.sum())).astype(np.float32)
+    y, am = run_gpu(x, k)
+    assert_same(x, k, y, am, "impulse")
+    xi = rng.integers(0, 4000, n).astype(np.int32)
+    y, am = run_gpu(xi, k)
+    assert_same(xi, k, y, am, "ties 0..3999")
+
+
 @pytest.mark.parametrize("k,n", [(1, 1), (1, 7), (3, 3), (3, 4), (3, 5), (5, 5), (101, 101), (101, 102),
                                  (101, 202), (101, 203), (1001, 1001), (1001, 2001), (1001, 2002),
                                  (4095, 4095), (4095, 8191), (4097, 4097), (4097, 8195), (9999, 9999),
