@@ -41,11 +41,15 @@ template <int NT>
 __device__ __forceinline__ u32 seg_excl_scan(u32 tot, int G, u32 *wave_tot)
 {
     const int lane = threadIdx.x & 63;
-    const int width = G < 64 ? G : 64;
-    u32 incl = tot;
-    for (int d = 1; d < width; d <<= 1) {
-        const u32 o = (u32)__shfl_up((int)incl, (unsigned)d, width);
-        if ((lane & (width - 1)) >= d) incl += o;
+    u32 incl;
+    if (G >= 64) {
+        incl = __ockl_wfscan_add_u32(tot, false) + tot;
+    } else {
+        incl = tot;
+        for (int d = 1; d < G; d <<= 1) {
+            const u32 o = (u32)__shfl_up((int)incl, (unsigned)d, G);
+            if ((lane & (G - 1)) >= d) incl += o;
+        }
     }
     if (G <= 64) return incl - tot;
     const int wave = threadIdx.x >> 6;
@@ -63,11 +67,7 @@ template <int NT>
 __device__ __forceinline__ u64 excl_scan64(u64 c, u64 *wave_tot)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    u64 incl = c;
-    for (int d = 1; d < 64; d <<= 1) {
-        const u64 o = __shfl_up(incl, (unsigned)d, 64);
-        if (lane >= d) incl += o;
-    }
+    const u64 incl = (u64)__ockl_wfscan_add_u64((unsigned long)c, false) + c;
     if (lane == 63) wave_tot[wave] = incl;
     __syncthreads();
     u64 add = 0ull;
@@ -486,11 +486,8 @@ __device__ bool global_pair_bucket(const Shape &s, const Tile &T, const TileMem 
                 mx = ok[q] && key > mx ? key : mx;
             }
         }
-        for (int dd = 32; dd >= 1; dd >>= 1) {
-            const u32 omn = (u32)__shfl_xor((int)mn, dd, 64), omx = (u32)__shfl_xor((int)mx, dd, 64);
-            mn = omn < mn ? omn : mn;
-            mx = omx > mx ? omx : mx;
-        }
+        mn = __ockl_wfred_min_u32(mn);
+        mx = __ockl_wfred_max_u32(mx);
         if ((tid & 63) == 0 && mn <= mx) {
             atomicMin(gsh + 0, mn);
             atomicMax(gsh + 1, mx);

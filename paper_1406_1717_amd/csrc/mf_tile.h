@@ -52,6 +52,15 @@
 struct uint4 { uint32_t x, y, z, w; };
 #endif
 
+#if defined(__HIPCC__)
+// Wave-wide reductions and exclusive scans of the ROCm device library (row
+// and wave shifts between lanes; every lane of the wave must be active).
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_min_u32(unsigned int);
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_max_u32(unsigned int);
+extern "C" __device__ unsigned int __ockl_wfscan_add_u32(unsigned int, bool);
+extern "C" __device__ unsigned long __ockl_wfscan_add_u64(unsigned long, bool);
+#endif
+
 namespace mf {
 
 typedef uint64_t u64;
@@ -999,11 +1008,8 @@ MF_HD void tile_minmax(const TileMem &m, const u64 (&v)[kRegs])
         }
     }
 #if defined(__HIP_DEVICE_COMPILE__)
-    for (int d = 32; d >= 1; d >>= 1) {
-        const u32 omn = (u32)__shfl_xor((int)mn, d, 64), omx = (u32)__shfl_xor((int)mx, d, 64);
-        mn = omn < mn ? omn : mn;
-        mx = omx > mx ? omx : mx;
-    }
+    mn = __ockl_wfred_min_u32(mn);
+    mx = __ockl_wfred_max_u32(mx);
     const bool lead = (threadIdx.x & 63) == 0;
 #else
     const bool lead = true;
@@ -1664,12 +1670,8 @@ MF_HD void tail_table_rows(const Shape &s, const Tile &T, const TileMem &m, int3
 MF_HD u32 wave_excl_scan(u32 v, int32_t lane)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    u32 incl = v;
-    for (int d = 1; d < 64; d <<= 1) {
-        const u32 o = (u32)__shfl_up((int)incl, (unsigned)d, 64);
-        if (lane >= d) incl += o;
-    }
-    return incl - v;
+    (void)lane;
+    return __ockl_wfscan_add_u32(v, false);
 #else
     (void)lane;
     return 0u * v;   // a single lane
