@@ -73,7 +73,11 @@ static const u32 kMPad = 0xFFFFu;          // merged-order padding: never a memb
 // Slot of merged position r in a pair's M row: within each group of 32
 // positions, dword j holds positions j and j + 16, so that the membership
 // bits of a group come out of its 16 dwords in position order.
-MF_HD int32_t mslot(int32_t r) { return (r & ~31) | ((r & 15) << 1) | ((r >> 4) & 1); }
+MF_HD int32_t mslot(int32_t r)
+{
+    const u32 u = (u32)r, rot = (u << 1) | ((u >> 4) & 1u);   // low five bits rotated left by one
+    return (int32_t)((rot & 31u) | (u & ~31u));
+}
 
 // Lane-wise 16-bit difference a - b of two packed halves.
 MF_HD uint32_t psub16(uint32_t a, uint32_t b)
@@ -1110,7 +1114,7 @@ MF_HD void tile_positions(const Shape &s, const Tile &T, const TileMem &m, u64 e
     // (table_hist_item for both merged positions of every item)
     const bool hist = s.C > 1;
     const u32 Lr = recip32(s.L);
-    const u32 wn1 = (u32)s.Wrow;
+    const u32 CW = (u32)(s.C * s.Wrow);   // cells of a pair's table
     u64 c = excl;
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
@@ -1120,7 +1124,9 @@ MF_HD void tile_positions(const Shape &s, const Tile &T, const TileMem &m, u64 e
         const u32 sh = 16u * b;
         // field q of R: earlier items of blocks q and q + 1 = rank in pair q
         const u64 R = c + (c >> 16);
-        const u32 row = hist ? udiv16(t, Lr) : 0u;
+        // the item's table row within its pairs (t/L; rows past the last
+        // pair's chunks only feed the column sums)
+        const u32 rowc = hist ? mul24(udiv16(t, Lr), (u32)s.Wrow) + mul24(b, CW) : 0u;
         const u32 cb = (u32)(c >> sh) & 0xFFFFu;
         if ((int32_t)b < T.P) {   // A of pair b
             const u32 r = (u32)(R >> sh) & 0xFFFFu;
@@ -1128,18 +1134,14 @@ MF_HD void tile_positions(const Shape &s, const Tile &T, const TileMem &m, u64 e
             const u32 pb = mul24(b, (u32)s.Pstride);
             ((u16 *)(m.pos + pb))[2u * t] = (u16)r;
             if (cb == (u32)s.h) m.pos[pb + (u32)s.k] = r;
-            if (hist) {
-                const u32 Cp = (u32)pair_chunks(s, T, (int32_t)b);
-                const u32 ra = row < Cp ? row : Cp - 1u;
-                cnt_add(m, (int32_t)(mul24(mul24(b, (u32)s.C) + ra, wn1) + (r >> 6)), 1u);
-            }
+            if (hist) cnt_add(m, (int32_t)(rowc + (r >> 6)), 1u);
         }
         if (b >= 1u) {    // B of pair b - 1
             const u32 r = (u32)(R >> (sh - 16u)) & 0xFFFFu;
             const u32 q = b - 1u;
             m.M[mul24(q, (u32)s.Mstride) + mslot((int32_t)r)] = (u16)(0x8000u | t);
             ((u16 *)(m.pos + mul24(q, (u32)s.Pstride)))[2u * t + 1u] = (u16)r;
-            if (hist) cnt_add(m, (int32_t)(mul24(mul24(q, (u32)s.C) + row, wn1) + (r >> 6)), 0x100u);
+            if (hist) cnt_add(m, (int32_t)(rowc - CW + (r >> 6)), 0x100u);
         }
         if (b == 0u && cb == (u32)s.h && T.j0 == 1) {   // output 0: the median of block 0
             y[0] = x[t];
@@ -1152,13 +1154,18 @@ MF_HD void tile_positions(const Shape &s, const Tile &T, const TileMem &m, u64 e
 // Thread tid's share of the merged-order padding (tile order).
 MF_HD void tile_mpad(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
 {
-    const int32_t npad = s.Mstride - s.k;
+    // positions [2k, Mstride) of every pair (2k is never a multiple of 64,
+    // so there is at least one), and [k + len B, 2k) of a last pair whose B
+    // is short
+    const int32_t npad = s.Mstride - 2 * s.k;
     const u32 padr = recip32(npad);
     for (int32_t it = tid; it < T.P * npad; it += NT) {
         const int32_t p = (int32_t)udiv16((u32)it, padr);
-        const int32_t r = s.k + it - p * npad;
-        if (r >= s.k + block_len(s, T, p + 1)) m.M[p * s.Mstride + mslot(r)] = (u16)kMPad;
+        m.M[p * s.Mstride + mslot(2 * s.k + it - p * npad)] = (u16)kMPad;
     }
+    if (T.P > 0)
+        for (int32_t r = s.k + T.lenLast + tid; r < 2 * s.k; r += NT)
+            m.M[(T.P - 1) * s.Mstride + mslot(r)] = (u16)kMPad;
 }
 
 // ---------------------------------------------------------------- 2+. presorted tiles
@@ -1304,26 +1311,26 @@ MF_HD void table_zero_item(const TileMem &m, int32_t e) { ((u32 *)m.cnt)[e] = 0u
 
 
 // Item = merged position r of pair p (r < k + len B): count its item in
-// bucket (min(t/L, chunks-1), r/64); A items in the low half, B items in the
-// high.  Lrcp = ceil(2^32 / L) makes t/L a high multiply (exact for t, L <
-// 2^16); Cp is the pair's chunk count.
-MF_HD void table_hist_item(const Shape &s, const TileMem &m, int32_t p, int32_t r, u32 Lrcp, int32_t Cp)
+// bucket (t/L, r/64); A items in the low half, B items in the high.  Every
+// pair has C rows: a last pair with a short B walks fewer chunks, and its
+// later rows hold only A items, which reach the earlier rows through the
+// column sums.  Lrcp = ceil(2^32 / L) makes t/L a high multiply (exact for
+// t, L < 2^16).
+MF_HD void table_hist_item(const Shape &s, const TileMem &m, int32_t p, int32_t r, u32 Lrcp)
 {
     const u32 e = m.M[p * s.Mstride + mslot(r)];
     const u32 t = e & 0x7FFFu;
 #if defined(__HIP_DEVICE_COMPILE__)
-    int32_t b = (int32_t)__umulhi(t, Lrcp);
+    const int32_t b = (int32_t)__umulhi(t, Lrcp);
 #else
-    int32_t b = (int32_t)(((u64)t * Lrcp) >> 32);
+    const int32_t b = (int32_t)(((u64)t * Lrcp) >> 32);
 #endif
-    if (b > Cp - 1) b = Cp - 1;        // only A items reach past the last chunk
     cnt_add(m, cnt_row_idx(s, p, b) + (r >> 6), (e & 0x8000u) ? 0x100u : 1u);
 }
 
 
 // Row c of pair p's histogram, counted from the position maps (for tables
-// in global memory): the items of chunk c, t in [cL, (c+1)L) (the pair's last
-// chunk also takes A's items past its last step), go into the row buffer rb
+// in global memory): the items with t in [cL, (c+1)L) go into the row buffer rb
 // (Wrow cells, zeroed) shared by the nl lanes of one wave (this is lane
 // `lane`), packed as in table_hist_item.
 MF_HD void table_hist_row(const Shape &s, const Tile &T, const TileMem &m, int32_t p, int32_t c, u32 *rb,
@@ -1331,7 +1338,7 @@ MF_HD void table_hist_row(const Shape &s, const Tile &T, const TileMem &m, int32
 {
     const int32_t lenB = block_len(s, T, p + 1);
     const int32_t t0 = c * s.L;
-    const int32_t tA = (c == pair_chunks(s, T, p) - 1 || t0 + s.L > s.k) ? s.k : t0 + s.L;
+    const int32_t tA = t0 + s.L < s.k ? t0 + s.L : s.k;
     const int32_t tB = t0 + s.L < lenB ? t0 + s.L : lenB;
     const u32 *pos = m.pos + p * s.Pstride;
     for (int32_t t = t0 + lane; t < tA; t += nl) {
@@ -1353,11 +1360,11 @@ MF_HD void table_hist_row(const Shape &s, const Tile &T, const TileMem &m, int32
 MF_HD int32_t col_rows(const Shape &s) { return (s.C + kColGroups - 1) / kColGroups; }
 
 // Phase one: the group's A and B totals (low and high halves) into ctot.
-MF_HD void table_colsum_item(const Shape &s, const TileMem &m, int32_t p, int32_t w, int32_t g, int32_t Cp)
+MF_HD void table_colsum_item(const Shape &s, const TileMem &m, int32_t p, int32_t w, int32_t g)
 {
     const int32_t stride = s.Wrow, R = col_rows(s);
     const u16 *col = cnt_row(s, m, p, 0) + w;
-    const int32_t c0 = g * R, c1 = (c0 + R < Cp) ? c0 + R : Cp;
+    const int32_t c0 = g * R, c1 = (c0 + R < s.C) ? c0 + R : s.C;
     u32 tot = 0u;
     for (int32_t c = c0; c < c1; c++) {
         const u32 v = col[c * stride];
@@ -1368,11 +1375,11 @@ MF_HD void table_colsum_item(const Shape &s, const TileMem &m, int32_t p, int32_
 
 // Phase two: A suffix sums and B exclusive prefix sums down the group,
 // starting from the totals of the other groups.
-MF_HD void table_colapply_item(const Shape &s, const TileMem &m, int32_t p, int32_t w, int32_t g, int32_t Cp)
+MF_HD void table_colapply_item(const Shape &s, const TileMem &m, int32_t p, int32_t w, int32_t g)
 {
     const int32_t stride = s.Wrow, R = col_rows(s);
     u16 *col = cnt_row(s, m, p, 0) + w;
-    const int32_t c0 = g * R, c1 = (c0 + R < Cp) ? c0 + R : Cp;
+    const int32_t c0 = g * R, c1 = (c0 + R < s.C) ? c0 + R : s.C;
     if (c0 >= c1) return;
     const u32 *gt = m.ctot + p * kColGroups * s.Wn + w;
     u32 sa = 0u, pb = 0u;
@@ -1600,7 +1607,7 @@ MF_HD void tail_table_hist(const Shape &s, const Tile &T, const TileMem &m, int3
     for (int32_t it = tid; it < T.P * per; it += NT) {
         const int32_t p = (int32_t)udiv16((u32)it, perr), r = it - p * per;
         const int32_t lenB = block_len(s, T, p + 1);
-        if (r < s.k + lenB) table_hist_item(s, m, p, r, Lr, pair_chunks(s, T, p));
+        if (r < s.k + lenB) table_hist_item(s, m, p, r, Lr);
     }
 }
 
@@ -1624,7 +1631,6 @@ MF_HD void tail_table_hist_rows(const Shape &s, const Tile &T, const TileMem &m,
     const u32 Cr = recip32(s.C);
     for (int32_t it = wave; it < T.P * s.C; it += nwaves) {
         const int32_t p = (int32_t)udiv16((u32)it, Cr), c = it - p * s.C;
-        if (c >= pair_chunks(s, T, p)) continue;
         for (int32_t d = lane; d < nd; d += nl) rb[d] = 0u;
         wave_sync();
         table_hist_row(s, T, m, p, c, rb, lane, nl);
@@ -1642,7 +1648,7 @@ MF_HD void tail_table_colsums(const Shape &s, const Tile &T, const TileMem &m, i
     for (int32_t it = tid; it < T.P * s.Wn * kColGroups; it += NT) {
         const int32_t pg = (int32_t)udiv16((u32)it, Wr), w = it - pg * s.Wn;
         const int32_t p = pg / kColGroups, g = pg % kColGroups;
-        table_colsum_item(s, m, p, w, g, pair_chunks(s, T, p));
+        table_colsum_item(s, m, p, w, g);
     }
 }
 
@@ -1653,7 +1659,7 @@ MF_HD void tail_table_colapply(const Shape &s, const Tile &T, const TileMem &m, 
     for (int32_t it = tid; it < T.P * s.Wn * kColGroups; it += NT) {
         const int32_t pg = (int32_t)udiv16((u32)it, Wr), w = it - pg * s.Wn;
         const int32_t p = pg / kColGroups, g = pg % kColGroups;
-        table_colapply_item(s, m, p, w, g, pair_chunks(s, T, p));
+        table_colapply_item(s, m, p, w, g);
     }
 }
 
