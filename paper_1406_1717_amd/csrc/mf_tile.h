@@ -1554,8 +1554,10 @@ MF_HD int walk_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, 
         const int32_t da = pa - base, db = pb - base;
         W ^= ((u32)da < 64u) ? (1ull << (da & 63)) : 0ull;
         W ^= ((u32)db < 64u) ? (1ull << (db & 63)) : 0ull;
-        const int32_t ltA = (int32_t)(pa < r), ltB = (int32_t)(pb < r);
-        const int32_t dir = (pa == r) ? 1 - 2 * ltB : ltA - ltB;
+        // +1: the median moves to the next member up, -1: down, 0: stays
+        // (when A[i] was the median itself, ltA is 0 and dir is 1 - 2 ltB)
+        const int32_t ltA = (int32_t)(pa < r), ltB = (int32_t)(pb < r), eq = (int32_t)(pa == r);
+        const int32_t dir = ltA - ltB + (eq & (1 - ltB));
         const int32_t rel = r - base;
         const u64 up = W & (~1ull << rel);
         const u64 dn = W & ((1ull << rel) - 1ull);
