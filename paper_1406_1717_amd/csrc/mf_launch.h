@@ -66,7 +66,7 @@ static const int kGlobalLds = 128 * 1024;
 static const int kBwdThreads = 256;
 static const int kBwdTargetsPerWave = 1024;
 static const int kBwdTargetsPerBlock = kBwdTargetsPerWave * (kBwdThreads / 64);
-static const int kBwdGroup = 8;   // candidate batches whose loads are issued together
+static const int kBwdGroup = 4;   // candidate batches whose loads are issued together
 
 // Which kernel family serves window k.
 Path path_for(int32_t k);
