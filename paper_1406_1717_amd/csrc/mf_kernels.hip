@@ -118,6 +118,8 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
 {
     const int tid = threadIdx.x;
     if (!merged) {
+        tail_pair_pad(s, T, m, tid, NT);
+        __syncthreads();
         tail_pair_merge(s, T, m, tid, NT, d.x, (u32 *)d.y, d.argmed);
         __syncthreads();
         // the median before each pair's first step is A's median: remember

@@ -1246,7 +1246,22 @@ MF_HD void presort_place(const Shape &s, const TileMem &m, const u64 (&v)[kRegs]
 // ---------------------------------------------------------------- 3. pair merge
 
 
-MF_HD int32_t merge_items_per_pair(const Shape &s) { return (s.Mstride + s.seg - 1) / s.seg; }
+MF_HD int32_t merge_items_per_pair(const Shape &s) { return (2 * s.k + s.seg - 1) / s.seg; }
+
+// 16-byte stores of merged-order padding per pair: every 32-position group
+// from the one holding the pair's last position on (the merge then writes
+// the group's real entries).
+MF_HD int32_t pad_items_per_pair(const Shape &s) { return (s.Mstride - (((s.k + 1) >> 5) << 5)) / 8; }
+
+// Item = (pair p, store q) of the padding.
+MF_HD void pair_pad_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, int32_t q)
+{
+    const int32_t mlen = s.k + block_len(s, T, p + 1);
+    const int32_t r0 = s.Mstride - 8 * (pad_items_per_pair(s) - q);
+    if (r0 < ((mlen >> 5) << 5)) return;
+    const uint4 pad = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    *(uint4 *)(m.M + p * s.Mstride + r0) = pad;
+}
 
 // Item = (pair p, segment g): merged positions [g*seg, (g+1)*seg) of pair p, by
 // merge path over the sorted blocks A = p and B = p + 1 (A first on equal
@@ -1261,11 +1276,7 @@ MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
     u16 *Mp = m.M + p * s.Mstride;
     u16 *pos = (u16 *)(m.pos + p * s.Pstride);
     const int32_t d = g * s.seg;
-    if (d >= mlen) {   // padding of the merged order
-        for (int q = 0; q < s.seg; q++)
-            if (d + q < s.Mstride) Mp[mslot(d + q)] = (u16)kMPad;
-        return;
-    }
+    if (d >= mlen) return;   // the padding is written by pair_pad_item
     int32_t lo = d > lenB ? d - lenB : 0;
     int32_t hi = d < lenA ? d : lenA;
     while (lo < hi) {
@@ -1278,10 +1289,7 @@ MF_HD void pair_merge_item(const Shape &s, const Tile &T, const TileMem &m,
     u64 va = a < lenA ? sorted_kt(s, m, A + a) : 0ull, vb = b < lenB ? sorted_kt(s, m, B + b) : 0ull;
     for (int q = 0; q < s.seg; q++) {
         const int32_t r = d + q;
-        if (r >= mlen) {
-            if (r < s.Mstride) Mp[mslot(r)] = (u16)kMPad;
-            continue;
-        }
+        if (r >= mlen) break;
         const bool takeA = a < lenA && (b >= lenB || sv_key(va) <= sv_key(vb));
         const u32 t = sv_t(takeA ? va : vb);
         Mp[mslot(r)] = (u16)(takeA ? t : (0x8000u | t));
@@ -1789,6 +1797,16 @@ MF_HD void output_first(const Shape &s, const Tile &T, const TileMem &m, const u
 }
 
 // Thread tid's share of the pair orders (phase 3) and output 0.
+MF_HD void tail_pair_pad(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
+{
+    const int32_t ipp = pad_items_per_pair(s);
+    const u32 ir = recip32(ipp);
+    for (int32_t it = tid; it < T.P * ipp; it += NT) {
+        const int32_t p = (int32_t)udiv16((u32)it, ir);
+        pair_pad_item(s, T, m, p, it - p * ipp);
+    }
+}
+
 MF_HD void tail_pair_merge(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT,
                            const u32 *x, u32 *y, int32_t *argmed)
 {

@@ -228,6 +228,7 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         }
         for (int q = 0; q < threads; q++) tile_mpad(s, T, m, q, threads);
     } else {
+        for (int q = 0; q < threads; q++) tail_pair_pad(s, T, m, q, threads);
         for (int q = 0; q < threads; q++) tail_pair_merge(s, T, m, q, threads, x, y, argmed);
         for (int q = 0; q < threads; q++) tail_first_medians(s, T, m, q, threads);
     }
