@@ -192,6 +192,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
     // (heavy ties across the tile), sort block by block and merge each pair
     const Shape st = tile_order_shape(s);
     bool tord = tile_order_ok(s);
+    const int32_t per = tile_buckets(s) / NT;   // counters per thread
 
     // 1. load into registers
     u64 v[kRegs];
@@ -204,14 +205,14 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
     // every thread).
     // Presorted tiles (flag bit 2 clear after the key-range pass) skip the
     // bucket sort.
-    bucket_zero_thread(m, tid);
+    bucket_zero_thread(m, tid, per);
     for (int b = tid; b < l.nbmax; b += NT) bucket_info_init(m, b);
     presort_note(s, m, tid, v);
     __syncthreads();
     bool fast = s.S >= kRegs;
     bool direct = false;   // items already in sort order
     int pass = 0;          // bucket map: 0 linear, 1 clamped logarithmic
-    u32 arr[kRegs], bkt[kRegs];
+    u32 arr[kRegs];   // arrival numbers (tile order: packed with the bucket)
     if (tord) {
         tile_minmax(m, v);
         presort_check(s, T, m, tid, NT, v, true);
@@ -227,15 +228,15 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
         }
     }
     if (tord && !direct) {
-        tile_count<F32>(st, m, v, arr, bkt, pass);
+        tile_count<F32>(st, m, v, arr, pass);
         __syncthreads();
         if ((m.flag[0] & 3u) != 0u) {
             __syncthreads();
             pass = 1;
-            bucket_zero_thread(m, tid);
+            bucket_zero_thread(m, tid, per);
             if (tid == 0) m.flag[0] = 0u;
             __syncthreads();
-            tile_count<F32>(st, m, v, arr, bkt, pass);
+            tile_count<F32>(st, m, v, arr, pass);
             __syncthreads();
         }
         if ((m.flag[0] & 1u) != 0u) {
@@ -243,12 +244,13 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
             tord = false;
             pass = 0;
             tile_to_block_values(s, T, tid, v);
-            bucket_zero_thread(m, tid);
+            bucket_zero_thread(m, tid, per);
             for (int b = tid; b < l.nbmax; b += NT) bucket_info_init(m, b);
             presort_note(s, m, tid, v);
             __syncthreads();
         }
     }
+    if (!tord && compact_tile(s)) fast = false;   // block order needs cap counters
     if (fast && !tord) {
         bucket_minmax(m, v);
         presort_check(s, T, m, tid, NT, v, false);
@@ -260,7 +262,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
             if ((m.flag[0] & 3u) != 0u) {
                 __syncthreads();
                 pass = 1;
-                bucket_zero_thread(m, tid);
+                bucket_zero_thread(m, tid, per);
                 if (tid == 0) m.flag[0] = 0u;
                 __syncthreads();
                 bucket_count<F32>(s, T, m, tid, v, arr, pass);
@@ -277,15 +279,15 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
             __syncthreads();
         } else {
             u32 c[kRegs];
-            const u32 tot = bucket_scan_local(m, tid, c);
-            const u32 excl = seg_excl_scan<NT>(tot, (tord ? st.S : s.S) / kRegs, wave_tot);
-            bucket_scan_store(m, tid, excl, c);
+            const u32 tot = bucket_scan_local(m, tid, c, per);
+            const u32 excl = seg_excl_scan<NT>(tot, tord ? NT : s.S / kRegs, wave_tot);
+            bucket_scan_store(m, tid, excl, c, per);
             __syncthreads();
-            if (tord) tile_scatter(m, v, arr, bkt);
+            if (tord) tile_scatter(m, v, arr);
             else bucket_scatter<F32>(s, T, m, tid, v, arr, pass);
             __syncthreads();
             u32 fin[kRegs];
-            if (tord) tile_rank(st, m, v, N, fin, bkt);
+            if (tord) tile_rank(st, m, v, N, fin, arr);
             else bucket_rank<F32>(s, T, m, tid, v, fin, pass);
             __syncthreads();
             if (tord) tile_place(m, v, fin);
@@ -329,7 +331,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
 // One workgroup per work unit.  512-thread tiles of at most 53 KB run three
 // workgroups per CU, which needs at most 80 VGPRs (six waves per SIMD).
 template <int NT, bool F32>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 6 : 4))) void k_tile_lds(Launch L, int *err)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 6 : 8))) void k_tile_lds(Launch L, int *err)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const Resolved d = unit_of(L, blockIdx.x);

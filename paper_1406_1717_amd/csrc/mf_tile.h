@@ -294,6 +294,14 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
     return 0;
 }
 
+// Tiles of one pair with 1024 threads (cap >= 8192 slots, two blocks of
+// 2048 < k <= 4096) keep their LDS near 80 KB, so that (up to k of about
+// 3900) two workgroups share a CU: the tile order counts into cap/2 buckets
+// placed right after the scattered values (2k of them), and block order,
+// which needs cap counters, is not used (such tiles take the merge sort).
+MF_HD bool compact_tile(const Shape &s) { return s.cap >= 8192 && s.Pmax == 1; }
+MF_HD int32_t tile_buckets(const Shape &s) { return compact_tile(s) ? s.cap / 2 : s.cap; }
+
 MF_HD void make_layout(const Shape &s, Layout *l)
 {
     int32_t off = 0;
@@ -306,9 +314,11 @@ MF_HD void make_layout(const Shape &s, Layout *l)
     off = (off + 15) & ~15;
     l->pos = off;    off += 4 * s.Pmax * s.Pstride;
     off = (off + 15) & ~15;
-    // bucket sort scratch, used before the pair orders are written
-    l->bk = 8 * s.cap;
-    l->info = l->bk + 4 * s.cap;
+    // bucket sort scratch, used before the pair orders are written: after the
+    // 64-bit scatter buffer (slot-indexed in block order, at most 2k values in
+    // the tile order of a compact tile)
+    l->bk = compact_tile(s) ? ((16 * s.k + 15) & ~15) : 8 * s.cap;
+    l->info = l->bk + 4 * tile_buckets(s);
     l->nbmax = s.Pmax + 1;
     const int32_t bend = l->info + 4 * (2 * (s.Pmax + 1) + 1);
     if (off < bend) off = (bend + 15) & ~15;
@@ -640,13 +650,13 @@ MF_HD void put_block_value(const Shape &s, const TileMem &m, int32_t q, u64 v)
 // Item = one of the tile's cap counters, or block info entry b < nbmax.
 MF_HD void bucket_zero_item(const TileMem &m, int32_t e) { m.bk[e] = 0u; }
 
-// The kRegs consecutive counters of thread tid (cap = threads * kRegs).
-MF_HD void bucket_zero_thread(const TileMem &m, int32_t tid)
+// Thread tid's `per` consecutive counters (per = 8, or 4 in a compact
+// tile: tile_buckets / threads).
+MF_HD void bucket_zero_thread(const TileMem &m, int32_t tid, int32_t per)
 {
-    uint4 *p = (uint4 *)(m.bk + tid * kRegs);
+    uint4 *p = (uint4 *)(m.bk + tid * per);
     const uint4 z = {0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int j = 0; j < kRegs / 4; j++) p[j] = z;
+    for (int j = 0; j < per / 4; j++) p[j] = z;
 }
 MF_HD void bucket_info_init(const TileMem &m, int32_t b)
 {
@@ -788,14 +798,14 @@ MF_HD void bucket_count(const Shape &s, const Tile &T, const TileMem &m, int32_t
 }
 
 // Per thread: the local part of the bucket scan.  Thread tid owns counters
-// [tid*kRegs, tid*kRegs + kRegs) (one block); on return c holds their
-// exclusive prefix within the thread and the thread total is returned.
-MF_HD u32 bucket_scan_local(const TileMem &m, int32_t tid, u32 (&c)[kRegs])
+// [tid*per, tid*per + per) (per = 8, or 4 in a compact tile); on return c
+// holds their exclusive prefix within the thread and the thread total is
+// returned.
+MF_HD u32 bucket_scan_local(const TileMem &m, int32_t tid, u32 (&c)[kRegs], int32_t per)
 {
-    const uint4 *src = (const uint4 *)(m.bk + tid * kRegs);
+    const uint4 *src = (const uint4 *)(m.bk + tid * per);
     u32 acc = 0u;
-#pragma unroll
-    for (int g = 0; g < kRegs / 4; g++) {
+    for (int g = 0; g < per / 4; g++) {
         const uint4 q = src[g];
         c[4 * g + 0] = acc; acc += q.x;
         c[4 * g + 1] = acc; acc += q.y;
@@ -807,11 +817,10 @@ MF_HD u32 bucket_scan_local(const TileMem &m, int32_t tid, u32 (&c)[kRegs])
 
 // Per thread: bucket starts = prefix of earlier threads of the block (excl)
 // plus the local prefix.
-MF_HD void bucket_scan_store(const TileMem &m, int32_t tid, u32 excl, const u32 (&c)[kRegs])
+MF_HD void bucket_scan_store(const TileMem &m, int32_t tid, u32 excl, const u32 (&c)[kRegs], int32_t per)
 {
-    uint4 *dst = (uint4 *)(m.bk + tid * kRegs);
-#pragma unroll
-    for (int g = 0; g < kRegs / 4; g++) {
+    uint4 *dst = (uint4 *)(m.bk + tid * per);
+    for (int g = 0; g < per / 4; g++) {
         uint4 q;
         q.x = excl + c[4 * g + 0];
         q.y = excl + c[4 * g + 1];
@@ -941,13 +950,13 @@ MF_HD bool tile_order_ok(const Shape &s) { return s.Pmax + 1 <= kTileOrderBlocks
 MF_HD u32 tv_key(u64 v) { return (u32)(v >> 32); }
 MF_HD u32 tv_slot(u64 v) { return (u32)(v & 0xFFFFu); }
 
-// The bucket sort's shape for the tile-wide segment.
+// The bucket sort's shape for the tile-wide segment (tile_buckets buckets).
 MF_HD Shape tile_order_shape(const Shape &s)
 {
     Shape st = s;
-    st.S = s.cap;
+    st.S = tile_buckets(s);
     int32_t l = 0;
-    while ((1 << l) < s.cap) l++;
+    while ((1 << l) < st.S) l++;
     st.logS = l;
     return st;
 }
@@ -1033,38 +1042,38 @@ MF_HD bool tile_many_ties(const TileMem &m, int32_t N)
     return (u64)range * 4u < (u64)N;
 }
 
-// Per thread: arrival numbers in the tile's buckets (st = tile_order_shape),
-// and the buckets themselves (for scatter and rank).
+// Per thread: each item's bucket and arrival number in it (st =
+// tile_order_shape), packed as bucket << 8 | arrival (arrivals stay below
+// kBucketMax, or the tile leaves the tile order), for scatter and rank.
 template <bool F32>
-MF_HD void tile_count(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], u32 (&arr)[kRegs],
-                      u32 (&bkt)[kRegs], int pass)
+MF_HD void tile_count(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], u32 (&ab)[kRegs], int pass)
 {
     const BucketFn f = bucket_fn<F32>(st, m, 0, pass);
     u32 mx = 0u;
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
-        arr[j] = 0u;
-        bkt[j] = 0u;
+        ab[j] = 0u;
         if (sv_valid(v[j])) {
-            bkt[j] = bucket_of<F32>(f, tv_key(v[j]));
-            arr[j] = MF_ADDRTN32(m.bk + bkt[j], 1u);
-            mx = arr[j] > mx ? arr[j] : mx;
+            const u32 bk = bucket_of<F32>(f, tv_key(v[j]));
+            const u32 a = MF_ADDRTN32(m.bk + bk, 1u);
+            mx = a > mx ? a : mx;
+            ab[j] = (bk << 8) | (a & 0xFFu);
         }
     }
     if (mx >= (u32)kBucketSoft) MF_OR32(m.flag, mx >= (u32)kBucketMax ? 3u : 2u);
 }
 
-MF_HD void tile_scatter(const TileMem &m, const u64 (&v)[kRegs], const u32 (&arr)[kRegs], const u32 (&bkt)[kRegs])
+MF_HD void tile_scatter(const TileMem &m, const u64 (&v)[kRegs], const u32 (&ab)[kRegs])
 {
 #pragma unroll
     for (int j = 0; j < kRegs; j++)
-        if (sv_valid(v[j])) m.mbuf[m.bk[bkt[j]] + arr[j]] = v[j];
+        if (sv_valid(v[j])) m.mbuf[m.bk[ab[j] >> 8] + (ab[j] & 0xFFu)] = v[j];
 }
 
 // Per thread: sorted position = bucket start + rank by the full value among
 // the bucket's items (as in bucket_rank).  N: valid items.
 MF_HD void tile_rank(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], int32_t N, u32 (&fin)[kRegs],
-                     const u32 (&bkt)[kRegs])
+                     const u32 (&ab)[kRegs])
 {
     u32 x[kRegs], hi[kRegs];
 #pragma unroll
@@ -1072,7 +1081,7 @@ MF_HD void tile_rank(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], i
         x[j] = 0u;
         hi[j] = 0u;
         if (sv_valid(v[j])) {
-            const u32 bk = bkt[j];
+            const u32 bk = ab[j] >> 8;
             x[j] = m.bk[bk];
             hi[j] = (bk + 1u < (u32)st.S) ? m.bk[bk + 1] : (u32)N;
         }

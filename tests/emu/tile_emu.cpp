@@ -32,6 +32,7 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
     TileMem m = tile_mem(lds.data(), l);
     bool tord = tile_order_ok(s);
     const Shape st = tile_order_shape(s);
+    const int per = tile_buckets(s) / threads;   // counters per thread
 
     std::vector<u64> regs((size_t)threads * kRegs), tmp((size_t)threads * kRegs);
     for (int q = 0; q < threads; q++) {
@@ -44,17 +45,16 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
     }
     auto V = [&](int q, u64 (&v)[kRegs]) { for (int j = 0; j < kRegs; j++) v[j] = regs[(size_t)q * kRegs + j]; };
     int pass = 0;
-    std::vector<u32> bkts((size_t)threads * kRegs);
     auto count = [&](std::vector<u32> &arr) {
         for (int q = 0; q < threads; q++) {
-            u64 v[kRegs]; V(q, v); u32 a[kRegs], bk[kRegs];
-            if (tord) tile_count<F32>(st, m, v, a, bk, pass);
-            else { bucket_count<F32>(s, T, m, q, v, a, pass); for (int j = 0; j < kRegs; j++) bk[j] = 0; }
-            for (int j = 0; j < kRegs; j++) { arr[(size_t)q * kRegs + j] = a[j]; bkts[(size_t)q * kRegs + j] = bk[j]; }
+            u64 v[kRegs]; V(q, v); u32 a[kRegs];
+            if (tord) tile_count<F32>(st, m, v, a, pass);
+            else bucket_count<F32>(s, T, m, q, v, a, pass);
+            for (int j = 0; j < kRegs; j++) arr[(size_t)q * kRegs + j] = a[j];
         }
     };
     // bucket path
-    for (int q = 0; q < threads; q++) bucket_zero_thread(m, q);
+    for (int q = 0; q < threads; q++) bucket_zero_thread(m, q, per);
     for (int b = 0; b < l.nbmax; b++) bucket_info_init(m, b);
     auto note = [&]() { for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); presort_note(s, m, q, v); } };
     auto to_block = [&]() {
@@ -74,7 +74,7 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         count(arr);
         if ((m.flag[0] & 3u) != 0u) {
             g_recount_tiles++;
-            for (int q = 0; q < threads; q++) bucket_zero_thread(m, q);
+            for (int q = 0; q < threads; q++) bucket_zero_thread(m, q, per);
             pass = 1;
             m.flag[0] = 0u;
             count(arr);
@@ -97,11 +97,12 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
             tord = false;
             pass = 0;
             to_block();
-            for (int q = 0; q < threads; q++) bucket_zero_thread(m, q);
+            for (int q = 0; q < threads; q++) bucket_zero_thread(m, q, per);
             for (int b = 0; b < l.nbmax; b++) bucket_info_init(m, b);
             note();
         }
     }
+    if (!tord && compact_tile(s)) fast = false;   // block order needs cap counters
     if (fast && !tord) {
         for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); bucket_minmax(m, v); }
         for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); presort_check(s, T, m, q, threads, v, false); }
@@ -141,12 +142,12 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         if (rc) return rc;
         g_fast_tiles++;
     } else if (fast) {
-        const int G = (tord ? st.S : s.S) / kRegs;
+        const int G = tord ? threads : s.S / kRegs;
         std::vector<u32> tot(threads);
         std::vector<std::vector<u32>> cl(threads, std::vector<u32>(kRegs));
         for (int q = 0; q < threads; q++) {
             u32 c[kRegs];
-            tot[q] = bucket_scan_local(m, q, c);
+            tot[q] = bucket_scan_local(m, q, c, per);
             for (int j = 0; j < kRegs; j++) cl[q][j] = c[j];
         }
         for (int q = 0; q < threads; q++) {
@@ -154,21 +155,18 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
             for (int r = q & ~(G - 1); r < q; r++) excl += tot[r];
             u32 c[kRegs];
             for (int j = 0; j < kRegs; j++) c[j] = cl[q][j];
-            bucket_scan_store(m, q, excl, c);
+            bucket_scan_store(m, q, excl, c, per);
         }
         for (int q = 0; q < threads; q++) {
             u64 v[kRegs]; V(q, v); u32 a[kRegs];
             for (int j = 0; j < kRegs; j++) a[j] = arr[(size_t)q * kRegs + j];
-            u32 bk[kRegs];
-            for (int j = 0; j < kRegs; j++) bk[j] = bkts[(size_t)q * kRegs + j];
-            if (tord) tile_scatter(m, v, a, bk);
+            if (tord) tile_scatter(m, v, a);
             else bucket_scatter<F32>(s, T, m, q, v, a, pass);
         }
         for (int q = 0; q < threads; q++) {
-            u64 v[kRegs]; V(q, v); u32 f[kRegs];
-            u32 bk[kRegs];
-            for (int j = 0; j < kRegs; j++) bk[j] = bkts[(size_t)q * kRegs + j];
-            if (tord) tile_rank(st, m, v, N, f, bk);
+            u64 v[kRegs]; V(q, v); u32 f[kRegs], a[kRegs];
+            for (int j = 0; j < kRegs; j++) a[j] = arr[(size_t)q * kRegs + j];
+            if (tord) tile_rank(st, m, v, N, f, a);
             else bucket_rank<F32>(s, T, m, q, v, f, pass);
             for (int j = 0; j < kRegs; j++) fin[(size_t)q * kRegs + j] = f[j];
         }
