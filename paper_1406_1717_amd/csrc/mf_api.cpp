@@ -60,7 +60,6 @@ struct Device {
 
 const int kMaxDevices = 64;
 Device g_dev[kMaxDevices];
-const int64_t kWsSlots = 256;           // concurrent tiles on the global path
 
 mf_status device_state(Device **out)
 {
@@ -150,7 +149,7 @@ mf_status forward_rows(const void *x, int64_t rows, int64_t n, int32_t k, void *
     const size_t lds = (size_t)lds_bytes_for(p, k);
     if (p == PATH_GLOBAL) {
         const int64_t stride = global_ws_stride(k);
-        const int64_t slots = std::min<int64_t>(kWsSlots, L.nunits);
+        const int64_t slots = std::min<int64_t>(global_ws_slots(lds), L.nunits);
         unsigned char *ws = nullptr;
         if ((s = acquire_ws(*D, stride * slots, st, &ws)) != MF_OK) return s;
         MF_HIP(launch_forward(p, f32, L, lds, ws, stride, slots, D->d_err, st), "forward launch");
@@ -257,7 +256,7 @@ static mf_status plan_add_group(mf_plan *p, int cfg, Path f, bool persistent, co
         if (g.d_units) (void)hipFree(g.d_units);
         return hip_fail(e, "plan work list");
     }
-    if (f == PATH_GLOBAL) p->ws_need = std::max(p->ws_need, ws_stride * std::min<int64_t>(kWsSlots, g.nunits));
+    if (f == PATH_GLOBAL) p->ws_need = std::max(p->ws_need, ws_stride * std::min<int64_t>(global_ws_slots(lds), g.nunits));
     p->groups[cfg].push_back(g);
     return MF_OK;
 }
@@ -381,7 +380,7 @@ static mf_status plan_enqueue(mf_plan *p, Device &D, const void *x, void *y, int
                    "batched persistent launch");
             continue;
         }
-        const int64_t slots = std::min<int64_t>(kWsSlots, g.nunits);
+        const int64_t slots = std::min<int64_t>(global_ws_slots(g.lds), g.nunits);
         MF_HIP(launch_forward(g.path, f32, L, g.lds, ws, g.ws_stride, slots, D.d_err, st), "batched launch");
     }
     return MF_OK;

@@ -624,9 +624,11 @@ __device__ bool global_pair_bucket(const Shape &s, const Tile &T, const TileMem 
     return true;
 }
 
-template <bool F32>
-__global__ __launch_bounds__(kGlobalThreads) void k_tile_global(Launch L, unsigned char *ws,
-                                                                int64_t ws_stride, int *err)
+// TWO: tiles of k <= 16383 (64 KB of LDS), compiled for two workgroups per
+// CU (at most 64 VGPRs).
+template <bool F32, bool TWO>
+__global__ __launch_bounds__(kGlobalThreads) __attribute__((amdgpu_waves_per_eu(TWO ? 8 : 4)))
+void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ u32 gsh[3];
@@ -871,9 +873,18 @@ int64_t lds_bytes_for(Path p, int32_t k)
     switch (p) {
     case PATH_LDS_SMALL: make_shape(1ll << 20, k, kLdsSmall, &s); make_layout(s, &l); return l.total;
     case PATH_LDS_LARGE: make_shape(1ll << 20, k, kLdsLarge, &s); make_layout(s, &l); return l.total;
-    case PATH_GLOBAL: return kGlobalLds;
+    case PATH_GLOBAL: {
+        int32_t S = 1;
+        while (S < k) S <<= 1;
+        return S <= 16384 ? kGlobalLdsSmall : kGlobalLdsLarge;
+    }
     default: return 0;
     }
+}
+
+int64_t global_ws_slots(size_t lds_bytes)
+{
+    return lds_bytes <= (size_t)kGlobalLdsSmall ? 512 : 256;
 }
 
 int64_t global_ws_stride(int32_t k)
@@ -900,8 +911,10 @@ hipError_t prepare_kernels()
     MF_ATTR((k_tile_lds_persistent<kLdsLarge, true>))
     MF_ATTR((k_tile_lds_persistent<kLdsSmall, false>))
     MF_ATTR((k_tile_lds_persistent<kLdsLarge, false>))
-    MF_ATTR((k_tile_global<true>))
-    MF_ATTR((k_tile_global<false>))
+    MF_ATTR((k_tile_global<true, false>))
+    MF_ATTR((k_tile_global<false, false>))
+    MF_ATTR((k_tile_global<true, true>))
+    MF_ATTR((k_tile_global<false, true>))
 #undef MF_ATTR
     return e;
 }
@@ -967,8 +980,14 @@ hipError_t launch_forward(Path p, bool f32, const Launch &L, size_t lds_bytes,
     }
     case PATH_GLOBAL: {
         const int64_t grid = L.nunits < ws_slots ? L.nunits : ws_slots;
-        if (f32) hipLaunchKernelGGL((k_tile_global<true>), dim3((unsigned)grid), dim3(kGlobalThreads), lds_bytes, st, L, ws, ws_stride, d_err);
-        else     hipLaunchKernelGGL((k_tile_global<false>), dim3((unsigned)grid), dim3(kGlobalThreads), lds_bytes, st, L, ws, ws_stride, d_err);
+        const dim3 g((unsigned)grid), b(kGlobalThreads);
+        if (lds_bytes <= (size_t)kGlobalLdsSmall) {
+            if (f32) hipLaunchKernelGGL((k_tile_global<true, true>), g, b, lds_bytes, st, L, ws, ws_stride, d_err);
+            else     hipLaunchKernelGGL((k_tile_global<false, true>), g, b, lds_bytes, st, L, ws, ws_stride, d_err);
+        } else {
+            if (f32) hipLaunchKernelGGL((k_tile_global<true, false>), g, b, lds_bytes, st, L, ws, ws_stride, d_err);
+            else     hipLaunchKernelGGL((k_tile_global<false, false>), g, b, lds_bytes, st, L, ws, ws_stride, d_err);
+        }
         break;
     }
     default:

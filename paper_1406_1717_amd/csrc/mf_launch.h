@@ -61,8 +61,10 @@ static const int kLdsLarge = 1024;
 static const int kGlobalThreads = 1024;
 // Dynamic LDS of a global-memory tile: the sort buffer, then the bucket
 // counters (2S 16-bit cells), the histogram row buffers and the copy of the
-// merged order (2 Mstride bytes); at most 128 KB for k <= 32767.
-static const int kGlobalLds = 128 * 1024;
+// merged order (2 Mstride bytes): 64 KB up to k = 16383 (two workgroups per
+// CU), 128 KB above.
+static const int kGlobalLdsSmall = 64 * 1024;
+static const int kGlobalLdsLarge = 128 * 1024;
 static const int kBwdThreads = 256;
 static const int kBwdTargetsPerWave = 1024;
 static const int kBwdTargetsPerBlock = kBwdTargetsPerWave * (kBwdThreads / 64);
@@ -75,6 +77,9 @@ int64_t tiles_for(Path p, int64_t n, int32_t k);
 int64_t lds_bytes_for(Path p, int32_t k);
 // Global workspace bytes of one workgroup on the global path.
 int64_t global_ws_stride(int32_t k);
+// Workspace slots (concurrent tiles) of a global-path launch with this much
+// dynamic LDS: two tiles per CU with 64 KB, one with 128 KB.
+int64_t global_ws_slots(size_t lds_bytes);
 
 hipError_t launch_forward(Path p, bool f32, const Launch &L, size_t lds_bytes,
                           unsigned char *ws, int64_t ws_stride, int64_t ws_slots,
