@@ -647,9 +647,6 @@ MF_HD void put_block_value(const Shape &s, const TileMem &m, int32_t q, u64 v)
     put_sorted(m, q, sv_key(v), ((u32)sv_block(v) << s.logS) | sv_t(v));
 }
 
-// Item = one of the tile's cap counters, or block info entry b < nbmax.
-MF_HD void bucket_zero_item(const TileMem &m, int32_t e) { m.bk[e] = 0u; }
-
 // Thread tid's `per` consecutive counters (per = 8, or 4 in a compact
 // tile: tile_buckets / threads).
 MF_HD void bucket_zero_thread(const TileMem &m, int32_t tid, int32_t per)
@@ -658,6 +655,7 @@ MF_HD void bucket_zero_thread(const TileMem &m, int32_t tid, int32_t per)
     const uint4 z = {0u, 0u, 0u, 0u};
     for (int j = 0; j < per / 4; j++) p[j] = z;
 }
+// Block info entry b < nbmax.
 MF_HD void bucket_info_init(const TileMem &m, int32_t b)
 {
     m.bmin[b] = 0xFFFFFFFFu;
