@@ -270,12 +270,23 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
     if (seg < 9) seg = 9;
     s->seg = seg | 1;
     // chunk length: odd (lanes walking neighbouring chunks then read the
-    // position maps on distinct LDS banks), at least 15, large enough that
+    // position maps on distinct LDS banks), at least 11, large enough that
     // the tile has no more chunks than threads and that the count tables,
     // their column-group totals and the staged medians of all pairs fit in
     // the sort buffer they reuse.  Windows up to 31 walk a pair in one chunk:
-    // the count tables cost more than the longer walk saves.
+    // the count tables cost more than the longer walk saves.  Below 1000 the
+    // table rows are narrow and the walk sets the pace: its steps are serial
+    // per lane, so shorter chunks pay until the 64 further chunks that add a
+    // wave to the walk (and to the tables) cost about two steps.
     int32_t L = 15;
+    if (k < 1000) {
+        int32_t best = 1 << 30;
+        for (int32_t l = 15; l >= 11; l -= 2) {
+            const u32 c = (uk + (u32)l - 1u) / (u32)l;
+            const int32_t cost = l + 2 * (int32_t)(((u32)P * c + 63u) >> 6);
+            if (cost < best) { best = cost; L = l; }
+        }
+    }
     const int32_t per_thread = (int32_t)(((u32)P * uk + ut - 1u) / ut);
     if (L < per_thread) L = per_thread | 1;
     if (k <= kOneChunkMax) L = k;
