@@ -5,7 +5,8 @@ benchmark's CPU-baseline leg are the only callers; the product library
 never imports, links or runs anything in this package.  It shares no code
 with the HIP path.
 
-Functions (all on numpy arrays, single-threaded C underneath):
+Functions (all on numpy arrays of float32, int32, float64 or int64,
+single-threaded C underneath):
 
   sortmedian(x, k)            the paper's method: piecewise stable sort,
                               block data structure on dancing links and the
@@ -49,11 +50,13 @@ def _lib():
         P = ctypes.c_void_p
         I64 = ctypes.c_int64
         I32 = ctypes.c_int32
-        for name in ("oracle_sortmedian_f32", "oracle_sortmedian_i32"):
+        for name in ("oracle_sortmedian_f32", "oracle_sortmedian_i32",
+                     "oracle_sortmedian_f64", "oracle_sortmedian_i64"):
             f = getattr(lib, name)
             f.argtypes = [P, I64, I32, P, P]
             f.restype = ctypes.c_int
-        for name in ("oracle_window_median_f32", "oracle_window_median_i32"):
+        for name in ("oracle_window_median_f32", "oracle_window_median_i32",
+                     "oracle_window_median_f64", "oracle_window_median_i64"):
             f = getattr(lib, name)
             f.argtypes = [P, I64, I32, P, I64, P]
             f.restype = ctypes.c_int
@@ -78,7 +81,11 @@ def _as_signal(x):
         return x, "f32"
     if x.dtype == np.int32:
         return x, "i32"
-    raise TypeError("oracle supports float32 and int32 signals, got %s" % x.dtype)
+    if x.dtype == np.float64:
+        return x, "f64"
+    if x.dtype == np.int64:
+        return x, "i64"
+    raise TypeError("oracle supports float32, int32, float64 and int64 signals, got %s" % x.dtype)
 
 
 def sortmedian(x, k):

@@ -34,6 +34,8 @@
  *     real pair, so real +inf data cannot collide with it.
  *   - Float order: -0.0 equals +0.0 (IEEE equality, tie broken by index);
  *     every NaN is above +inf and all NaNs are equal (tie broken by index).
+ *   - 32-bit and 64-bit elements (Section 7 benchmarks both widths) follow
+ *     the same rules; signed integers compare as signed.
  *   - k must be odd with 1 <= k <= n.
  *
  * Backward (not in the paper): grad_x[j] = sum of grad_y[o] over all o with
@@ -49,23 +51,42 @@ enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2, OR_EINVARIANT = -3 };
 /* ---------------------------------------------------------------------- */
 /* Value order.  cmp returns <0, 0, >0.                                    */
 
+/* Element types: the paper benchmarks 32-bit and 64-bit versions
+ * (Section 7); the order rules are the same for both widths. */
+enum { T_I32 = 0, T_F32 = 1, T_I64 = 2, T_F64 = 3 };
+
 typedef struct {
     const void *x;       /* the whole signal */
-    int is_f32;          /* 1: float, 0: int32 */
+    int type;            /* T_I32, T_F32, T_I64 or T_F64 */
 } values_t;
 
 static int cmp_value(const values_t *v, int64_t a, int64_t b)
 {
-    if (v->is_f32) {
+    switch (v->type) {
+    case T_F32: {
         const float fa = ((const float *)v->x)[a];
         const float fb = ((const float *)v->x)[b];
         const int na = isnan(fa) != 0, nb = isnan(fb) != 0;
         if (na || nb) return na - nb;            /* NaN above all; NaNs tie */
         return (fa > fb) - (fa < fb);            /* -0.0 == +0.0 */
-    } else {
+    }
+    case T_F64: {
+        const double fa = ((const double *)v->x)[a];
+        const double fb = ((const double *)v->x)[b];
+        const int na = isnan(fa) != 0, nb = isnan(fb) != 0;
+        if (na || nb) return na - nb;
+        return (fa > fb) - (fa < fb);
+    }
+    case T_I64: {
+        const int64_t ia = ((const int64_t *)v->x)[a];
+        const int64_t ib = ((const int64_t *)v->x)[b];
+        return (ia > ib) - (ia < ib);
+    }
+    default: {
         const int32_t ia = ((const int32_t *)v->x)[a];
         const int32_t ib = ((const int32_t *)v->x)[b];
         return (ia > ib) - (ia < ib);
+    }
     }
 }
 
@@ -133,14 +154,28 @@ static int window_oracle(const values_t *v, int64_t n, int32_t k,
 int oracle_window_median_f32(const float *x, int64_t n, int32_t k,
                              const int64_t *outs, int64_t count, int32_t *argmed)
 {
-    values_t v = {x, 1};
+    values_t v = {x, T_F32};
     return window_oracle(&v, n, k, outs, count, argmed);
 }
 
 int oracle_window_median_i32(const int32_t *x, int64_t n, int32_t k,
                              const int64_t *outs, int64_t count, int32_t *argmed)
 {
-    values_t v = {x, 0};
+    values_t v = {x, T_I32};
+    return window_oracle(&v, n, k, outs, count, argmed);
+}
+
+int oracle_window_median_f64(const double *x, int64_t n, int32_t k,
+                             const int64_t *outs, int64_t count, int32_t *argmed)
+{
+    values_t v = {x, T_F64};
+    return window_oracle(&v, n, k, outs, count, argmed);
+}
+
+int oracle_window_median_i64(const int64_t *x, int64_t n, int32_t k,
+                             const int64_t *outs, int64_t count, int32_t *argmed)
+{
+    values_t v = {x, T_I64};
     return window_oracle(&v, n, k, outs, count, argmed);
 }
 
@@ -322,7 +357,7 @@ static int sortmedian(const values_t *v, int64_t n, int32_t k, int32_t *argmed)
 
 int oracle_sortmedian_f32(const float *x, int64_t n, int32_t k, float *y, int32_t *argmed)
 {
-    values_t v = {x, 1};
+    values_t v = {x, T_F32};
     const int rc = sortmedian(&v, n, k, argmed);
     if (rc != OR_OK) return rc;
     if (y)
@@ -332,7 +367,27 @@ int oracle_sortmedian_f32(const float *x, int64_t n, int32_t k, float *y, int32_
 
 int oracle_sortmedian_i32(const int32_t *x, int64_t n, int32_t k, int32_t *y, int32_t *argmed)
 {
-    values_t v = {x, 0};
+    values_t v = {x, T_I32};
+    const int rc = sortmedian(&v, n, k, argmed);
+    if (rc != OR_OK) return rc;
+    if (y)
+        for (int64_t o = 0; o + k <= n; o++) y[o] = x[argmed[o]];
+    return OR_OK;
+}
+
+int oracle_sortmedian_f64(const double *x, int64_t n, int32_t k, double *y, int32_t *argmed)
+{
+    values_t v = {x, T_F64};
+    const int rc = sortmedian(&v, n, k, argmed);
+    if (rc != OR_OK) return rc;
+    if (y)
+        for (int64_t o = 0; o + k <= n; o++) memcpy(&y[o], &x[argmed[o]], sizeof(double));
+    return OR_OK;
+}
+
+int oracle_sortmedian_i64(const int64_t *x, int64_t n, int32_t k, int64_t *y, int32_t *argmed)
+{
+    values_t v = {x, T_I64};
     const int rc = sortmedian(&v, n, k, argmed);
     if (rc != OR_OK) return rc;
     if (y)

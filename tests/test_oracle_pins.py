@@ -257,3 +257,125 @@ def test_planted_mistakes_are_caught(tmp_path, idx):
         if caught:
             break
     assert caught, "mutation %d survived the exhaustive pin" % idx
+
+
+# --- 64-bit signals (Section 7 benchmarks 32- and 64-bit versions) ---------
+
+@pytest.mark.parametrize("dtype", [np.int64, np.float64])
+def test_exhaustive_small_alphabet_64(dtype):
+    """Every vector over {0,1,2} of length 1..7, every odd k <= n."""
+    for n in range(1, 8):
+        vecs = np.array(list(itertools.product(range(3), repeat=n)), dtype=dtype)
+        for k in range(1, n + 1, 2):
+            for v in vecs:
+                want = rank_count_argmed(v, k)
+                y, a = oracle.sortmedian(v, k)
+                assert np.array_equal(a, want), (v, k, a, want)
+                assert _same_bits(y, v[want])
+
+
+def _special_vector_f64(rng, n):
+    # values that collide in float32 but not in float64, and the specials
+    pool = np.array([0.0, -0.0, 1.0, 1.0 + 2.0 ** -40, 1.0 - 2.0 ** -50, -1.0, 5e-324, -5e-324,
+                     np.inf, -np.inf, np.nan, 3.0, 3.0, 1e300, -1e300], dtype=np.float64)
+    x = rng.standard_normal(n)
+    pick = rng.random(n) < 0.6
+    x[pick] = rng.choice(pool, int(pick.sum()))
+    if n > 3:
+        x[rng.integers(0, n)] = np.frombuffer(np.uint64(0xFFF8000000000001).tobytes(), np.float64)[0]
+    return x
+
+
+def test_random_with_specials_f64():
+    rng = np.random.default_rng(21)
+    for _ in range(200):
+        n = int(rng.integers(1, 201))
+        k = int(rng.integers(0, (n + 1) // 2)) * 2 + 1
+        x = _special_vector_f64(rng, n)
+        want = argsort_argmed(x, k)
+        assert np.array_equal(rank_count_argmed(x, k), want)
+        y, a = oracle.sortmedian(x, k)
+        assert np.array_equal(a, want), (n, k)
+        assert _same_bits(y, x[want])
+        assert np.array_equal(oracle.window_median(x, k, np.arange(n - k + 1)), want)
+
+
+def _i64_vector(rng, n):
+    """Values whose order is decided by the high word only, by the low word
+    only, or by the sign: a comparison narrower than 64 bits fails."""
+    hi = rng.choice(np.array([-2, -1, 0, 1, 7], dtype=np.int64), n)
+    lo = rng.choice(np.array([0, 1, 2**31, 2**32 - 1], dtype=np.int64), n)
+    x = hi * (1 << 32) + lo
+    x[rng.random(n) < 0.05] = np.iinfo(np.int64).max
+    x[rng.random(n) < 0.05] = np.iinfo(np.int64).min
+    return x
+
+
+def test_random_ties_i64():
+    rng = np.random.default_rng(22)
+    for _ in range(200):
+        n = int(rng.integers(1, 201))
+        k = int(rng.integers(0, (n + 1) // 2)) * 2 + 1
+        x = _i64_vector(rng, n)
+        want = argsort_argmed(x, k)
+        assert np.array_equal(rank_count_argmed(x, k), want)
+        y, a = oracle.sortmedian(x, k)
+        assert np.array_equal(a, want), (n, k)
+        assert np.array_equal(y, x[want])
+
+
+@pytest.mark.parametrize("k", [3, 101, 1001])
+def test_sortmedian_vs_definition_larger_64(k):
+    rng = np.random.default_rng(100 + k)
+    n = 30_000 + 7
+    xi = _i64_vector(rng, n)
+    xf = np.cumsum(rng.standard_normal(n)) * 1e-9 + 1.0   # distinct only in float64
+    for x in (xi, xf):
+        y, a = oracle.sortmedian(x, k)
+        outs = rng.integers(0, n - k + 1, 2000)
+        outs[:3] = [0, n - k, (n - k) // 2]
+        assert np.array_equal(oracle.window_median(x, k, outs), a[outs])
+        assert np.array_equal(argsort_argmed(x[: 3 * k + 5], k), a[: 2 * k + 6])
+
+
+MUTATIONS_64 = [
+    # 64-bit integers compared through a 32-bit truncation
+    ("const int64_t ia = ((const int64_t *)v->x)[a];\n        const int64_t ib = ((const int64_t *)v->x)[b];",
+     "const int32_t ia = (int32_t)((const int64_t *)v->x)[a];\n        const int32_t ib = (int32_t)((const int64_t *)v->x)[b];",
+     "i64"),
+    # doubles compared in single precision
+    ("const double fa = ((const double *)v->x)[a];\n        const double fb = ((const double *)v->x)[b];",
+     "const float fa = (float)((const double *)v->x)[a];\n        const float fb = (float)((const double *)v->x)[b];",
+     "f64"),
+    # the NaN rule dropped for doubles
+    ("if (na || nb) return na - nb;\n        return (fa > fb) - (fa < fb);\n    }\n    case T_I64",
+     "return (fa > fb) - (fa < fb);\n    }\n    case T_I64", "f64"),
+]
+
+
+@pytest.mark.parametrize("idx", range(len(MUTATIONS_64)))
+def test_planted_mistakes_64_are_caught(tmp_path, idx):
+    old, new, tag = MUTATIONS_64[idx]
+    src = open(oracle._build.SRC).read()
+    assert old in src, old
+    path = tmp_path / ("mut64_%d.c" % idx)
+    path.write_text(src.replace(old, new, 1))
+    lib = tmp_path / ("mut64_%d.so" % idx)
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-w", "-o", str(lib), str(path), "-lm"],
+                   check=True)
+    f = getattr(ctypes.CDLL(str(lib)), "oracle_sortmedian_" + tag)
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    rng = np.random.default_rng(23)
+    caught = False
+    for _ in range(200):
+        n = int(rng.integers(5, 120))
+        k = int(rng.integers(1, (n + 1) // 2)) * 2 + 1
+        x = _i64_vector(rng, n) if tag == "i64" else _special_vector_f64(rng, n)
+        a = np.empty(n - k + 1, dtype=np.int32)
+        y = np.empty(n - k + 1, dtype=x.dtype)
+        rc = f(x.ctypes.data, n, k, y.ctypes.data, a.ctypes.data)
+        if rc != 0 or not np.array_equal(a, argsort_argmed(x, k)):
+            caught = True
+            break
+    assert caught, "64-bit mutation %d survived" % idx
