@@ -55,6 +55,20 @@ mf_status mf_median_filter(const float *x, int64_t n, int32_t k,
 mf_status mf_median_filter_i32(const int32_t *x, int64_t n, int32_t k,
                                int32_t *y, int32_t *argmed, void *stream);
 
+/* 64-bit signals (the paper measures 32- and 64-bit versions, Section 7):
+ * float64 (same order rules as float32: -0.0 equals +0.0, NaNs above +inf)
+ * and int64.  y: n-k+1 elements of the input type, bit copies of
+ * x[argmed[o]].  Windows up to 4095 (MF_ERR_UNSUPPORTED above).  Each tile's
+ * items are first ranked by (value, index) into 32-bit keys in the
+ * library's workspace (about 4 B per input item, plus 4 B per output when
+ * argmed is NULL); the 32-bit tile kernels then run on those keys, and y is
+ * gathered from x.  The first half of y's bytes serves as scratch before
+ * y is written. */
+mf_status mf_median_filter_f64(const double *x, int64_t n, int32_t k,
+                               double *y, int32_t *argmed, void *stream);
+mf_status mf_median_filter_i64(const int64_t *x, int64_t n, int32_t k,
+                               int64_t *y, int32_t *argmed, void *stream);
+
 /* Uniform batch: `rows` float32 signals of length n stored back to back
  * (row r at x + r*n), one window k.  Outputs row-major: y + r*(n-k+1). */
 mf_status mf_median_filter_rows(const float *x, int64_t rows, int64_t n, int32_t k,

@@ -5,7 +5,8 @@ memory and streams, every step of the filter runs in the library's HIP
 kernels.
 
   median_filter(x, k)                 -> (y, argmed); x float32/int32 on a
-                                         GPU, shape (n,) or (rows, n)
+                                         GPU, shape (n,) or (rows, n), or a
+                                         float64/int64 signal (k <= 4095)
   median_filter_batched(x, offsets, ks) -> packed (y, argmed) of a ragged batch
   median_filter_backward(grad_y, argmed, n, k) -> grad_x
   MedianFilterFn.apply(x, k)          autograd: y, with grad routed to argmed
@@ -44,8 +45,12 @@ def median_filter(x, k, with_argmed=True):
             lib.mf_median_filter(x, n, k, y, am)
         elif x.dtype == torch.int32:
             lib.mf_median_filter_i32(x, n, k, y, am)
+        elif x.dtype == torch.float64:
+            lib.mf_median_filter_f64(x, n, k, y, am)
+        elif x.dtype == torch.int64:
+            lib.mf_median_filter_i64(x, n, k, y, am)
         else:
-            raise TypeError("x must be float32 or int32")
+            raise TypeError("x must be float32, int32, float64 or int64")
     elif x.dim() == 2:
         if x.dtype != torch.float32:
             raise TypeError("row batches must be float32")

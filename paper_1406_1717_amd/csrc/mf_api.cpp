@@ -159,6 +159,52 @@ mf_status forward_rows(const void *x, int64_t rows, int64_t n, int32_t k, void *
     return MF_OK;
 }
 
+// Forward of one 64-bit signal: the rank pre-pass writes 32-bit keys tile
+// by tile into the workspace, the int32 tile kernel runs on them (each tile
+// reading its own span) and writes argmed, with its y stores going to the
+// first half of y, which the gather then overwrites with x[argmed].
+mf_status forward64(const void *x, int64_t n, int32_t k, void *y, int32_t *argmed, bool f64, hipStream_t st)
+{
+    if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
+    mf_status s = check_signal(n, k);
+    if (s != MF_OK) return s;
+    const Path p = path_for(k);
+    if (p != PATH_IDENTITY && p != PATH_LDS_SMALL && p != PATH_LDS_LARGE)
+        return fail(MF_ERR_UNSUPPORTED, "k = %d: 64-bit signals take windows up to 4095", k);
+    Device *D = nullptr;
+    if ((s = device_state(&D)) != MF_OK) return s;
+    if (p == PATH_IDENTITY) {
+        MF_HIP(launch_identity64(x, y, argmed, n, st), "64-bit identity launch");
+        return MF_OK;
+    }
+    const int64_t nout = n - k + 1;
+    const int64_t tiles = tiles_for(p, n, k);
+    if (tiles > 0x7FFFFFFFll) return fail(MF_ERR_UNSUPPORTED, "too many tiles (%lld)", (long long)tiles);
+    const int64_t stride = rank64_stride_for(p, k);
+    const int64_t key_bytes = (tiles * stride * 4 + 255) & ~255ll;
+    const int64_t am_bytes = argmed ? 0 : nout * 4;
+    unsigned char *ws = nullptr;
+    if ((s = acquire_ws(*D, key_bytes + am_bytes, st, &ws)) != MF_OK) return s;
+    uint32_t *keys = (uint32_t *)ws;
+    int32_t *am = argmed ? argmed : (int32_t *)(ws + key_bytes);
+    MF_HIP(launch_rank64(p, f64, x, n, k, keys, stride, tiles, st), "64-bit rank launch");
+    Launch L;
+    memset(&L, 0, sizeof L);
+    L.x = keys;
+    L.y = y;
+    L.argmed = am;
+    L.one.n = n;
+    L.one.k = k;
+    L.rows = 1;
+    L.tpr = tiles;
+    L.nunits = tiles;
+    L.xshift = k;
+    MF_HIP(launch_forward(p, false, L, (size_t)lds_bytes_for(p, k), nullptr, 0, 0, D->d_err, st),
+           "64-bit forward launch");
+    MF_HIP(launch_gather64(x, n, am, y, nout, st), "64-bit gather launch");
+    return release_ws(*D, st);
+}
+
 mf_status backward_rows(const float *gy, const int32_t *argmed, int64_t rows, int64_t n,
                         int32_t k, float *gx, hipStream_t st)
 {
@@ -571,6 +617,18 @@ extern "C" mf_status mf_median_filter_i32(const int32_t *x, int64_t n, int32_t k
                                           int32_t *argmed, void *stream)
 {
     return forward_rows(x, 1, n, k, y, argmed, false, (hipStream_t)stream);
+}
+
+extern "C" mf_status mf_median_filter_f64(const double *x, int64_t n, int32_t k, double *y, int32_t *argmed,
+                                          void *stream)
+{
+    return forward64(x, n, k, y, argmed, true, (hipStream_t)stream);
+}
+
+extern "C" mf_status mf_median_filter_i64(const int64_t *x, int64_t n, int32_t k, int64_t *y,
+                                          int32_t *argmed, void *stream)
+{
+    return forward64(x, n, k, y, argmed, false, (hipStream_t)stream);
 }
 
 extern "C" mf_status mf_median_filter_rows(const float *x, int64_t rows, int64_t n, int32_t k, float *y,

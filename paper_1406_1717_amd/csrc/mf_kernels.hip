@@ -97,7 +97,7 @@ __device__ __forceinline__ Resolved unit_of(const Launch &L, int64_t uidx)
         const int64_t row = uidx / L.tpr;
         tile = uidx - row * L.tpr;
         d = L.one;
-        d.x_off += row * d.n;
+        d.x_off += row * d.n + tile * L.xshift;
         d.y_off += row * (d.n - d.k + 1);
     }
     Resolved r;
@@ -388,6 +388,75 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         d = dn;
 #pragma unroll
         for (int j = 0; j < kRegs; j++) raw[j] = rawn[j];
+    }
+}
+
+// ------------------------------------------------------------------ 64-bit inputs
+
+// The tile's items sorted by their values: bitonic sort in registers, then
+// merge-path levels through buf (NT * kRegs u64).  Ends with a barrier.
+template <int NT>
+__device__ __forceinline__ void merge_sort_tile(u64 *buf, int tid, u64 (&v)[kRegs])
+{
+    sort_regs(v);
+    for (int w = kRegs; w < NT * kRegs; w <<= 1) {
+        store_regs(buf + tid * kRegs, v);
+        __syncthreads();
+        merge_level(buf, w, tid, v);
+        __syncthreads();
+    }
+}
+
+// Rank pre-pass of a 64-bit signal: one workgroup per tile of the NT-thread
+// LDS path; writes the ranks of tile t's items by (key, index) to
+// keys[t * stride + slot].  LDS: the merge buffer (8 B per slot, later the
+// ranks) and the high key halves (4 B per slot, later the first order's
+// slots).
+template <int NT, bool F64>
+__global__ __launch_bounds__(NT) void k_rank64(const u64 *x, int64_t n, int32_t k, u32 *keys, int64_t stride)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int tid = threadIdx.x;
+    u64 *buf = (u64 *)lds;
+    u32 *hik = (u32 *)(lds + 8 * NT * kRegs);
+    Shape s;
+    make_shape(n, k, NT, &s);
+    const Tile T = make_tile(s, blockIdx.x);
+    const int32_t span = tile_items(s, T);
+    u64 v[kRegs];
+    rank64_load<F64>(s, T, x, tid, NT, hik, v);
+    merge_sort_tile<NT>(buf, tid, v);            // its first barrier covers hik
+    u32 slot[kRegs];
+    rank64_second(span, tid, hik, v, slot);
+    __syncthreads();                             // every high half is read
+    rank64_slots(span, tid, (u16 *)hik, slot);
+    merge_sort_tile<NT>(buf, tid, v);            // its first barrier covers the slots
+    rank64_ranks(span, tid, (const u16 *)hik, v, (u32 *)buf);
+    __syncthreads();
+    u32 *out = keys + (int64_t)blockIdx.x * stride;
+    const u32 *rank = (const u32 *)buf;
+    for (int32_t i = tid; i < span; i += NT) out[i] = rank[i];
+}
+
+// y[o] = x[argmed[o]] for 64-bit elements (an index outside the signal,
+// which a consistent walk never produces, reads x[0]).
+__global__ __launch_bounds__(256) void k_gather64(const u64 *x, int64_t n, const int32_t *argmed, u64 *y,
+                                                  int64_t nout)
+{
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o < nout) {
+        const int64_t a = argmed[o];
+        y[o] = x[(a >= 0 && a < n) ? a : 0];
+    }
+}
+
+// k = 1 for 64-bit elements: y = x, argmed[o] = o.
+__global__ __launch_bounds__(256) void k_identity64(const u64 *x, u64 *y, int32_t *argmed, int64_t n)
+{
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o < n) {
+        y[o] = x[o];
+        if (argmed) argmed[o] = (int32_t)o;
     }
 }
 
@@ -915,6 +984,10 @@ hipError_t prepare_kernels()
     MF_ATTR((k_tile_global<false, false>))
     MF_ATTR((k_tile_global<true, true>))
     MF_ATTR((k_tile_global<false, true>))
+    MF_ATTR((k_rank64<kLdsSmall, true>))
+    MF_ATTR((k_rank64<kLdsSmall, false>))
+    MF_ATTR((k_rank64<kLdsLarge, true>))
+    MF_ATTR((k_rank64<kLdsLarge, false>))
 #undef MF_ATTR
     return e;
 }
@@ -1028,6 +1101,51 @@ hipError_t launch_backward(const BwdLaunch &L, hipStream_t st)
     if (L.nunits <= 0) return hipSuccess;
     const int64_t grid = L.nunits < (1ll << 20) ? L.nunits : (1ll << 20);
     hipLaunchKernelGGL(k_backward, dim3((unsigned)grid), dim3(kBwdThreads), 0, st, L);
+    return hipGetLastError();
+}
+
+
+int64_t rank64_stride_for(Path p, int32_t k)
+{
+    Shape s;
+    if (p != PATH_LDS_SMALL && p != PATH_LDS_LARGE) return 0;
+    make_shape(1ll << 20, k, p == PATH_LDS_SMALL ? kLdsSmall : kLdsLarge, &s);
+    return rank64_stride(s);
+}
+
+hipError_t launch_rank64(Path p, bool f64, const void *x, int64_t n, int32_t k, u32 *keys, int64_t stride,
+                         int64_t ntiles, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const dim3 g((unsigned)ntiles);
+    if (p == PATH_LDS_SMALL) {
+        const size_t lds = 12u * kLdsSmall * kRegs;
+        if (f64) hipLaunchKernelGGL((k_rank64<kLdsSmall, true>), g, dim3(kLdsSmall), lds, st, (const u64 *)x, n, k, keys, stride);
+        else     hipLaunchKernelGGL((k_rank64<kLdsSmall, false>), g, dim3(kLdsSmall), lds, st, (const u64 *)x, n, k, keys, stride);
+    } else if (p == PATH_LDS_LARGE) {
+        const size_t lds = 12u * kLdsLarge * kRegs;
+        if (f64) hipLaunchKernelGGL((k_rank64<kLdsLarge, true>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride);
+        else     hipLaunchKernelGGL((k_rank64<kLdsLarge, false>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather64(const void *x, int64_t n, const int32_t *argmed, void *y, int64_t nout,
+                           hipStream_t st)
+{
+    if (nout <= 0) return hipSuccess;
+    const dim3 g((unsigned)((nout + 255) / 256));
+    hipLaunchKernelGGL(k_gather64, g, dim3(256), 0, st, (const u64 *)x, n, argmed, (u64 *)y, nout);
+    return hipGetLastError();
+}
+
+hipError_t launch_identity64(const void *x, void *y, int32_t *argmed, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const dim3 g((unsigned)((n + 255) / 256));
+    hipLaunchKernelGGL(k_identity64, g, dim3(256), 0, st, (const u64 *)x, (u64 *)y, argmed, n);
     return hipGetLastError();
 }
 

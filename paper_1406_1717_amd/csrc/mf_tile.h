@@ -1837,4 +1837,91 @@ MF_HD void tail_pair_merge(const Shape &s, const Tile &T, const TileMem &m, int3
     if (T.j0 == 1 && tid == 0) output_first(s, T, m, x, y, argmed);
 }
 
+// ---------------------------------------------------------------- 64-bit inputs
+//
+// The tile phases compare 32-bit keys.  A 64-bit signal (Section 7 measures
+// 32- and 64-bit versions) first has each tile's items ranked by (64-bit
+// key, index): a total order without ties.  The ranks, written tile by tile
+// ((Pmax + 1) k entries per tile, so a block shared by two tiles appears in
+// both), are 32-bit keys that order every tile's items exactly as the
+// 64-bit values with the index tie-break do; the 32-bit tile phases then run
+// on them unchanged and produce the 64-bit signal's argmed.
+//
+// The ranking is two merge sorts of 32-bit halves, least significant first:
+// (low half, slot), then (high half, position in the first order).  Slots
+// are item offsets from the tile's first item, at most kRegs * threads.
+
+// Order-preserving unsigned key of a double: -0.0 as +0.0, every NaN above
+// +inf (all NaNs equal).
+MF_HD u64 key_of_f64(u64 u)
+{
+    if ((u & 0x7FFFFFFFFFFFFFFFull) > 0x7FF0000000000000ull) return ~0ull;
+    if (u == 0x8000000000000000ull) u = 0ull;
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+MF_HD u64 key_of_i64(u64 u) { return u ^ 0x8000000000000000ull; }
+
+// First sort's values of thread tid: items j*NT + tid as (low half << 32 |
+// slot); their high halves go to hik[slot].  Slots past the tile's items
+// hold kPadAll, which sorts after every item.
+template <bool F64>
+MF_HD void rank64_load(const Shape &s, const Tile &T, const u64 *x, int32_t tid, int32_t NT, u32 *hik,
+                       u64 (&v)[kRegs])
+{
+    const int32_t span = tile_items(s, T);
+    const u64 *xt = x + T.e0;
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        const int32_t i = j * NT + tid;
+        v[j] = kPadAll;
+        if (i < span) {
+            const u64 key = F64 ? key_of_f64(xt[i]) : key_of_i64(xt[i]);
+            hik[i] = (u32)(key >> 32);
+            v[j] = (key << 32) | (u64)(u32)i;
+        }
+    }
+}
+
+// Second sort's values from the first order (the thread holds positions
+// tid*kRegs + j): (high half << 32 | position); slot[j] is the item there.
+MF_HD void rank64_second(int32_t span, int32_t tid, const u32 *hik, u64 (&v)[kRegs], u32 (&slot)[kRegs])
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        const int32_t p = tid * kRegs + j;
+        slot[j] = 0u;
+        if (p < span) {
+            slot[j] = (u32)v[j];
+            v[j] = ((u64)hik[slot[j]] << 32) | (u64)(u32)p;
+        } else {
+            v[j] = kPadAll;
+        }
+    }
+}
+
+// The first order's items by position (sl: u16 per position).
+MF_HD void rank64_slots(int32_t span, int32_t tid, u16 *sl, const u32 (&slot)[kRegs])
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        const int32_t p = tid * kRegs + j;
+        if (p < span) sl[p] = (u16)slot[j];
+    }
+}
+
+// Rank of each item: its position in the second order (the thread holds
+// positions tid*kRegs + j, each naming a first-order position).
+MF_HD void rank64_ranks(int32_t span, int32_t tid, const u16 *sl, const u64 (&v)[kRegs], u32 *rank)
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        const int32_t q = tid * kRegs + j;
+        if (q < span) rank[sl[(u32)v[j]]] = (u32)q;
+    }
+}
+
+// Entries per tile of the rank buffer.
+MF_HD int64_t rank64_stride(const Shape &s) { return (int64_t)(s.Pmax + 1) * s.k; }
+
 }  // namespace mf

@@ -35,6 +35,8 @@ def load():
     sig = {
         "mf_median_filter": [P, I64, I32, P, P, P],
         "mf_median_filter_i32": [P, I64, I32, P, P, P],
+        "mf_median_filter_f64": [P, I64, I32, P, P, P],
+        "mf_median_filter_i64": [P, I64, I32, P, P, P],
         "mf_median_filter_rows": [P, I64, I64, I32, P, P, P],
         "mf_median_filter_batched": [P, P, P, I32, P, P, P],
         "mf_median_filter_batched_i32": [P, P, P, I32, P, P, P],
@@ -111,6 +113,14 @@ def mf_median_filter(x, n, k, y, argmed, stream=None):
 
 def mf_median_filter_i32(x, n, k, y, argmed, stream=None):
     _check(load().mf_median_filter_i32(_ptr(x), int(n), int(k), _ptr(y), _ptr(argmed), _stream(stream)))
+
+
+def mf_median_filter_f64(x, n, k, y, argmed, stream=None):
+    _check(load().mf_median_filter_f64(_ptr(x), int(n), int(k), _ptr(y), _ptr(argmed), _stream(stream)))
+
+
+def mf_median_filter_i64(x, n, k, y, argmed, stream=None):
+    _check(load().mf_median_filter_i64(_ptr(x), int(n), int(k), _ptr(y), _ptr(argmed), _stream(stream)))
 
 
 def mf_median_filter_rows(x, rows, n, k, y, argmed, stream=None):

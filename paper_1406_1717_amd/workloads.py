@@ -16,6 +16,8 @@ Workloads (names are what the data is, with its sizes):
                           N(0,1) values with 5% impulses uniform in (-50, 50)
   distinct_normal_256     256 rows x 262,144 float32 N(0,1), distinct per row,
                           k = 201, with an N(0,1) upstream gradient
+  int64_full_64m          int64 uniform over the full range, n = 2**26, k = 1001
+  random_walk_f64_16m     float64 cumulative sum of N(0,1) steps, n = 2**24
 
 The seven generator families of the paper's experiments (Section 7.3:
 ascending, descending, both with small uniform noise, large and small
@@ -32,6 +34,8 @@ SEEDS = {
     "distinct_normal_256": 501,
     "distinct_normal_256_grad": 502,
     "fd_slice": 503,
+    "int64_full_64m": 601,
+    "random_walk_f64_16m": 602,
 }
 
 
@@ -122,6 +126,43 @@ def _violators(row, min_gap, window):
     return np.nonzero(dup)[0]
 
 
+def int64_full(n, seed):
+    info = np.iinfo(np.int64)
+    return rng_for(seed).integers(info.min, info.max, n, dtype=np.int64, endpoint=True)
+
+
+def random_walk_f64(n, seed):
+    return np.cumsum(rng_for(seed).standard_normal(n))
+
+
+def int64_words(n, seed):
+    """int64 values whose order is decided by the high 32-bit word for some
+    pairs and by the low word for others, with many equal values and both
+    extremes."""
+    rng = rng_for(seed)
+    hi = rng.choice(np.array([-3, -1, 0, 1, 5, 2**30], dtype=np.int64), n)
+    lo = rng.choice(np.array([0, 1, 7, 2**31 - 1, 2**31, 2**32 - 1], dtype=np.int64), n)
+    x = hi * (1 << 32) + lo
+    x[rng.random(n) < 0.02] = np.iinfo(np.int64).max
+    x[rng.random(n) < 0.02] = np.iinfo(np.int64).min
+    return x
+
+
+def f64_specials(n, seed):
+    """float64 N(0,1) with 40% of the items replaced by specials: signed
+    zeros, infinities, NaNs (one with a payload), subnormals and values that
+    are equal in float32 but not in float64."""
+    rng = rng_for(seed)
+    pool = np.array([0.0, -0.0, 1.0, 1.0 + 2.0 ** -40, 1.0 - 2.0 ** -50, -1.0, 5e-324, -5e-324,
+                     np.inf, -np.inf, np.nan, 3.0, 1e300, -1e300], dtype=np.float64)
+    x = rng.standard_normal(n)
+    m = rng.random(n) < 0.4
+    x[m] = rng.choice(pool, int(m.sum()))
+    if n > 0:
+        x[rng.integers(0, n)] = np.frombuffer(np.uint64(0xFFF8000000000001).tobytes(), np.float64)[0]
+    return x
+
+
 def normal_f32(shape, seed):
     return rng_for(seed).standard_normal(shape, dtype=np.float32)
 
@@ -172,6 +213,10 @@ def workload(name):
         return {"x": int32_bytes(2**26, SEEDS[name]), "k": 1001}
     if name == "random_walk_f32_16m":
         return {"x": random_walk_f32(2**24, SEEDS[name]), "ks": [3, 31, 301, 3001, 30001]}
+    if name == "int64_full_64m":
+        return {"x": int64_full(2**26, SEEDS[name]), "k": 1001}
+    if name == "random_walk_f64_16m":
+        return {"x": random_walk_f64(2**24, SEEDS[name]), "ks": [3, 31, 301, 3001]}
     if name == "sorted_walk_f32_16m":
         return {"x": sorted_walk_f32(2**24, SEEDS["random_walk_f32_16m"]),
                 "ks": [3, 31, 301, 3001, 30001]}

@@ -263,3 +263,88 @@ extern "C" int emu_median_filter(const void *x, int64_t n, int32_t k, int is_f32
     }
     return 0;
 }
+
+// 64-bit signals: the rank pre-pass (each phase of the kernel as one sweep
+// over the threads, barriers between sweeps), a check that each tile's
+// ranks are a permutation, the 32-bit tiles on the ranks (tile t reading its
+// span at keys + t*k) and the gather y = x[argmed].
+extern "C" int emu_median_filter64(const void *x, int64_t n, int32_t k, int is_f64, int threads,
+                                   void *y, int32_t *argmed)
+{
+    if (k < 3 || (k & 1) == 0 || n < k) return -1;
+    Shape s;
+    if (make_shape(n, k, threads, &s) != 0) return -2;
+    Layout l;
+    make_layout(s, &l);
+    if (l.total < 0) return -3;
+    const int64_t stride = rank64_stride(s);
+    const int cap = threads * kRegs;
+    std::vector<u32> keys((size_t)(s.ntiles * stride), 0xA5A5A5A5u);
+    std::vector<u64> regs(cap), tmp(cap), buf(cap);
+    std::vector<u32> hik(cap), slots(cap), rank(cap);
+    auto sort = [&]() {
+        for (int q = 0; q < threads; q++) {
+            u64 v[kRegs];
+            for (int j = 0; j < kRegs; j++) v[j] = regs[(size_t)q * kRegs + j];
+            sort_regs(v);
+            for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
+        }
+        for (int w = kRegs; w < cap; w *= 2) {
+            buf = regs;
+            for (int q = 0; q < threads; q++) {
+                u64 out[kRegs];
+                merge_level(buf.data(), w, q, out);
+                for (int j = 0; j < kRegs; j++) tmp[(size_t)q * kRegs + j] = out[j];
+            }
+            regs.swap(tmp);
+        }
+    };
+    for (int64_t t = 0; t < s.ntiles; t++) {
+        const Tile T = make_tile(s, t);
+        const int32_t span = tile_items(s, T);
+        std::fill(hik.begin(), hik.end(), 0xA5A5A5A5u);
+        for (int q = 0; q < threads; q++) {
+            u64 v[kRegs];
+            if (is_f64) rank64_load<true>(s, T, (const u64 *)x, q, threads, hik.data(), v);
+            else rank64_load<false>(s, T, (const u64 *)x, q, threads, hik.data(), v);
+            for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
+        }
+        sort();
+        for (int q = 0; q < threads; q++) {
+            u64 v[kRegs];
+            u32 sl[kRegs];
+            for (int j = 0; j < kRegs; j++) v[j] = regs[(size_t)q * kRegs + j];
+            rank64_second(span, q, hik.data(), v, sl);
+            for (int j = 0; j < kRegs; j++) {
+                regs[(size_t)q * kRegs + j] = v[j];
+                slots[(size_t)q * kRegs + j] = sl[j];
+            }
+        }
+        for (int q = 0; q < threads; q++) {
+            u32 sl[kRegs];
+            for (int j = 0; j < kRegs; j++) sl[j] = slots[(size_t)q * kRegs + j];
+            rank64_slots(span, q, (u16 *)hik.data(), sl);
+        }
+        sort();
+        std::fill(rank.begin(), rank.end(), 0xFFFFFFFFu);
+        for (int q = 0; q < threads; q++) {
+            u64 v[kRegs];
+            for (int j = 0; j < kRegs; j++) v[j] = regs[(size_t)q * kRegs + j];
+            rank64_ranks(span, q, (const u16 *)hik.data(), v, rank.data());
+        }
+        std::vector<char> seen(span, 0);
+        for (int32_t i = 0; i < span; i++) {
+            if (rank[i] >= (u32)span || seen[rank[i]]) return -20;
+            seen[rank[i]] = 1;
+            keys[(size_t)(t * stride + i)] = rank[i];
+        }
+    }
+    std::vector<unsigned char> lds((size_t)l.total + 64);
+    std::vector<u32> yj((size_t)(n - k + 1));
+    for (int64_t t = 0; t < s.ntiles; t++) {
+        const int rc = run_tile<false>(s, l, t, threads, keys.data() + t * k, yj.data(), argmed, lds);
+        if (rc != 0) return rc;
+    }
+    for (int64_t o = 0; o + k <= n; o++) ((u64 *)y)[o] = ((const u64 *)x)[argmed[o]];
+    return 0;
+}

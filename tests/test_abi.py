@@ -59,13 +59,25 @@ def test_forward_validation(n, k, code):
     L = lib.load()
     assert L.mf_median_filter(FAKE, n, k, FAKE, None, None) == code
     assert L.mf_median_filter_i32(FAKE, n, k, FAKE, None, None) == code
+    assert L.mf_median_filter_f64(FAKE, n, k, FAKE, None, None) == code
+    assert L.mf_median_filter_i64(FAKE, n, k, FAKE, None, None) == code
     assert lib.last_error()
+
+
+@pytest.mark.parametrize("k", [4097, 9999, 32767])
+def test_forward64_window_limit(k):
+    L = lib.load()
+    assert L.mf_median_filter_f64(FAKE, 100000, k, FAKE, None, None) == 2
+    assert L.mf_median_filter_i64(FAKE, 100000, k, FAKE, None, None) == 2
+    assert "4095" in lib.last_error()
 
 
 def test_null_pointers_rejected():
     L = lib.load()
     assert L.mf_median_filter(None, 10, 3, FAKE, None, None) == 1
     assert L.mf_median_filter(FAKE, 10, 3, None, None, None) == 1
+    assert L.mf_median_filter_f64(None, 10, 3, FAKE, None, None) == 1
+    assert L.mf_median_filter_i64(FAKE, 10, 3, None, None, None) == 1
     assert L.mf_median_filter_backward(None, FAKE, 10, 3, FAKE, None) == 1
     assert L.mf_median_filter_rows(FAKE, 0, 10, 3, FAKE, None, None) == 1
     h = ctypes.c_void_p()

@@ -111,3 +111,41 @@ def test_presorted_tiles(emu):
         assert rc == 0 and np.array_equal(a, ao), (k, n, kind, rc)
         assert np.array_equal(y.view(np.uint32), yo.view(np.uint32))
     assert emu.emu_presorted_tiles() > before
+
+
+def _emu64(emu, x, k, threads):
+    emu.emu_median_filter64.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    n = len(x)
+    y = np.empty(n - k + 1, dtype=x.dtype)
+    am = np.full(n - k + 1, -1, dtype=np.int32)
+    rc = emu.emu_median_filter64(x.ctypes.data, n, k, int(x.dtype == np.float64), threads,
+                                 y.ctypes.data, am.ctypes.data)
+    return rc, y, am
+
+
+@pytest.mark.parametrize("kind", ["f64_specials", "int64_words", "int64_full", "walk_f64"])
+def test_tile_phases_64bit_match_oracle(emu, kind):
+    """64-bit signals: the rank pre-pass then the 32-bit tiles on the ranks
+    (each tile reading its own span), against the 64-bit oracle."""
+    from paper_1406_1717_amd import workloads as W
+    gen = {"f64_specials": W.f64_specials, "int64_words": W.int64_words,
+           "int64_full": W.int64_full, "walk_f64": W.random_walk_f64}[kind]
+    for i, k in enumerate((3, 5, 31, 33, 101, 701, 1001, 2047, 2049, 4095)):
+        n = {3: 3001, 5: 999, 31: 4000, 33: 5003, 101: 9000}.get(k, 3 * k + 17 + i)
+        x = gen(n, 700 + i)
+        rc, y, am = _emu64(emu, x, k, threads_for(k))
+        assert rc == 0, (kind, k, rc)
+        _, want = oracle.sortmedian(x, k)
+        assert np.array_equal(am, want), (kind, k)
+        assert np.array_equal(y.view(np.uint64), x[want].view(np.uint64))
+
+
+def test_tile_phases_64bit_presorted_and_single_block(emu):
+    from paper_1406_1717_amd import workloads as W
+    for k, n in ((101, 101), (101, 150), (1001, 5000), (3001, 3001)):
+        for x in (np.sort(W.random_walk_f64(n, 3)), np.arange(n, 0, -1, dtype=np.int64) << 33):
+            rc, y, am = _emu64(emu, x, k, threads_for(k))
+            assert rc == 0, (k, n, rc)
+            _, want = oracle.sortmedian(x, k)
+            assert np.array_equal(am, want), (k, n)
