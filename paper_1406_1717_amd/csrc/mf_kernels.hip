@@ -393,48 +393,42 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
 // ------------------------------------------------------------------ 64-bit inputs
 
-// The tile's items sorted by their values: bitonic sort in registers, then
-// merge-path levels through buf (NT * kRegs u64).  Ends with a barrier.
-template <int NT>
-__device__ __forceinline__ void merge_sort_tile(u64 *buf, int tid, u64 (&v)[kRegs])
-{
-    sort_regs(v);
-    for (int w = kRegs; w < NT * kRegs; w <<= 1) {
-        store_regs(buf + tid * kRegs, v);
-        __syncthreads();
-        merge_level(buf, w, tid, v);
-        __syncthreads();
-    }
-}
-
 // Rank pre-pass of a 64-bit signal: one workgroup per tile of the NT-thread
-// LDS path; writes the ranks of tile t's items by (key, index) to
-// keys[t * stride + slot].  LDS: the merge buffer (8 B per slot, later the
-// ranks) and the high key halves (4 B per slot, later the first order's
-// slots).
+// LDS path sorts the tile's (key, slot) pairs (registers, then stable
+// merge-path levels through LDS: 8 B of key and 2 B of slot per position)
+// and writes each item's sorted position to keys[t * stride + slot].
 template <int NT, bool F64>
 __global__ __launch_bounds__(NT) void k_rank64(const u64 *x, int64_t n, int32_t k, u32 *keys, int64_t stride)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const int tid = threadIdx.x;
-    u64 *buf = (u64 *)lds;
-    u32 *hik = (u32 *)(lds + 8 * NT * kRegs);
+    u64 *K = (u64 *)lds;
+    u16 *S = (u16 *)(lds + 8 * NT * kRegs);
     Shape s;
     make_shape(n, k, NT, &s);
     const Tile T = make_tile(s, blockIdx.x);
     const int32_t span = tile_items(s, T);
-    u64 v[kRegs];
-    rank64_load<F64>(s, T, x, tid, NT, hik, v);
-    merge_sort_tile<NT>(buf, tid, v);            // its first barrier covers hik
-    u32 slot[kRegs];
-    rank64_second(span, tid, hik, v, slot);
-    __syncthreads();                             // every high half is read
-    rank64_slots(span, tid, (u16 *)hik, slot);
-    merge_sort_tile<NT>(buf, tid, v);            // its first barrier covers the slots
-    rank64_ranks(span, tid, (const u16 *)hik, v, (u32 *)buf);
+    u64 kv[kRegs];
+    u32 sv[kRegs];
+    static_assert(kRegs == 8, "slots are stored as one 16-byte word per thread");
+    rank64_load<F64>(s, T, x, tid, kv, sv);
+    sort_regs_ks(kv, sv);
+    for (int w = kRegs; w < NT * kRegs; w <<= 1) {
+        store_regs(K + tid * kRegs, kv);
+        uint4 sp;
+        sp.x = sv[0] | (sv[1] << 16);
+        sp.y = sv[2] | (sv[3] << 16);
+        sp.z = sv[4] | (sv[5] << 16);
+        sp.w = sv[6] | (sv[7] << 16);
+        *(uint4 *)(S + tid * kRegs) = sp;
+        __syncthreads();
+        merge_level_ks(K, S, w, tid, kv, sv);
+        __syncthreads();
+    }
+    rank64_ranks(span, tid, sv, (u32 *)K);
     __syncthreads();
     u32 *out = keys + (int64_t)blockIdx.x * stride;
-    const u32 *rank = (const u32 *)buf;
+    const u32 *rank = (const u32 *)K;
     for (int32_t i = tid; i < span; i += NT) out[i] = rank[i];
 }
 
@@ -1119,11 +1113,11 @@ hipError_t launch_rank64(Path p, bool f64, const void *x, int64_t n, int32_t k, 
     if (ntiles <= 0) return hipSuccess;
     const dim3 g((unsigned)ntiles);
     if (p == PATH_LDS_SMALL) {
-        const size_t lds = 12u * kLdsSmall * kRegs;
+        const size_t lds = 10u * kLdsSmall * kRegs;
         if (f64) hipLaunchKernelGGL((k_rank64<kLdsSmall, true>), g, dim3(kLdsSmall), lds, st, (const u64 *)x, n, k, keys, stride);
         else     hipLaunchKernelGGL((k_rank64<kLdsSmall, false>), g, dim3(kLdsSmall), lds, st, (const u64 *)x, n, k, keys, stride);
     } else if (p == PATH_LDS_LARGE) {
-        const size_t lds = 12u * kLdsLarge * kRegs;
+        const size_t lds = 10u * kLdsLarge * kRegs;
         if (f64) hipLaunchKernelGGL((k_rank64<kLdsLarge, true>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride);
         else     hipLaunchKernelGGL((k_rank64<kLdsLarge, false>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride);
     } else {

@@ -1847,9 +1847,11 @@ MF_HD void tail_pair_merge(const Shape &s, const Tile &T, const TileMem &m, int3
 // 64-bit values with the index tie-break do; the 32-bit tile phases then run
 // on them unchanged and produce the 64-bit signal's argmed.
 //
-// The ranking is two merge sorts of 32-bit halves, least significant first:
-// (low half, slot), then (high half, position in the first order).  Slots
-// are item offsets from the tile's first item, at most kRegs * threads.
+// The ranking is one merge sort of (key, slot) pairs, slots being item
+// offsets from the tile's first item (at most kRegs * threads).  A thread
+// starts with kRegs consecutive slots, sorted in registers by (key, slot);
+// the merges are stable (ties take the left run, whose slots are all
+// smaller), so every run stays in (key, slot) order.
 
 // Order-preserving unsigned key of a double: -0.0 as +0.0, every NaN above
 // +inf (all NaNs equal).
@@ -1862,63 +1864,92 @@ MF_HD u64 key_of_f64(u64 u)
 
 MF_HD u64 key_of_i64(u64 u) { return u ^ 0x8000000000000000ull; }
 
-// First sort's values of thread tid: items j*NT + tid as (low half << 32 |
-// slot); their high halves go to hik[slot].  Slots past the tile's items
-// hold kPadAll, which sorts after every item.
+// Keys and slots of thread tid: slots tid*kRegs + j; slots past the tile's
+// items get the largest key (their slots order them after every item).
 template <bool F64>
-MF_HD void rank64_load(const Shape &s, const Tile &T, const u64 *x, int32_t tid, int32_t NT, u32 *hik,
-                       u64 (&v)[kRegs])
+MF_HD void rank64_load(const Shape &s, const Tile &T, const u64 *x, int32_t tid, u64 (&kv)[kRegs],
+                       u32 (&sv)[kRegs])
 {
     const int32_t span = tile_items(s, T);
-    const u64 *xt = x + T.e0;
+    const int32_t i0 = tid * kRegs;
+    const u64 *src = x + T.e0 + i0;
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
-        const int32_t i = j * NT + tid;
-        v[j] = kPadAll;
-        if (i < span) {
-            const u64 key = F64 ? key_of_f64(xt[i]) : key_of_i64(xt[i]);
-            hik[i] = (u32)(key >> 32);
-            v[j] = (key << 32) | (u64)(u32)i;
+        sv[j] = (u32)(i0 + j);
+        kv[j] = ~0ull;
+        if (i0 + j < span) kv[j] = F64 ? key_of_f64(src[j]) : key_of_i64(src[j]);
+    }
+}
+
+MF_HD void cswap_ks(u64 &ka, u32 &sa, u64 &kb, u32 &sb, bool up)
+{
+    const bool gt = ka > kb || (ka == kb && sa > sb);
+    const bool sw = up ? gt : !gt;
+    const u64 k0 = sw ? kb : ka, k1 = sw ? ka : kb;
+    const u32 s0 = sw ? sb : sa, s1 = sw ? sa : sb;
+    ka = k0; kb = k1; sa = s0; sb = s1;
+}
+
+// Bitonic sort of the thread's kRegs pairs by (key, slot), ascending.
+MF_HD void sort_regs_ks(u64 (&kv)[kRegs], u32 (&sv)[kRegs])
+{
+#pragma unroll
+    for (int size = 2; size <= kRegs; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+#pragma unroll
+            for (int i = 0; i < kRegs; i++) {
+                const int j = i ^ stride;
+                if (j > i) cswap_ks(kv[i], sv[i], kv[j], sv[j], (i & size) == 0);
+            }
         }
     }
 }
 
-// Second sort's values from the first order (the thread holds positions
-// tid*kRegs + j): (high half << 32 | position); slot[j] is the item there.
-MF_HD void rank64_second(int32_t span, int32_t tid, const u32 *hik, u64 (&v)[kRegs], u32 (&slot)[kRegs])
+// One stable merge-path level over keys K and slots S (runs of length w):
+// thread tid produces sorted positions [tid*kRegs, tid*kRegs + kRegs).
+MF_HD void merge_level_ks(const u64 *K, const u16 *S, int32_t w, int32_t tid, u64 (&ko)[kRegs],
+                          u32 (&so)[kRegs])
 {
+    const int32_t first = tid * kRegs;
+    const int32_t s0 = first & ~(2 * w - 1);
+    const u64 *A = K + s0, *B = K + s0 + w;
+    const u16 *SA = S + s0, *SB = S + s0 + w;
+    const int32_t d = first - s0;
+    int32_t lo = d > w ? d - w : 0;
+    int32_t hi = d < w ? d : w;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (A[mid] <= B[d - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    int32_t a = lo, b = d - lo;
+    u64 va = a < w ? A[a] : 0ull, vb = b < w ? B[b] : 0ull;
+    u32 sa = a < w ? SA[a] : 0u, sb = b < w ? SB[b] : 0u;
 #pragma unroll
-    for (int j = 0; j < kRegs; j++) {
-        const int32_t p = tid * kRegs + j;
-        slot[j] = 0u;
-        if (p < span) {
-            slot[j] = (u32)v[j];
-            v[j] = ((u64)hik[slot[j]] << 32) | (u64)(u32)p;
+    for (int q = 0; q < kRegs; q++) {
+        const bool takeA = (b >= w) || (a < w && va <= vb);
+        ko[q] = takeA ? va : vb;
+        so[q] = takeA ? sa : sb;
+        if (takeA) {
+            a++;
+            va = a < w ? A[a] : 0ull;
+            sa = a < w ? SA[a] : 0u;
         } else {
-            v[j] = kPadAll;
+            b++;
+            vb = b < w ? B[b] : 0ull;
+            sb = b < w ? SB[b] : 0u;
         }
     }
 }
 
-// The first order's items by position (sl: u16 per position).
-MF_HD void rank64_slots(int32_t span, int32_t tid, u16 *sl, const u32 (&slot)[kRegs])
+// Rank of each item: its position in the sorted order (the thread holds
+// positions tid*kRegs + j).
+MF_HD void rank64_ranks(int32_t span, int32_t tid, const u32 (&sv)[kRegs], u32 *rank)
 {
 #pragma unroll
-    for (int j = 0; j < kRegs; j++) {
-        const int32_t p = tid * kRegs + j;
-        if (p < span) sl[p] = (u16)slot[j];
-    }
-}
-
-// Rank of each item: its position in the second order (the thread holds
-// positions tid*kRegs + j, each naming a first-order position).
-MF_HD void rank64_ranks(int32_t span, int32_t tid, const u16 *sl, const u64 (&v)[kRegs], u32 *rank)
-{
-#pragma unroll
-    for (int j = 0; j < kRegs; j++) {
-        const int32_t q = tid * kRegs + j;
-        if (q < span) rank[sl[(u32)v[j]]] = (u32)q;
-    }
+    for (int j = 0; j < kRegs; j++)
+        if ((int32_t)sv[j] < span) rank[sv[j]] = (u32)(tid * kRegs + j);
 }
 
 // Entries per tile of the rank buffer.

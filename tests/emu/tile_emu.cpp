@@ -280,57 +280,43 @@ extern "C" int emu_median_filter64(const void *x, int64_t n, int32_t k, int is_f
     const int64_t stride = rank64_stride(s);
     const int cap = threads * kRegs;
     std::vector<u32> keys((size_t)(s.ntiles * stride), 0xA5A5A5A5u);
-    std::vector<u64> regs(cap), tmp(cap), buf(cap);
-    std::vector<u32> hik(cap), slots(cap), rank(cap);
-    auto sort = [&]() {
-        for (int q = 0; q < threads; q++) {
-            u64 v[kRegs];
-            for (int j = 0; j < kRegs; j++) v[j] = regs[(size_t)q * kRegs + j];
-            sort_regs(v);
-            for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
-        }
-        for (int w = kRegs; w < cap; w *= 2) {
-            buf = regs;
-            for (int q = 0; q < threads; q++) {
-                u64 out[kRegs];
-                merge_level(buf.data(), w, q, out);
-                for (int j = 0; j < kRegs; j++) tmp[(size_t)q * kRegs + j] = out[j];
-            }
-            regs.swap(tmp);
-        }
-    };
+    std::vector<u64> kr(cap), kt(cap), K(cap);
+    std::vector<u32> sr(cap), st(cap), rank(cap);
+    std::vector<u16> S(cap);
     for (int64_t t = 0; t < s.ntiles; t++) {
         const Tile T = make_tile(s, t);
         const int32_t span = tile_items(s, T);
-        std::fill(hik.begin(), hik.end(), 0xA5A5A5A5u);
         for (int q = 0; q < threads; q++) {
-            u64 v[kRegs];
-            if (is_f64) rank64_load<true>(s, T, (const u64 *)x, q, threads, hik.data(), v);
-            else rank64_load<false>(s, T, (const u64 *)x, q, threads, hik.data(), v);
-            for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
-        }
-        sort();
-        for (int q = 0; q < threads; q++) {
-            u64 v[kRegs];
-            u32 sl[kRegs];
-            for (int j = 0; j < kRegs; j++) v[j] = regs[(size_t)q * kRegs + j];
-            rank64_second(span, q, hik.data(), v, sl);
+            u64 kv[kRegs];
+            u32 sv[kRegs];
+            if (is_f64) rank64_load<true>(s, T, (const u64 *)x, q, kv, sv);
+            else rank64_load<false>(s, T, (const u64 *)x, q, kv, sv);
+            sort_regs_ks(kv, sv);
             for (int j = 0; j < kRegs; j++) {
-                regs[(size_t)q * kRegs + j] = v[j];
-                slots[(size_t)q * kRegs + j] = sl[j];
+                kr[(size_t)q * kRegs + j] = kv[j];
+                sr[(size_t)q * kRegs + j] = sv[j];
             }
         }
-        for (int q = 0; q < threads; q++) {
-            u32 sl[kRegs];
-            for (int j = 0; j < kRegs; j++) sl[j] = slots[(size_t)q * kRegs + j];
-            rank64_slots(span, q, (u16 *)hik.data(), sl);
+        for (int w = kRegs; w < cap; w *= 2) {
+            K = kr;
+            for (int i = 0; i < cap; i++) S[i] = (u16)sr[i];
+            for (int q = 0; q < threads; q++) {
+                u64 ko[kRegs];
+                u32 so[kRegs];
+                merge_level_ks(K.data(), S.data(), w, q, ko, so);
+                for (int j = 0; j < kRegs; j++) {
+                    kt[(size_t)q * kRegs + j] = ko[j];
+                    st[(size_t)q * kRegs + j] = so[j];
+                }
+            }
+            kr.swap(kt);
+            sr.swap(st);
         }
-        sort();
         std::fill(rank.begin(), rank.end(), 0xFFFFFFFFu);
         for (int q = 0; q < threads; q++) {
-            u64 v[kRegs];
-            for (int j = 0; j < kRegs; j++) v[j] = regs[(size_t)q * kRegs + j];
-            rank64_ranks(span, q, (const u16 *)hik.data(), v, rank.data());
+            u32 sv[kRegs];
+            for (int j = 0; j < kRegs; j++) sv[j] = sr[(size_t)q * kRegs + j];
+            rank64_ranks(span, q, sv, rank.data());
         }
         std::vector<char> seen(span, 0);
         for (int32_t i = 0; i < span; i++) {
