@@ -393,39 +393,102 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
 // ------------------------------------------------------------------ 64-bit inputs
 
+__device__ __forceinline__ u64 wave_min_u64(u64 v)
+{
+    for (int d = 32; d > 0; d >>= 1) {
+        const u64 o = (u64)__shfl_xor((unsigned long long)v, d);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ u64 wave_max_u64(u64 v)
+{
+    for (int d = 32; d > 0; d >>= 1) {
+        const u64 o = (u64)__shfl_xor((unsigned long long)v, d);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
 // Rank pre-pass of a 64-bit signal: one workgroup per tile of the NT-thread
-// LDS path sorts the tile's (key, slot) pairs (registers, then stable
-// merge-path levels through LDS: 8 B of key and 2 B of slot per position)
-// and writes each item's sorted position to keys[t * stride + slot].
+// LDS path sorts the tile's (key, slot) pairs and writes each item's sorted
+// position to keys[t * stride + slot].  The sort is a bucket sort over cap
+// buckets, or, for a tile with a crowded bucket, a merge sort (registers,
+// then stable merge-path levels).  LDS: keys (8 B per position), slots
+// (2 B), 16-bit bucket counters (2 B per bucket); the ranks reuse the keys.
 template <int NT, bool F64>
-__global__ __launch_bounds__(NT) void k_rank64(const u64 *x, int64_t n, int32_t k, u32 *keys, int64_t stride)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 6 : 4))) void k_rank64(const u64 *x, int64_t n, int32_t k, u32 *keys, int64_t stride)
 {
     extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ u64 red_lo[NT / 64], red_hi[NT / 64];
+    __shared__ u32 wave_tot[NT / 64];
+    __shared__ u32 full;
+    static_assert(kRegs == 8, "slots are stored as one 16-byte word per thread");
     const int tid = threadIdx.x;
+    const int32_t cap = NT * kRegs;
     u64 *K = (u64 *)lds;
-    u16 *S = (u16 *)(lds + 8 * NT * kRegs);
+    u16 *S = (u16 *)(lds + 8 * cap);
+    u32 *C = (u32 *)(lds + 10 * cap);
     Shape s;
     make_shape(n, k, NT, &s);
     const Tile T = make_tile(s, blockIdx.x);
     const int32_t span = tile_items(s, T);
     u64 kv[kRegs];
     u32 sv[kRegs];
-    static_assert(kRegs == 8, "slots are stored as one 16-byte word per thread");
     rank64_load<F64>(s, T, x, tid, kv, sv);
-    sort_regs_ks(kv, sv);
-    for (int w = kRegs; w < NT * kRegs; w <<= 1) {
-        store_regs(K + tid * kRegs, kv);
-        uint4 sp;
-        sp.x = sv[0] | (sv[1] << 16);
-        sp.y = sv[2] | (sv[3] << 16);
-        sp.z = sv[4] | (sv[5] << 16);
-        sp.w = sv[6] | (sv[7] << 16);
-        *(uint4 *)(S + tid * kRegs) = sp;
-        __syncthreads();
-        merge_level_ks(K, S, w, tid, kv, sv);
-        __syncthreads();
+#pragma unroll
+    for (int w = 0; w < kRegs / 2; w++) C[tid * (kRegs / 2) + w] = 0u;
+    if (tid == 0) full = 0u;
+    u64 lo, hi;
+    rank64_range(span, kv, sv, lo, hi);
+    lo = wave_min_u64(lo);
+    hi = wave_max_u64(hi);
+    if ((tid & 63) == 0) {
+        red_lo[tid >> 6] = lo;
+        red_hi[tid >> 6] = hi;
     }
-    rank64_ranks(span, tid, sv, (u32 *)K);
+    __syncthreads();
+    lo = red_lo[0];
+    hi = red_hi[0];
+    for (int w = 1; w < NT / 64; w++) {
+        lo = red_lo[w] < lo ? red_lo[w] : lo;
+        hi = red_hi[w] > hi ? red_hi[w] : hi;
+    }
+    const int32_t lognb = NT == 512 ? 12 : 13;
+    static_assert(NT * kRegs == 512 * 8 || NT * kRegs == 1024 * 8, "cap is 4096 or 8192");
+    const u32 sh = rank64_shift(lo, hi, lognb);
+    u32 arr[kRegs];
+    if (rank64_count(span, kv, sv, lo, sh, C, arr)) full = 1u;
+    __syncthreads();
+    if (full == 0u) {
+        u32 c[kRegs];
+        const u32 tot = rank64_scan_local(C, tid, c);
+        const u32 excl = seg_excl_scan<NT>(tot, NT, wave_tot);
+        rank64_scan_store(C, tid, excl, c);
+        __syncthreads();
+        rank64_scatter(span, kv, sv, lo, sh, C, arr, K, S);
+        __syncthreads();
+        u32 fin[kRegs];
+        rank64_bucket_rank(span, kv, sv, lo, sh, C, (u32)cap, K, S, fin);
+        __syncthreads();
+        rank64_place(span, sv, fin, (u32 *)K);
+    } else {
+        sort_regs_ks(kv, sv);
+        for (int w = kRegs; w < cap; w <<= 1) {
+            store_regs(K + tid * kRegs, kv);
+            uint4 sp;
+            sp.x = sv[0] | (sv[1] << 16);
+            sp.y = sv[2] | (sv[3] << 16);
+            sp.z = sv[4] | (sv[5] << 16);
+            sp.w = sv[6] | (sv[7] << 16);
+            *(uint4 *)(S + tid * kRegs) = sp;
+            __syncthreads();
+            merge_level_ks(K, S, w, tid, kv, sv);
+            __syncthreads();
+        }
+        rank64_ranks(span, tid, sv, (u32 *)K);
+    }
     __syncthreads();
     u32 *out = keys + (int64_t)blockIdx.x * stride;
     const u32 *rank = (const u32 *)K;
@@ -1113,11 +1176,11 @@ hipError_t launch_rank64(Path p, bool f64, const void *x, int64_t n, int32_t k, 
     if (ntiles <= 0) return hipSuccess;
     const dim3 g((unsigned)ntiles);
     if (p == PATH_LDS_SMALL) {
-        const size_t lds = 10u * kLdsSmall * kRegs;
+        const size_t lds = 12u * kLdsSmall * kRegs;
         if (f64) hipLaunchKernelGGL((k_rank64<kLdsSmall, true>), g, dim3(kLdsSmall), lds, st, (const u64 *)x, n, k, keys, stride);
         else     hipLaunchKernelGGL((k_rank64<kLdsSmall, false>), g, dim3(kLdsSmall), lds, st, (const u64 *)x, n, k, keys, stride);
     } else if (p == PATH_LDS_LARGE) {
-        const size_t lds = 10u * kLdsLarge * kRegs;
+        const size_t lds = 12u * kLdsLarge * kRegs;
         if (f64) hipLaunchKernelGGL((k_rank64<kLdsLarge, true>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride);
         else     hipLaunchKernelGGL((k_rank64<kLdsLarge, false>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride);
     } else {

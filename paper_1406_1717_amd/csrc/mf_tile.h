@@ -1952,6 +1952,124 @@ MF_HD void rank64_ranks(int32_t span, int32_t tid, const u32 (&sv)[kRegs], u32 *
         if ((int32_t)sv[j] < span) rank[sv[j]] = (u32)(tid * kRegs + j);
 }
 
+// Common path of the ranking: a bucket sort.  The tile's keys are spread
+// over cap buckets by their top bits above the tile's minimum key, counted
+// (16-bit counters, two to an LDS word), scanned, scattered in bucket order
+// and ranked within their bucket by (key, slot).  A tile with a bucket of
+// kRank64BucketMax or more items (heavy ties, clustered keys) takes the
+// merge sort instead.
+static const u32 kRank64BucketMax = 32;
+
+// The thread's key range over its items (lo = ~0, hi = 0 if none).
+MF_HD void rank64_range(int32_t span, const u64 (&kv)[kRegs], const u32 (&sv)[kRegs], u64 &lo, u64 &hi)
+{
+    lo = ~0ull;
+    hi = 0ull;
+#pragma unroll
+    for (int j = 0; j < kRegs; j++)
+        if ((int32_t)sv[j] < span) {
+            lo = kv[j] < lo ? kv[j] : lo;
+            hi = kv[j] > hi ? kv[j] : hi;
+        }
+}
+
+// Shift mapping [lo, hi] onto 2^lognb buckets: (key - lo) >> sh.
+MF_HD u32 rank64_shift(u64 lo, u64 hi, int32_t lognb)
+{
+    const u64 r = hi - lo;
+    const int32_t bits = r ? hibit64(r) + 1 : 0;
+    return bits > lognb ? (u32)(bits - lognb) : 0u;
+}
+
+MF_HD u32 rank64_bucket(u64 key, u64 lo, u32 sh) { return (u32)((key - lo) >> sh); }
+
+// 16-bit counter b of the packed array C (two per word).
+MF_HD u32 cnt16(const u32 *C, u32 b) { return (C[b >> 1] >> ((b & 1u) << 4)) & 0xFFFFu; }
+
+// Arrival numbers of the thread's items in their buckets; true if one
+// reaches kRank64BucketMax.
+MF_HD bool rank64_count(int32_t span, const u64 (&kv)[kRegs], const u32 (&sv)[kRegs], u64 lo, u32 sh,
+                        u32 *C, u32 (&arr)[kRegs])
+{
+    bool full = false;
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        arr[j] = 0u;
+        if ((int32_t)sv[j] < span) {
+            const u32 b = rank64_bucket(kv[j], lo, sh);
+            const u32 sft = (b & 1u) << 4;
+            arr[j] = (MF_ADDRTN32(C + (b >> 1), 1u << sft) >> sft) & 0xFFFFu;
+            full = full || arr[j] >= kRank64BucketMax;
+        }
+    }
+    return full;
+}
+
+// Bucket counts of thread tid (buckets tid*kRegs .. +kRegs) into their
+// exclusive prefix within the thread; returns the thread's total.
+MF_HD u32 rank64_scan_local(const u32 *C, int32_t tid, u32 (&c)[kRegs])
+{
+    u32 run = 0u;
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        const u32 v = cnt16(C, (u32)(tid * kRegs + j));
+        c[j] = run;
+        run += v;
+    }
+    return run;
+}
+
+// Bucket starts (16-bit, packed) from the thread's prefix and its offset.
+MF_HD void rank64_scan_store(u32 *C, int32_t tid, u32 excl, const u32 (&c)[kRegs])
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; j += 2)
+        C[(tid * kRegs + j) >> 1] = ((excl + c[j]) & 0xFFFFu) | ((excl + c[j + 1]) << 16);
+}
+
+// Items into bucket order: keys to K, slots to S.
+MF_HD void rank64_scatter(int32_t span, const u64 (&kv)[kRegs], const u32 (&sv)[kRegs], u64 lo, u32 sh,
+                          const u32 *C, const u32 (&arr)[kRegs], u64 *K, u16 *S)
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; j++)
+        if ((int32_t)sv[j] < span) {
+            const u32 pos = cnt16(C, rank64_bucket(kv[j], lo, sh)) + arr[j];
+            K[pos] = kv[j];
+            S[pos] = (u16)sv[j];
+        }
+}
+
+// Sorted position of each item: its bucket's start plus the bucket's items
+// below it by (key, slot); nb buckets, the last ending at span.
+MF_HD void rank64_bucket_rank(int32_t span, const u64 (&kv)[kRegs], const u32 (&sv)[kRegs], u64 lo, u32 sh,
+                              const u32 *C, u32 nb, const u64 *K, const u16 *S, u32 (&fin)[kRegs])
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        fin[j] = 0u;
+        if ((int32_t)sv[j] < span) {
+            const u32 b = rank64_bucket(kv[j], lo, sh);
+            const u32 st = cnt16(C, b);
+            const u32 en = b + 1u < nb ? cnt16(C, b + 1u) : (u32)span;
+            u32 below = 0u;
+            for (u32 e = st; e < en; e++) {
+                const u64 ke = K[e];
+                below += (ke < kv[j] || (ke == kv[j] && (u32)S[e] < sv[j])) ? 1u : 0u;
+            }
+            fin[j] = st + below;
+        }
+    }
+}
+
+// rank[slot] = sorted position, for the thread's items.
+MF_HD void rank64_place(int32_t span, const u32 (&sv)[kRegs], const u32 (&fin)[kRegs], u32 *rank)
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; j++)
+        if ((int32_t)sv[j] < span) rank[sv[j]] = fin[j];
+}
+
 // Entries per tile of the rank buffer.
 MF_HD int64_t rank64_stride(const Shape &s) { return (int64_t)(s.Pmax + 1) * s.k; }
 

@@ -16,6 +16,9 @@ using namespace mf;
 static int g_force_merge = 0;
 static long g_fast_tiles = 0, g_slow_tiles = 0, g_recount_tiles = 0, g_tile_order_tiles = 0, g_presorted_tiles = 0;
 extern "C" void emu_set_force_merge(int v) { g_force_merge = v; }
+static long g_rank_bucket_tiles = 0, g_rank_merge_tiles = 0;
+extern "C" long emu_rank_bucket_tiles(void) { return g_rank_bucket_tiles; }
+extern "C" long emu_rank_merge_tiles(void) { return g_rank_merge_tiles; }
 extern "C" long emu_fast_tiles(void) { return g_fast_tiles; }
 extern "C" long emu_slow_tiles(void) { return g_slow_tiles; }
 extern "C" long emu_recount_tiles(void) { return g_recount_tiles; }
@@ -283,14 +286,84 @@ extern "C" int emu_median_filter64(const void *x, int64_t n, int32_t k, int is_f
     std::vector<u64> kr(cap), kt(cap), K(cap);
     std::vector<u32> sr(cap), st(cap), rank(cap);
     std::vector<u16> S(cap);
+    std::vector<u32> C((size_t)cap / 2), arr(cap), fin(cap), cpre(cap), tot(threads);
+    int lognb = 0;
+    while ((1 << lognb) < cap) lognb++;
     for (int64_t t = 0; t < s.ntiles; t++) {
         const Tile T = make_tile(s, t);
         const int32_t span = tile_items(s, T);
+        u64 lo = ~0ull, hi = 0ull;
         for (int q = 0; q < threads; q++) {
-            u64 kv[kRegs];
+            u64 kv[kRegs], l, h;
             u32 sv[kRegs];
             if (is_f64) rank64_load<true>(s, T, (const u64 *)x, q, kv, sv);
             else rank64_load<false>(s, T, (const u64 *)x, q, kv, sv);
+            rank64_range(span, kv, sv, l, h);
+            lo = l < lo ? l : lo;
+            hi = h > hi ? h : hi;
+            for (int j = 0; j < kRegs; j++) {
+                kr[(size_t)q * kRegs + j] = kv[j];
+                sr[(size_t)q * kRegs + j] = sv[j];
+            }
+        }
+        auto regs = [&](int q, u64 (&kv)[kRegs], u32 (&sv)[kRegs]) {
+            for (int j = 0; j < kRegs; j++) {
+                kv[j] = kr[(size_t)q * kRegs + j];
+                sv[j] = sr[(size_t)q * kRegs + j];
+            }
+        };
+        const u32 sh = rank64_shift(lo, hi, lognb);
+        std::fill(C.begin(), C.end(), 0u);
+        bool full = false;
+        for (int q = 0; q < threads; q++) {
+            u64 kv[kRegs];
+            u32 sv[kRegs], a[kRegs];
+            regs(q, kv, sv);
+            if (rank64_count(span, kv, sv, lo, sh, C.data(), a)) full = true;
+            for (int j = 0; j < kRegs; j++) arr[(size_t)q * kRegs + j] = a[j];
+        }
+        std::fill(rank.begin(), rank.end(), 0xFFFFFFFFu);
+        if (!full && !g_force_merge) {
+            for (int q = 0; q < threads; q++) {
+                u32 c[kRegs];
+                tot[q] = rank64_scan_local(C.data(), q, c);
+                for (int j = 0; j < kRegs; j++) cpre[(size_t)q * kRegs + j] = c[j];
+            }
+            u32 excl = 0;
+            for (int q = 0; q < threads; q++) {
+                u32 c[kRegs];
+                for (int j = 0; j < kRegs; j++) c[j] = cpre[(size_t)q * kRegs + j];
+                rank64_scan_store(C.data(), q, excl, c);
+                excl += tot[q];
+            }
+            std::fill(K.begin(), K.end(), 0xA5A5A5A5A5A5A5A5ull);
+            for (int q = 0; q < threads; q++) {
+                u64 kv[kRegs];
+                u32 sv[kRegs], a[kRegs];
+                regs(q, kv, sv);
+                for (int j = 0; j < kRegs; j++) a[j] = arr[(size_t)q * kRegs + j];
+                rank64_scatter(span, kv, sv, lo, sh, C.data(), a, K.data(), S.data());
+            }
+            for (int q = 0; q < threads; q++) {
+                u64 kv[kRegs];
+                u32 sv[kRegs], f[kRegs];
+                regs(q, kv, sv);
+                rank64_bucket_rank(span, kv, sv, lo, sh, C.data(), (u32)cap, K.data(), S.data(), f);
+                for (int j = 0; j < kRegs; j++) fin[(size_t)q * kRegs + j] = f[j];
+            }
+            for (int q = 0; q < threads; q++) {
+                u64 kv[kRegs];
+                u32 sv[kRegs], f[kRegs];
+                regs(q, kv, sv);
+                for (int j = 0; j < kRegs; j++) f[j] = fin[(size_t)q * kRegs + j];
+                rank64_place(span, sv, f, rank.data());
+            }
+            g_rank_bucket_tiles++;
+        } else {
+        for (int q = 0; q < threads; q++) {
+            u64 kv[kRegs];
+            u32 sv[kRegs];
+            regs(q, kv, sv);
             sort_regs_ks(kv, sv);
             for (int j = 0; j < kRegs; j++) {
                 kr[(size_t)q * kRegs + j] = kv[j];
@@ -312,11 +385,12 @@ extern "C" int emu_median_filter64(const void *x, int64_t n, int32_t k, int is_f
             kr.swap(kt);
             sr.swap(st);
         }
-        std::fill(rank.begin(), rank.end(), 0xFFFFFFFFu);
         for (int q = 0; q < threads; q++) {
             u32 sv[kRegs];
             for (int j = 0; j < kRegs; j++) sv[j] = sr[(size_t)q * kRegs + j];
             rank64_ranks(span, q, sv, rank.data());
+        }
+        g_rank_merge_tiles++;
         }
         std::vector<char> seen(span, 0);
         for (int32_t i = 0; i < span; i++) {

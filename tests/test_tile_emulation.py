@@ -124,21 +124,37 @@ def _emu64(emu, x, k, threads):
     return rc, y, am
 
 
+@pytest.mark.parametrize("force_merge", [0, 1])
 @pytest.mark.parametrize("kind", ["f64_specials", "int64_words", "int64_full", "walk_f64"])
-def test_tile_phases_64bit_match_oracle(emu, kind):
-    """64-bit signals: the rank pre-pass then the 32-bit tiles on the ranks
-    (each tile reading its own span), against the 64-bit oracle."""
+def test_tile_phases_64bit_match_oracle(emu, kind, force_merge):
+    """64-bit signals: the rank pre-pass (bucket sort, or the merge sort it
+    falls back to) then the 32-bit tiles on the ranks (each tile reading its
+    own span), against the 64-bit oracle."""
     from paper_1406_1717_amd import workloads as W
     gen = {"f64_specials": W.f64_specials, "int64_words": W.int64_words,
            "int64_full": W.int64_full, "walk_f64": W.random_walk_f64}[kind]
-    for i, k in enumerate((3, 5, 31, 33, 101, 701, 1001, 2047, 2049, 4095)):
-        n = {3: 3001, 5: 999, 31: 4000, 33: 5003, 101: 9000}.get(k, 3 * k + 17 + i)
-        x = gen(n, 700 + i)
-        rc, y, am = _emu64(emu, x, k, threads_for(k))
-        assert rc == 0, (kind, k, rc)
-        _, want = oracle.sortmedian(x, k)
-        assert np.array_equal(am, want), (kind, k)
-        assert np.array_equal(y.view(np.uint64), x[want].view(np.uint64))
+    emu.emu_rank_bucket_tiles.restype = ctypes.c_long
+    emu.emu_rank_merge_tiles.restype = ctypes.c_long
+    emu.emu_set_force_merge(force_merge)
+    b0, m0 = emu.emu_rank_bucket_tiles(), emu.emu_rank_merge_tiles()
+    try:
+        for i, k in enumerate((3, 5, 31, 33, 101, 701, 1001, 2047, 2049, 4095)):
+            n = {3: 3001, 5: 999, 31: 4000, 33: 5003, 101: 9000}.get(k, 3 * k + 17 + i)
+            x = gen(n, 700 + i)
+            rc, y, am = _emu64(emu, x, k, threads_for(k))
+            assert rc == 0, (kind, k, rc)
+            _, want = oracle.sortmedian(x, k)
+            assert np.array_equal(am, want), (kind, k)
+            assert np.array_equal(y.view(np.uint64), x[want].view(np.uint64))
+    finally:
+        emu.emu_set_force_merge(0)
+    b, m = emu.emu_rank_bucket_tiles() - b0, emu.emu_rank_merge_tiles() - m0
+    if force_merge:
+        assert b == 0 and m > 0
+    elif kind in ("int64_full", "walk_f64"):
+        assert b > 0          # spread keys take the bucket sort
+    elif kind == "int64_words":
+        assert m > 0          # few distinct values crowd the buckets
 
 
 def test_tile_phases_64bit_presorted_and_single_block(emu):
