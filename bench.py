@@ -235,6 +235,30 @@ def extras(torch, mf, lib, workloads, args):
                            "hbm_frac": (4.0 * n + 8.0 * (n - k + 1)) / np.mean(per) / 1e9 / HBM_PEAK_GBS}
         out[name] = res
         del xr
+    # 64-bit signals (rank pre-pass, int32 tiles on the ranks, gather)
+    w = workloads.workload("int64_full_64m")
+    x64 = torch.from_numpy(w["x"]).to(dev)
+    n, k = len(w["x"]), w["k"]
+    y = torch.empty(n - k + 1, dtype=torch.int64, device=dev)
+    a = torch.empty(n - k + 1, dtype=torch.int32, device=dev)
+    total, per = timed_steps(lambda: lib.mf_median_filter_i64(x64, n, k, y, a), args.steps, args.warmup, torch)
+    out["int64_full_64m"] = {"k": k, "outputs_per_s": (n - k + 1) * args.steps / total,
+                             "hbm_frac": (8.0 * n + 12.0 * (n - k + 1)) / np.mean(per) / 1e9 / HBM_PEAK_GBS,
+                             "checked": sampled_windows_ok(w["x"], k, y.cpu().numpy(), a.cpu().numpy(),
+                                                           samples=300)}
+    del x64, y, a
+    w = workloads.workload("random_walk_f64_16m")
+    xr = torch.from_numpy(w["x"]).to(dev)
+    n = len(w["x"])
+    res = {}
+    for k in w["ks"]:
+        y = torch.empty(n - k + 1, dtype=torch.float64, device=dev)
+        a = torch.empty(n - k + 1, dtype=torch.int32, device=dev)
+        total, per = timed_steps(lambda: lib.mf_median_filter_f64(xr, n, k, y, a), 5, 1, torch)
+        res[str(k)] = {"outputs_per_s": (n - k + 1) * 5 / total,
+                       "hbm_frac": (8.0 * n + 12.0 * (n - k + 1)) / np.mean(per) / 1e9 / HBM_PEAK_GBS}
+    out["random_walk_f64_16m"] = res
+    del xr
     # differentiable rows: forward vs forward + backward
     rows, n, k = 256, 262_144, 201
     xs = torch.randn(rows, n, device=dev)
@@ -279,14 +303,18 @@ def extras(torch, mf, lib, workloads, args):
                                  "autotune_s": tune_s}
     plan.close()
     out["paper_generators"] = paper_sweep(torch, lib, workloads)
+    out["paper_generators_64"] = paper_sweep(torch, lib, workloads, hs=(1, 10, 100, 1000), bits=64)
     return out
 
 
-def paper_sweep(torch, lib, workloads, bh=10**7, hs=(1, 10, 100, 1000, 10000)):
+def paper_sweep(torch, lib, workloads, bh=10**7, hs=(1, 10, 100, 1000, 10000), bits=32):
     """The paper's generator families (Section 7.3) with b*h fixed and the
-    half-window h varied (n = (2h+1) b, k = 2h+1), int32: median outputs/s
-    of the forward, each output spot-checked by the median property."""
+    half-window h varied (n = (2h+1) b, k = 2h+1), int32 or int64: median
+    outputs/s of the forward, each output spot-checked by the median
+    property."""
     dev = torch.device("cuda:0")
+    dt = torch.int32 if bits == 32 else torch.int64
+    fn = lib.mf_median_filter_i32 if bits == 32 else lib.mf_median_filter_i64
     res = {}
     for fam in ("asc", "desc", "r-asc", "r-desc", "r-large", "r-small", "r-block"):
         row = {}
@@ -294,11 +322,11 @@ def paper_sweep(torch, lib, workloads, bh=10**7, hs=(1, 10, 100, 1000, 10000)):
             b = bh // h
             k = 2 * h + 1
             n = b * k
-            x_host = workloads.paper_family(fam, n, 700 + h)
+            x_host = workloads.paper_family(fam, n, 700 + h, bits=bits)
             x = torch.from_numpy(x_host).to(dev)
-            y = torch.empty(n - k + 1, dtype=torch.int32, device=dev)
+            y = torch.empty(n - k + 1, dtype=dt, device=dev)
             a = torch.empty(n - k + 1, dtype=torch.int32, device=dev)
-            total, _ = timed_steps(lambda: lib.mf_median_filter_i32(x, n, k, y, a), 3, 1, torch)
+            total, _ = timed_steps(lambda: fn(x, n, k, y, a), 3, 1, torch)
             ok = sampled_windows_ok(x_host, k, y.cpu().numpy(), a.cpu().numpy(), samples=200)
             row[str(h)] = {"n": n, "k": k, "outputs_per_s": (n - k + 1) * 3 / total, "checked": ok}
             del x, y, a
