@@ -175,8 +175,9 @@ __device__ __forceinline__ void unit_shape(const Resolved &d, Shape &s, Tile &T)
 }
 
 // One tile of the LDS path, every buffer in the workgroup's LDS; raw holds
-// the thread's inputs (load_raw).
-template <int NT, bool F32>
+// the thread's inputs (load_raw).  RK: the inputs are rank keys of a 64-bit
+// signal (each tile's items' distinct tile-order positions).
+template <int NT, bool F32, bool RK = false>
 __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, const Tile &T,
                                          const u32 (&raw)[kRegs], unsigned char *lds, int *err)
 {
@@ -192,6 +193,9 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
     // (heavy ties across the tile), sort block by block and merge each pair
     const Shape st = tile_order_shape(s);
     bool tord = tile_order_ok(s);
+    // rank keys are distinct positions: a tile-order tile places each item
+    // at its key without sorting
+    const bool ranked = RK && tord;
     const int32_t per = tile_buckets(s) / NT;   // counters per thread
 
     // 1. load into registers
@@ -213,7 +217,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
     bool direct = false;   // items already in sort order
     int pass = 0;          // bucket map: 0 linear, 1 clamped logarithmic
     u32 arr[kRegs];   // arrival numbers (tile order: packed with the bucket)
-    if (tord) {
+    if (tord && !ranked) {
         tile_minmax(m, v);
         presort_check(s, T, m, tid, NT, v, true);
         __syncthreads();
@@ -227,7 +231,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
             __syncthreads();
         }
     }
-    if (tord && !direct) {
+    if (tord && !direct && !ranked) {
         tile_count<F32>(st, m, v, arr, pass);
         __syncthreads();
         if ((m.flag[0] & 3u) != 0u) {
@@ -276,6 +280,12 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
         const int32_t N = tile_items(s, T);
         if (direct) {
             presort_place(s, m, v, tord);
+            __syncthreads();
+        } else if (ranked) {
+            u32 fin[kRegs];
+#pragma unroll
+            for (int j = 0; j < kRegs; j++) fin[j] = tv_key(v[j]) ^ 0x80000000u;
+            tile_place(m, v, fin);
             __syncthreads();
         } else {
             u32 c[kRegs];
@@ -330,7 +340,8 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
 
 // One workgroup per work unit.  512-thread tiles of at most 53 KB run three
 // workgroups per CU, which needs at most 80 VGPRs (six waves per SIMD).
-template <int NT, bool F32>
+// RK: the int32 form for the rank keys of 64-bit signals.
+template <int NT, bool F32, bool RK = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 6 : 8))) void k_tile_lds(Launch L, int *err)
 {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -340,7 +351,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 
     unit_shape<NT>(d, s, T);
     u32 raw[kRegs];
     load_raw(s, T, d.x, threadIdx.x, raw);
-    lds_tile<NT, F32>(d, s, T, raw, lds, err);
+    lds_tile<NT, F32, RK>(d, s, T, raw, lds, err);
 }
 
 // Persistent form for ragged work lists: a grid sized to the resident
@@ -1033,6 +1044,8 @@ hipError_t prepare_kernels()
     MF_ATTR((k_tile_lds<kLdsSmall, false>))
     MF_ATTR((k_tile_lds<kLdsLarge, true>))
     MF_ATTR((k_tile_lds<kLdsLarge, false>))
+    MF_ATTR((k_tile_lds<kLdsSmall, false, true>))
+    MF_ATTR((k_tile_lds<kLdsLarge, false, true>))
     MF_ATTR((k_tile_lds_persistent<kLdsSmall, true>))
     MF_ATTR((k_tile_lds_persistent<kLdsLarge, true>))
     MF_ATTR((k_tile_lds_persistent<kLdsSmall, false>))
@@ -1101,9 +1114,11 @@ hipError_t launch_forward(Path p, bool f32, const Launch &L, size_t lds_bytes,
         const dim3 g((unsigned)L.nunits), b((unsigned)nt);
         if (p == PATH_LDS_SMALL) {
             if (f32) hipLaunchKernelGGL((k_tile_lds<kLdsSmall, true>), g, b, lds_bytes, st, L, d_err);
+            else if (L.xshift) hipLaunchKernelGGL((k_tile_lds<kLdsSmall, false, true>), g, b, lds_bytes, st, L, d_err);
             else     hipLaunchKernelGGL((k_tile_lds<kLdsSmall, false>), g, b, lds_bytes, st, L, d_err);
         } else {
             if (f32) hipLaunchKernelGGL((k_tile_lds<kLdsLarge, true>), g, b, lds_bytes, st, L, d_err);
+            else if (L.xshift) hipLaunchKernelGGL((k_tile_lds<kLdsLarge, false, true>), g, b, lds_bytes, st, L, d_err);
             else     hipLaunchKernelGGL((k_tile_lds<kLdsLarge, false>), g, b, lds_bytes, st, L, d_err);
         }
         break;

@@ -36,7 +36,8 @@ struct Launch {
     const SigDesc *sigs;
     const Unit *units;
     int64_t nunits;
-    int64_t xshift;      // items added to x per tile of `one` (64-bit rank keys)
+    int64_t xshift;      // items added to x per tile of `one`; nonzero: x holds the
+                         // rank keys of a 64-bit signal (int32 kernels only)
 };
 
 // Backward launch: grad_y / argmed + y_off (n-k+1), grad_x + x_off (n).

@@ -25,9 +25,13 @@ extern "C" long emu_recount_tiles(void) { return g_recount_tiles; }
 extern "C" long emu_tile_order_tiles(void) { return g_tile_order_tiles; }
 extern "C" long emu_presorted_tiles(void) { return g_presorted_tiles; }
 
+static long g_ranked_tiles = 0;
+extern "C" long emu_ranked_tiles(void) { return g_ranked_tiles; }
+
 template <bool F32>
 static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
-                    const u32 *x, u32 *y, int32_t *argmed, std::vector<unsigned char> &lds)
+                    const u32 *x, u32 *y, int32_t *argmed, std::vector<unsigned char> &lds,
+                    bool ranked_keys = false)
 {
     const Tile T = make_tile(s, t);
     // poison the tile memory so that reads of unwritten data show up
@@ -70,6 +74,7 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
     note();
     bool fast = s.S >= kRegs && !g_force_merge;
     bool direct = false;
+    const bool ranked = tord && ranked_keys && !g_force_merge;
     std::vector<u32> arr((size_t)threads * kRegs), fin((size_t)threads * kRegs);
     const int32_t N = tile_items(s, T);
     auto attempt_counts = [&]() {
@@ -83,7 +88,7 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
             count(arr);
         }
     };
-    if (fast && tord) {
+    if (fast && tord && !ranked) {
         for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); tile_minmax(m, v); }
         for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); presort_check(s, T, m, q, threads, v, true); }
         direct = (m.flag[0] & 4u) == 0u;
@@ -94,7 +99,7 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
             note();
         }
     }
-    if (fast && tord && !direct) {
+    if (fast && tord && !direct && !ranked) {
         attempt_counts();
         if ((m.flag[0] & 1u) != 0u) {
             tord = false;
@@ -138,7 +143,18 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         }
         return 0;
     };
-    if (fast && direct) {
+    if (fast && ranked) {
+        g_ranked_tiles++;
+        for (int q = 0; q < threads; q++) {
+            u64 v[kRegs]; V(q, v);
+            u32 f[kRegs];
+            for (int j = 0; j < kRegs; j++) f[j] = tv_key(v[j]) ^ 0x80000000u;
+            tile_place(m, v, f);
+        }
+        const int rc = check_sorted();
+        if (rc) return rc;
+        g_fast_tiles++;
+    } else if (fast && direct) {
         g_presorted_tiles++;
         for (int q = 0; q < threads; q++) { u64 v[kRegs]; V(q, v); presort_place(s, m, v, tord); }
         const int rc = check_sorted();
@@ -402,7 +418,7 @@ extern "C" int emu_median_filter64(const void *x, int64_t n, int32_t k, int is_f
     std::vector<unsigned char> lds((size_t)l.total + 64);
     std::vector<u32> yj((size_t)(n - k + 1));
     for (int64_t t = 0; t < s.ntiles; t++) {
-        const int rc = run_tile<false>(s, l, t, threads, keys.data() + t * k, yj.data(), argmed, lds);
+        const int rc = run_tile<false>(s, l, t, threads, keys.data() + t * k, yj.data(), argmed, lds, true);
         if (rc != 0) return rc;
     }
     for (int64_t o = 0; o + k <= n; o++) ((u64 *)y)[o] = ((const u64 *)x)[argmed[o]];

@@ -149,6 +149,9 @@ def test_tile_phases_64bit_match_oracle(emu, kind, force_merge):
     finally:
         emu.emu_set_force_merge(0)
     b, m = emu.emu_rank_bucket_tiles() - b0, emu.emu_rank_merge_tiles() - m0
+    emu.emu_ranked_tiles.restype = ctypes.c_long
+    if not force_merge:
+        assert emu.emu_ranked_tiles() > 0     # tile-order tiles placed straight from the ranks
     if force_merge:
         assert b == 0 and m > 0
     elif kind in ("int64_full", "walk_f64"):
