@@ -160,9 +160,8 @@ mf_status forward_rows(const void *x, int64_t rows, int64_t n, int32_t k, void *
 }
 
 // Forward of one 64-bit signal: the rank pre-pass writes 32-bit keys tile
-// by tile into the workspace, the int32 tile kernel runs on them (each tile
-// reading its own span) and writes argmed, with its y stores going to the
-// first half of y, which the gather then overwrites with x[argmed].
+// by tile into the workspace; the int32 tile kernel runs on them (each tile
+// reading its own span) and copies each median from the 64-bit x to y.
 mf_status forward64(const void *x, int64_t n, int32_t k, void *y, int32_t *argmed, bool f64, hipStream_t st)
 {
     if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
@@ -177,31 +176,28 @@ mf_status forward64(const void *x, int64_t n, int32_t k, void *y, int32_t *argme
         MF_HIP(launch_identity64(x, y, argmed, n, st), "64-bit identity launch");
         return MF_OK;
     }
-    const int64_t nout = n - k + 1;
     const int64_t tiles = tiles_for(p, n, k);
     if (tiles > 0x7FFFFFFFll) return fail(MF_ERR_UNSUPPORTED, "too many tiles (%lld)", (long long)tiles);
     const int64_t stride = rank64_stride_for(p, k);
     const int64_t key_bytes = (tiles * stride * 4 + 255) & ~255ll;
-    const int64_t am_bytes = argmed ? 0 : nout * 4;
     unsigned char *ws = nullptr;
-    if ((s = acquire_ws(*D, key_bytes + am_bytes, st, &ws)) != MF_OK) return s;
+    if ((s = acquire_ws(*D, key_bytes, st, &ws)) != MF_OK) return s;
     uint32_t *keys = (uint32_t *)ws;
-    int32_t *am = argmed ? argmed : (int32_t *)(ws + key_bytes);
     MF_HIP(launch_rank64(p, f64, x, n, k, keys, stride, tiles, st), "64-bit rank launch");
     Launch L;
     memset(&L, 0, sizeof L);
     L.x = keys;
     L.y = y;
-    L.argmed = am;
+    L.argmed = argmed;
     L.one.n = n;
     L.one.k = k;
     L.rows = 1;
     L.tpr = tiles;
     L.nunits = tiles;
     L.xshift = k;
+    L.x64 = x;
     MF_HIP(launch_forward(p, false, L, (size_t)lds_bytes_for(p, k), nullptr, 0, 0, D->d_err, st),
            "64-bit forward launch");
-    MF_HIP(launch_gather64(x, n, am, y, nout, st), "64-bit gather launch");
     return release_ws(*D, st);
 }
 

@@ -111,16 +111,17 @@ __device__ __forceinline__ Resolved unit_of(const Launch &L, int64_t uidx)
 }
 
 // Phases 3-6 of a tile (pair merge, tables, walk, output); phases 1-2 have
-// filled m.srt.  NT threads, barriers between phases.
-template <int NT>
+// filled m.srt.  NT threads, barriers between phases.  The medians are
+// copied from xo to yo (V: 32- or 64-bit elements).
+template <int NT, typename V>
 __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
-                                          int *err, bool merged, u32 *rowbuf = nullptr)
+                                          const V *xo, V *yo, int *err, bool merged, u32 *rowbuf = nullptr)
 {
     const int tid = threadIdx.x;
     if (!merged) {
         tail_pair_pad(s, T, m, tid, NT);
         __syncthreads();
-        tail_pair_merge(s, T, m, tid, NT, d.x, (u32 *)d.y, d.argmed);
+        tail_pair_merge(s, T, m, tid, NT, xo, yo, d.argmed);
         __syncthreads();
         // the median before each pair's first step is A's median: remember
         // its merged position (before the count tables reuse the sort buffer)
@@ -156,12 +157,12 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
         __syncthreads();
         if (tail_walk(s, T, ml, tid, NT)) atomicOr(err, 1);
         __syncthreads();
-        tail_output(s, T, ml, tid, NT, d.x, (u32 *)d.y, d.argmed);
+        tail_output(s, T, ml, tid, NT, xo, yo, d.argmed);
         return;
     }
     if (tail_walk(s, T, m, tid, NT)) atomicOr(err, 1);
     __syncthreads();
-    tail_output(s, T, m, tid, NT, d.x, (u32 *)d.y, d.argmed);
+    tail_output(s, T, m, tid, NT, xo, yo, d.argmed);
 }
 
 // ------------------------------------------------------------------ LDS path
@@ -176,10 +177,12 @@ __device__ __forceinline__ void unit_shape(const Resolved &d, Shape &s, Tile &T)
 
 // One tile of the LDS path, every buffer in the workgroup's LDS; raw holds
 // the thread's inputs (load_raw).  RK: the inputs are rank keys of a 64-bit
-// signal (each tile's items' distinct tile-order positions).
-template <int NT, bool F32, bool RK = false>
+// signal (each tile's items' distinct tile-order positions).  The medians
+// are copied from xo to yo (V: u32, or u64 for a 64-bit signal).
+template <int NT, bool F32, bool RK = false, typename V = u32>
 __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, const Tile &T,
-                                         const u32 (&raw)[kRegs], unsigned char *lds, int *err)
+                                         const u32 (&raw)[kRegs], unsigned char *lds, int *err,
+                                         const V *xo, V *yo)
 {
     const int tid = threadIdx.x;
     Layout l;
@@ -313,7 +316,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
                 tail_table_zero(s, T, m, tid, NT);
                 __syncthreads();
             }
-            tile_positions(s, T, m, ex, w, d.x, (u32 *)d.y, d.argmed);
+            tile_positions(s, T, m, ex, w, xo, yo, d.argmed);
             tile_mpad(s, T, m, tid, NT);
             __syncthreads();
             merged = true;
@@ -335,7 +338,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
         __syncthreads();
     }
 
-    tile_tail<NT>(s, T, m, d, err, merged);
+    tile_tail<NT>(s, T, m, d, xo, yo, err, merged);
 }
 
 // One workgroup per work unit.  512-thread tiles of at most 53 KB run three
@@ -351,7 +354,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 
     unit_shape<NT>(d, s, T);
     u32 raw[kRegs];
     load_raw(s, T, d.x, threadIdx.x, raw);
-    lds_tile<NT, F32, RK>(d, s, T, raw, lds, err);
+    if constexpr (RK) {
+        // a 64-bit signal: medians gathered from its elements (one signal)
+        lds_tile<NT, F32, RK>(d, s, T, raw, lds, err, (const u64 *)L.x64, (u64 *)L.y);
+    } else {
+        lds_tile<NT, F32>(d, s, T, raw, lds, err, d.x, d.y);
+    }
 }
 
 // Persistent form for ragged work lists: a grid sized to the resident
@@ -394,7 +402,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         Shape s;
         Tile T;
         unit_shape<NT>(d, s, T);
-        lds_tile<NT, F32>(d, s, T, raw, lds, err);
+        lds_tile<NT, F32>(d, s, T, raw, lds, err, d.x, d.y);
         if (!more) break;
         d = dn;
 #pragma unroll
@@ -504,18 +512,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 
     u32 *out = keys + (int64_t)blockIdx.x * stride;
     const u32 *rank = (const u32 *)K;
     for (int32_t i = tid; i < span; i += NT) out[i] = rank[i];
-}
-
-// y[o] = x[argmed[o]] for 64-bit elements (an index outside the signal,
-// which a consistent walk never produces, reads x[0]).
-__global__ __launch_bounds__(256) void k_gather64(const u64 *x, int64_t n, const int32_t *argmed, u64 *y,
-                                                  int64_t nout)
-{
-    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (o < nout) {
-        const int64_t a = argmed[o];
-        y[o] = x[(a >= 0 && a < n) ? a : 0];
-    }
 }
 
 // k = 1 for 64-bit elements: y = x, argmed[o] = o.
@@ -798,7 +794,7 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
         // one-pair tiles: bucket sort of the pair (the sort buffer holds the
         // counters, then the waves' histogram row buffers)
         if (T.P == 1 && s.S >= 8192 && global_pair_bucket<F32>(s, T, m, d, srt, (u16 *)srt2, (u32 *)lds, gsh, wave_tot)) {
-            tile_tail<kGlobalThreads>(s, T, m, d, err, true, (u32 *)lds);
+            tile_tail<kGlobalThreads>(s, T, m, d, d.x, d.y, err, true, (u32 *)lds);
             continue;
         }
         // otherwise (a single block, or buckets that overflow on heavy ties):
@@ -854,7 +850,7 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
         }
         __syncthreads();
         // the sort buffer is free: it holds the waves' histogram row buffers
-        tile_tail<kGlobalThreads>(s, T, m, d, err, false, (u32 *)lds);
+        tile_tail<kGlobalThreads>(s, T, m, d, d.x, d.y, err, false, (u32 *)lds);
     }
 }
 
@@ -1201,15 +1197,6 @@ hipError_t launch_rank64(Path p, bool f64, const void *x, int64_t n, int32_t k, 
     } else {
         return hipErrorInvalidValue;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_gather64(const void *x, int64_t n, const int32_t *argmed, void *y, int64_t nout,
-                           hipStream_t st)
-{
-    if (nout <= 0) return hipSuccess;
-    const dim3 g((unsigned)((nout + 255) / 256));
-    hipLaunchKernelGGL(k_gather64, g, dim3(256), 0, st, (const u64 *)x, n, argmed, (u64 *)y, nout);
     return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ struct Launch {
     int64_t nunits;
     int64_t xshift;      // items added to x per tile of `one`; nonzero: x holds the
                          // rank keys of a 64-bit signal (int32 kernels only)
+    const void *x64;     // that 64-bit signal (y then holds 64-bit medians)
 };
 
 // Backward launch: grad_y / argmed + y_off (n-k+1), grad_x + x_off (n).
@@ -97,14 +98,12 @@ hipError_t launch_backward(const BwdLaunch &L, hipStream_t st);
 // Backward tiles of a signal of length n.
 int64_t bwd_tiles_for(int64_t n);
 
-// 64-bit signals on an LDS path: entries per tile of the rank buffer, the
-// rank pre-pass (one workgroup per tile), and y[o] = x[argmed[o]]; k = 1
-// copies x and writes argmed[o] = o.
+// 64-bit signals on an LDS path: entries per tile of the rank buffer and
+// the rank pre-pass (one workgroup per tile); k = 1 copies x and writes
+// argmed[o] = o.
 int64_t rank64_stride_for(Path p, int32_t k);
 hipError_t launch_rank64(Path p, bool f64, const void *x, int64_t n, int32_t k, uint32_t *keys, int64_t stride,
                          int64_t ntiles, hipStream_t st);
-hipError_t launch_gather64(const void *x, int64_t n, const int32_t *argmed, void *y, int64_t nout,
-                           hipStream_t st);
 hipError_t launch_identity64(const void *x, void *y, int32_t *argmed, int64_t n, hipStream_t st);
 
 hipError_t prepare_kernels();

@@ -1124,9 +1124,11 @@ MF_HD u64 tile_label_counts(const Shape &s, const TileMem &m, int32_t tid, int32
 
 // Per thread: with excl = the packed counts of all earlier items, the
 // merged positions of its items in both of their pairs (M and the position
-// maps), each pair's first median (A's item of own rank h) and output 0.
+// maps), each pair's first median (A's item of own rank h) and output 0
+// (x, y: the elements output 0 is copied from and to, 32- or 64-bit).
+template <typename V>
 MF_HD void tile_positions(const Shape &s, const Tile &T, const TileMem &m, u64 excl, const u32 (&w)[kRegs],
-                          const u32 *x, u32 *y, int32_t *argmed)
+                          const V *x, V *y, int32_t *argmed)
 {
     // with more than one walk chunk, also the count histogram of phase 4
     // (table_hist_item for both merged positions of every item)
@@ -1768,25 +1770,26 @@ MF_HD int64_t tile_outputs(const Shape &s, const Tile &T)
     return cnt;
 }
 
+template <typename V>
 MF_HD void tail_output(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT,
-                       const u32 *x, u32 *y, int32_t *argmed)
+                       const V *x, V *y, int32_t *argmed)
 {
     // the tile's outputs are o0 + it for it = p*k + i, it < (P-1)k + len of
     // the last block; every gather is issued before the first store
-    const u32 *xt = x + T.e0;
-    u32 *yt = y + T.o0;
+    const V *xt = x + T.e0;
+    V *yt = y + T.o0;
     int32_t *at = argmed ? argmed + T.o0 : nullptr;
     const int32_t e0 = (int32_t)T.e0;
     const int32_t nout = (T.P - 1) * s.k + T.lenLast;
     const u32 kr = recip32(s.k);
     for (int32_t base = 0; base < nout; base += NT * kRegs) {
-        u32 v[kRegs];
+        V v[kRegs];
         int32_t g[kRegs];
 #pragma unroll
         for (int j = 0; j < kRegs; j++) {
             const int32_t it = base + j * NT + tid;
             g[j] = 0;
-            v[j] = 0u;
+            v[j] = 0;
             if (it < nout) {
                 const int32_t p = (int32_t)udiv16((u32)it, kr);
                 const int32_t r = m.stage[it];
@@ -1807,7 +1810,8 @@ MF_HD void tail_output(const Shape &s, const Tile &T, const TileMem &m, int32_t 
 }
 
 // Output 0: the median of block 0 (Section 3: Y_0's only element).
-MF_HD void output_first(const Shape &s, const Tile &T, const TileMem &m, const u32 *x, u32 *y, int32_t *argmed)
+template <typename V>
+MF_HD void output_first(const Shape &s, const Tile &T, const TileMem &m, const V *x, V *y, int32_t *argmed)
 {
     const int32_t t = (int32_t)(m.sslot[s.h] & (u32)(s.S - 1));
     y[0] = x[t];
@@ -1825,8 +1829,9 @@ MF_HD void tail_pair_pad(const Shape &s, const Tile &T, const TileMem &m, int32_
     }
 }
 
+template <typename V>
 MF_HD void tail_pair_merge(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT,
-                           const u32 *x, u32 *y, int32_t *argmed)
+                           const V *x, V *y, int32_t *argmed)
 {
     const int32_t ipp = merge_items_per_pair(s);
     const u32 ir = recip32(ipp);

@@ -28,9 +28,12 @@ extern "C" long emu_presorted_tiles(void) { return g_presorted_tiles; }
 static long g_ranked_tiles = 0;
 extern "C" long emu_ranked_tiles(void) { return g_ranked_tiles; }
 
-template <bool F32>
+// x: the 32-bit inputs the tile sorts; xo, yo: the elements the medians are
+// copied from and to (x and y, or a 64-bit signal's elements when x holds
+// its rank keys).
+template <bool F32, typename E>
 static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
-                    const u32 *x, u32 *y, int32_t *argmed, std::vector<unsigned char> &lds,
+                    const u32 *x, const E *xo, E *yo, int32_t *argmed, std::vector<unsigned char> &lds,
                     bool ranked_keys = false)
 {
     const Tile T = make_tile(s, t);
@@ -240,13 +243,13 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         for (int q = 0; q < threads; q++) {
             u32 ww[kRegs];
             for (int j = 0; j < kRegs; j++) ww[j] = w[(size_t)q * kRegs + j];
-            tile_positions(s, T, m, ex, ww, x, y, argmed);
+            tile_positions(s, T, m, ex, ww, xo, yo, argmed);
             ex += cnt[q];
         }
         for (int q = 0; q < threads; q++) tile_mpad(s, T, m, q, threads);
     } else {
         for (int q = 0; q < threads; q++) tail_pair_pad(s, T, m, q, threads);
-        for (int q = 0; q < threads; q++) tail_pair_merge(s, T, m, q, threads, x, y, argmed);
+        for (int q = 0; q < threads; q++) tail_pair_merge(s, T, m, q, threads, xo, yo, argmed);
         for (int q = 0; q < threads; q++) tail_first_medians(s, T, m, q, threads);
     }
     if (s.C > 1) {
@@ -260,7 +263,7 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
     }
     for (int q = 0; q < threads; q++)
         if (tail_walk(s, T, m, q, threads)) return -11;
-    for (int q = 0; q < threads; q++) tail_output(s, T, m, q, threads, x, y, argmed);
+    for (int q = 0; q < threads; q++) tail_output(s, T, m, q, threads, xo, yo, argmed);
     return 0;
 }
 
@@ -276,8 +279,8 @@ extern "C" int emu_median_filter(const void *x, int64_t n, int32_t k, int is_f32
     if (out_pmax) *out_pmax = s.Pmax;
     std::vector<unsigned char> lds((size_t)l.total + 64);
     for (int64_t t = 0; t < s.ntiles; t++) {
-        const int rc = is_f32 ? run_tile<true>(s, l, t, threads, (const u32 *)x, (u32 *)y, argmed, lds)
-                              : run_tile<false>(s, l, t, threads, (const u32 *)x, (u32 *)y, argmed, lds);
+        const int rc = is_f32 ? run_tile<true>(s, l, t, threads, (const u32 *)x, (const u32 *)x, (u32 *)y, argmed, lds)
+                              : run_tile<false>(s, l, t, threads, (const u32 *)x, (const u32 *)x, (u32 *)y, argmed, lds);
         if (rc != 0) return rc;
     }
     return 0;
@@ -285,8 +288,8 @@ extern "C" int emu_median_filter(const void *x, int64_t n, int32_t k, int is_f32
 
 // 64-bit signals: the rank pre-pass (each phase of the kernel as one sweep
 // over the threads, barriers between sweeps), a check that each tile's
-// ranks are a permutation, the 32-bit tiles on the ranks (tile t reading its
-// span at keys + t*k) and the gather y = x[argmed].
+// ranks are a permutation, then the 32-bit tiles on the ranks (tile t
+// reading its span at keys + t*k) copying the medians from the 64-bit x.
 extern "C" int emu_median_filter64(const void *x, int64_t n, int32_t k, int is_f64, int threads,
                                    void *y, int32_t *argmed)
 {
@@ -416,11 +419,10 @@ extern "C" int emu_median_filter64(const void *x, int64_t n, int32_t k, int is_f
         }
     }
     std::vector<unsigned char> lds((size_t)l.total + 64);
-    std::vector<u32> yj((size_t)(n - k + 1));
     for (int64_t t = 0; t < s.ntiles; t++) {
-        const int rc = run_tile<false>(s, l, t, threads, keys.data() + t * k, yj.data(), argmed, lds, true);
+        const int rc = run_tile<false>(s, l, t, threads, keys.data() + t * k, (const u64 *)x, (u64 *)y, argmed,
+                                       lds, true);
         if (rc != 0) return rc;
     }
-    for (int64_t o = 0; o + k <= n; o++) ((u64 *)y)[o] = ((const u64 *)x)[argmed[o]];
     return 0;
 }
