@@ -426,3 +426,34 @@ extern "C" int emu_median_filter64(const void *x, int64_t n, int32_t k, int is_f
     }
     return 0;
 }
+
+// Tiles [t0, t1) of a signal of length n (a check of the index arithmetic
+// near the end of long signals): x, y and argmed point at element `base` of
+// the signal, input and outputs, so that only x[base ..], y[base ..] and
+// argmed[base ..] need to exist.
+extern "C" int emu_tile_range(const float *x_at_base, int64_t base, int64_t n, int32_t k, int threads,
+                              int64_t t0, int64_t t1, float *y_at_base, int32_t *argmed_at_base)
+{
+    Shape s;
+    if (make_shape(n, k, threads, &s) != 0) return -2;
+    Layout l;
+    make_layout(s, &l);
+    if (l.total < 0) return -3;
+    if (t1 > s.ntiles) t1 = s.ntiles;
+    std::vector<unsigned char> lds((size_t)l.total + 64);
+    const u32 *x = (const u32 *)x_at_base - base;
+    u32 *y = (u32 *)y_at_base - base;
+    int32_t *am = argmed_at_base - base;
+    for (int64_t t = t0; t < t1; t++) {
+        const int rc = run_tile<true>(s, l, t, threads, x, x, y, am, lds);
+        if (rc != 0) return rc;
+    }
+    return 0;
+}
+
+extern "C" int64_t emu_ntiles(int64_t n, int32_t k, int threads)
+{
+    Shape s;
+    if (make_shape(n, k, threads, &s) != 0) return -1;
+    return s.ntiles;
+}

@@ -168,3 +168,31 @@ def test_tile_phases_64bit_presorted_and_single_block(emu):
             assert rc == 0, (k, n, rc)
             _, want = oracle.sortmedian(x, k)
             assert np.array_equal(am, want), (k, n)
+
+
+@pytest.mark.parametrize("k,threads", [(3, 512), (31, 512), (1001, 512), (2047, 512), (4095, 1024)])
+def test_last_tiles_of_longest_signal(emu, k, threads):
+    """The index arithmetic of the last tiles of an n = 2^31 - 1 signal (the
+    largest argmed index): only the signal's tail is allocated, and the
+    outputs the last three tiles write are checked against the definition."""
+    emu.emu_tile_range.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
+                                   ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+    emu.emu_ntiles.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int]
+    emu.emu_ntiles.restype = ctypes.c_int64
+    n = 2**31 - 1
+    nt = emu.emu_ntiles(n, k, threads)
+    base = n - 3 * 8192 * 4          # before the first item of the last three tiles
+    xs = np.random.default_rng(k).random(n - base).astype(np.float32)
+    y = np.full(n - base, np.nan, np.float32)
+    am = np.full(n - base, -1, np.int32)
+    rc = emu.emu_tile_range(xs.ctypes.data, base, n, k, threads, nt - 3, nt, y.ctypes.data, am.ctypes.data)
+    assert rc == 0
+    nout = n - k + 1
+    written = np.nonzero(am >= 0)[0]
+    assert written.max() + base == nout - 1
+    outs = np.arange(base + written.min(), nout, dtype=np.int64)
+    assert np.all(am[outs - base] >= 0)
+    sel = outs[:: max(1, len(outs) // 300)]
+    want = oracle.window_median(xs, k, sel - base) + base
+    assert np.array_equal(am[sel - base], want)
+    assert np.array_equal(y[sel - base].view(np.uint32), xs[want - base].view(np.uint32))
