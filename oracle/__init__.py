@@ -19,6 +19,9 @@ single-threaded C underneath):
                               scatter of the upstream gradient to the
                               selected inputs, float64 accumulation in
                               increasing output index, one rounding.
+  backward_f64(grad_y, argmed, n, k)
+                              the same for a float64 upstream gradient
+                              (float64 result, no rounding).
   sortmedian_batched(x, offsets, ks)
                               sortmedian applied per signal of a packed
                               ragged batch.
@@ -62,6 +65,8 @@ def _lib():
             f.restype = ctypes.c_int
         lib.oracle_backward.argtypes = [P, P, I64, I32, P, P]
         lib.oracle_backward.restype = ctypes.c_int
+        lib.oracle_backward_f64.argtypes = [P, P, I64, I32, P]
+        lib.oracle_backward_f64.restype = ctypes.c_int
         _LIB = lib
     return _LIB
 
@@ -120,6 +125,15 @@ def backward(grad_y, argmed, n, k):
     _check(_lib().oracle_backward(_ptr(grad_y), _ptr(argmed), int(n), int(k),
                                   _ptr(g64), _ptr(g32)))
     return g32, g64
+
+
+def backward_f64(grad_y, argmed, n, k):
+    """grad_x (float64) for a float64 upstream gradient."""
+    grad_y = np.ascontiguousarray(grad_y, dtype=np.float64)
+    argmed = np.ascontiguousarray(argmed, dtype=np.int32)
+    g = np.empty(int(n), dtype=np.float64)
+    _check(_lib().oracle_backward_f64(_ptr(grad_y), _ptr(argmed), int(n), int(k), _ptr(g)))
+    return g
 
 
 def sortmedian_batched(x, offsets, ks):

@@ -39,7 +39,8 @@
  *   - k must be odd with 1 <= k <= n.
  *
  * Backward (not in the paper): grad_x[j] = sum of grad_y[o] over all o with
- * argmed[o] == j, accumulated in float64 in increasing o, rounded once.
+ * argmed[o] == j, accumulated in float64 in increasing o, rounded once
+ * (float32 gradients) or not at all (float64 gradients).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -410,5 +411,20 @@ int oracle_backward(const float *grad_y, const int32_t *argmed, int64_t n, int32
     }
     if (grad_x)
         for (int64_t j = 0; j < n; j++) grad_x[j] = (float)grad_x64[j];
+    return OR_OK;
+}
+
+/* The same scatter for a float64 upstream gradient (float64 signals): the
+ * float64 sums in increasing o are the result, with no final rounding. */
+int oracle_backward_f64(const double *grad_y, const int32_t *argmed, int64_t n, int32_t k,
+                        double *grad_x)
+{
+    if (k < 1 || (k & 1) == 0 || n < k) return OR_EINVAL;
+    for (int64_t j = 0; j < n; j++) grad_x[j] = 0.0;
+    for (int64_t o = 0; o + k <= n; o++) {
+        const int32_t j = argmed[o];
+        if (j < o || j > o + k - 1) return OR_EINVAL;
+        grad_x[j] += grad_y[o];
+    }
     return OR_OK;
 }

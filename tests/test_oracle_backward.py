@@ -84,3 +84,46 @@ def test_finite_differences_fd_slice():
         xm[j] = np.float32(x[j] - eps)
         fd = (L(xp) - L(xm)) / (float(xp[j]) - float(xm[j]))
         assert abs(fd - g64[j]) <= 1e-4 * (1 + abs(fd)), (j, fd, g64[j])
+
+
+def test_backward_f64_integer_exact_and_dense():
+    """float64 upstream gradients: integer values give exact sums (against a
+    bincount), and random values match the dense Jacobian product within
+    the float64 accumulation bound."""
+    rng = np.random.default_rng(31)
+    for k in (1, 3, 31, 201):
+        n = 10_000
+        x = rng.standard_normal(n)
+        _, a = oracle.sortmedian(x, k)
+        g = rng.integers(-10**12, 10**12, n - k + 1)
+        got = oracle.backward_f64(g.astype(np.float64), a, n, k)
+        exact = np.zeros(n, dtype=np.int64)
+        np.add.at(exact, a, g)
+        assert np.array_equal(got, exact.astype(np.float64))
+    n, k = 300, 9
+    x = rng.standard_normal(n)
+    am = rank_count_argmed(x, k)
+    J = np.zeros((n - k + 1, n))
+    J[np.arange(n - k + 1), am] = 1.0
+    g = rng.standard_normal(n - k + 1)
+    got = oracle.backward_f64(g, oracle.sortmedian(x, k)[1], n, k)
+    ref = J.T @ g
+    assert np.allclose(got, ref, rtol=0, atol=k * 2.0 ** -52 * np.abs(g).max() * 4)
+
+
+def test_backward_f64_finite_differences():
+    """Central differences of L(x) = sum_o g_o y_o(x) through the float64
+    forward oracle, on well-separated values (the step never reorders a
+    window)."""
+    rng = np.random.default_rng(32)
+    n, k, eps = 2000, 31, 1e-6
+    x = rng.permutation(n).astype(np.float64) * 1e-3      # neighbours 1e-3 apart
+    g = rng.standard_normal(n - k + 1)
+    _, a = oracle.sortmedian(x, k)
+    got = oracle.backward_f64(g, a, n, k)
+    for j in rng.integers(0, n, 60):
+        xp, xm = x.copy(), x.copy()
+        xp[j] += eps
+        xm[j] -= eps
+        fd = (np.dot(g, oracle.sortmedian(xp, k)[0]) - np.dot(g, oracle.sortmedian(xm, k)[0])) / (2 * eps)
+        assert abs(fd - got[j]) <= 1e-6 * max(1.0, abs(got[j])), (j, fd, got[j])
