@@ -97,6 +97,13 @@ mf_status mf_median_filter_batched_i32(const int32_t *x, const int64_t *x_offset
 mf_status mf_median_filter_backward(const float *grad_y, const int32_t *argmed,
                                     int64_t n, int32_t k, float *grad_x, void *stream);
 
+/* Backward of mf_median_filter_f64 (and of the int64 forward's argmed):
+ * float64 gradients, grad_x[j] = sum of grad_y[o] over the outputs o with
+ * argmed[o] == j, accumulated in float64 in increasing o (no rounding);
+ * 0 where no output selects j.  Deterministic; grad_x fully overwritten. */
+mf_status mf_median_filter_backward_f64(const double *grad_y, const int32_t *argmed,
+                                        int64_t n, int32_t k, double *grad_x, void *stream);
+
 /* Backward of mf_median_filter_rows (same layouts). */
 mf_status mf_median_filter_backward_rows(const float *grad_y, const int32_t *argmed,
                                          int64_t rows, int64_t n, int32_t k,

@@ -85,8 +85,16 @@ def median_filter_batched(x, x_offsets, ks, with_argmed=True):
 
 
 def median_filter_backward(grad_y, argmed, n, k):
+    """grad_x of y = x[argmed]: float32 for a float32 grad_y (rows too),
+    float64 for a float64 grad_y of one signal."""
     _require_gpu(grad_y, "grad_y")
     _require_gpu(argmed, "argmed")
+    if grad_y.dtype == torch.float64:
+        if grad_y.dim() != 1:
+            raise TypeError("float64 gradients take one signal")
+        gx = torch.empty(int(n), dtype=torch.float64, device=grad_y.device)
+        lib.mf_median_filter_backward_f64(grad_y, argmed, n, k, gx)
+        return gx
     if grad_y.dim() == 1:
         gx = torch.empty(int(n), dtype=torch.float32, device=grad_y.device)
         lib.mf_median_filter_backward(grad_y, argmed, n, k, gx)
@@ -104,11 +112,13 @@ def median_filter_backward_batched(grad_y, argmed, x_offsets, ks):
 
 
 class MedianFilterFn(torch.autograd.Function):
-    """y = median filter of x (float32, shape (n,) or (rows, n)).
+    """y = median filter of x (float32, shape (n,) or (rows, n); or one
+    float64 signal).
 
     The backward routes each upstream gradient entry to the input selected as
     that window's median (argmed), summed per input in increasing output
-    index in float64 and rounded once: deterministic run to run."""
+    index in float64 (and rounded once for float32): deterministic run to
+    run."""
 
     @staticmethod
     def forward(ctx, x, k):
@@ -117,11 +127,14 @@ class MedianFilterFn(torch.autograd.Function):
         ctx.save_for_backward(am)
         ctx.n = x.shape[-1]
         ctx.k = int(k)
+        ctx.f64 = x.dtype == torch.float64
         ctx.mark_non_differentiable(am)
         return y, am
 
     @staticmethod
     def backward(ctx, grad_y, grad_am):
         (am,) = ctx.saved_tensors
-        gx = median_filter_backward(grad_y.contiguous().float(), am, ctx.n, ctx.k)
+        g = grad_y.contiguous()
+        g = g.double() if ctx.f64 else g.float()
+        gx = median_filter_backward(g, am, ctx.n, ctx.k)
         return gx, None

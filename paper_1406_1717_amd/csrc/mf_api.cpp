@@ -201,8 +201,9 @@ mf_status forward64(const void *x, int64_t n, int32_t k, void *y, int32_t *argme
     return release_ws(*D, st);
 }
 
-mf_status backward_rows(const float *gy, const int32_t *argmed, int64_t rows, int64_t n,
-                        int32_t k, float *gx, hipStream_t st)
+// Backward over `rows` equal signals; f64: float64 gradients.
+mf_status backward_rows(const void *gy, const int32_t *argmed, int64_t rows, int64_t n,
+                        int32_t k, void *gx, bool f64, hipStream_t st)
 {
     if (!gy || !argmed || !gx) return fail(MF_ERR_INVALID_VALUE, "grad_y, argmed and grad_x must not be null");
     if (rows < 1) return fail(MF_ERR_INVALID_VALUE, "rows = %lld must be >= 1", (long long)rows);
@@ -220,7 +221,7 @@ mf_status backward_rows(const float *gy, const int32_t *argmed, int64_t rows, in
     L.rows = rows;
     L.tpr = bwd_tiles_for(n);
     L.nunits = rows * L.tpr;
-    MF_HIP(launch_backward(L, st), "backward launch");
+    MF_HIP(launch_backward(L, f64, st), "backward launch");
     return MF_OK;
 }
 
@@ -490,7 +491,7 @@ extern "C" mf_status mf_plan_execute_backward(mf_plan *p, const float *grad_y, c
     L.sigs = p->d_sigs;
     L.units = p->d_bunits;
     L.nunits = p->nbunits;
-    MF_HIP(launch_backward(L, (hipStream_t)stream), "batched backward launch");
+    MF_HIP(launch_backward(L, false, (hipStream_t)stream), "batched backward launch");
     return MF_OK;
 }
 
@@ -656,13 +657,19 @@ extern "C" mf_status mf_median_filter_batched_i32(const int32_t *x, const int64_
 extern "C" mf_status mf_median_filter_backward(const float *grad_y, const int32_t *argmed, int64_t n,
                                                int32_t k, float *grad_x, void *stream)
 {
-    return backward_rows(grad_y, argmed, 1, n, k, grad_x, (hipStream_t)stream);
+    return backward_rows(grad_y, argmed, 1, n, k, grad_x, false, (hipStream_t)stream);
+}
+
+extern "C" mf_status mf_median_filter_backward_f64(const double *grad_y, const int32_t *argmed, int64_t n,
+                                                   int32_t k, double *grad_x, void *stream)
+{
+    return backward_rows(grad_y, argmed, 1, n, k, grad_x, true, (hipStream_t)stream);
 }
 
 extern "C" mf_status mf_median_filter_backward_rows(const float *grad_y, const int32_t *argmed, int64_t rows,
                                                     int64_t n, int32_t k, float *grad_x, void *stream)
 {
-    return backward_rows(grad_y, argmed, rows, n, k, grad_x, (hipStream_t)stream);
+    return backward_rows(grad_y, argmed, rows, n, k, grad_x, false, (hipStream_t)stream);
 }
 
 extern "C" mf_status mf_median_filter_backward_batched(const float *grad_y, const int32_t *argmed,

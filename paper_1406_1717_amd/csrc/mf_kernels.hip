@@ -882,14 +882,15 @@ __global__ void k_identity(Launch L)
 // terms in increasing o.
 __device__ __forceinline__ u64 wave_ballot(bool p) { return (u64)__ballot(p); }
 
+template <typename GT>
 __global__ __launch_bounds__(kBwdThreads) void k_backward(BwdLaunch L)
 {
     __shared__ double acc[kBwdThreads / 64][kBwdTargetsPerWave];
-    __shared__ float gstage[kBwdThreads / 64][64];
+    __shared__ GT gstage[kBwdThreads / 64][64];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     double *A = acc[wave];
-    float *G = gstage[wave];
+    GT *G = gstage[wave];
 
     for (int64_t uidx = blockIdx.x; uidx < L.nunits; uidx += gridDim.x) {
         SigDesc sd;
@@ -906,12 +907,12 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(BwdLaunch L)
             sd.y_off += row * (sd.n - sd.k + 1);
         }
         struct {
-            const float *grad_y;
+            const GT *grad_y;
             const int32_t *argmed;
-            float *grad_x;
+            GT *grad_x;
             int64_t n;
             int32_t k;
-        } d = {L.grad_y + sd.y_off, L.argmed + sd.y_off, L.grad_x + sd.x_off, sd.n, sd.k};
+        } d = {(const GT *)L.grad_y + sd.y_off, L.argmed + sd.y_off, (GT *)L.grad_x + sd.x_off, sd.n, sd.k};
         const int64_t nout = d.n - d.k + 1;
         const int64_t j0 = tile * kBwdTargetsPerBlock + (int64_t)wave * kBwdTargetsPerWave;
         for (int t = lane; t < kBwdTargetsPerWave; t += 64) A[t] = 0.0;
@@ -927,7 +928,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(BwdLaunch L)
             // order (increasing o)
             for (int64_t g0 = olo; g0 < ohi; g0 += 64 * kBwdGroup) {
                 int tgt[kBwdGroup];
-                float gv[kBwdGroup];
+                GT gv[kBwdGroup];
 #pragma unroll
                 for (int q = 0; q < kBwdGroup; q++) {
                     const int64_t o = g0 + q * 64 + lane;
@@ -968,7 +969,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(BwdLaunch L)
                 }
             }
             for (int t = lane; t < kBwdTargetsPerWave; t += 64)
-                if (j0 + t < d.n) d.grad_x[j0 + t] = (float)A[t];
+                if (j0 + t < d.n) d.grad_x[j0 + t] = (GT)A[t];
         }
         __syncthreads();
     }
@@ -1164,11 +1165,12 @@ hipError_t launch_forward_persistent(Path p, bool f32, const Launch &L, size_t l
 
 int64_t bwd_tiles_for(int64_t n) { return (n + kBwdTargetsPerBlock - 1) / kBwdTargetsPerBlock; }
 
-hipError_t launch_backward(const BwdLaunch &L, hipStream_t st)
+hipError_t launch_backward(const BwdLaunch &L, bool f64, hipStream_t st)
 {
     if (L.nunits <= 0) return hipSuccess;
     const int64_t grid = L.nunits < (1ll << 20) ? L.nunits : (1ll << 20);
-    hipLaunchKernelGGL(k_backward, dim3((unsigned)grid), dim3(kBwdThreads), 0, st, L);
+    if (f64) hipLaunchKernelGGL(k_backward<double>, dim3((unsigned)grid), dim3(kBwdThreads), 0, st, L);
+    else     hipLaunchKernelGGL(k_backward<float>, dim3((unsigned)grid), dim3(kBwdThreads), 0, st, L);
     return hipGetLastError();
 }
 

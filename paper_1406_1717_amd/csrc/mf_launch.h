@@ -41,11 +41,12 @@ struct Launch {
     const void *x64;     // that 64-bit signal (y then holds 64-bit medians)
 };
 
-// Backward launch: grad_y / argmed + y_off (n-k+1), grad_x + x_off (n).
+// Backward launch: grad_y / argmed + y_off (n-k+1), grad_x + x_off (n);
+// gradients are float32, or float64 with the 64-bit entry points.
 struct BwdLaunch {
-    const float *grad_y;
+    const void *grad_y;
     const int32_t *argmed;
-    float *grad_x;
+    void *grad_x;
     SigDesc one;
     int64_t rows;
     int64_t tpr;
@@ -93,7 +94,7 @@ hipError_t launch_forward(Path p, bool f32, const Launch &L, size_t lds_bytes,
 hipError_t launch_forward_persistent(Path p, bool f32, const Launch &L, size_t lds_bytes, uint32_t *next,
                                     int *d_err, hipStream_t st);
 
-hipError_t launch_backward(const BwdLaunch &L, hipStream_t st);
+hipError_t launch_backward(const BwdLaunch &L, bool f64, hipStream_t st);
 
 // Backward tiles of a signal of length n.
 int64_t bwd_tiles_for(int64_t n);

@@ -100,3 +100,31 @@ def test_finite_differences_on_gpu_forward():
     for q, j in enumerate(probe):
         fd = (L[2 * q] - L[2 * q + 1]) / (float(xs[2 * q, j]) - float(xs[2 * q + 1, j]))
         assert abs(fd - gx[j]) <= 1e-4 * (1 + abs(fd)), (j, fd, gx[j])
+
+
+@pytest.mark.parametrize("k", [1, 3, 101, 1001, 4095])
+def test_backward_f64_bitwise_vs_oracle(k):
+    """float64 signal and gradient: forward on the GPU, backward on the GPU
+    against the oracle's float64 scatter, bit for bit."""
+    from paper_1406_1717_amd import workloads
+    n = max(3 * k, 30_000) + 11
+    x = workloads.random_walk_f64(n, 40 + k)
+    g = np.random.default_rng(41 + k).standard_normal(n - k + 1)
+    xt = torch.from_numpy(x).to(DEV).requires_grad_(True)
+    y, am = mf.MedianFilterFn.apply(xt, k)
+    y.backward(torch.from_numpy(g).to(DEV))
+    torch.cuda.synchronize()
+    _, ao = oracle.sortmedian(x, k)
+    assert np.array_equal(am.cpu().numpy(), ao)
+    want = oracle.backward_f64(g, ao, n, k)
+    got = xt.grad.cpu().numpy()
+    assert got.dtype == np.float64
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def test_backward_f64_gradcheck():
+    """torch.autograd.gradcheck in float64 on well-separated values."""
+    n, k = 600, 31
+    x = torch.from_numpy(np.random.default_rng(42).permutation(n).astype(np.float64) * 1e-2).to(DEV)
+    x.requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda t: mf.MedianFilterFn.apply(t, k)[0], (x,), eps=1e-6, atol=1e-7)
