@@ -159,9 +159,10 @@ mf_status forward_rows(const void *x, int64_t rows, int64_t n, int32_t k, void *
     return MF_OK;
 }
 
-// Forward of one 64-bit signal: the rank pre-pass writes 32-bit keys tile
-// by tile into the workspace; the int32 tile kernel runs on them (each tile
-// reading its own span) and copies each median from the 64-bit x to y.
+// Forward of one 64-bit signal through the int32 tile kernels on 32-bit
+// rank keys, which copy each median from the 64-bit x to y.  512-thread
+// tiles rank their items in LDS; for 1024-thread tiles a pre-pass writes
+// the keys tile by tile into the workspace and each tile reads its span.
 mf_status forward64(const void *x, int64_t n, int32_t k, void *y, int32_t *argmed, bool f64, hipStream_t st)
 {
     if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
@@ -178,6 +179,23 @@ mf_status forward64(const void *x, int64_t n, int32_t k, void *y, int32_t *argme
     }
     const int64_t tiles = tiles_for(p, n, k);
     if (tiles > 0x7FFFFFFFll) return fail(MF_ERR_UNSUPPORTED, "too many tiles (%lld)", (long long)tiles);
+    if (p == PATH_LDS_SMALL) {   // 512-thread tiles rank their items in LDS
+        Launch L;
+        memset(&L, 0, sizeof L);
+        L.x = x;
+        L.y = y;
+        L.argmed = argmed;
+        L.one.n = n;
+        L.one.k = k;
+        L.rows = 1;
+        L.tpr = tiles;
+        L.nunits = tiles;
+        L.rank_mode = f64 ? 3 : 2;
+        L.x64 = x;
+        MF_HIP(launch_forward(p, false, L, (size_t)rank64_lds_bytes_for(p, k), nullptr, 0, 0, D->d_err, st),
+               "64-bit forward launch");
+        return MF_OK;
+    }
     const int64_t stride = rank64_stride_for(p, k);
     const int64_t key_bytes = (tiles * stride * 4 + 255) & ~255ll;
     unsigned char *ws = nullptr;
@@ -194,6 +212,7 @@ mf_status forward64(const void *x, int64_t n, int32_t k, void *y, int32_t *argme
     L.rows = 1;
     L.tpr = tiles;
     L.nunits = tiles;
+    L.rank_mode = 1;
     L.xshift = k;
     L.x64 = x;
     MF_HIP(launch_forward(p, false, L, (size_t)lds_bytes_for(p, k), nullptr, 0, 0, D->d_err, st),

@@ -1,16 +1,20 @@
 // HIP kernels of the sorting-based median filter (arXiv:1406.1717) for
 // gfx950.  The per-tile phases live in mf_tile.h; this file runs them:
 //
-//   k_tile_lds<NT>   k <= 4096: one workgroup per tile, every tile buffer
+//   k_tile_lds<NT>   k <= 4095: one workgroup per tile, every tile buffer
 //                    in LDS (NT = 512 threads for blocks up to 2048 slots,
-//                    1024 above).
+//                    1024 above); a ranked int32 form runs on the rank keys
+//                    of 64-bit signals and copies 64-bit medians.
 //   k_tile_lds_persistent  the same tiles for ragged batches: a resident
 //                    grid taking units from a work counter.
-//   k_tile_global    4096 < k <= 32767: one pair per tile, the first sort
-//                    levels in LDS and the tile buffers in a per-workgroup
-//                    global workspace; workgroups loop over tiles.
-//   k_identity       k = 1.
-//   k_backward       deterministic scatter of the upstream gradient.
+//   k_tile_global    4096 < k <= 32767: one pair per tile, bucket-sorted
+//                    with the tile buffers in a per-workgroup global
+//                    workspace; workgroups loop over tiles.
+//   k_rank64         64-bit signals: each tile's items ranked by (key,
+//                    index) into 32-bit keys.
+//   k_identity, k_identity64   k = 1.
+//   k_backward       deterministic scatter of the upstream gradient
+//                    (float32 or float64).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -163,6 +167,120 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
     if (tail_walk(s, T, m, tid, NT)) atomicOr(err, 1);
     __syncthreads();
     tail_output(s, T, m, tid, NT, xo, yo, d.argmed);
+}
+
+// ------------------------------------------------------------------ 64-bit ranks
+
+__device__ __forceinline__ u64 wave_min_u64(u64 v)
+{
+    for (int d = 32; d > 0; d >>= 1) {
+        const u64 o = (u64)__shfl_xor((unsigned long long)v, d);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ u64 wave_max_u64(u64 v)
+{
+    for (int d = 32; d > 0; d >>= 1) {
+        const u64 o = (u64)__shfl_xor((unsigned long long)v, d);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// The ranks of tile T's items by (64-bit key, index), left in LDS as u32
+// per item offset from the tile's first item (at lds).  The sort is a
+// bucket sort over cap buckets, or, for a tile with a crowded bucket, a
+// merge sort (registers, then stable merge-path levels).  LDS: keys (8 B
+// per position), slots (2 B), 16-bit bucket counters (2 B per bucket); the
+// ranks reuse the keys.  Ends with a barrier.
+template <int NT, bool F64>
+__device__ __forceinline__ void rank_tile(const Shape &s, const Tile &T, const u64 *x, unsigned char *lds)
+{
+    __shared__ u64 red_lo[NT / 64], red_hi[NT / 64];
+    __shared__ u32 wave_tot[NT / 64];
+    __shared__ u32 full;
+    static_assert(kRegs == 8, "slots are stored as one 16-byte word per thread");
+    const int tid = threadIdx.x;
+    const int32_t cap = NT * kRegs;
+    u64 *K = (u64 *)lds;
+    u16 *S = (u16 *)(lds + 8 * cap);
+    u32 *C = (u32 *)(lds + 10 * cap);
+    const int32_t span = tile_items(s, T);
+    u64 kv[kRegs];
+    u32 sv[kRegs];
+    rank64_load<F64>(s, T, x, tid, kv, sv);
+#pragma unroll
+    for (int w = 0; w < kRegs / 2; w++) C[tid * (kRegs / 2) + w] = 0u;
+    if (tid == 0) full = 0u;
+    u64 lo, hi;
+    rank64_range(span, kv, sv, lo, hi);
+    lo = wave_min_u64(lo);
+    hi = wave_max_u64(hi);
+    if ((tid & 63) == 0) {
+        red_lo[tid >> 6] = lo;
+        red_hi[tid >> 6] = hi;
+    }
+    __syncthreads();
+    lo = red_lo[0];
+    hi = red_hi[0];
+    for (int w = 1; w < NT / 64; w++) {
+        lo = red_lo[w] < lo ? red_lo[w] : lo;
+        hi = red_hi[w] > hi ? red_hi[w] : hi;
+    }
+    const int32_t lognb = NT == 512 ? 12 : 13;
+    static_assert(NT * kRegs == 512 * 8 || NT * kRegs == 1024 * 8, "cap is 4096 or 8192");
+    const u32 sh = rank64_shift(lo, hi, lognb);
+    u32 arr[kRegs];
+    if (rank64_count(span, kv, sv, lo, sh, C, arr)) full = 1u;
+    __syncthreads();
+    if (full == 0u) {
+        u32 c[kRegs];
+        const u32 tot = rank64_scan_local(C, tid, c);
+        const u32 excl = seg_excl_scan<NT>(tot, NT, wave_tot);
+        rank64_scan_store(C, tid, excl, c);
+        __syncthreads();
+        rank64_scatter(span, kv, sv, lo, sh, C, arr, K, S);
+        __syncthreads();
+        u32 fin[kRegs];
+        rank64_bucket_rank(span, kv, sv, lo, sh, C, (u32)cap, K, S, fin);
+        __syncthreads();
+        rank64_place(span, sv, fin, (u32 *)K);
+    } else {
+        sort_regs_ks(kv, sv);
+        for (int w = kRegs; w < cap; w <<= 1) {
+            store_regs(K + tid * kRegs, kv);
+            uint4 sp;
+            sp.x = sv[0] | (sv[1] << 16);
+            sp.y = sv[2] | (sv[3] << 16);
+            sp.z = sv[4] | (sv[5] << 16);
+            sp.w = sv[6] | (sv[7] << 16);
+            *(uint4 *)(S + tid * kRegs) = sp;
+            __syncthreads();
+            merge_level_ks(K, S, w, tid, kv, sv);
+            __syncthreads();
+        }
+        rank64_ranks(span, tid, sv, (u32 *)K);
+    }
+    __syncthreads();
+}
+
+// Rank pre-pass of a 64-bit signal for tiles ranked outside the tile kernel
+// (the 1024-thread tiles): one workgroup per tile writes its items' ranks
+// to keys[t * stride + item offset].
+template <int NT, bool F64>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 6 : 4))) void k_rank64(const u64 *x, int64_t n, int32_t k, u32 *keys, int64_t stride)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    Shape s;
+    make_shape(n, k, NT, &s);
+    const Tile T = make_tile(s, blockIdx.x);
+    rank_tile<NT, F64>(s, T, x, lds);
+    const int32_t span = tile_items(s, T);
+    u32 *out = keys + (int64_t)blockIdx.x * stride;
+    const u32 *rank = (const u32 *)lds;
+    for (int32_t i = threadIdx.x; i < span; i += NT) out[i] = rank[i];
 }
 
 // ------------------------------------------------------------------ LDS path
@@ -343,8 +461,11 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
 
 // One workgroup per work unit.  512-thread tiles of at most 53 KB run three
 // workgroups per CU, which needs at most 80 VGPRs (six waves per SIMD).
-// RK: the int32 form for the rank keys of 64-bit signals.
-template <int NT, bool F32, bool RK = false>
+// RK, the int32 forms for 64-bit signals: 1, the inputs are rank keys laid
+// out by the rank pre-pass; 2 (int64) and 3 (float64), the tile ranks the
+// 64-bit signal L.x64 in its own LDS first.  With RK, the medians are copied
+// from L.x64 to the 64-bit y.
+template <int NT, bool F32, int RK = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 6 : 8))) void k_tile_lds(Launch L, int *err)
 {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -353,10 +474,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 
     Tile T;
     unit_shape<NT>(d, s, T);
     u32 raw[kRegs];
-    load_raw(s, T, d.x, threadIdx.x, raw);
-    if constexpr (RK) {
-        // a 64-bit signal: medians gathered from its elements (one signal)
-        lds_tile<NT, F32, RK>(d, s, T, raw, lds, err, (const u64 *)L.x64, (u64 *)L.y);
+    if constexpr (RK >= 2) {
+        rank_tile<NT, RK == 3>(s, T, (const u64 *)L.x64, lds);
+        rank_raw(s, T, (const u32 *)lds, threadIdx.x, raw);
+        __syncthreads();   // the tile phases reuse the LDS
+    } else {
+        load_raw(s, T, d.x, threadIdx.x, raw);
+    }
+    if constexpr (RK != 0) {
+        lds_tile<NT, F32, true>(d, s, T, raw, lds, err, (const u64 *)L.x64, (u64 *)L.y);
     } else {
         lds_tile<NT, F32>(d, s, T, raw, lds, err, d.x, d.y);
     }
@@ -411,108 +537,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 }
 
 // ------------------------------------------------------------------ 64-bit inputs
-
-__device__ __forceinline__ u64 wave_min_u64(u64 v)
-{
-    for (int d = 32; d > 0; d >>= 1) {
-        const u64 o = (u64)__shfl_xor((unsigned long long)v, d);
-        v = o < v ? o : v;
-    }
-    return v;
-}
-
-__device__ __forceinline__ u64 wave_max_u64(u64 v)
-{
-    for (int d = 32; d > 0; d >>= 1) {
-        const u64 o = (u64)__shfl_xor((unsigned long long)v, d);
-        v = o > v ? o : v;
-    }
-    return v;
-}
-
-// Rank pre-pass of a 64-bit signal: one workgroup per tile of the NT-thread
-// LDS path sorts the tile's (key, slot) pairs and writes each item's sorted
-// position to keys[t * stride + slot].  The sort is a bucket sort over cap
-// buckets, or, for a tile with a crowded bucket, a merge sort (registers,
-// then stable merge-path levels).  LDS: keys (8 B per position), slots
-// (2 B), 16-bit bucket counters (2 B per bucket); the ranks reuse the keys.
-template <int NT, bool F64>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 6 : 4))) void k_rank64(const u64 *x, int64_t n, int32_t k, u32 *keys, int64_t stride)
-{
-    extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ u64 red_lo[NT / 64], red_hi[NT / 64];
-    __shared__ u32 wave_tot[NT / 64];
-    __shared__ u32 full;
-    static_assert(kRegs == 8, "slots are stored as one 16-byte word per thread");
-    const int tid = threadIdx.x;
-    const int32_t cap = NT * kRegs;
-    u64 *K = (u64 *)lds;
-    u16 *S = (u16 *)(lds + 8 * cap);
-    u32 *C = (u32 *)(lds + 10 * cap);
-    Shape s;
-    make_shape(n, k, NT, &s);
-    const Tile T = make_tile(s, blockIdx.x);
-    const int32_t span = tile_items(s, T);
-    u64 kv[kRegs];
-    u32 sv[kRegs];
-    rank64_load<F64>(s, T, x, tid, kv, sv);
-#pragma unroll
-    for (int w = 0; w < kRegs / 2; w++) C[tid * (kRegs / 2) + w] = 0u;
-    if (tid == 0) full = 0u;
-    u64 lo, hi;
-    rank64_range(span, kv, sv, lo, hi);
-    lo = wave_min_u64(lo);
-    hi = wave_max_u64(hi);
-    if ((tid & 63) == 0) {
-        red_lo[tid >> 6] = lo;
-        red_hi[tid >> 6] = hi;
-    }
-    __syncthreads();
-    lo = red_lo[0];
-    hi = red_hi[0];
-    for (int w = 1; w < NT / 64; w++) {
-        lo = red_lo[w] < lo ? red_lo[w] : lo;
-        hi = red_hi[w] > hi ? red_hi[w] : hi;
-    }
-    const int32_t lognb = NT == 512 ? 12 : 13;
-    static_assert(NT * kRegs == 512 * 8 || NT * kRegs == 1024 * 8, "cap is 4096 or 8192");
-    const u32 sh = rank64_shift(lo, hi, lognb);
-    u32 arr[kRegs];
-    if (rank64_count(span, kv, sv, lo, sh, C, arr)) full = 1u;
-    __syncthreads();
-    if (full == 0u) {
-        u32 c[kRegs];
-        const u32 tot = rank64_scan_local(C, tid, c);
-        const u32 excl = seg_excl_scan<NT>(tot, NT, wave_tot);
-        rank64_scan_store(C, tid, excl, c);
-        __syncthreads();
-        rank64_scatter(span, kv, sv, lo, sh, C, arr, K, S);
-        __syncthreads();
-        u32 fin[kRegs];
-        rank64_bucket_rank(span, kv, sv, lo, sh, C, (u32)cap, K, S, fin);
-        __syncthreads();
-        rank64_place(span, sv, fin, (u32 *)K);
-    } else {
-        sort_regs_ks(kv, sv);
-        for (int w = kRegs; w < cap; w <<= 1) {
-            store_regs(K + tid * kRegs, kv);
-            uint4 sp;
-            sp.x = sv[0] | (sv[1] << 16);
-            sp.y = sv[2] | (sv[3] << 16);
-            sp.z = sv[4] | (sv[5] << 16);
-            sp.w = sv[6] | (sv[7] << 16);
-            *(uint4 *)(S + tid * kRegs) = sp;
-            __syncthreads();
-            merge_level_ks(K, S, w, tid, kv, sv);
-            __syncthreads();
-        }
-        rank64_ranks(span, tid, sv, (u32 *)K);
-    }
-    __syncthreads();
-    u32 *out = keys + (int64_t)blockIdx.x * stride;
-    const u32 *rank = (const u32 *)K;
-    for (int32_t i = tid; i < span; i += NT) out[i] = rank[i];
-}
 
 // k = 1 for 64-bit elements: y = x, argmed[o] = o.
 __global__ __launch_bounds__(256) void k_identity64(const u64 *x, u64 *y, int32_t *argmed, int64_t n)
@@ -1041,8 +1065,9 @@ hipError_t prepare_kernels()
     MF_ATTR((k_tile_lds<kLdsSmall, false>))
     MF_ATTR((k_tile_lds<kLdsLarge, true>))
     MF_ATTR((k_tile_lds<kLdsLarge, false>))
-    MF_ATTR((k_tile_lds<kLdsSmall, false, true>))
-    MF_ATTR((k_tile_lds<kLdsLarge, false, true>))
+    MF_ATTR((k_tile_lds<kLdsSmall, false, 2>))
+    MF_ATTR((k_tile_lds<kLdsSmall, false, 3>))
+    MF_ATTR((k_tile_lds<kLdsLarge, false, 1>))
     MF_ATTR((k_tile_lds_persistent<kLdsSmall, true>))
     MF_ATTR((k_tile_lds_persistent<kLdsLarge, true>))
     MF_ATTR((k_tile_lds_persistent<kLdsSmall, false>))
@@ -1051,8 +1076,6 @@ hipError_t prepare_kernels()
     MF_ATTR((k_tile_global<false, false>))
     MF_ATTR((k_tile_global<true, true>))
     MF_ATTR((k_tile_global<false, true>))
-    MF_ATTR((k_rank64<kLdsSmall, true>))
-    MF_ATTR((k_rank64<kLdsSmall, false>))
     MF_ATTR((k_rank64<kLdsLarge, true>))
     MF_ATTR((k_rank64<kLdsLarge, false>))
 #undef MF_ATTR
@@ -1111,11 +1134,14 @@ hipError_t launch_forward(Path p, bool f32, const Launch &L, size_t lds_bytes,
         const dim3 g((unsigned)L.nunits), b((unsigned)nt);
         if (p == PATH_LDS_SMALL) {
             if (f32) hipLaunchKernelGGL((k_tile_lds<kLdsSmall, true>), g, b, lds_bytes, st, L, d_err);
-            else if (L.xshift) hipLaunchKernelGGL((k_tile_lds<kLdsSmall, false, true>), g, b, lds_bytes, st, L, d_err);
+            else if (L.rank_mode == 2) hipLaunchKernelGGL((k_tile_lds<kLdsSmall, false, 2>), g, b, lds_bytes, st, L, d_err);
+            else if (L.rank_mode == 3) hipLaunchKernelGGL((k_tile_lds<kLdsSmall, false, 3>), g, b, lds_bytes, st, L, d_err);
+            else if (L.rank_mode != 0) return hipErrorInvalidValue;
             else     hipLaunchKernelGGL((k_tile_lds<kLdsSmall, false>), g, b, lds_bytes, st, L, d_err);
         } else {
             if (f32) hipLaunchKernelGGL((k_tile_lds<kLdsLarge, true>), g, b, lds_bytes, st, L, d_err);
-            else if (L.xshift) hipLaunchKernelGGL((k_tile_lds<kLdsLarge, false, true>), g, b, lds_bytes, st, L, d_err);
+            else if (L.rank_mode == 1) hipLaunchKernelGGL((k_tile_lds<kLdsLarge, false, 1>), g, b, lds_bytes, st, L, d_err);
+            else if (L.rank_mode != 0) return hipErrorInvalidValue;
             else     hipLaunchKernelGGL((k_tile_lds<kLdsLarge, false>), g, b, lds_bytes, st, L, d_err);
         }
         break;
@@ -1175,6 +1201,13 @@ hipError_t launch_backward(const BwdLaunch &L, bool f64, hipStream_t st)
 }
 
 
+int64_t rank64_lds_bytes_for(Path p, int32_t k)
+{
+    const int64_t tile = lds_bytes_for(p, k);
+    const int64_t rank = 12ll * (p == PATH_LDS_SMALL ? kLdsSmall : kLdsLarge) * kRegs;
+    return tile > rank ? tile : rank;
+}
+
 int64_t rank64_stride_for(Path p, int32_t k)
 {
     Shape s;
@@ -1187,18 +1220,11 @@ hipError_t launch_rank64(Path p, bool f64, const void *x, int64_t n, int32_t k, 
                          int64_t ntiles, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
+    if (p != PATH_LDS_LARGE) return hipErrorInvalidValue;   // 512-thread tiles rank in their own LDS
     const dim3 g((unsigned)ntiles);
-    if (p == PATH_LDS_SMALL) {
-        const size_t lds = 12u * kLdsSmall * kRegs;
-        if (f64) hipLaunchKernelGGL((k_rank64<kLdsSmall, true>), g, dim3(kLdsSmall), lds, st, (const u64 *)x, n, k, keys, stride);
-        else     hipLaunchKernelGGL((k_rank64<kLdsSmall, false>), g, dim3(kLdsSmall), lds, st, (const u64 *)x, n, k, keys, stride);
-    } else if (p == PATH_LDS_LARGE) {
-        const size_t lds = 12u * kLdsLarge * kRegs;
-        if (f64) hipLaunchKernelGGL((k_rank64<kLdsLarge, true>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride);
-        else     hipLaunchKernelGGL((k_rank64<kLdsLarge, false>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride);
-    } else {
-        return hipErrorInvalidValue;
-    }
+    const size_t lds = 12u * kLdsLarge * kRegs;
+    if (f64) hipLaunchKernelGGL((k_rank64<kLdsLarge, true>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride);
+    else     hipLaunchKernelGGL((k_rank64<kLdsLarge, false>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride);
     return hipGetLastError();
 }
 

@@ -36,9 +36,12 @@ struct Launch {
     const SigDesc *sigs;
     const Unit *units;
     int64_t nunits;
-    int64_t xshift;      // items added to x per tile of `one`; nonzero: x holds the
-                         // rank keys of a 64-bit signal (int32 kernels only)
-    const void *x64;     // that 64-bit signal (y then holds 64-bit medians)
+    // 64-bit signals (int32 LDS kernels only): rank_mode 1, x holds the rank
+    // keys of the 64-bit signal x64, tile t's at x + t * xshift; 2 (int64)
+    // and 3 (float64), each tile ranks x64 itself.  y holds 64-bit medians.
+    int32_t rank_mode;
+    int64_t xshift;      // items added to x per tile of `one`
+    const void *x64;
 };
 
 // Backward launch: grad_y / argmed + y_off (n-k+1), grad_x + x_off (n);
@@ -100,9 +103,11 @@ hipError_t launch_backward(const BwdLaunch &L, bool f64, hipStream_t st);
 int64_t bwd_tiles_for(int64_t n);
 
 // 64-bit signals on an LDS path: entries per tile of the rank buffer and
-// the rank pre-pass (one workgroup per tile); k = 1 copies x and writes
-// argmed[o] = o.
+// the rank pre-pass (one workgroup per 1024-thread tile); k = 1 copies x and
+// writes argmed[o] = o.
 int64_t rank64_stride_for(Path p, int32_t k);
+// Dynamic LDS of a tile that ranks its 64-bit items itself.
+int64_t rank64_lds_bytes_for(Path p, int32_t k);
 hipError_t launch_rank64(Path p, bool f64, const void *x, int64_t n, int32_t k, uint32_t *keys, int64_t stride,
                          int64_t ntiles, hipStream_t st);
 hipError_t launch_identity64(const void *x, void *y, int32_t *argmed, int64_t n, hipStream_t st);

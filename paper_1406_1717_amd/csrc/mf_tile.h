@@ -40,7 +40,8 @@
 //                one position of the merged order.  A 64-bit register window
 //                of membership bits around the median is kept up to date.
 //   6. output    y[o] = x[argmed[o]] (bit copy, gathered from x, which the
-//                tile has just read), argmed[o] global index.
+//                tile has just read; for a 64-bit signal from its 64-bit
+//                elements), argmed[o] global index.
 #pragma once
 #include <stdint.h>
 
@@ -2073,6 +2074,19 @@ MF_HD void rank64_place(int32_t span, const u32 (&sv)[kRegs], const u32 (&fin)[k
 #pragma unroll
     for (int j = 0; j < kRegs; j++)
         if ((int32_t)sv[j] < span) rank[sv[j]] = fin[j];
+}
+
+// The rank keys of thread tid's slots, as load_raw gives a tile's inputs,
+// from the tile's ranks by item offset (rank64_place / rank64_ranks).
+MF_HD void rank_raw(const Shape &s, const Tile &T, const u32 *rank, int32_t tid, u32 (&raw)[kRegs])
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; j++) {
+        const int32_t u = tid * kRegs + j;
+        const int32_t b = u >> s.logS, t = u & (s.S - 1);
+        const int32_t len = b < T.NB ? block_len(s, T, b) : 0;
+        raw[j] = t < len ? rank[b * s.k + t] : 0u;
+    }
 }
 
 // Entries per tile of the rank buffer.

@@ -34,7 +34,7 @@ extern "C" long emu_ranked_tiles(void) { return g_ranked_tiles; }
 template <bool F32, typename E>
 static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
                     const u32 *x, const E *xo, E *yo, int32_t *argmed, std::vector<unsigned char> &lds,
-                    bool ranked_keys = false)
+                    bool ranked_keys = false, const u32 *rank_lds = nullptr)
 {
     const Tile T = make_tile(s, t);
     // poison the tile memory so that reads of unwritten data show up
@@ -48,7 +48,8 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
     for (int q = 0; q < threads; q++) {
         u64 v[kRegs];
         u32 raw[kRegs];
-        load_raw(s, T, x, q, raw);
+        if (rank_lds) rank_raw(s, T, rank_lds, q, raw);   // a tile that ranked its 64-bit items
+        else load_raw(s, T, x, q, raw);
         if (tord) load_tile_values<F32>(s, T, m, raw, q, v);
         else load_sort_values<F32>(s, T, m, raw, q, v);
         for (int j = 0; j < kRegs; j++) regs[(size_t)q * kRegs + j] = v[j];
@@ -420,8 +421,13 @@ extern "C" int emu_median_filter64(const void *x, int64_t n, int32_t k, int is_f
     }
     std::vector<unsigned char> lds((size_t)l.total + 64);
     for (int64_t t = 0; t < s.ntiles; t++) {
-        const int rc = run_tile<false>(s, l, t, threads, keys.data() + t * k, (const u64 *)x, (u64 *)y, argmed,
-                                       lds, true);
+        // 512-thread tiles rank their items in LDS (raw from the tile's
+        // ranks); 1024-thread tiles read the pre-pass keys at keys + t*k
+        const int rc = threads == 512
+                           ? run_tile<false>(s, l, t, threads, nullptr, (const u64 *)x, (u64 *)y, argmed, lds, true,
+                                             keys.data() + t * stride)
+                           : run_tile<false>(s, l, t, threads, keys.data() + t * k, (const u64 *)x, (u64 *)y, argmed,
+                                             lds, true);
         if (rc != 0) return rc;
     }
     return 0;
