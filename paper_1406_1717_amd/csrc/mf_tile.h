@@ -1847,11 +1847,12 @@ MF_HD void tail_pair_merge(const Shape &s, const Tile &T, const TileMem &m, int3
 //
 // The tile phases compare 32-bit keys.  A 64-bit signal (Section 7 measures
 // 32- and 64-bit versions) first has each tile's items ranked by (64-bit
-// key, index): a total order without ties.  The ranks, written tile by tile
-// ((Pmax + 1) k entries per tile, so a block shared by two tiles appears in
-// both), are 32-bit keys that order every tile's items exactly as the
-// 64-bit values with the index tie-break do; the 32-bit tile phases then run
-// on them unchanged and produce the 64-bit signal's argmed.
+// key, index): a total order without ties.  The ranks (kept in the tile's
+// LDS, or written tile by tile, (Pmax + 1) k entries per tile, so that a
+// block shared by two tiles appears in both) are 32-bit keys that order
+// every tile's items exactly as the 64-bit values with the index tie-break
+// do; the 32-bit tile phases then run on them unchanged and produce the
+// 64-bit signal's argmed.
 //
 // The ranking is one merge sort of (key, slot) pairs, slots being item
 // offsets from the tile's first item (at most kRegs * threads).  A thread
