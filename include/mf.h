@@ -58,11 +58,11 @@ mf_status mf_median_filter_i32(const int32_t *x, int64_t n, int32_t k,
 /* 64-bit signals (the paper measures 32- and 64-bit versions, Section 7):
  * float64 (same order rules as float32: -0.0 equals +0.0, NaNs above +inf)
  * and int64.  y: n-k+1 elements of the input type, bit copies of
- * x[argmed[o]].  Windows up to 4095 (MF_ERR_UNSUPPORTED above).  Each tile's
- * items are first ranked by (value, index) into 32-bit keys (in LDS for
- * k <= 2047; above, in the library's workspace, about 8 B per input item);
- * the 32-bit tile kernels then run on those keys and copy each median
- * from x. */
+ * x[argmed[o]].  The same windows as the 32-bit calls.  Each tile's items
+ * are first ranked by (value, index) into 32-bit keys (in LDS for
+ * k <= 2047; above, in the library's workspace: about 8 B per input item,
+ * and for k > 4095 also 48k bytes per concurrent pair); the 32-bit tile
+ * kernels then run on those keys and copy each median from x. */
 mf_status mf_median_filter_f64(const double *x, int64_t n, int32_t k,
                                double *y, int32_t *argmed, void *stream);
 mf_status mf_median_filter_i64(const int64_t *x, int64_t n, int32_t k,

@@ -6,7 +6,7 @@ kernels.
 
   median_filter(x, k)                 -> (y, argmed); x float32/int32 on a
                                          GPU, shape (n,) or (rows, n), or a
-                                         float64/int64 signal (k <= 4095)
+                                         float64/int64 signal
   median_filter_batched(x, offsets, ks) -> packed (y, argmed) of a ragged batch
   median_filter_backward(grad_y, argmed, n, k) -> grad_x
   MedianFilterFn.apply(x, k)          autograd: y, with grad routed to argmed

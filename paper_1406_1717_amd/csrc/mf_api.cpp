@@ -169,8 +169,6 @@ mf_status forward64(const void *x, int64_t n, int32_t k, void *y, int32_t *argme
     mf_status s = check_signal(n, k);
     if (s != MF_OK) return s;
     const Path p = path_for(k);
-    if (p != PATH_IDENTITY && p != PATH_LDS_SMALL && p != PATH_LDS_LARGE)
-        return fail(MF_ERR_UNSUPPORTED, "k = %d: 64-bit signals take windows up to 4095", k);
     Device *D = nullptr;
     if ((s = device_state(&D)) != MF_OK) return s;
     if (p == PATH_IDENTITY) {
@@ -198,6 +196,38 @@ mf_status forward64(const void *x, int64_t n, int32_t k, void *y, int32_t *argme
     }
     const int64_t stride = rank64_stride_for(p, k);
     const int64_t key_bytes = (tiles * stride * 4 + 255) & ~255ll;
+    if (p == PATH_GLOBAL) {
+        // one pair per tile: a pre-pass ranks each pair through its
+        // workgroup's scratch, then the global-path tiles run on the ranks;
+        // the scratch of the pre-pass and the tiles' workspace share memory
+        const size_t lds = (size_t)lds_bytes_for(p, k);
+        const int64_t gstride = global_ws_stride(k);
+        const int64_t gslots = std::min<int64_t>(global_ws_slots(lds), tiles);
+        const int64_t pstride = rank64_pair_scratch(k);
+        const int64_t pslots = std::min<int64_t>(256, tiles);
+        const int64_t scratch = std::max<int64_t>(gstride * gslots, pstride * pslots);
+        unsigned char *ws = nullptr;
+        if ((s = acquire_ws(*D, key_bytes + scratch, st, &ws)) != MF_OK) return s;
+        uint32_t *keys = (uint32_t *)ws;
+        MF_HIP(launch_rank64_pair(f64, x, n, k, keys, stride, ws + key_bytes, pstride, pslots, tiles, st),
+               "64-bit pair rank launch");
+        Launch L;
+        memset(&L, 0, sizeof L);
+        L.x = keys;
+        L.y = y;
+        L.argmed = argmed;
+        L.one.n = n;
+        L.one.k = k;
+        L.rows = 1;
+        L.tpr = tiles;
+        L.nunits = tiles;
+        L.rank_mode = 1;
+        L.xshift = k;
+        L.x64 = x;
+        MF_HIP(launch_forward(p, false, L, lds, ws + key_bytes, gstride, gslots, D->d_err, st),
+               "64-bit forward launch");
+        return release_ws(*D, st);
+    }
     unsigned char *ws = nullptr;
     if ((s = acquire_ws(*D, key_bytes, st, &ws)) != MF_OK) return s;
     uint32_t *keys = (uint32_t *)ws;

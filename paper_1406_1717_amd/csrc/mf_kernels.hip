@@ -189,14 +189,14 @@ __device__ __forceinline__ u64 wave_max_u64(u64 v)
     return v;
 }
 
-// The ranks of tile T's items by (64-bit key, index), left in LDS as u32
-// per item offset from the tile's first item (at lds).  The sort is a
+// The ranks of the span items at xt by (64-bit key, index), left in LDS
+// as u32 per item offset (at lds); span <= NT * kRegs.  The sort is a
 // bucket sort over cap buckets, or, for a tile with a crowded bucket, a
 // merge sort (registers, then stable merge-path levels).  LDS: keys (8 B
 // per position), slots (2 B), 16-bit bucket counters (2 B per bucket); the
 // ranks reuse the keys.  Ends with a barrier.
 template <int NT, bool F64>
-__device__ __forceinline__ void rank_tile(const Shape &s, const Tile &T, const u64 *x, unsigned char *lds)
+__device__ __forceinline__ void rank_items(const u64 *xt, int32_t span, unsigned char *lds)
 {
     __shared__ u64 red_lo[NT / 64], red_hi[NT / 64];
     __shared__ u32 wave_tot[NT / 64];
@@ -207,10 +207,9 @@ __device__ __forceinline__ void rank_tile(const Shape &s, const Tile &T, const u
     u64 *K = (u64 *)lds;
     u16 *S = (u16 *)(lds + 8 * cap);
     u32 *C = (u32 *)(lds + 10 * cap);
-    const int32_t span = tile_items(s, T);
     u64 kv[kRegs];
     u32 sv[kRegs];
-    rank64_load<F64>(s, T, x, tid, kv, sv);
+    rank64_load<F64>(xt, span, tid, kv, sv);
 #pragma unroll
     for (int w = 0; w < kRegs / 2; w++) C[tid * (kRegs / 2) + w] = 0u;
     if (tid == 0) full = 0u;
@@ -264,6 +263,12 @@ __device__ __forceinline__ void rank_tile(const Shape &s, const Tile &T, const u
         rank64_ranks(span, tid, sv, (u32 *)K);
     }
     __syncthreads();
+}
+
+template <int NT, bool F64>
+__device__ __forceinline__ void rank_tile(const Shape &s, const Tile &T, const u64 *x, unsigned char *lds)
+{
+    rank_items<NT, F64>(x + T.e0, tile_items(s, T), lds);
 }
 
 // Rank pre-pass of a 64-bit signal for tiles ranked outside the tile kernel
@@ -599,9 +604,10 @@ __host__ __device__ inline int global_shape(int64_t n, int32_t k, Shape *s)
 // first median (pos[k]) and output 0.  Returns false, having written only
 // scratch, if a bucket overflows even under the logarithmic map; the
 // caller then takes the merge sort.
-template <bool F32>
+template <bool F32, typename V>
 __device__ bool global_pair_bucket(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
-                                   u64 *srt, u16 *arrv, u32 *lcnt, u32 *gsh, u32 *wave_tot)
+                                   u64 *srt, u16 *arrv, u32 *lcnt, u32 *gsh, u32 *wave_tot,
+                                   const V *xo, V *yo)
 {
     const int tid = threadIdx.x;
     const int NT = kGlobalThreads;
@@ -768,7 +774,7 @@ __device__ bool global_pair_bucket(const Shape &s, const Tile &T, const TileMem 
                 if (c == h) {
                     m.pos[s.k] = (u32)r;
                     if (T.j0 == 1) {   // output 0: the median of block 0
-                        d.y[0] = d.x[e];
+                        yo[0] = xo[e];
                         if (d.argmed) d.argmed[0] = (int32_t)e;
                     }
                     break;
@@ -782,8 +788,9 @@ __device__ bool global_pair_bucket(const Shape &s, const Tile &T, const TileMem 
 }
 
 // TWO: tiles of k <= 16383 (64 KB of LDS), compiled for two workgroups per
-// CU (at most 64 VGPRs).
-template <bool F32, bool TWO>
+// CU (at most 64 VGPRs).  RK: int32 rank keys of a 64-bit signal (tile t's
+// at L.x + t * L.xshift), medians copied from L.x64 to the 64-bit y.
+template <bool F32, bool TWO, bool RK = false>
 __global__ __launch_bounds__(kGlobalThreads) __attribute__((amdgpu_waves_per_eu(TWO ? 8 : 4)))
 void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
 {
@@ -813,12 +820,15 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
         u64 *srt2 = (u64 *)(base + g.srt2);
         const Tile T = make_tile(s, tile);
         const u32 *x = d.x;
+        const auto xo = [&]() { if constexpr (RK) return (const u64 *)L.x64; else return d.x; }();
+        const auto yo = [&]() { if constexpr (RK) return (u64 *)L.y; else return d.y; }();
 
         __syncthreads();   // the previous tile is done with the workspace
         // one-pair tiles: bucket sort of the pair (the sort buffer holds the
         // counters, then the waves' histogram row buffers)
-        if (T.P == 1 && s.S >= 8192 && global_pair_bucket<F32>(s, T, m, d, srt, (u16 *)srt2, (u32 *)lds, gsh, wave_tot)) {
-            tile_tail<kGlobalThreads>(s, T, m, d, d.x, d.y, err, true, (u32 *)lds);
+        if (T.P == 1 && s.S >= 8192 &&
+            global_pair_bucket<F32>(s, T, m, d, srt, (u16 *)srt2, (u32 *)lds, gsh, wave_tot, xo, yo)) {
+            tile_tail<kGlobalThreads>(s, T, m, d, xo, yo, err, true, (u32 *)lds);
             continue;
         }
         // otherwise (a single block, or buckets that overflow on heavy ties):
@@ -874,7 +884,59 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
         }
         __syncthreads();
         // the sort buffer is free: it holds the waves' histogram row buffers
-        tile_tail<kGlobalThreads>(s, T, m, d, d.x, d.y, err, false, (u32 *)lds);
+        tile_tail<kGlobalThreads>(s, T, m, d, xo, yo, err, false, (u32 *)lds);
+    }
+}
+
+// Rank pre-pass of a 64-bit signal on the global path (one pair of up to
+// 2k items per tile): workgroups loop over tiles; each ranks its pair in
+// chunks of kGlobalThreads * kRegs items in LDS, writes each chunk in sorted
+// (key, offset) order to its scratch, merges the runs there (merge path,
+// two copies) and writes keys[t * stride + offset] = rank.
+template <bool F64>
+__global__ __launch_bounds__(kGlobalThreads) void k_rank64_pair(const u64 *x, int64_t n, int32_t k, u32 *keys,
+                                                                int64_t stride, unsigned char *ws,
+                                                                int64_t ws_stride, int64_t ntiles)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    constexpr int NT = kGlobalThreads;
+    constexpr int32_t kSeg = 16;   // merge outputs per thread and pass
+    const int tid = threadIdx.x;
+    const int32_t C = NT * kRegs;
+    const int32_t smax = 2 * k;
+    u64 *K0 = (u64 *)(ws + (int64_t)blockIdx.x * ws_stride);
+    u64 *K1 = K0 + smax;
+    u32 *O0 = (u32 *)(K1 + smax);
+    u32 *O1 = O0 + smax;
+    Shape s;
+    global_shape(n, k, &s);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile T = make_tile(s, t);
+        const int32_t span = tile_items(s, T);
+        const u64 *xt = x + T.e0;
+        for (int32_t c0 = 0; c0 < span; c0 += C) {
+            const int32_t len = span - c0 < C ? span - c0 : C;
+            rank_items<NT, F64>(xt + c0, len, lds);
+            const u32 *rank = (const u32 *)lds;
+            for (int32_t i = tid; i < len; i += NT) {
+                const u32 r = rank[i];
+                K0[c0 + r] = F64 ? key_of_f64(xt[c0 + i]) : key_of_i64(xt[c0 + i]);
+                O0[c0 + r] = (u32)(c0 + i);
+            }
+            __syncthreads();   // the next chunk reuses the LDS
+        }
+        u64 *Kin = K0, *Kout = K1;
+        u32 *Oin = O0, *Oout = O1;
+        for (int32_t w = C; w < span; w <<= 1) {
+            for (int32_t p0 = tid * kSeg; p0 < span; p0 += NT * kSeg)
+                merge_seg_ko(Kin, Oin, Kout, Oout, span, w, p0, kSeg);
+            __syncthreads();
+            u64 *tk = Kin; Kin = Kout; Kout = tk;
+            u32 *to = Oin; Oin = Oout; Oout = to;
+        }
+        u32 *out = keys + t * stride;
+        for (int32_t p = tid; p < span; p += NT) out[Oin[p]] = (u32)p;
+        __syncthreads();   // the next tile reuses the scratch
     }
 }
 
@@ -1076,6 +1138,10 @@ hipError_t prepare_kernels()
     MF_ATTR((k_tile_global<false, false>))
     MF_ATTR((k_tile_global<true, true>))
     MF_ATTR((k_tile_global<false, true>))
+    MF_ATTR((k_tile_global<false, true, true>))
+    MF_ATTR((k_tile_global<false, false, true>))
+    MF_ATTR((k_rank64_pair<true>))
+    MF_ATTR((k_rank64_pair<false>))
     MF_ATTR((k_rank64<kLdsLarge, true>))
     MF_ATTR((k_rank64<kLdsLarge, false>))
 #undef MF_ATTR
@@ -1149,11 +1215,14 @@ hipError_t launch_forward(Path p, bool f32, const Launch &L, size_t lds_bytes,
     case PATH_GLOBAL: {
         const int64_t grid = L.nunits < ws_slots ? L.nunits : ws_slots;
         const dim3 g((unsigned)grid), b(kGlobalThreads);
+        if (L.rank_mode != 0 && (f32 || L.rank_mode != 1)) return hipErrorInvalidValue;
         if (lds_bytes <= (size_t)kGlobalLdsSmall) {
             if (f32) hipLaunchKernelGGL((k_tile_global<true, true>), g, b, lds_bytes, st, L, ws, ws_stride, d_err);
+            else if (L.rank_mode) hipLaunchKernelGGL((k_tile_global<false, true, true>), g, b, lds_bytes, st, L, ws, ws_stride, d_err);
             else     hipLaunchKernelGGL((k_tile_global<false, true>), g, b, lds_bytes, st, L, ws, ws_stride, d_err);
         } else {
             if (f32) hipLaunchKernelGGL((k_tile_global<true, false>), g, b, lds_bytes, st, L, ws, ws_stride, d_err);
+            else if (L.rank_mode) hipLaunchKernelGGL((k_tile_global<false, false, true>), g, b, lds_bytes, st, L, ws, ws_stride, d_err);
             else     hipLaunchKernelGGL((k_tile_global<false, false>), g, b, lds_bytes, st, L, ws, ws_stride, d_err);
         }
         break;
@@ -1211,6 +1280,10 @@ int64_t rank64_lds_bytes_for(Path p, int32_t k)
 int64_t rank64_stride_for(Path p, int32_t k)
 {
     Shape s;
+    if (p == PATH_GLOBAL) {
+        global_shape(1ll << 20, k, &s);
+        return rank64_stride(s);
+    }
     if (p != PATH_LDS_SMALL && p != PATH_LDS_LARGE) return 0;
     make_shape(1ll << 20, k, p == PATH_LDS_SMALL ? kLdsSmall : kLdsLarge, &s);
     return rank64_stride(s);
@@ -1225,6 +1298,21 @@ hipError_t launch_rank64(Path p, bool f64, const void *x, int64_t n, int32_t k, 
     const size_t lds = 12u * kLdsLarge * kRegs;
     if (f64) hipLaunchKernelGGL((k_rank64<kLdsLarge, true>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride);
     else     hipLaunchKernelGGL((k_rank64<kLdsLarge, false>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride);
+    return hipGetLastError();
+}
+
+int64_t rank64_pair_scratch(int32_t k) { return pair_rank_scratch(k); }
+
+hipError_t launch_rank64_pair(bool f64, const void *x, int64_t n, int32_t k, u32 *keys, int64_t stride,
+                              unsigned char *ws, int64_t ws_stride, int64_t slots, int64_t ntiles, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const dim3 g((unsigned)(slots < ntiles ? slots : ntiles));
+    const size_t lds = 12u * kGlobalThreads * kRegs;
+    if (f64) hipLaunchKernelGGL((k_rank64_pair<true>), g, dim3(kGlobalThreads), lds, st, (const u64 *)x, n, k, keys,
+                                stride, ws, ws_stride, ntiles);
+    else     hipLaunchKernelGGL((k_rank64_pair<false>), g, dim3(kGlobalThreads), lds, st, (const u64 *)x, n, k, keys,
+                                stride, ws, ws_stride, ntiles);
     return hipGetLastError();
 }
 

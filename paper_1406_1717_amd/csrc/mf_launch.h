@@ -110,6 +110,12 @@ int64_t rank64_stride_for(Path p, int32_t k);
 int64_t rank64_lds_bytes_for(Path p, int32_t k);
 hipError_t launch_rank64(Path p, bool f64, const void *x, int64_t n, int32_t k, uint32_t *keys, int64_t stride,
                          int64_t ntiles, hipStream_t st);
+// 64-bit signals on the global path: scratch bytes of one workgroup of the
+// pair pre-pass, and the pre-pass itself (a grid of `slots` workgroups
+// looping over the tiles).
+int64_t rank64_pair_scratch(int32_t k);
+hipError_t launch_rank64_pair(bool f64, const void *x, int64_t n, int32_t k, uint32_t *keys, int64_t stride,
+                              unsigned char *ws, int64_t ws_stride, int64_t slots, int64_t ntiles, hipStream_t st);
 hipError_t launch_identity64(const void *x, void *y, int32_t *argmed, int64_t n, hipStream_t st);
 
 hipError_t prepare_kernels();

@@ -1871,15 +1871,14 @@ MF_HD u64 key_of_f64(u64 u)
 
 MF_HD u64 key_of_i64(u64 u) { return u ^ 0x8000000000000000ull; }
 
-// Keys and slots of thread tid: slots tid*kRegs + j; slots past the tile's
-// items get the largest key (their slots order them after every item).
+// Keys and slots of thread tid over the span items at xt: slots
+// tid*kRegs + j; slots past the span get the largest key (their slots order
+// them after every item).
 template <bool F64>
-MF_HD void rank64_load(const Shape &s, const Tile &T, const u64 *x, int32_t tid, u64 (&kv)[kRegs],
-                       u32 (&sv)[kRegs])
+MF_HD void rank64_load(const u64 *xt, int32_t span, int32_t tid, u64 (&kv)[kRegs], u32 (&sv)[kRegs])
 {
-    const int32_t span = tile_items(s, T);
     const int32_t i0 = tid * kRegs;
-    const u64 *src = x + T.e0 + i0;
+    const u64 *src = xt + i0;
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
         sv[j] = (u32)(i0 + j);
@@ -2089,6 +2088,49 @@ MF_HD void rank_raw(const Shape &s, const Tile &T, const u32 *rank, int32_t tid,
         raw[j] = t < len ? rank[b * s.k + t] : 0u;
     }
 }
+
+// Ranks of a pair of more than NT * kRegs items (windows above 4095): the
+// pair is cut into chunks of that many items, each chunk is ranked in LDS
+// and written in sorted order (key, offset), and merge-path levels merge the
+// sorted runs in global memory.  One level: outputs [p0, p0 + seg) of the
+// merge of runs of w at Kin/Oin (span items in all; seg divides 2w).
+MF_HD void merge_seg_ko(const u64 *Kin, const u32 *Oin, u64 *Kout, u32 *Oout, int32_t span, int32_t w,
+                        int32_t p0, int32_t seg)
+{
+    const int32_t s0 = p0 & ~(2 * w - 1);
+    const int32_t rest = span - s0;
+    const int32_t lenA = rest < w ? rest : w;
+    const int32_t lenB = rest - lenA < w ? rest - lenA : w;
+    const u64 *KA = Kin + s0, *KB = Kin + s0 + w;
+    const u32 *OA = Oin + s0, *OB = Oin + s0 + w;
+    const int32_t d = p0 - s0;
+    int32_t lo = d > lenB ? d - lenB : 0;
+    int32_t hi = d < lenA ? d : lenA;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        const int32_t bm = d - 1 - mid;
+        const bool aless = KA[mid] < KB[bm] || (KA[mid] == KB[bm] && OA[mid] < OB[bm]);
+        if (aless) lo = mid + 1;
+        else hi = mid;
+    }
+    int32_t a = lo, b = d - lo;
+    for (int32_t q = 0; q < seg && p0 + q < span; q++) {
+        const bool takeA = b >= lenB || (a < lenA && (KA[a] < KB[b] || (KA[a] == KB[b] && OA[a] < OB[b])));
+        if (takeA) {
+            Kout[p0 + q] = KA[a];
+            Oout[p0 + q] = OA[a];
+            a++;
+        } else {
+            Kout[p0 + q] = KB[b];
+            Oout[p0 + q] = OB[b];
+            b++;
+        }
+    }
+}
+
+// Scratch bytes of one workgroup ranking a pair of window k: two copies of
+// (key, offset) for 2k items.
+MF_HD int64_t pair_rank_scratch(int32_t k) { return ((24ll * 2 * k) + 255) & ~255ll; }
 
 // Entries per tile of the rank buffer.
 MF_HD int64_t rank64_stride(const Shape &s) { return (int64_t)(s.Pmax + 1) * s.k; }

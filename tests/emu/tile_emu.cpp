@@ -287,99 +287,85 @@ extern "C" int emu_median_filter(const void *x, int64_t n, int32_t k, int is_f32
     return 0;
 }
 
-// 64-bit signals: the rank pre-pass (each phase of the kernel as one sweep
-// over the threads, barriers between sweeps), a check that each tile's
-// ranks are a permutation, then the 32-bit tiles on the ranks (tile t
-// reading its span at keys + t*k) copying the medians from the 64-bit x.
-extern "C" int emu_median_filter64(const void *x, int64_t n, int32_t k, int is_f64, int threads,
-                                   void *y, int32_t *argmed)
+// Ranks of the span items at xt by (key, offset), the kernels' rank_items
+// with each phase as one sweep over the threads (barriers between sweeps):
+// bucket sort, or the merge sort for a crowded bucket.  Checks that the
+// ranks are a permutation.  Returns 0, or -20.
+static int emu_rank_items(const u64 *xt, int32_t span, int threads, bool f64, std::vector<u32> &rank)
 {
-    if (k < 3 || (k & 1) == 0 || n < k) return -1;
-    Shape s;
-    if (make_shape(n, k, threads, &s) != 0) return -2;
-    Layout l;
-    make_layout(s, &l);
-    if (l.total < 0) return -3;
-    const int64_t stride = rank64_stride(s);
     const int cap = threads * kRegs;
-    std::vector<u32> keys((size_t)(s.ntiles * stride), 0xA5A5A5A5u);
     std::vector<u64> kr(cap), kt(cap), K(cap);
-    std::vector<u32> sr(cap), st(cap), rank(cap);
+    std::vector<u32> sr(cap), st(cap), C((size_t)cap / 2), arr(cap), fin(cap), cpre(cap), tot(threads);
     std::vector<u16> S(cap);
-    std::vector<u32> C((size_t)cap / 2), arr(cap), fin(cap), cpre(cap), tot(threads);
     int lognb = 0;
     while ((1 << lognb) < cap) lognb++;
-    for (int64_t t = 0; t < s.ntiles; t++) {
-        const Tile T = make_tile(s, t);
-        const int32_t span = tile_items(s, T);
-        u64 lo = ~0ull, hi = 0ull;
-        for (int q = 0; q < threads; q++) {
-            u64 kv[kRegs], l, h;
-            u32 sv[kRegs];
-            if (is_f64) rank64_load<true>(s, T, (const u64 *)x, q, kv, sv);
-            else rank64_load<false>(s, T, (const u64 *)x, q, kv, sv);
-            rank64_range(span, kv, sv, l, h);
-            lo = l < lo ? l : lo;
-            hi = h > hi ? h : hi;
-            for (int j = 0; j < kRegs; j++) {
-                kr[(size_t)q * kRegs + j] = kv[j];
-                sr[(size_t)q * kRegs + j] = sv[j];
-            }
+    u64 lo = ~0ull, hi = 0ull;
+    for (int q = 0; q < threads; q++) {
+        u64 kv[kRegs], l, h;
+        u32 sv[kRegs];
+        if (f64) rank64_load<true>(xt, span, q, kv, sv);
+        else rank64_load<false>(xt, span, q, kv, sv);
+        rank64_range(span, kv, sv, l, h);
+        lo = l < lo ? l : lo;
+        hi = h > hi ? h : hi;
+        for (int j = 0; j < kRegs; j++) {
+            kr[(size_t)q * kRegs + j] = kv[j];
+            sr[(size_t)q * kRegs + j] = sv[j];
         }
-        auto regs = [&](int q, u64 (&kv)[kRegs], u32 (&sv)[kRegs]) {
-            for (int j = 0; j < kRegs; j++) {
-                kv[j] = kr[(size_t)q * kRegs + j];
-                sv[j] = sr[(size_t)q * kRegs + j];
-            }
-        };
-        const u32 sh = rank64_shift(lo, hi, lognb);
-        std::fill(C.begin(), C.end(), 0u);
-        bool full = false;
+    }
+    auto regs = [&](int q, u64 (&kv)[kRegs], u32 (&sv)[kRegs]) {
+        for (int j = 0; j < kRegs; j++) {
+            kv[j] = kr[(size_t)q * kRegs + j];
+            sv[j] = sr[(size_t)q * kRegs + j];
+        }
+    };
+    const u32 sh = rank64_shift(lo, hi, lognb);
+    bool full = false;
+    for (int q = 0; q < threads; q++) {
+        u64 kv[kRegs];
+        u32 sv[kRegs], a[kRegs];
+        regs(q, kv, sv);
+        if (rank64_count(span, kv, sv, lo, sh, C.data(), a)) full = true;
+        for (int j = 0; j < kRegs; j++) arr[(size_t)q * kRegs + j] = a[j];
+    }
+    rank.assign(cap, 0xFFFFFFFFu);
+    if (!full && !g_force_merge) {
+        for (int q = 0; q < threads; q++) {
+            u32 c[kRegs];
+            tot[q] = rank64_scan_local(C.data(), q, c);
+            for (int j = 0; j < kRegs; j++) cpre[(size_t)q * kRegs + j] = c[j];
+        }
+        u32 excl = 0;
+        for (int q = 0; q < threads; q++) {
+            u32 c[kRegs];
+            for (int j = 0; j < kRegs; j++) c[j] = cpre[(size_t)q * kRegs + j];
+            rank64_scan_store(C.data(), q, excl, c);
+            excl += tot[q];
+        }
+        std::fill(K.begin(), K.end(), 0xA5A5A5A5A5A5A5A5ull);
         for (int q = 0; q < threads; q++) {
             u64 kv[kRegs];
             u32 sv[kRegs], a[kRegs];
             regs(q, kv, sv);
-            if (rank64_count(span, kv, sv, lo, sh, C.data(), a)) full = true;
-            for (int j = 0; j < kRegs; j++) arr[(size_t)q * kRegs + j] = a[j];
+            for (int j = 0; j < kRegs; j++) a[j] = arr[(size_t)q * kRegs + j];
+            rank64_scatter(span, kv, sv, lo, sh, C.data(), a, K.data(), S.data());
         }
-        std::fill(rank.begin(), rank.end(), 0xFFFFFFFFu);
-        if (!full && !g_force_merge) {
-            for (int q = 0; q < threads; q++) {
-                u32 c[kRegs];
-                tot[q] = rank64_scan_local(C.data(), q, c);
-                for (int j = 0; j < kRegs; j++) cpre[(size_t)q * kRegs + j] = c[j];
-            }
-            u32 excl = 0;
-            for (int q = 0; q < threads; q++) {
-                u32 c[kRegs];
-                for (int j = 0; j < kRegs; j++) c[j] = cpre[(size_t)q * kRegs + j];
-                rank64_scan_store(C.data(), q, excl, c);
-                excl += tot[q];
-            }
-            std::fill(K.begin(), K.end(), 0xA5A5A5A5A5A5A5A5ull);
-            for (int q = 0; q < threads; q++) {
-                u64 kv[kRegs];
-                u32 sv[kRegs], a[kRegs];
-                regs(q, kv, sv);
-                for (int j = 0; j < kRegs; j++) a[j] = arr[(size_t)q * kRegs + j];
-                rank64_scatter(span, kv, sv, lo, sh, C.data(), a, K.data(), S.data());
-            }
-            for (int q = 0; q < threads; q++) {
-                u64 kv[kRegs];
-                u32 sv[kRegs], f[kRegs];
-                regs(q, kv, sv);
-                rank64_bucket_rank(span, kv, sv, lo, sh, C.data(), (u32)cap, K.data(), S.data(), f);
-                for (int j = 0; j < kRegs; j++) fin[(size_t)q * kRegs + j] = f[j];
-            }
-            for (int q = 0; q < threads; q++) {
-                u64 kv[kRegs];
-                u32 sv[kRegs], f[kRegs];
-                regs(q, kv, sv);
-                for (int j = 0; j < kRegs; j++) f[j] = fin[(size_t)q * kRegs + j];
-                rank64_place(span, sv, f, rank.data());
-            }
-            g_rank_bucket_tiles++;
-        } else {
+        for (int q = 0; q < threads; q++) {
+            u64 kv[kRegs];
+            u32 sv[kRegs], f[kRegs];
+            regs(q, kv, sv);
+            rank64_bucket_rank(span, kv, sv, lo, sh, C.data(), (u32)cap, K.data(), S.data(), f);
+            for (int j = 0; j < kRegs; j++) fin[(size_t)q * kRegs + j] = f[j];
+        }
+        for (int q = 0; q < threads; q++) {
+            u64 kv[kRegs];
+            u32 sv[kRegs], f[kRegs];
+            regs(q, kv, sv);
+            for (int j = 0; j < kRegs; j++) f[j] = fin[(size_t)q * kRegs + j];
+            rank64_place(span, sv, f, rank.data());
+        }
+        g_rank_bucket_tiles++;
+    } else {
         for (int q = 0; q < threads; q++) {
             u64 kv[kRegs];
             u32 sv[kRegs];
@@ -411,24 +397,90 @@ extern "C" int emu_median_filter64(const void *x, int64_t n, int32_t k, int is_f
             rank64_ranks(span, q, sv, rank.data());
         }
         g_rank_merge_tiles++;
-        }
-        std::vector<char> seen(span, 0);
-        for (int32_t i = 0; i < span; i++) {
-            if (rank[i] >= (u32)span || seen[rank[i]]) return -20;
-            seen[rank[i]] = 1;
-            keys[(size_t)(t * stride + i)] = rank[i];
-        }
+    }
+    std::vector<char> seen(span, 0);
+    for (int32_t i = 0; i < span; i++) {
+        if (rank[i] >= (u32)span || seen[rank[i]]) return -20;
+        seen[rank[i]] = 1;
+    }
+    return 0;
+}
+
+// 64-bit signals: each tile's ranks (emu_rank_items), then the 32-bit tiles
+// on them: 512-thread tiles read their slots' ranks from the rank array
+// (as from their LDS), 1024-thread tiles read the pre-pass keys at
+// keys + t*k.  The medians are copied from the 64-bit x.
+extern "C" int emu_median_filter64(const void *x, int64_t n, int32_t k, int is_f64, int threads,
+                                   void *y, int32_t *argmed)
+{
+    if (k < 3 || (k & 1) == 0 || n < k) return -1;
+    Shape s;
+    if (make_shape(n, k, threads, &s) != 0) return -2;
+    Layout l;
+    make_layout(s, &l);
+    if (l.total < 0) return -3;
+    const int64_t stride = rank64_stride(s);
+    std::vector<u32> keys((size_t)(s.ntiles * stride), 0xA5A5A5A5u), rank;
+    for (int64_t t = 0; t < s.ntiles; t++) {
+        const Tile T = make_tile(s, t);
+        const int32_t span = tile_items(s, T);
+        const int rc = emu_rank_items((const u64 *)x + T.e0, span, threads, is_f64 != 0, rank);
+        if (rc != 0) return rc;
+        for (int32_t i = 0; i < span; i++) keys[(size_t)(t * stride + i)] = rank[i];
     }
     std::vector<unsigned char> lds((size_t)l.total + 64);
     for (int64_t t = 0; t < s.ntiles; t++) {
-        // 512-thread tiles rank their items in LDS (raw from the tile's
-        // ranks); 1024-thread tiles read the pre-pass keys at keys + t*k
         const int rc = threads == 512
                            ? run_tile<false>(s, l, t, threads, nullptr, (const u64 *)x, (u64 *)y, argmed, lds, true,
                                              keys.data() + t * stride)
                            : run_tile<false>(s, l, t, threads, keys.data() + t * k, (const u64 *)x, (u64 *)y, argmed,
                                              lds, true);
         if (rc != 0) return rc;
+    }
+    return 0;
+}
+
+// The pair pre-pass of 64-bit signals on the global path (k > 4095): for
+// every pair tile of the shape (threads = 2S / kRegs, one pair per tile),
+// chunks of 8192 items ranked (emu_rank_items, 1024 threads), written in
+// sorted (key, offset) order, merged by merge_seg_ko levels (segments of 16
+// outputs, every segment of a level before the next), then
+// keys[t * stride + offset] = rank.
+extern "C" int emu_rank_pairs64(const void *x, int64_t n, int32_t k, int is_f64, uint32_t *keys, int64_t *out_stride,
+                                int64_t *out_tiles)
+{
+    int32_t S = 1;
+    while (S < k) S <<= 1;
+    Shape s;
+    if (make_shape(n, k, 2 * S / kRegs, &s) != 0) return -2;
+    const int64_t stride = rank64_stride(s);
+    *out_stride = stride;
+    *out_tiles = s.ntiles;
+    if (!keys) return 0;
+    const int32_t C = 1024 * kRegs, seg = 16;
+    std::vector<u64> K0(2 * (size_t)k), K1(2 * (size_t)k);
+    std::vector<u32> O0(2 * (size_t)k), O1(2 * (size_t)k), rank;
+    for (int64_t t = 0; t < s.ntiles; t++) {
+        const Tile T = make_tile(s, t);
+        const int32_t span = tile_items(s, T);
+        const u64 *xt = (const u64 *)x + T.e0;
+        for (int32_t c0 = 0; c0 < span; c0 += C) {
+            const int32_t len = span - c0 < C ? span - c0 : C;
+            const int rc = emu_rank_items(xt + c0, len, 1024, is_f64 != 0, rank);
+            if (rc != 0) return rc;
+            for (int32_t i = 0; i < len; i++) {
+                K0[c0 + rank[i]] = is_f64 ? key_of_f64(xt[c0 + i]) : key_of_i64(xt[c0 + i]);
+                O0[c0 + rank[i]] = (u32)(c0 + i);
+            }
+        }
+        u64 *Kin = K0.data(), *Kout = K1.data();
+        u32 *Oin = O0.data(), *Oout = O1.data();
+        for (int32_t w = C; w < span; w <<= 1) {
+            for (int32_t p0 = 0; p0 < span; p0 += seg) merge_seg_ko(Kin, Oin, Kout, Oout, span, w, p0, seg);
+            std::swap(Kin, Kout);
+            std::swap(Oin, Oout);
+        }
+        for (int32_t p = 0; p < span; p++) keys[t * stride + Oin[p]] = (u32)p;
     }
     return 0;
 }

@@ -64,14 +64,6 @@ def test_forward_validation(n, k, code):
     assert lib.last_error()
 
 
-@pytest.mark.parametrize("k", [4097, 9999, 32767])
-def test_forward64_window_limit(k):
-    L = lib.load()
-    assert L.mf_median_filter_f64(FAKE, 100000, k, FAKE, None, None) == 2
-    assert L.mf_median_filter_i64(FAKE, 100000, k, FAKE, None, None) == 2
-    assert "4095" in lib.last_error()
-
-
 def test_null_pointers_rejected():
     L = lib.load()
     assert L.mf_median_filter(None, 10, 3, FAKE, None, None) == 1

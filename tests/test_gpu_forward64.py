@@ -1,8 +1,9 @@
 """GPU forward parity for 64-bit signals (float64, int64): HIP path vs the
 CPU oracle.  Medians (bit patterns) and argmedians must be identical.
 
-Cases: every window family that takes 64-bit signals (k = 1; 512- and
-1024-thread tiles up to k = 4095), several tiles and ragged last blocks,
+Cases: every window family (k = 1; 512- and 1024-thread tiles up to
+k = 4095; one-pair tiles of the workspace path up to k = 32767), several
+tiles and ragged last blocks,
 n = k and n = k + 1, values ordered only by their high or only by their low
 32-bit word, float64 specials, presorted signals, argmed = NULL, the
 full-size workloads on sampled windows, and the argument errors.
@@ -20,7 +21,8 @@ from paper_1406_1717_amd import lib, workloads
 pytestmark = pytest.mark.gpu
 
 DEV = torch.device("cuda:0")
-KS = [1, 3, 5, 7, 15, 31, 33, 101, 129, 301, 701, 1001, 1025, 2047, 2049, 3001, 4095]
+KS = [1, 3, 5, 7, 15, 31, 33, 101, 129, 301, 701, 1001, 1025, 2047, 2049, 3001, 4095,
+      4097, 5001, 8191, 9999, 16385, 20001, 32767]
 GENS = {"f64_specials": workloads.f64_specials, "int64_words": workloads.int64_words,
         "int64_full": workloads.int64_full, "walk_f64": workloads.random_walk_f64}
 
@@ -52,7 +54,7 @@ def test_64bit_several_tiles(kind, k):
     assert_same(x, k, y, am, kind)
 
 
-@pytest.mark.parametrize("k", [1, 3, 101, 1001, 2049, 4095])
+@pytest.mark.parametrize("k", [1, 3, 101, 1001, 2049, 4095, 5001, 32767])
 def test_64bit_degenerate_lengths(k):
     for n in (k, k + 1, 2 * k - 1, 2 * k, 2 * k + 1):
         for x in (workloads.f64_specials(n, n), workloads.int64_words(n, n)):
@@ -60,7 +62,7 @@ def test_64bit_degenerate_lengths(k):
             assert_same(x, k, y, am, "n=%d" % n)
 
 
-@pytest.mark.parametrize("k", [3, 301, 3001])
+@pytest.mark.parametrize("k", [3, 301, 3001, 9999])
 def test_64bit_presorted_and_reversed(k):
     n = 20_000 + 17
     walk = workloads.random_walk_f64(n, 41)
@@ -108,10 +110,14 @@ def test_64bit_errors():
     x = torch.zeros(10_000, dtype=torch.float64, device=DEV)
     y = torch.empty(10_000, dtype=torch.float64, device=DEV)
     am = torch.empty(10_000, dtype=torch.int32, device=DEV)
-    for k, status in ((4097, 2), (9999, 2), (2, 1), (0, 1), (10_001, 1)):
+    for k, status in ((2, 1), (0, 1), (10_001, 1)):
         with pytest.raises(lib.MFError) as e:
             lib.mf_median_filter_f64(x, 10_000, k, y, am)
         assert e.value.status == status, k
+    big = torch.zeros(40_000, dtype=torch.float64, device=DEV)
+    with pytest.raises(lib.MFError) as e:
+        lib.mf_median_filter_f64(big, 40_000, 32769, y, am)
+    assert e.value.status == 2
     assert lib.load().mf_median_filter_i64(None, 100, 3, ctypes.c_void_p(y.data_ptr()), None, None) == 1
     # the library stays usable after the errors
     xs = workloads.int64_words(5000, 1)

@@ -196,3 +196,35 @@ def test_last_tiles_of_longest_signal(emu, k, threads):
     want = oracle.window_median(xs, k, sel - base) + base
     assert np.array_equal(am[sel - base], want)
     assert np.array_equal(y[sel - base].view(np.uint32), xs[want - base].view(np.uint32))
+
+
+@pytest.mark.parametrize("kind", ["f64_specials", "int64_words", "int64_full", "walk_f64"])
+def test_pair_ranks_64bit(emu, kind):
+    """The pair pre-pass of 64-bit signals on the global path (k > 4095):
+    chunks ranked as in LDS, sorted runs merged by merge-path segments; every
+    pair's ranks must equal its items' positions in (value, index) order
+    (numpy: dense value ranks under the float convention, then lexsort)."""
+    from paper_1406_1717_amd import workloads as W
+    from tests.brute import value_rank
+    gen = {"f64_specials": W.f64_specials, "int64_words": W.int64_words,
+           "int64_full": W.int64_full, "walk_f64": W.random_walk_f64}[kind]
+    emu.emu_rank_pairs64.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    for i, k in enumerate((4097, 5001, 8193, 16385, 32767)):
+        n = 3 * k + 1234 + i
+        x = gen(n, 800 + i)
+        stride, tiles = ctypes.c_int64(), ctypes.c_int64()
+        assert emu.emu_rank_pairs64(x.ctypes.data, n, k, int(x.dtype == np.float64), None,
+                                    ctypes.byref(stride), ctypes.byref(tiles)) == 0
+        keys = np.full(tiles.value * stride.value, 0xFFFFFFFF, dtype=np.uint32)
+        assert emu.emu_rank_pairs64(x.ctypes.data, n, k, int(x.dtype == np.float64), keys.ctypes.data,
+                                    ctypes.byref(stride), ctypes.byref(tiles)) == 0
+        for t in range(tiles.value):
+            e0 = t * k
+            span = min(n - e0, 2 * k)
+            seg = x[e0:e0 + span]
+            order = np.lexsort((np.arange(span), value_rank(seg)))
+            want = np.empty(span, dtype=np.uint32)
+            want[order] = np.arange(span, dtype=np.uint32)
+            got = keys[t * stride.value: t * stride.value + span]
+            assert np.array_equal(got, want), (kind, k, t)
