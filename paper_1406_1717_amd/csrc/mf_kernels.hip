@@ -891,8 +891,9 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
 // Rank pre-pass of a 64-bit signal on the global path (one pair of up to
 // 2k items per tile): workgroups loop over tiles; each ranks its pair in
 // chunks of kGlobalThreads * kRegs items in LDS, writes each chunk in sorted
-// (key, offset) order to its scratch, merges the runs there (merge path,
-// two copies) and writes keys[t * stride + offset] = rank.
+// (key, offset) order to its scratch, merges the runs there (two copies;
+// output tiles staged through LDS) and writes keys[t * stride + offset] =
+// rank.
 template <bool F64>
 __global__ __launch_bounds__(kGlobalThreads) void k_rank64_pair(const u64 *x, int64_t n, int32_t k, u32 *keys,
                                                                 int64_t stride, unsigned char *ws,
@@ -900,7 +901,7 @@ __global__ __launch_bounds__(kGlobalThreads) void k_rank64_pair(const u64 *x, in
 {
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int NT = kGlobalThreads;
-    constexpr int32_t kSeg = 16;   // merge outputs per thread and pass
+    __shared__ int32_t split[2];
     const int tid = threadIdx.x;
     const int32_t C = NT * kRegs;
     const int32_t smax = 2 * k;
@@ -927,10 +928,37 @@ __global__ __launch_bounds__(kGlobalThreads) void k_rank64_pair(const u64 *x, in
         }
         u64 *Kin = K0, *Kout = K1;
         u32 *Oin = O0, *Oout = O1;
+        u64 *LK = (u64 *)lds;
+        u32 *LO = (u32 *)(lds + 8 * C);
         for (int32_t w = C; w < span; w <<= 1) {
-            for (int32_t p0 = tid * kSeg; p0 < span; p0 += NT * kSeg)
-                merge_seg_ko(Kin, Oin, Kout, Oout, span, w, p0, kSeg);
-            __syncthreads();
+            for (int32_t ob = 0; ob < span; ob += C) {
+                int32_t s0, lenA, lenB;
+                merge_runs(span, w, ob, s0, lenA, lenB);
+                const int32_t d0 = ob - s0;
+                const int32_t d1 = d0 + C < lenA + lenB ? d0 + C : lenA + lenB;
+                if (tid < 2)
+                    split[tid] = merge_split_ko(Kin + s0, Oin + s0, lenA, Kin + s0 + w, Oin + s0 + w, lenB,
+                                                tid ? d1 : d0);
+                __syncthreads();
+                const int32_t a0 = split[0], na = split[1] - a0;
+                const int32_t b0 = d0 - a0, nb = (d1 - d0) - na;
+                for (int32_t i = tid; i < na + nb; i += NT) {
+                    const int32_t src = i < na ? s0 + a0 + i : s0 + w + b0 + (i - na);
+                    LK[i] = Kin[src];
+                    LO[i] = Oin[src];
+                }
+                __syncthreads();
+                u64 kv[kRegs];
+                u32 ov[kRegs];
+                const int32_t cnt = merge_local_ko(LK, LO, na, nb, tid * kRegs, kv, ov);
+#pragma unroll
+                for (int j = 0; j < kRegs; j++)
+                    if (j < cnt) {
+                        Kout[ob + tid * kRegs + j] = kv[j];
+                        Oout[ob + tid * kRegs + j] = ov[j];
+                    }
+                __syncthreads();   // the next tile restages the LDS
+            }
             u64 *tk = Kin; Kin = Kout; Kout = tk;
             u32 *to = Oin; Oin = Oout; Oout = to;
         }

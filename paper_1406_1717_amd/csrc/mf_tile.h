@@ -2091,41 +2091,61 @@ MF_HD void rank_raw(const Shape &s, const Tile &T, const u32 *rank, int32_t tid,
 
 // Ranks of a pair of more than NT * kRegs items (windows above 4095): the
 // pair is cut into chunks of that many items, each chunk is ranked in LDS
-// and written in sorted order (key, offset), and merge-path levels merge the
-// sorted runs in global memory.  One level: outputs [p0, p0 + seg) of the
-// merge of runs of w at Kin/Oin (span items in all; seg divides 2w).
-MF_HD void merge_seg_ko(const u64 *Kin, const u32 *Oin, u64 *Kout, u32 *Oout, int32_t span, int32_t w,
-                        int32_t p0, int32_t seg)
+// and written in sorted order (key, offset), and merge levels combine the
+// sorted runs in global memory, one output tile of NT * kRegs items at a
+// time: merge path at the tile's first and last output gives the tile's
+// input range of each run, both ranges are staged in LDS, and each thread
+// merges kRegs outputs from there.
+//
+// The number of A items among the first d outputs of the merge of runs A
+// and B ((key, offset) pairs, all distinct).
+MF_HD int32_t merge_split_ko(const u64 *KA, const u32 *OA, int32_t lenA, const u64 *KB, const u32 *OB,
+                             int32_t lenB, int32_t d)
 {
-    const int32_t s0 = p0 & ~(2 * w - 1);
-    const int32_t rest = span - s0;
-    const int32_t lenA = rest < w ? rest : w;
-    const int32_t lenB = rest - lenA < w ? rest - lenA : w;
-    const u64 *KA = Kin + s0, *KB = Kin + s0 + w;
-    const u32 *OA = Oin + s0, *OB = Oin + s0 + w;
-    const int32_t d = p0 - s0;
     int32_t lo = d > lenB ? d - lenB : 0;
     int32_t hi = d < lenA ? d : lenA;
     while (lo < hi) {
         const int32_t mid = (lo + hi) >> 1;
         const int32_t bm = d - 1 - mid;
-        const bool aless = KA[mid] < KB[bm] || (KA[mid] == KB[bm] && OA[mid] < OB[bm]);
-        if (aless) lo = mid + 1;
+        const u64 ka = KA[mid], kb = KB[bm];
+        if (ka < kb || (ka == kb && OA[mid] < OB[bm])) lo = mid + 1;
         else hi = mid;
     }
-    int32_t a = lo, b = d - lo;
-    for (int32_t q = 0; q < seg && p0 + q < span; q++) {
-        const bool takeA = b >= lenB || (a < lenA && (KA[a] < KB[b] || (KA[a] == KB[b] && OA[a] < OB[b])));
-        if (takeA) {
-            Kout[p0 + q] = KA[a];
-            Oout[p0 + q] = OA[a];
-            a++;
-        } else {
-            Kout[p0 + q] = KB[b];
-            Oout[p0 + q] = OB[b];
-            b++;
-        }
+    return lo;
+}
+
+// Thread outputs [q0, q0 + kRegs) (fewer at the end) of the merge of the
+// staged runs LK/LO[0, na) and LK/LO[na, na + nb); returns their number.
+MF_HD int32_t merge_local_ko(const u64 *LK, const u32 *LO, int32_t na, int32_t nb, int32_t q0,
+                             u64 (&kv)[kRegs], u32 (&ov)[kRegs])
+{
+    const int32_t tot = na + nb;
+    if (q0 >= tot) return 0;
+    int32_t a = merge_split_ko(LK, LO, na, LK + na, LO + na, nb, q0);
+    int32_t b = q0 - a;
+    const u64 *KB = LK + na;
+    const u32 *OB = LO + na;
+    const int32_t cnt = tot - q0 < kRegs ? tot - q0 : kRegs;
+#pragma unroll
+    for (int q = 0; q < kRegs; q++) {
+        if (q >= cnt) break;
+        const bool takeA = b >= nb || (a < na && (LK[a] < KB[b] || (LK[a] == KB[b] && LO[a] < OB[b])));
+        kv[q] = takeA ? LK[a] : KB[b];
+        ov[q] = takeA ? LO[a] : OB[b];
+        if (takeA) a++;
+        else b++;
     }
+    return cnt;
+}
+
+// The runs of the merge that output position ob belongs to: start s0 and
+// lengths of A = [s0, s0 + lenA) and B = [s0 + w, s0 + w + lenB).
+MF_HD void merge_runs(int32_t span, int32_t w, int32_t ob, int32_t &s0, int32_t &lenA, int32_t &lenB)
+{
+    s0 = ob & ~(2 * w - 1);
+    const int32_t rest = span - s0;
+    lenA = rest < w ? rest : w;
+    lenB = rest - lenA < w ? rest - lenA : w;
 }
 
 // Scratch bytes of one workgroup ranking a pair of window k: two copies of

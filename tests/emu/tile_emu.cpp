@@ -443,8 +443,9 @@ extern "C" int emu_median_filter64(const void *x, int64_t n, int32_t k, int is_f
 // The pair pre-pass of 64-bit signals on the global path (k > 4095): for
 // every pair tile of the shape (threads = 2S / kRegs, one pair per tile),
 // chunks of 8192 items ranked (emu_rank_items, 1024 threads), written in
-// sorted (key, offset) order, merged by merge_seg_ko levels (segments of 16
-// outputs, every segment of a level before the next), then
+// sorted (key, offset) order, merged level by level in output tiles of 8192
+// staged as the kernel stages them in LDS (merge_split_ko, merge_local_ko
+// for each of the 1024 threads), then
 // keys[t * stride + offset] = rank.
 extern "C" int emu_rank_pairs64(const void *x, int64_t n, int32_t k, int is_f64, uint32_t *keys, int64_t *out_stride,
                                 int64_t *out_tiles)
@@ -457,7 +458,7 @@ extern "C" int emu_rank_pairs64(const void *x, int64_t n, int32_t k, int is_f64,
     *out_stride = stride;
     *out_tiles = s.ntiles;
     if (!keys) return 0;
-    const int32_t C = 1024 * kRegs, seg = 16;
+    const int32_t C = 1024 * kRegs;
     std::vector<u64> K0(2 * (size_t)k), K1(2 * (size_t)k);
     std::vector<u32> O0(2 * (size_t)k), O1(2 * (size_t)k), rank;
     for (int64_t t = 0; t < s.ntiles; t++) {
@@ -475,8 +476,34 @@ extern "C" int emu_rank_pairs64(const void *x, int64_t n, int32_t k, int is_f64,
         }
         u64 *Kin = K0.data(), *Kout = K1.data();
         u32 *Oin = O0.data(), *Oout = O1.data();
+        std::vector<u64> LK(C);
+        std::vector<u32> LO(C);
         for (int32_t w = C; w < span; w <<= 1) {
-            for (int32_t p0 = 0; p0 < span; p0 += seg) merge_seg_ko(Kin, Oin, Kout, Oout, span, w, p0, seg);
+            for (int32_t ob = 0; ob < span; ob += C) {
+                int32_t s0, lenA, lenB;
+                merge_runs(span, w, ob, s0, lenA, lenB);
+                const int32_t d0 = ob - s0;
+                const int32_t d1 = d0 + C < lenA + lenB ? d0 + C : lenA + lenB;
+                const int32_t a0 = merge_split_ko(Kin + s0, Oin + s0, lenA, Kin + s0 + w, Oin + s0 + w, lenB, d0);
+                const int32_t a1 = merge_split_ko(Kin + s0, Oin + s0, lenA, Kin + s0 + w, Oin + s0 + w, lenB, d1);
+                const int32_t na = a1 - a0, b0 = d0 - a0, nb = (d1 - d0) - na;
+                if (na < 0 || nb < 0 || na + nb > C) return -21;
+                std::fill(LK.begin(), LK.end(), 0xA5A5A5A5A5A5A5A5ull);
+                for (int32_t i = 0; i < na + nb; i++) {
+                    const int32_t src = i < na ? s0 + a0 + i : s0 + w + b0 + (i - na);
+                    LK[i] = Kin[src];
+                    LO[i] = Oin[src];
+                }
+                for (int q = 0; q < 1024; q++) {
+                    u64 kv[kRegs];
+                    u32 ov[kRegs];
+                    const int32_t cnt = merge_local_ko(LK.data(), LO.data(), na, nb, q * kRegs, kv, ov);
+                    for (int j = 0; j < cnt; j++) {
+                        Kout[ob + q * kRegs + j] = kv[j];
+                        Oout[ob + q * kRegs + j] = ov[j];
+                    }
+                }
+            }
             std::swap(Kin, Kout);
             std::swap(Oin, Oout);
         }
