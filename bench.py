@@ -303,7 +303,7 @@ def extras(torch, mf, lib, workloads, args):
                                  "autotune_s": tune_s}
     plan.close()
     out["paper_generators"] = paper_sweep(torch, lib, workloads)
-    out["paper_generators_64"] = paper_sweep(torch, lib, workloads, hs=(1, 10, 100, 1000), bits=64)
+    out["paper_generators_64"] = paper_sweep(torch, lib, workloads, bits=64)
     return out
 
 

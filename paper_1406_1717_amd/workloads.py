@@ -216,7 +216,7 @@ def workload(name):
     if name == "int64_full_64m":
         return {"x": int64_full(2**26, SEEDS[name]), "k": 1001}
     if name == "random_walk_f64_16m":
-        return {"x": random_walk_f64(2**24, SEEDS[name]), "ks": [3, 31, 301, 3001]}
+        return {"x": random_walk_f64(2**24, SEEDS[name]), "ks": [3, 31, 301, 3001, 30001]}
     if name == "sorted_walk_f32_16m":
         return {"x": sorted_walk_f32(2**24, SEEDS["random_walk_f32_16m"]),
                 "ks": [3, 31, 301, 3001, 30001]}

@@ -99,7 +99,7 @@ def test_64bit_full_size_int64_full_64m():
     _sampled(x, k, am, y, 3000, 5)
 
 
-@pytest.mark.parametrize("k", [301, 3001])
+@pytest.mark.parametrize("k", [301, 3001, 30001])
 def test_64bit_full_size_random_walk_f64_16m(k):
     x = workloads.workload("random_walk_f64_16m")["x"]
     y, am = run_gpu(x, k)
