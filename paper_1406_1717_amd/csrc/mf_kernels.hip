@@ -901,7 +901,7 @@ __global__ __launch_bounds__(kGlobalThreads) void k_rank64_pair(const u64 *x, in
 {
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int NT = kGlobalThreads;
-    __shared__ int32_t split[2];
+    __shared__ int32_t split[16];   // two merge-path splits per output tile
     const int tid = threadIdx.x;
     const int32_t C = NT * kRegs;
     const int32_t smax = 2 * k;
@@ -915,32 +915,63 @@ __global__ __launch_bounds__(kGlobalThreads) void k_rank64_pair(const u64 *x, in
         const Tile T = make_tile(s, t);
         const int32_t span = tile_items(s, T);
         const u64 *xt = x + T.e0;
+        u64 *LK = (u64 *)lds;
+        u32 *LO = (u32 *)(lds + 8 * C);
         for (int32_t c0 = 0; c0 < span; c0 += C) {
             const int32_t len = span - c0 < C ? span - c0 : C;
             rank_items<NT, F64>(xt + c0, len, lds);
-            const u32 *rank = (const u32 *)lds;
-            for (int32_t i = tid; i < len; i += NT) {
-                const u32 r = rank[i];
-                K0[c0 + r] = F64 ? key_of_f64(xt[c0 + i]) : key_of_i64(xt[c0 + i]);
-                O0[c0 + r] = (u32)(c0 + i);
+            // the chunk in sorted order through LDS, then written contiguously
+            u32 rr[kRegs];
+            u64 kk[kRegs];
+#pragma unroll
+            for (int j = 0; j < kRegs; j++) {
+                const int32_t i = tid * kRegs + j;
+                rr[j] = 0u;
+                kk[j] = 0ull;
+                if (i < len) {
+                    rr[j] = ((const u32 *)lds)[i];
+                    kk[j] = F64 ? key_of_f64(xt[c0 + i]) : key_of_i64(xt[c0 + i]);
+                }
+            }
+            __syncthreads();   // every rank is read
+#pragma unroll
+            for (int j = 0; j < kRegs; j++) {
+                const int32_t i = tid * kRegs + j;
+                if (i < len) {
+                    LK[rr[j]] = kk[j];
+                    LO[rr[j]] = (u32)(c0 + i);
+                }
+            }
+            __syncthreads();
+            for (int32_t p = tid; p < len; p += NT) {
+                K0[c0 + p] = LK[p];
+                O0[c0 + p] = LO[p];
             }
             __syncthreads();   // the next chunk reuses the LDS
         }
         u64 *Kin = K0, *Kout = K1;
         u32 *Oin = O0, *Oout = O1;
-        u64 *LK = (u64 *)lds;
-        u32 *LO = (u32 *)(lds + 8 * C);
+        const int32_t ntile = (span + C - 1) / C;   // at most 8 (2k < 65536)
         for (int32_t w = C; w < span; w <<= 1) {
+            // the merge-path splits at the first and last output of every
+            // output tile of the level, searched concurrently
+            if (tid < 2 * ntile) {
+                int32_t s0, lenA, lenB;
+                const int32_t ob = (tid >> 1) * C;
+                merge_runs(span, w, ob, s0, lenA, lenB);
+                const int32_t d0 = ob - s0;
+                const int32_t d1 = d0 + C < lenA + lenB ? d0 + C : lenA + lenB;
+                split[tid] = merge_split_ko(Kin + s0, Oin + s0, lenA, Kin + s0 + w, Oin + s0 + w, lenB,
+                                            (tid & 1) ? d1 : d0);
+            }
+            __syncthreads();
             for (int32_t ob = 0; ob < span; ob += C) {
                 int32_t s0, lenA, lenB;
                 merge_runs(span, w, ob, s0, lenA, lenB);
                 const int32_t d0 = ob - s0;
                 const int32_t d1 = d0 + C < lenA + lenB ? d0 + C : lenA + lenB;
-                if (tid < 2)
-                    split[tid] = merge_split_ko(Kin + s0, Oin + s0, lenA, Kin + s0 + w, Oin + s0 + w, lenB,
-                                                tid ? d1 : d0);
-                __syncthreads();
-                const int32_t a0 = split[0], na = split[1] - a0;
+                const int32_t ti = ob / C;
+                const int32_t a0 = split[2 * ti], na = split[2 * ti + 1] - a0;
                 const int32_t b0 = d0 - a0, nb = (d1 - d0) - na;
                 for (int32_t i = tid; i < na + nb; i += NT) {
                     const int32_t src = i < na ? s0 + a0 + i : s0 + w + b0 + (i - na);
