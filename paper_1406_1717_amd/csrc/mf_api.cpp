@@ -683,6 +683,12 @@ extern "C" mf_status mf_median_filter_rows(const float *x, int64_t rows, int64_t
     return forward_rows(x, rows, n, k, y, argmed, true, (hipStream_t)stream);
 }
 
+extern "C" mf_status mf_median_filter_rows_i32(const int32_t *x, int64_t rows, int64_t n, int32_t k, int32_t *y,
+                                               int32_t *argmed, void *stream)
+{
+    return forward_rows(x, rows, n, k, y, argmed, false, (hipStream_t)stream);
+}
+
 extern "C" mf_status mf_median_filter_batched(const float *x, const int64_t *x_offsets, const int32_t *ks,
                                               int32_t num_signals, float *y, int32_t *argmed, void *stream)
 {

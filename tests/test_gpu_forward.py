@@ -139,6 +139,24 @@ def test_rows_matches_single():
         assert np.array_equal(am[r], ao) and np.array_equal(y[r], yo)
 
 
+@pytest.mark.parametrize("k", [3, 201, 3001, 5001])
+def test_rows_int32(k):
+    """int32 rows (the LDS paths and the workspace path), each row against
+    the oracle, with rows of full-range values and of heavy ties."""
+    rng = np.random.default_rng(10 + k)
+    rows, n = 5, 3 * k + 2001
+    x = rng.integers(-2**31, 2**31, (rows, n), dtype=np.int32)
+    x[1] = rng.integers(0, 5, n)
+    y, am = mf.median_filter(torch.from_numpy(x).to(DEV), k)
+    torch.cuda.synchronize()
+    mf.lib.mf_check_device_error()
+    y = y.cpu().numpy()
+    am = am.cpu().numpy()
+    for r in range(rows):
+        yo, ao = oracle.sortmedian(x[r], k)
+        assert np.array_equal(am[r], ao) and np.array_equal(y[r], yo), r
+
+
 def test_without_argmed():
     rng = np.random.default_rng(10)
     x = rng.standard_normal(10_000).astype(np.float32)
