@@ -96,3 +96,13 @@ def test_batched_plan_validation():
     k = np.array([3, 3], dtype=np.int32)
     assert L.mf_plan_create_batched(bad.ctypes.data_as(ctypes.c_void_p), k.ctypes.data_as(ctypes.c_void_p),
                                     2, ctypes.byref(h)) == 1
+
+
+def test_binding_refuses_without_the_library(monkeypatch, tmp_path):
+    """No fallback: without libmf.so every call fails loudly."""
+    monkeypatch.setattr(lib, "_lib", None)
+    monkeypatch.setattr(lib, "LIB_PATH", str(tmp_path / "missing" / "libmf.so"))
+    with pytest.raises(ImportError):
+        lib.load()
+    with pytest.raises(ImportError):
+        lib.mf_output_length(10, 3)
