@@ -16,7 +16,8 @@ def value_rank(x):
     """Dense rank of each value under the float/int convention."""
     x = np.asarray(x)
     if x.dtype.kind == "f":
-        v = x.astype(np.float64)
+        with np.errstate(invalid="ignore"):      # NaN payloads
+            v = x.astype(np.float64)
         nan = np.isnan(v)
         v = np.where(nan, 0.0, v)
         v = np.where(v == 0.0, 0.0, v)          # fold -0.0 onto +0.0

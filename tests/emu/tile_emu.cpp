@@ -542,3 +542,16 @@ extern "C" int64_t emu_ntiles(int64_t n, int32_t k, int threads)
     if (make_shape(n, k, threads, &s) != 0) return -1;
     return s.ntiles;
 }
+
+// The order-preserving keys of the tile phases, element by element: kind 0
+// float32, 1 int32 (32-bit keys into out32), 2 float64, 3 int64 (64-bit keys
+// into out64).
+extern "C" void emu_keys(const void *x, int64_t n, int kind, uint32_t *out32, uint64_t *out64)
+{
+    for (int64_t i = 0; i < n; i++) {
+        if (kind == 0) out32[i] = key_of_f32(((const u32 *)x)[i]);
+        else if (kind == 1) out32[i] = key_of_i32(((const u32 *)x)[i]);
+        else if (kind == 2) out64[i] = key_of_f64(((const u64 *)x)[i]);
+        else out64[i] = key_of_i64(((const u64 *)x)[i]);
+    }
+}

@@ -228,3 +228,43 @@ def test_pair_ranks_64bit(emu, kind):
             want[order] = np.arange(span, dtype=np.uint32)
             got = keys[t * stride.value: t * stride.value + span]
             assert np.array_equal(got, want), (kind, k, t)
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+def test_key_transforms_order(emu, kind):
+    """Sorting by the kernels' unsigned keys (with the index as tie-break)
+    gives numpy's stable order under the value convention: -0.0 equal to
+    +0.0, every NaN above +inf and equal to the others, signed integers."""
+    from tests.brute import value_rank
+    rng = np.random.default_rng(50 + kind)
+    n = 20_000
+    if kind == 0:
+        pool = np.array([0.0, -0.0, np.inf, -np.inf, np.nan, 1e-45, -1e-45, 3.4e38, -3.4e38, 1.0, -1.0], np.float32)
+        x = rng.standard_normal(n).astype(np.float32)
+        m = rng.random(n) < 0.3
+        x[m] = rng.choice(pool, int(m.sum()))
+        x[:3] = np.frombuffer(np.array([0xFFC00001, 0x7F800001, 0xFFFFFFFF], np.uint32).tobytes(), np.float32)
+    elif kind == 1:
+        x = rng.integers(-2**31, 2**31, n, dtype=np.int32)
+        x[:4] = [np.iinfo(np.int32).min, np.iinfo(np.int32).max, 0, -1]
+        x[rng.random(n) < 0.2] = 7
+    elif kind == 2:
+        from paper_1406_1717_amd import workloads as W
+        x = W.f64_specials(n, 51)
+        x[:3] = np.frombuffer(np.array([0xFFF8000000000001, 0x7FF0000000000001, 0xFFFFFFFFFFFFFFFF],
+                                       np.uint64).tobytes(), np.float64)
+    else:
+        from paper_1406_1717_amd import workloads as W
+        x = W.int64_words(n, 52)
+    wide = kind >= 2
+    out32 = np.zeros(n, np.uint32)
+    out64 = np.zeros(n, np.uint64)
+    emu.emu_keys.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    emu.emu_keys(x.ctypes.data, n, kind, out32.ctypes.data, out64.ctypes.data)
+    keys = out64 if wide else out32
+    got = np.lexsort((np.arange(n), keys))
+    want = np.lexsort((np.arange(n), value_rank(x)))
+    assert np.array_equal(got, want)
+    # equal values (and only those) share a key
+    vr = value_rank(x)
+    assert np.array_equal(keys[got][1:] == keys[got][:-1], vr[got][1:] == vr[got][:-1])
