@@ -24,6 +24,9 @@
  * - Limits: n <= 2^31 - 1 (argmed is int32), k <= 32767.
  * - Thread safety: entry points may be called from several host threads;
  *   one plan must not be executed from two threads at once.
+ * - Environment: MF_WS_LIMIT=<bytes> makes workspace requests above it fail
+ *   with MF_ERR_NOMEM (a test switch); MF_LOG=1 prints plan and autotune
+ *   decisions on stderr.
  */
 #ifndef MF_H
 #define MF_H

@@ -6,6 +6,7 @@
 #include <stdarg.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -45,6 +46,28 @@ static mf_status hip_fail(hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(e_, what); \
     } while (0)
 
+// ------------------------------------------------------------------ environment
+
+namespace {
+
+// Diagnostics and test switches, read from the environment at each use:
+//   MF_WS_LIMIT=<bytes>  workspace requests above it fail with
+//                        MF_ERR_NOMEM, as a failed allocation would;
+//   MF_LOG=1             plan and autotune decisions on stderr.
+int64_t env_ws_limit()
+{
+    const char *e = getenv("MF_WS_LIMIT");
+    return e ? atoll(e) : 0;
+}
+
+bool env_log()
+{
+    const char *e = getenv("MF_LOG");
+    return e && e[0] == '1';
+}
+
+}  // namespace
+
 // ------------------------------------------------------------------ device state
 
 namespace {
@@ -83,6 +106,10 @@ mf_status device_state(Device **out)
 // workspace are serialized across streams through ws_done.
 mf_status acquire_ws(Device &D, int64_t bytes, hipStream_t st, unsigned char **ws)
 {
+    const int64_t limit = env_ws_limit();
+    if (limit > 0 && bytes > limit)
+        return fail(MF_ERR_NOMEM, "workspace of %lld bytes (over MF_WS_LIMIT = %lld)", (long long)bytes,
+                    (long long)limit);
     std::lock_guard<std::mutex> lk(D.mu);
     if (D.ws_bytes < bytes) {
         if (D.ws) {
@@ -449,6 +476,14 @@ extern "C" mf_status mf_plan_create_batched(const int64_t *x_offsets, const int3
         if (e == hipSuccess) e = hipMemcpy(p->d_bunits, bunits.data(), sizeof(Unit) * bunits.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) { plan_free(p); return hip_fail(e, "plan backward work list"); }
     }
+    if (env_log()) {
+        static const char *names[] = {"k=1", "lds512", "lds1024", "global"};
+        fprintf(stderr, "mf: plan of %d signals, %lld outputs\n", num_signals, (long long)p->total_out);
+        for (int c = 0; c < kConfigs; c++)
+            for (const PathGroup &g : p->groups[c])
+                fprintf(stderr, "mf:   config %d: %s, %lld units, %zu B LDS%s\n", c, names[g.path],
+                        (long long)g.nunits, g.lds, g.persistent ? ", persistent" : "");
+    }
     *out = p;
     return MF_OK;
 }
@@ -605,6 +640,9 @@ extern "C" mf_status mf_plan_autotune(mf_plan *p, const float *x, float *y, int3
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     p->config = (s == MF_OK && best >= 0) ? best : before;
+    if (env_log() && s == MF_OK)
+        fprintf(stderr, "mf: autotune %.3f / %.3f / %.3f ms per execute, config %d\n", p->tuned_ms[0],
+                p->tuned_ms[1], p->tuned_ms[2], p->config);
     return s;
 }
 

@@ -117,3 +117,43 @@ def test_distinct_normal_256_fwd_bwd():
     for r in range(rows):
         outs = rng.integers(0, n - k + 1, 64)
         assert np.array_equal(amh[r][outs], oracle.window_median(x[r], k, outs)), "row %d" % r
+
+
+def test_workspace_limit_and_log(monkeypatch, capfd):
+    """MF_WS_LIMIT makes workspace requests above it fail with
+    MF_ERR_NOMEM before anything is enqueued (the outputs stay untouched),
+    and the library works again without it; MF_LOG=1 reports plan and
+    autotune decisions on stderr."""
+    import paper_1406_1717_amd as mf
+    from paper_1406_1717_amd import lib
+    import oracle
+    dev = torch.device("cuda:0")
+    n, k = 40_000, 5001
+    x = torch.from_numpy(workloads.random_walk_f32(n, 7)).to(dev)
+    y = torch.full((n - k + 1,), -1.0, device=dev)
+    am = torch.full((n - k + 1,), -1, dtype=torch.int32, device=dev)
+    monkeypatch.setenv("MF_WS_LIMIT", "4096")
+    with pytest.raises(lib.MFError) as e:
+        lib.mf_median_filter(x, n, k, y, am)
+    assert e.value.status == 3 and "MF_WS_LIMIT" in str(e.value)
+    torch.cuda.synchronize()
+    assert bool((am == -1).all())
+    x64 = torch.from_numpy(workloads.int64_words(n, 8)).to(dev)
+    with pytest.raises(lib.MFError) as e:
+        mf.median_filter(x64, 3001)
+    assert e.value.status == 3
+    monkeypatch.delenv("MF_WS_LIMIT")
+    y2, am2 = mf.median_filter(x, k)
+    torch.cuda.synchronize()
+    assert np.array_equal(am2.cpu().numpy(), oracle.sortmedian(x.cpu().numpy(), k)[1])
+    monkeypatch.setenv("MF_LOG", "1")
+    off = np.array([0, 20_000, 45_000], dtype=np.int64)
+    ks = np.array([101, 3001], dtype=np.int32)
+    xb = torch.from_numpy(workloads.uniform_f32(45_000, 9)).to(dev)
+    yb = torch.empty(45_000 - 100 - 3000, device=dev)
+    ab = torch.empty_like(yb, dtype=torch.int32)
+    plan = mf.Plan(off, ks)
+    plan.autotune(xb, yb, ab, reps=1)
+    plan.close()
+    err = capfd.readouterr().err
+    assert "mf: plan of 2 signals" in err and "mf: autotune" in err
