@@ -80,6 +80,12 @@ mf_status mf_median_filter_rows(const float *x, int64_t rows, int64_t n, int32_t
 mf_status mf_median_filter_rows_i32(const int32_t *x, int64_t rows, int64_t n, int32_t k,
                                     int32_t *y, int32_t *argmed, void *stream);
 
+/* 64-bit rows (float64, int64): the same layouts as mf_median_filter_rows. */
+mf_status mf_median_filter_rows_f64(const double *x, int64_t rows, int64_t n, int32_t k,
+                                    double *y, int32_t *argmed, void *stream);
+mf_status mf_median_filter_rows_i64(const int64_t *x, int64_t rows, int64_t n, int32_t k,
+                                    int64_t *y, int32_t *argmed, void *stream);
+
 /* Ragged batch of float32 signals in one launch.  Signal s is
  * x[x_offsets[s] .. x_offsets[s+1]) with odd window ks[s] <= its length.
  * Outputs are packed in signal order: signal s writes

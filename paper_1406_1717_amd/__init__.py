@@ -5,8 +5,8 @@ memory and streams, every step of the filter runs in the library's HIP
 kernels.
 
   median_filter(x, k)                 -> (y, argmed); x float32/int32 on a
-                                         GPU, shape (n,) or (rows, n), or a
-                                         float64/int64 signal (n,)
+                                         GPU (also float64/int64), shape (n,)
+                                         or (rows, n)
   median_filter_batched(x, offsets, ks) -> packed (y, argmed) of a ragged batch
   median_filter_backward(grad_y, argmed, n, k) -> grad_x
   MedianFilterFn.apply(x, k)          autograd: y, with grad routed to argmed
@@ -56,8 +56,12 @@ def median_filter(x, k, with_argmed=True):
             lib.mf_median_filter_rows(x, x.shape[0], n, k, y, am)
         elif x.dtype == torch.int32:
             lib.mf_median_filter_rows_i32(x, x.shape[0], n, k, y, am)
+        elif x.dtype == torch.float64:
+            lib.mf_median_filter_rows_f64(x, x.shape[0], n, k, y, am)
+        elif x.dtype == torch.int64:
+            lib.mf_median_filter_rows_i64(x, x.shape[0], n, k, y, am)
         else:
-            raise TypeError("row batches must be float32 or int32")
+            raise TypeError("x must be float32, int32, float64 or int64")
     else:
         raise ValueError("x must have 1 or 2 dimensions")
     return y, am

@@ -186,92 +186,76 @@ mf_status forward_rows(const void *x, int64_t rows, int64_t n, int32_t k, void *
     return MF_OK;
 }
 
-// Forward of one 64-bit signal through the int32 tile kernels on 32-bit
-// rank keys, which copy each median from the 64-bit x to y.  512-thread
-// tiles rank their items in LDS; for 1024-thread tiles a pre-pass writes
-// the keys tile by tile into the workspace and each tile reads its span.
-mf_status forward64(const void *x, int64_t n, int32_t k, void *y, int32_t *argmed, bool f64, hipStream_t st)
+// Forward of `rows` 64-bit signals of length n (back to back) through the
+// int32 tile kernels on 32-bit rank keys, which copy each median from the
+// 64-bit x to y.  512-thread tiles rank their items in LDS; for 1024-thread
+// tiles and one-pair tiles a pre-pass writes the keys unit by unit
+// (unit = row * tiles + tile, (P+1)k entries each) into the workspace and
+// each tile reads its span.
+mf_status forward64(const void *x, int64_t rows, int64_t n, int32_t k, void *y, int32_t *argmed, bool f64,
+                    hipStream_t st)
 {
     if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
+    if (rows < 1) return fail(MF_ERR_INVALID_VALUE, "rows = %lld must be >= 1", (long long)rows);
     mf_status s = check_signal(n, k);
     if (s != MF_OK) return s;
     const Path p = path_for(k);
+    const int64_t tiles = tiles_for(p, n, k);
+    if (p != PATH_IDENTITY && p != PATH_GLOBAL && rows * tiles > 0x7FFFFFFFll)
+        return fail(MF_ERR_UNSUPPORTED, "too many tiles (%lld)", (long long)(rows * tiles));
     Device *D = nullptr;
     if ((s = device_state(&D)) != MF_OK) return s;
     if (p == PATH_IDENTITY) {
-        MF_HIP(launch_identity64(x, y, argmed, n, st), "64-bit identity launch");
+        MF_HIP(launch_identity64(x, y, argmed, rows * n, n, st), "64-bit identity launch");
         return MF_OK;
     }
-    const int64_t tiles = tiles_for(p, n, k);
-    if (tiles > 0x7FFFFFFFll) return fail(MF_ERR_UNSUPPORTED, "too many tiles (%lld)", (long long)tiles);
+    const int64_t units = rows * tiles;
+    Launch L;
+    memset(&L, 0, sizeof L);
+    L.y = y;
+    L.argmed = argmed;
+    L.one.n = n;
+    L.one.k = k;
+    L.rows = rows;
+    L.tpr = tiles;
+    L.nunits = units;
+    L.x64 = x;
     if (p == PATH_LDS_SMALL) {   // 512-thread tiles rank their items in LDS
-        Launch L;
-        memset(&L, 0, sizeof L);
         L.x = x;
-        L.y = y;
-        L.argmed = argmed;
-        L.one.n = n;
-        L.one.k = k;
-        L.rows = 1;
-        L.tpr = tiles;
-        L.nunits = tiles;
         L.rank_mode = f64 ? 3 : 2;
-        L.x64 = x;
         MF_HIP(launch_forward(p, false, L, (size_t)rank64_lds_bytes_for(p, k), nullptr, 0, 0, D->d_err, st),
                "64-bit forward launch");
         return MF_OK;
     }
     const int64_t stride = rank64_stride_for(p, k);
-    const int64_t key_bytes = (tiles * stride * 4 + 255) & ~255ll;
+    const int64_t key_bytes = (units * stride * 4 + 255) & ~255ll;
+    L.rank_mode = 1;
+    L.xshift = k;
+    L.xrow = tiles * stride;
+    unsigned char *ws = nullptr;
     if (p == PATH_GLOBAL) {
         // one pair per tile: a pre-pass ranks each pair through its
         // workgroup's scratch, then the global-path tiles run on the ranks;
         // the scratch of the pre-pass and the tiles' workspace share memory
         const size_t lds = (size_t)lds_bytes_for(p, k);
         const int64_t gstride = global_ws_stride(k);
-        const int64_t gslots = std::min<int64_t>(global_ws_slots(lds), tiles);
+        const int64_t gslots = std::min<int64_t>(global_ws_slots(lds), units);
         const int64_t pstride = rank64_pair_scratch(k);
-        const int64_t pslots = std::min<int64_t>(256, tiles);
+        const int64_t pslots = std::min<int64_t>(256, units);
         const int64_t scratch = std::max<int64_t>(gstride * gslots, pstride * pslots);
-        unsigned char *ws = nullptr;
         if ((s = acquire_ws(*D, key_bytes + scratch, st, &ws)) != MF_OK) return s;
         uint32_t *keys = (uint32_t *)ws;
-        MF_HIP(launch_rank64_pair(f64, x, n, k, keys, stride, ws + key_bytes, pstride, pslots, tiles, st),
+        MF_HIP(launch_rank64_pair(f64, x, n, k, keys, stride, ws + key_bytes, pstride, pslots, tiles, units, st),
                "64-bit pair rank launch");
-        Launch L;
-        memset(&L, 0, sizeof L);
         L.x = keys;
-        L.y = y;
-        L.argmed = argmed;
-        L.one.n = n;
-        L.one.k = k;
-        L.rows = 1;
-        L.tpr = tiles;
-        L.nunits = tiles;
-        L.rank_mode = 1;
-        L.xshift = k;
-        L.x64 = x;
         MF_HIP(launch_forward(p, false, L, lds, ws + key_bytes, gstride, gslots, D->d_err, st),
                "64-bit forward launch");
         return release_ws(*D, st);
     }
-    unsigned char *ws = nullptr;
     if ((s = acquire_ws(*D, key_bytes, st, &ws)) != MF_OK) return s;
     uint32_t *keys = (uint32_t *)ws;
-    MF_HIP(launch_rank64(p, f64, x, n, k, keys, stride, tiles, st), "64-bit rank launch");
-    Launch L;
-    memset(&L, 0, sizeof L);
+    MF_HIP(launch_rank64(p, f64, x, n, k, keys, stride, tiles, units, st), "64-bit rank launch");
     L.x = keys;
-    L.y = y;
-    L.argmed = argmed;
-    L.one.n = n;
-    L.one.k = k;
-    L.rows = 1;
-    L.tpr = tiles;
-    L.nunits = tiles;
-    L.rank_mode = 1;
-    L.xshift = k;
-    L.x64 = x;
     MF_HIP(launch_forward(p, false, L, (size_t)lds_bytes_for(p, k), nullptr, 0, 0, D->d_err, st),
            "64-bit forward launch");
     return release_ws(*D, st);
@@ -706,13 +690,13 @@ extern "C" mf_status mf_median_filter_i32(const int32_t *x, int64_t n, int32_t k
 extern "C" mf_status mf_median_filter_f64(const double *x, int64_t n, int32_t k, double *y, int32_t *argmed,
                                           void *stream)
 {
-    return forward64(x, n, k, y, argmed, true, (hipStream_t)stream);
+    return forward64(x, 1, n, k, y, argmed, true, (hipStream_t)stream);
 }
 
 extern "C" mf_status mf_median_filter_i64(const int64_t *x, int64_t n, int32_t k, int64_t *y,
                                           int32_t *argmed, void *stream)
 {
-    return forward64(x, n, k, y, argmed, false, (hipStream_t)stream);
+    return forward64(x, 1, n, k, y, argmed, false, (hipStream_t)stream);
 }
 
 extern "C" mf_status mf_median_filter_rows(const float *x, int64_t rows, int64_t n, int32_t k, float *y,
@@ -725,6 +709,18 @@ extern "C" mf_status mf_median_filter_rows_i32(const int32_t *x, int64_t rows, i
                                                int32_t *argmed, void *stream)
 {
     return forward_rows(x, rows, n, k, y, argmed, false, (hipStream_t)stream);
+}
+
+extern "C" mf_status mf_median_filter_rows_f64(const double *x, int64_t rows, int64_t n, int32_t k, double *y,
+                                               int32_t *argmed, void *stream)
+{
+    return forward64(x, rows, n, k, y, argmed, true, (hipStream_t)stream);
+}
+
+extern "C" mf_status mf_median_filter_rows_i64(const int64_t *x, int64_t rows, int64_t n, int32_t k, int64_t *y,
+                                               int32_t *argmed, void *stream)
+{
+    return forward64(x, rows, n, k, y, argmed, false, (hipStream_t)stream);
 }
 
 extern "C" mf_status mf_median_filter_batched(const float *x, const int64_t *x_offsets, const int32_t *ks,

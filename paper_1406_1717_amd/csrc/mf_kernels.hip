@@ -101,7 +101,7 @@ __device__ __forceinline__ Resolved unit_of(const Launch &L, int64_t uidx)
         const int64_t row = uidx / L.tpr;
         tile = uidx - row * L.tpr;
         d = L.one;
-        d.x_off += row * d.n + tile * L.xshift;
+        d.x_off += row * (L.xrow ? L.xrow : d.n) + tile * L.xshift;
         d.y_off += row * (d.n - d.k + 1);
     }
     Resolved r;
@@ -271,17 +271,19 @@ __device__ __forceinline__ void rank_tile(const Shape &s, const Tile &T, const u
     rank_items<NT, F64>(x + T.e0, tile_items(s, T), lds);
 }
 
-// Rank pre-pass of a 64-bit signal for tiles ranked outside the tile kernel
-// (the 1024-thread tiles): one workgroup per tile writes its items' ranks
-// to keys[t * stride + item offset].
+// Rank pre-pass of 64-bit signals for tiles ranked outside the tile kernel
+// (the 1024-thread tiles): one workgroup per unit u = row * tiles + tile (rows
+// of n items at x + row * n) writes its items' ranks to
+// keys[u * stride + item offset].
 template <int NT, bool F64>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 6 : 4))) void k_rank64(const u64 *x, int64_t n, int32_t k, u32 *keys, int64_t stride)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 6 : 4))) void k_rank64(const u64 *x, int64_t n, int32_t k, u32 *keys, int64_t stride, int64_t tiles)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     Shape s;
     make_shape(n, k, NT, &s);
-    const Tile T = make_tile(s, blockIdx.x);
-    rank_tile<NT, F64>(s, T, x, lds);
+    const int64_t row = blockIdx.x / tiles;
+    const Tile T = make_tile(s, blockIdx.x - row * tiles);
+    rank_tile<NT, F64>(s, T, x + row * n, lds);
     const int32_t span = tile_items(s, T);
     u32 *out = keys + (int64_t)blockIdx.x * stride;
     const u32 *rank = (const u32 *)lds;
@@ -479,15 +481,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 
     Tile T;
     unit_shape<NT>(d, s, T);
     u32 raw[kRegs];
+    // a 64-bit signal's row of the launch (rows of n items, n-k+1 outputs)
+    const int64_t row = RK != 0 ? (int64_t)blockIdx.x / L.tpr : 0;
+    const u64 *x64 = (const u64 *)L.x64 + row * d.n;
+    u64 *y64 = (u64 *)L.y + row * (d.n - d.k + 1);
     if constexpr (RK >= 2) {
-        rank_tile<NT, RK == 3>(s, T, (const u64 *)L.x64, lds);
+        rank_tile<NT, RK == 3>(s, T, x64, lds);
         rank_raw(s, T, (const u32 *)lds, threadIdx.x, raw);
         __syncthreads();   // the tile phases reuse the LDS
     } else {
         load_raw(s, T, d.x, threadIdx.x, raw);
     }
     if constexpr (RK != 0) {
-        lds_tile<NT, F32, true>(d, s, T, raw, lds, err, (const u64 *)L.x64, (u64 *)L.y);
+        lds_tile<NT, F32, true>(d, s, T, raw, lds, err, x64, y64);
     } else {
         lds_tile<NT, F32>(d, s, T, raw, lds, err, d.x, d.y);
     }
@@ -544,12 +550,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // ------------------------------------------------------------------ 64-bit inputs
 
 // k = 1 for 64-bit elements: y = x, argmed[o] = o.
-__global__ __launch_bounds__(256) void k_identity64(const u64 *x, u64 *y, int32_t *argmed, int64_t n)
+__global__ __launch_bounds__(256) void k_identity64(const u64 *x, u64 *y, int32_t *argmed, int64_t total,
+                                                    int64_t n)
 {
     const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (o < n) {
+    if (o < total) {
         y[o] = x[o];
-        if (argmed) argmed[o] = (int32_t)o;
+        if (argmed) argmed[o] = (int32_t)(o - (o / n) * n);
     }
 }
 
@@ -820,8 +827,12 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
         u64 *srt2 = (u64 *)(base + g.srt2);
         const Tile T = make_tile(s, tile);
         const u32 *x = d.x;
-        const auto xo = [&]() { if constexpr (RK) return (const u64 *)L.x64; else return d.x; }();
-        const auto yo = [&]() { if constexpr (RK) return (u64 *)L.y; else return d.y; }();
+        const int64_t row = RK ? uidx / L.tpr : 0;   // rows of a 64-bit launch
+        const auto xo = [&]() { if constexpr (RK) return (const u64 *)L.x64 + row * d.n; else return d.x; }();
+        const auto yo = [&]() {
+            if constexpr (RK) return (u64 *)L.y + row * (d.n - d.k + 1);
+            else return d.y;
+        }();
 
         __syncthreads();   // the previous tile is done with the workspace
         // one-pair tiles: bucket sort of the pair (the sort buffer holds the
@@ -897,7 +908,7 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
 template <bool F64>
 __global__ __launch_bounds__(kGlobalThreads) void k_rank64_pair(const u64 *x, int64_t n, int32_t k, u32 *keys,
                                                                 int64_t stride, unsigned char *ws,
-                                                                int64_t ws_stride, int64_t ntiles)
+                                                                int64_t ws_stride, int64_t ntiles, int64_t nunits)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int NT = kGlobalThreads;
@@ -911,10 +922,11 @@ __global__ __launch_bounds__(kGlobalThreads) void k_rank64_pair(const u64 *x, in
     u32 *O1 = O0 + smax;
     Shape s;
     global_shape(n, k, &s);
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const Tile T = make_tile(s, t);
+    for (int64_t u = blockIdx.x; u < nunits; u += gridDim.x) {
+        const int64_t row = u / ntiles;
+        const Tile T = make_tile(s, u - row * ntiles);
         const int32_t span = tile_items(s, T);
-        const u64 *xt = x + T.e0;
+        const u64 *xt = x + row * n + T.e0;
         u64 *LK = (u64 *)lds;
         u32 *LO = (u32 *)(lds + 8 * C);
         for (int32_t c0 = 0; c0 < span; c0 += C) {
@@ -993,7 +1005,7 @@ __global__ __launch_bounds__(kGlobalThreads) void k_rank64_pair(const u64 *x, in
             u64 *tk = Kin; Kin = Kout; Kout = tk;
             u32 *to = Oin; Oin = Oout; Oout = to;
         }
-        u32 *out = keys + t * stride;
+        u32 *out = keys + u * stride;
         for (int32_t p = tid; p < span; p += NT) out[Oin[p]] = (u32)p;
         __syncthreads();   // the next tile reuses the scratch
     }
@@ -1349,37 +1361,38 @@ int64_t rank64_stride_for(Path p, int32_t k)
 }
 
 hipError_t launch_rank64(Path p, bool f64, const void *x, int64_t n, int32_t k, u32 *keys, int64_t stride,
-                         int64_t ntiles, hipStream_t st)
+                         int64_t ntiles, int64_t nunits, hipStream_t st)
 {
-    if (ntiles <= 0) return hipSuccess;
+    if (nunits <= 0) return hipSuccess;
     if (p != PATH_LDS_LARGE) return hipErrorInvalidValue;   // 512-thread tiles rank in their own LDS
-    const dim3 g((unsigned)ntiles);
+    const dim3 g((unsigned)nunits);
     const size_t lds = 12u * kLdsLarge * kRegs;
-    if (f64) hipLaunchKernelGGL((k_rank64<kLdsLarge, true>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride);
-    else     hipLaunchKernelGGL((k_rank64<kLdsLarge, false>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride);
+    if (f64) hipLaunchKernelGGL((k_rank64<kLdsLarge, true>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride, ntiles);
+    else     hipLaunchKernelGGL((k_rank64<kLdsLarge, false>), g, dim3(kLdsLarge), lds, st, (const u64 *)x, n, k, keys, stride, ntiles);
     return hipGetLastError();
 }
 
 int64_t rank64_pair_scratch(int32_t k) { return pair_rank_scratch(k); }
 
 hipError_t launch_rank64_pair(bool f64, const void *x, int64_t n, int32_t k, u32 *keys, int64_t stride,
-                              unsigned char *ws, int64_t ws_stride, int64_t slots, int64_t ntiles, hipStream_t st)
+                              unsigned char *ws, int64_t ws_stride, int64_t slots, int64_t ntiles, int64_t nunits,
+                              hipStream_t st)
 {
-    if (ntiles <= 0) return hipSuccess;
-    const dim3 g((unsigned)(slots < ntiles ? slots : ntiles));
+    if (nunits <= 0) return hipSuccess;
+    const dim3 g((unsigned)(slots < nunits ? slots : nunits));
     const size_t lds = 12u * kGlobalThreads * kRegs;
     if (f64) hipLaunchKernelGGL((k_rank64_pair<true>), g, dim3(kGlobalThreads), lds, st, (const u64 *)x, n, k, keys,
-                                stride, ws, ws_stride, ntiles);
+                                stride, ws, ws_stride, ntiles, nunits);
     else     hipLaunchKernelGGL((k_rank64_pair<false>), g, dim3(kGlobalThreads), lds, st, (const u64 *)x, n, k, keys,
-                                stride, ws, ws_stride, ntiles);
+                                stride, ws, ws_stride, ntiles, nunits);
     return hipGetLastError();
 }
 
-hipError_t launch_identity64(const void *x, void *y, int32_t *argmed, int64_t n, hipStream_t st)
+hipError_t launch_identity64(const void *x, void *y, int32_t *argmed, int64_t total, int64_t n, hipStream_t st)
 {
-    if (n <= 0) return hipSuccess;
-    const dim3 g((unsigned)((n + 255) / 256));
-    hipLaunchKernelGGL(k_identity64, g, dim3(256), 0, st, (const u64 *)x, (u64 *)y, argmed, n);
+    if (total <= 0) return hipSuccess;
+    const dim3 g((unsigned)((total + 255) / 256));
+    hipLaunchKernelGGL(k_identity64, g, dim3(256), 0, st, (const u64 *)x, (u64 *)y, argmed, total, n);
     return hipGetLastError();
 }
 

@@ -41,6 +41,7 @@ struct Launch {
     // and 3 (float64), each tile ranks x64 itself.  y holds 64-bit medians.
     int32_t rank_mode;
     int64_t xshift;      // items added to x per tile of `one`
+    int64_t xrow;        // items of x per row of `one` (0: n)
     const void *x64;
 };
 
@@ -103,20 +104,21 @@ hipError_t launch_backward(const BwdLaunch &L, bool f64, hipStream_t st);
 int64_t bwd_tiles_for(int64_t n);
 
 // 64-bit signals on an LDS path: entries per tile of the rank buffer and
-// the rank pre-pass (one workgroup per 1024-thread tile); k = 1 copies x and
-// writes argmed[o] = o.
+// the rank pre-pass (one workgroup per 1024-thread tile of each row); k = 1
+// copies x (`total` items, rows of n) and writes each row's argmed[o] = o.
 int64_t rank64_stride_for(Path p, int32_t k);
 // Dynamic LDS of a tile that ranks its 64-bit items itself.
 int64_t rank64_lds_bytes_for(Path p, int32_t k);
 hipError_t launch_rank64(Path p, bool f64, const void *x, int64_t n, int32_t k, uint32_t *keys, int64_t stride,
-                         int64_t ntiles, hipStream_t st);
+                         int64_t ntiles, int64_t nunits, hipStream_t st);
 // 64-bit signals on the global path: scratch bytes of one workgroup of the
 // pair pre-pass, and the pre-pass itself (a grid of `slots` workgroups
 // looping over the tiles).
 int64_t rank64_pair_scratch(int32_t k);
 hipError_t launch_rank64_pair(bool f64, const void *x, int64_t n, int32_t k, uint32_t *keys, int64_t stride,
-                              unsigned char *ws, int64_t ws_stride, int64_t slots, int64_t ntiles, hipStream_t st);
-hipError_t launch_identity64(const void *x, void *y, int32_t *argmed, int64_t n, hipStream_t st);
+                              unsigned char *ws, int64_t ws_stride, int64_t slots, int64_t ntiles, int64_t nunits,
+                              hipStream_t st);
+hipError_t launch_identity64(const void *x, void *y, int32_t *argmed, int64_t total, int64_t n, hipStream_t st);
 
 hipError_t prepare_kernels();
 

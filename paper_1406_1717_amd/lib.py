@@ -39,6 +39,8 @@ def load():
         "mf_median_filter_i64": [P, I64, I32, P, P, P],
         "mf_median_filter_rows": [P, I64, I64, I32, P, P, P],
         "mf_median_filter_rows_i32": [P, I64, I64, I32, P, P, P],
+        "mf_median_filter_rows_f64": [P, I64, I64, I32, P, P, P],
+        "mf_median_filter_rows_i64": [P, I64, I64, I32, P, P, P],
         "mf_median_filter_batched": [P, P, P, I32, P, P, P],
         "mf_median_filter_batched_i32": [P, P, P, I32, P, P, P],
         "mf_median_filter_backward": [P, P, I64, I32, P, P],
@@ -132,6 +134,16 @@ def mf_median_filter_rows(x, rows, n, k, y, argmed, stream=None):
 
 def mf_median_filter_rows_i32(x, rows, n, k, y, argmed, stream=None):
     _check(load().mf_median_filter_rows_i32(_ptr(x), int(rows), int(n), int(k), _ptr(y), _ptr(argmed),
+                                            _stream(stream)))
+
+
+def mf_median_filter_rows_f64(x, rows, n, k, y, argmed, stream=None):
+    _check(load().mf_median_filter_rows_f64(_ptr(x), int(rows), int(n), int(k), _ptr(y), _ptr(argmed),
+                                            _stream(stream)))
+
+
+def mf_median_filter_rows_i64(x, rows, n, k, y, argmed, stream=None):
+    _check(load().mf_median_filter_rows_i64(_ptr(x), int(rows), int(n), int(k), _ptr(y), _ptr(argmed),
                                             _stream(stream)))
 
 

@@ -76,6 +76,8 @@ def test_null_pointers_rejected():
     assert L.mf_median_filter_rows(FAKE, 0, 10, 3, FAKE, None, None) == 1
     assert L.mf_median_filter_rows_i32(FAKE, 0, 10, 3, FAKE, None, None) == 1
     assert L.mf_median_filter_rows_i32(None, 2, 10, 3, FAKE, None, None) == 1
+    assert L.mf_median_filter_rows_f64(FAKE, 0, 10, 3, FAKE, None, None) == 1
+    assert L.mf_median_filter_rows_i64(FAKE, 2, 10, 4, FAKE, None, None) == 1
     h = ctypes.c_void_p()
     assert L.mf_plan_create_batched(None, None, 1, ctypes.byref(h)) == 1
     assert L.mf_plan_execute(None, FAKE, FAKE, None, None) == 1

@@ -123,3 +123,23 @@ def test_64bit_errors():
     xs = workloads.int64_words(5000, 1)
     yy, aa = run_gpu(xs, 101)
     assert_same(xs, 101, yy, aa, "after errors")
+
+
+@pytest.mark.parametrize("k", [1, 101, 1001, 3001, 5001, 20001])
+@pytest.mark.parametrize("dtype", ["f64", "i64"])
+def test_64bit_rows(dtype, k):
+    """64-bit rows on every path (k = 1, in-LDS ranking, the 1024-thread
+    pre-pass, the pair pre-pass): each row against the oracle."""
+    rows = 3
+    n = 2 * k + 3001
+    gen = workloads.f64_specials if dtype == "f64" else workloads.int64_words
+    x = np.stack([gen(n, 900 + 10 * k + r) for r in range(rows)])
+    y, am = mf.median_filter(torch.from_numpy(x).to(DEV), k)
+    torch.cuda.synchronize()
+    lib.mf_check_device_error()
+    y = y.cpu().numpy()
+    am = am.cpu().numpy()
+    for r in range(rows):
+        yo, ao = oracle.sortmedian(x[r], k)
+        assert np.array_equal(am[r], ao), (dtype, k, r)
+        assert np.array_equal(y[r].view(np.uint64), yo.view(np.uint64)), (dtype, k, r)
