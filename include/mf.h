@@ -118,6 +118,11 @@ mf_status mf_median_filter_backward(const float *grad_y, const int32_t *argmed,
 mf_status mf_median_filter_backward_f64(const double *grad_y, const int32_t *argmed,
                                         int64_t n, int32_t k, double *grad_x, void *stream);
 
+/* Backward of the 64-bit rows (float64 gradients, same layouts). */
+mf_status mf_median_filter_backward_rows_f64(const double *grad_y, const int32_t *argmed,
+                                             int64_t rows, int64_t n, int32_t k,
+                                             double *grad_x, void *stream);
+
 /* Backward of mf_median_filter_rows (same layouts). */
 mf_status mf_median_filter_backward_rows(const float *grad_y, const int32_t *argmed,
                                          int64_t rows, int64_t n, int32_t k,

@@ -92,15 +92,17 @@ def median_filter_batched(x, x_offsets, ks, with_argmed=True):
 
 
 def median_filter_backward(grad_y, argmed, n, k):
-    """grad_x of y = x[argmed]: float32 for a float32 grad_y (rows too),
-    float64 for a float64 grad_y of one signal."""
+    """grad_x of y = x[argmed], of the grad_y's type (float32 or float64),
+    for one signal or rows."""
     _require_gpu(grad_y, "grad_y")
     _require_gpu(argmed, "argmed")
     if grad_y.dtype == torch.float64:
-        if grad_y.dim() != 1:
-            raise TypeError("float64 gradients take one signal")
-        gx = torch.empty(int(n), dtype=torch.float64, device=grad_y.device)
-        lib.mf_median_filter_backward_f64(grad_y, argmed, n, k, gx)
+        if grad_y.dim() == 1:
+            gx = torch.empty(int(n), dtype=torch.float64, device=grad_y.device)
+            lib.mf_median_filter_backward_f64(grad_y, argmed, n, k, gx)
+        else:
+            gx = torch.empty((grad_y.shape[0], int(n)), dtype=torch.float64, device=grad_y.device)
+            lib.mf_median_filter_backward_rows_f64(grad_y, argmed, grad_y.shape[0], n, k, gx)
         return gx
     if grad_y.dim() == 1:
         gx = torch.empty(int(n), dtype=torch.float32, device=grad_y.device)
@@ -119,8 +121,7 @@ def median_filter_backward_batched(grad_y, argmed, x_offsets, ks):
 
 
 class MedianFilterFn(torch.autograd.Function):
-    """y = median filter of x (float32, shape (n,) or (rows, n); or one
-    float64 signal).
+    """y = median filter of x (float32 or float64, shape (n,) or (rows, n)).
 
     The backward routes each upstream gradient entry to the input selected as
     that window's median (argmed), summed per input in increasing output

@@ -755,6 +755,12 @@ extern "C" mf_status mf_median_filter_backward_f64(const double *grad_y, const i
     return backward_rows(grad_y, argmed, 1, n, k, grad_x, true, (hipStream_t)stream);
 }
 
+extern "C" mf_status mf_median_filter_backward_rows_f64(const double *grad_y, const int32_t *argmed, int64_t rows,
+                                                        int64_t n, int32_t k, double *grad_x, void *stream)
+{
+    return backward_rows(grad_y, argmed, rows, n, k, grad_x, true, (hipStream_t)stream);
+}
+
 extern "C" mf_status mf_median_filter_backward_rows(const float *grad_y, const int32_t *argmed, int64_t rows,
                                                     int64_t n, int32_t k, float *grad_x, void *stream)
 {

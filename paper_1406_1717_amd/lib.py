@@ -46,6 +46,7 @@ def load():
         "mf_median_filter_backward": [P, P, I64, I32, P, P],
         "mf_median_filter_backward_rows": [P, P, I64, I64, I32, P, P],
         "mf_median_filter_backward_f64": [P, P, I64, I32, P, P],
+        "mf_median_filter_backward_rows_f64": [P, P, I64, I64, I32, P, P],
         "mf_median_filter_backward_batched": [P, P, P, P, I32, P, P],
         "mf_plan_create_batched": [P, P, I32, P],
         "mf_plan_execute": [P, P, P, P, P],
@@ -169,6 +170,11 @@ def mf_median_filter_backward(grad_y, argmed, n, k, grad_x, stream=None):
 def mf_median_filter_backward_f64(grad_y, argmed, n, k, grad_x, stream=None):
     _check(load().mf_median_filter_backward_f64(_ptr(grad_y), _ptr(argmed), int(n), int(k), _ptr(grad_x),
                                                 _stream(stream)))
+
+
+def mf_median_filter_backward_rows_f64(grad_y, argmed, rows, n, k, grad_x, stream=None):
+    _check(load().mf_median_filter_backward_rows_f64(_ptr(grad_y), _ptr(argmed), int(rows), int(n), int(k),
+                                                     _ptr(grad_x), _stream(stream)))
 
 
 def mf_median_filter_backward_rows(grad_y, argmed, rows, n, k, grad_x, stream=None):

@@ -73,6 +73,7 @@ def test_null_pointers_rejected():
     assert L.mf_median_filter_backward(None, FAKE, 10, 3, FAKE, None) == 1
     assert L.mf_median_filter_backward_f64(FAKE, None, 10, 3, FAKE, None) == 1
     assert L.mf_median_filter_backward_f64(FAKE, FAKE, 10, 4, FAKE, None) == 1
+    assert L.mf_median_filter_backward_rows_f64(FAKE, FAKE, 0, 10, 3, FAKE, None) == 1
     assert L.mf_median_filter_rows(FAKE, 0, 10, 3, FAKE, None, None) == 1
     assert L.mf_median_filter_rows_i32(FAKE, 0, 10, 3, FAKE, None, None) == 1
     assert L.mf_median_filter_rows_i32(None, 2, 10, 3, FAKE, None, None) == 1

@@ -128,3 +128,21 @@ def test_backward_f64_gradcheck():
     x = torch.from_numpy(np.random.default_rng(42).permutation(n).astype(np.float64) * 1e-2).to(DEV)
     x.requires_grad_(True)
     assert torch.autograd.gradcheck(lambda t: mf.MedianFilterFn.apply(t, k)[0], (x,), eps=1e-6, atol=1e-7)
+
+
+def test_backward_f64_rows():
+    """float64 rows through autograd: each row's gradient bit for bit against
+    the oracle's float64 scatter."""
+    rows, n, k = 3, 20_011, 101
+    x = np.stack([workloads.random_walk_f64(n, 60 + r) for r in range(rows)])
+    g = np.random.default_rng(61).standard_normal((rows, n - k + 1))
+    xt = torch.from_numpy(x).to(DEV).requires_grad_(True)
+    y, am = mf.MedianFilterFn.apply(xt, k)
+    y.backward(torch.from_numpy(g).to(DEV))
+    torch.cuda.synchronize()
+    got = xt.grad.cpu().numpy()
+    for r in range(rows):
+        _, ao = oracle.sortmedian(x[r], k)
+        assert np.array_equal(am[r].cpu().numpy(), ao)
+        want = oracle.backward_f64(g[r], ao, n, k)
+        assert np.array_equal(got[r].view(np.uint64), want.view(np.uint64)), r
