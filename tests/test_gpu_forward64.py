@@ -71,7 +71,7 @@ def test_64bit_presorted_and_reversed(k):
         assert_same(x, k, y, am, "sorted")
 
 
-@pytest.mark.parametrize("k", [1, 5, 1001, 4095])
+@pytest.mark.parametrize("k", [1, 5, 1001, 4095, 5001, 20001])
 def test_64bit_without_argmed(k):
     n = 3 * k + 1000
     x = workloads.int64_words(n, 77)
