@@ -116,7 +116,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported "
-              "(the median filter shards by output range with a k-1 halo, see DESIGN.md)" % args.gpus,
+              "(the median filter would shard by output range, each GPU reading a k-1 halo)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch

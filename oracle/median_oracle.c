@@ -24,7 +24,7 @@
  *                            postprocessing phase"), with the invariant of
  *                            eq. (inv) checked at run time.
  *
- * Readings taken where the paper is silent (each is listed in the design doc):
+ * Readings taken where the paper is silent:
  *   - Arbitrary n (Section 3 says the extension is straightforward): blocks
  *     of length k, the last one partial with r = n - (b-1)k items; the last
  *     pair walks r steps.  Output o (0-based) is the median of x[o..o+k-1].
