@@ -6,7 +6,8 @@ k = 4095; one-pair tiles of the workspace path up to k = 32767), several
 tiles and ragged last blocks,
 n = k and n = k + 1, values ordered only by their high or only by their low
 32-bit word, float64 specials, presorted signals, argmed = NULL, the
-full-size workloads on sampled windows, and the argument errors.
+full-size workloads on sampled windows, the paper's generator families,
+and the argument errors.
 """
 import ctypes
 
@@ -52,6 +53,16 @@ def test_64bit_several_tiles(kind, k):
     x = GENS[kind](n, 3100 + k)
     y, am = run_gpu(x, k)
     assert_same(x, k, y, am, kind)
+
+
+@pytest.mark.parametrize("k", [21, 201, 2001, 3001, 5001])
+def test_paper_families_int64(k):
+    # the seven generator families of Section 7.3 at 64 bits, on every
+    # 64-bit tile kind (in-tile ranks, rank pre-pass, pair pre-pass)
+    for fam in ("asc", "desc", "r-asc", "r-desc", "r-large", "r-small", "r-block"):
+        x = workloads.paper_family(fam, 40_000 + k // 3, seed=70 + k, bits=64)
+        y, am = run_gpu(x, k)
+        assert_same(x, k, y, am, fam)
 
 
 @pytest.mark.parametrize("k", [1, 3, 101, 1001, 2049, 4095, 5001, 32767])
