@@ -1594,6 +1594,22 @@ MF_HD int walk_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, 
         const int32_t ndn = dn ? base + hibit64(dn) : -1;
         const int32_t nr0 = dir > 0 ? nup : ndn;
         int32_t nr = dir == 0 ? r : nr0;
+        if (nr < 0 && (dir > 0 ? rel >= 32 : rel < 32)) {
+            // the median drifts out of the window (sorted or slowly varying
+            // input): slide the window half its width toward the move, which
+            // keeps the half that holds r and reads one membership dword
+            if (dir > 0) {
+                base += 32;
+                W = (W >> 32) | ((u64)member_dword(s, Mp, (base >> 5) + 1, i) << 32);
+                const u64 u2 = W & (~1ull << (rel - 32));
+                nr = u2 ? base + ctz64(u2) : -1;
+            } else {
+                base -= 32;
+                W = (W << 32) | (u64)member_dword(s, Mp, base >> 5, i);
+                const u64 d2 = W & ((1ull << (rel + 32)) - 1ull);
+                nr = d2 ? base + hibit64(d2) : -1;
+            }
+        }
         if (nr < 0) {
             nr = win_search_far(s, Mp, r, dir, i);
             if (nr < 0) {

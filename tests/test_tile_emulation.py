@@ -83,6 +83,29 @@ def test_tile_phases_match_oracle(emu, force_merge, wide):
     emu.emu_set_force_merge(0)
 
 
+def test_walk_window_slides(emu):
+    """Inputs whose median drifts through the merged order step after step
+    (ascending, descending, random walks, a sawtooth): the walk's register
+    window slides up and down by half its width or falls back to a search
+    of M, and every output still matches the oracle."""
+    rng = np.random.default_rng(41)
+    for k in (15, 31, 33, 101, 301, 1001, 2047, 3001):
+        n = 6 * k + int(rng.integers(0, k))
+        ramp = np.arange(n, dtype=np.float32)
+        saw = (np.arange(n) % (2 * k + 7)).astype(np.float32)
+        walk = np.cumsum(rng.standard_normal(n) + 0.3).astype(np.float32)
+        for x in (ramp, ramp[::-1].copy(), saw, walk, -walk):
+            y = np.empty(n - k + 1, x.dtype)
+            a = np.empty(n - k + 1, np.int32)
+            pm = ctypes.c_int32()
+            rc = emu.emu_median_filter(x.ctypes.data, n, k, 1, threads_for(k), y.ctypes.data, a.ctypes.data,
+                                       ctypes.byref(pm))
+            yo, ao = oracle.sortmedian(x, k)
+            assert rc == 0, (k, n, rc)
+            assert np.array_equal(a, ao), (k, n)
+            assert np.array_equal(y.view(np.uint32), yo.view(np.uint32)), (k, n)
+
+
 def test_presorted_tiles(emu):
     """Ascending inputs (with ties) skip the bucket sort; a single descent
     anywhere in a tile must send that tile through the sort."""
