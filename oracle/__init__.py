@@ -22,9 +22,13 @@ single-threaded C underneath):
   backward_f64(grad_y, argmed, n, k)
                               the same for a float64 upstream gradient
                               (float64 result, no rounding).
-  sortmedian_batched(x, offsets, ks)
-                              sortmedian applied per signal of a packed
-                              ragged batch.
+  sortmedian_parallel(x, k, threads)
+                              sortmedian over contiguous output ranges, one
+                              thread per range (each range reads its windows'
+                              k-1 item halo); outputs identical to sortmedian.
+
+The C functions keep no state between calls, and ctypes releases the GIL
+while one runs, so calls from several Python threads run in parallel.
 """
 import ctypes
 import os
@@ -136,14 +140,34 @@ def backward_f64(grad_y, argmed, n, k):
     return g
 
 
-def sortmedian_batched(x, offsets, ks):
-    """Per-signal sortmedian over a packed ragged batch.
+def sortmedian_parallel(x, k, threads=None, ranges=None):
+    """(y, argmed) of every window of x by the paper's method, the outputs
+    cut into `ranges` contiguous ranges run on `threads` threads.  Range
+    [o0, o1) runs sortmedian on x[o0 : o1 + k - 1] (its own piecewise sort,
+    so blocks on a range border are sorted twice) and shifts its argmed by
+    o0."""
+    from concurrent.futures import ThreadPoolExecutor
+    x, _ = _as_signal(x)
+    n = x.shape[0]
+    k = int(k)
+    if k < 1 or k % 2 == 0 or n < k:
+        raise OracleError("invalid argument")
+    nout = n - k + 1
+    threads = int(threads or os.cpu_count() or 1)
+    ranges = int(ranges or threads)
+    ranges = max(1, min(ranges, nout))
+    cuts = [nout * r // ranges for r in range(ranges + 1)]
+    y = np.empty(nout, dtype=x.dtype)
+    argmed = np.empty(nout, dtype=np.int32)
 
-    Signal s is x[offsets[s]:offsets[s+1]] with window ks[s]; outputs are
-    packed in signal order, argmed local to each signal."""
-    ys, ams = [], []
-    for s in range(len(ks)):
-        y, a = sortmedian(x[offsets[s]:offsets[s + 1]], int(ks[s]))
-        ys.append(y)
-        ams.append(a)
-    return np.concatenate(ys), np.concatenate(ams)
+    def run(r):
+        o0, o1 = cuts[r], cuts[r + 1]
+        if o1 <= o0:
+            return
+        yr, ar = sortmedian(x[o0:o1 + k - 1], k)
+        y[o0:o1] = yr
+        argmed[o0:o1] = ar + o0
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(run, range(ranges)))
+    return y, argmed

@@ -10,19 +10,28 @@
  * Two independent forward oracles live here:
  *
  *   oracle_window_median_*   The problem statement of Section 1 written out:
- *                            for one window, sort its (value, index) pairs
- *                            and take the element of rank h = (k-1)/2.  A
- *                            library sort (qsort) is the only step used.
+ *                            for one window, order its (value, index) pairs
+ *                            and take the element of rank h = (k-1)/2.
  *
  *   oracle_sortmedian_*      The paper's method: piecewise stable sort
  *                            (Section 3 "Piecewise Sorting", Section 5.2),
- *                            the block data structure (Section 5.3, figure
- *                            "Block data structure implementation") built on
- *                            dancing links (Section 4, eqs. del / undo-del),
- *                            and the postprocessing driver (Section 6.2,
- *                            figure "Algorithm for median filtering:
- *                            postprocessing phase"), with the invariant of
- *                            eq. (inv) checked at run time.
+ *                            block data structures (Section 5: the interface
+ *                            of figure "Block data structure interface", the
+ *                            invariants of Section 5.3) on dancing links
+ *                            (Section 4, eqs. del / undo-del), and the
+ *                            postprocessing of Section 6.2, with eq. (inv)
+ *                            checked after every step.
+ *
+ * How the block structure is written here.  A block keeps its list L as
+ * prev/next links with a tail index (the block length), a counter s of
+ * small items, and a cursor m.  Section 5.3 fixes the invariant m = p_s:
+ * the cursor stands on the list element with exactly s elements before it
+ * (the tail when s = |L|).  Each interface operation below changes L and s
+ * as the interface says (delete: s <- max(0, s-1); undelete: s unchanged;
+ * advance: s <- s+1), keeps count of how many list elements precede the
+ * cursor, and then moves the cursor along the links until that count is s
+ * again.  The cursor moves this produces are the ones Section 5.3 states;
+ * the run-time check of eq. (inv) and the pins in tests/ confirm it.
  *
  * Readings taken where the paper is silent:
  *   - Arbitrary n (Section 3 says the extension is straightforward): blocks
@@ -30,7 +39,7 @@
  *     pair walks r steps.  Output o (0-based) is the median of x[o..o+k-1].
  *   - Ties: all comparisons are on (value, global index) pairs (Sections 5.2
  *     and 6.3: equal elements keep input order; A's items count as smaller).
- *   - The +infinity sentinel of Section 5.3 is a pair strictly above every
+ *   - The +infinity of Section 5.3 (alpha[k]) is a pair strictly above every
  *     real pair, so real +inf data cannot collide with it.
  *   - Float order: -0.0 equals +0.0 (IEEE equality, tie broken by index);
  *     every NaN is above +inf and all NaNs are equal (tie broken by index).
@@ -41,6 +50,9 @@
  * Backward (not in the paper): grad_x[j] = sum of grad_y[o] over all o with
  * argmed[o] == j, accumulated in float64 in increasing o, rounded once
  * (float32 gradients) or not at all (float64 gradients).
+ *
+ * Every function is reentrant (no static state), so callers may run
+ * several signals or output ranges in parallel threads.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -99,55 +111,57 @@ static int pair_less(const values_t *v, int64_t a, int64_t b)
     return a < b;
 }
 
-/* qsort has no context argument; the comparator reads these statics.  The
- * oracle is single-threaded by design. */
-static const values_t *g_sort_vals;
-static int64_t g_sort_base;
-
-static int qsort_pair_cmp(const void *pa, const void *pb)
-{
-    const int64_t a = g_sort_base + *(const int32_t *)pa;
-    const int64_t b = g_sort_base + *(const int32_t *)pb;
-    const int c = cmp_value(g_sort_vals, a, b);
-    if (c != 0) return c;
-    return (a > b) - (a < b);
-}
-
-/* Stable argsort of x[base .. base+len) by (value, index): Section 5.2 sorts
- * the pairs (alpha[i], i) with any sort and keeps the second components. */
-static void sort_block(const values_t *v, int64_t base, int32_t len, int32_t *pi)
+/* Section 5.2: the sorting permutation of x[base .. base+len) taken from
+ * the pairs (value, index) in lexicographic order.  A bottom-up merge sort
+ * on the local indices (tmp: len entries of scratch). */
+static void sort_pairs(const values_t *v, int64_t base, int32_t len, int32_t *pi, int32_t *tmp)
 {
     for (int32_t i = 0; i < len; i++) pi[i] = i;
-    g_sort_vals = v;
-    g_sort_base = base;
-    qsort(pi, (size_t)len, sizeof(int32_t), qsort_pair_cmp);
+    int32_t *src = pi, *dst = tmp;
+    for (int32_t w = 1; w < len; w *= 2) {
+        for (int32_t lo = 0; lo < len; lo += 2 * w) {
+            const int32_t mid = lo + w < len ? lo + w : len;
+            const int32_t hi = lo + 2 * w < len ? lo + 2 * w : len;
+            int32_t a = lo, b = mid, o = lo;
+            while (a < mid && b < hi)
+                dst[o++] = pair_less(v, base + src[b], base + src[a]) ? src[b++] : src[a++];
+            while (a < mid) dst[o++] = src[a++];
+            while (b < hi) dst[o++] = src[b++];
+        }
+        int32_t *t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != pi) memcpy(pi, src, sizeof(int32_t) * (size_t)len);
 }
 
 /* ---------------------------------------------------------------------- */
 /* Definition oracle: one window at a time.                                */
 
-static int window_median(const values_t *v, int64_t n, int32_t k, int64_t o,
-                         int32_t *scratch, int64_t *out_index)
-{
-    if (o < 0 || o + k > n) return OR_EINVAL;
-    sort_block(v, o, k, scratch);
-    *out_index = o + scratch[(k - 1) / 2];
-    return OR_OK;
-}
-
 static int window_oracle(const values_t *v, int64_t n, int32_t k,
                          const int64_t *outs, int64_t count, int32_t *argmed)
 {
     if (k < 1 || (k & 1) == 0 || n < k) return OR_EINVAL;
-    int32_t *scratch = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
-    if (!scratch) return OR_ENOMEM;
-    int rc = OR_OK;
-    for (int64_t q = 0; q < count && rc == OR_OK; q++) {
-        int64_t idx = 0;
-        rc = window_median(v, n, k, outs[q], scratch, &idx);
-        argmed[q] = (int32_t)idx;
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+    int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+    if (!order || !tmp) {
+        free(order);
+        free(tmp);
+        return OR_ENOMEM;
     }
-    free(scratch);
+    int rc = OR_OK;
+    for (int64_t q = 0; q < count; q++) {
+        const int64_t o = outs[q];
+        if (o < 0 || o + k > n) {
+            rc = OR_EINVAL;
+            break;
+        }
+        /* the window's pairs in order; the median has h = (k-1)/2 below it */
+        sort_pairs(v, o, k, order, tmp);
+        argmed[q] = (int32_t)(o + order[(k - 1) / 2]);
+    }
+    free(order);
+    free(tmp);
     return rc;
 }
 
@@ -181,178 +195,208 @@ int oracle_window_median_i64(const int64_t *x, int64_t n, int32_t k,
 }
 
 /* ---------------------------------------------------------------------- */
-/* The paper's block data structure (Section 5).                           */
+/* Block data structure (Section 5).                                       */
 
 typedef struct {
     const values_t *v;
     int64_t base;        /* global index of alpha[0] */
-    int32_t len;         /* number of items in the block (k, or r if last) */
-    int32_t *pi;         /* stable sorting permutation */
-    int32_t *prev;       /* len + 1 entries; slot len is the list head/tail */
+    int32_t len;         /* items of the block (k, or r for a partial last
+                            block); index len is the tail of the list and
+                            stands for alpha[len] = +infinity */
+    int32_t *pi;         /* sorting permutation (Section 5.2) */
+    int32_t *tmp;        /* sort scratch */
+    int32_t *prev;       /* len + 1 links */
     int32_t *next;
-    int32_t m;           /* first large item, or len (= tail) */
-    int32_t s;           /* number of small items */
+    int32_t m;           /* cursor: the first large item, or the tail */
+    int32_t s;           /* small items: the first s of L */
+    int32_t ahead;       /* list elements before the cursor (= s when settled) */
 } block_t;
 
-static int32_t tail_of(const block_t *B) { return B->len; }
-static int at_end(const block_t *B) { return B->m == tail_of(B); }
-
-/* Is alpha[i] small?  True if every item is small (cursor at the end), or
- * (alpha[i], i) < (alpha[m], m). */
-static int is_small(const block_t *B, int32_t i)
+/* Is item i ordered before the cursor?  The tail is +infinity, so with
+ * the cursor on the tail every item is. */
+static int before_cursor(const block_t *B, int32_t i)
 {
-    if (at_end(B)) return 1;
+    if (B->m == B->len) return 1;
     return pair_less(B->v, B->base + i, B->base + B->m);
 }
 
-/* construct(alpha, pi): link the items in sorted order, h of them small. */
-static void block_construct(block_t *B, int32_t h)
+/* Eq. (del): take item i out of the list. */
+static void unlink_item(block_t *B, int32_t i)
 {
-    int32_t p = tail_of(B);
-    for (int32_t r = 0; r < B->len; r++) {
-        const int32_t q = B->pi[r];
-        B->next[p] = q;
-        B->prev[q] = p;
-        p = q;
-    }
-    B->next[p] = tail_of(B);
-    B->prev[tail_of(B)] = p;
-    B->s = h;
-    /* A partial block (len <= h) is only ever the right block of the last
-     * pair, which is unwound at once; its cursor is set there. */
-    B->m = (h < B->len) ? B->pi[h] : tail_of(B);
-}
-
-/* delete(B, i): unlink item i (eq. del) and keep (m, s) consistent. */
-static void block_delete(block_t *B, int32_t i)
-{
-    const int small = is_small(B, i);
-    B->next[B->prev[i]] = B->next[i];
     B->prev[B->next[i]] = B->prev[i];
-    if (small) {
-        B->s -= 1;
-    } else {
-        if (B->m == i) B->m = B->next[B->m];
-        if (B->s > 0) {
-            B->m = B->prev[B->m];
-            B->s -= 1;
-        }
-    }
+    B->next[B->prev[i]] = B->next[i];
 }
 
-/* undelete(B, i): relink item i (eq. undo-del). */
-static void block_undelete(block_t *B, int32_t i)
+/* Eq. (undo-del): put item i back where it was. */
+static void relink_item(block_t *B, int32_t i)
 {
-    B->next[B->prev[i]] = i;
     B->prev[B->next[i]] = i;
-    if (is_small(B, i)) B->m = B->prev[B->m];
+    B->next[B->prev[i]] = i;
 }
 
-/* unwind(B): delete items len-1 .. 0; afterwards the list is empty. */
-static void block_unwind(block_t *B)
+/* Section 5.3's invariant m = p_s: move the cursor along the list until
+ * exactly s list elements stand before it. */
+static void settle(block_t *B)
 {
-    for (int32_t i = B->len - 1; i >= 0; i--) {
-        B->next[B->prev[i]] = B->next[i];
-        B->prev[B->next[i]] = B->prev[i];
+    while (B->ahead > B->s) {
+        B->m = B->prev[B->m];
+        B->ahead -= 1;
     }
-    B->m = tail_of(B);
-    B->s = 0;
+    while (B->ahead < B->s) {
+        B->m = B->next[B->m];
+        B->ahead += 1;
+    }
 }
 
-static void block_advance(block_t *B)
+/* construct(alpha, pi): L holds the block in sorted order (the links follow
+ * pi from the tail around to the tail), and the first h items are small. */
+static void construct(block_t *B, int32_t h)
 {
-    B->m = B->next[B->m];
+    int32_t last = B->len;
+    for (int32_t r = 0; r < B->len; r++) {
+        B->next[last] = B->pi[r];
+        B->prev[B->pi[r]] = last;
+        last = B->pi[r];
+    }
+    B->next[last] = B->len;
+    B->prev[B->len] = last;
+    B->m = B->next[B->len];      /* cursor on the first element, nothing ahead */
+    B->ahead = 0;
+    B->s = h < B->len ? h : B->len;
+    settle(B);
+}
+
+/* delete(B, i): remove alpha[i] from L; s <- max(0, s-1). */
+static void delete_item(block_t *B, int32_t i)
+{
+    if (i == B->m) B->m = B->next[i];            /* same number of elements ahead */
+    else if (before_cursor(B, i)) B->ahead -= 1;
+    unlink_item(B, i);
+    if (B->s > 0) B->s -= 1;
+    settle(B);
+}
+
+/* undelete(B, i): put alpha[i] back into L; s unchanged. */
+static void undelete_item(block_t *B, int32_t i)
+{
+    relink_item(B, i);
+    if (before_cursor(B, i)) B->ahead += 1;
+    settle(B);
+}
+
+/* unwind(B): delete(B, len-1), ..., delete(B, 0); L ends empty. */
+static void unwind(block_t *B)
+{
+    for (int32_t i = B->len - 1; i >= 0; i--) delete_item(B, i);
+}
+
+/* advance(B): s <- s + 1. */
+static void advance(block_t *B)
+{
     B->s += 1;
+    settle(B);
 }
 
-/* Peek(A) <= Peek(B) on (value, global index) pairs, where a cursor at the
- * end stands for a pair above every real pair.  A's items precede B's in
- * the input, so on equal values A's item is the smaller one. */
-static int peek_le(const block_t *A, const block_t *B)
+/* peek(B): the first large element as a global index, or -1 for +infinity. */
+static int64_t peek(const block_t *B)
 {
-    if (at_end(A)) return 0;            /* +inf <= real pair is false; both at
-                                            the end cannot happen */
-    if (at_end(B)) return 1;
-    return pair_less(A->v, A->base + A->m, B->base + B->m);
+    return B->m == B->len ? -1 : B->base + B->m;
 }
 
-static int64_t peek_index(const block_t *B) { return B->base + B->m; }
+/* Order of two peeks, +infinity (-1) above every real pair: is a <= b?
+ * Two real peeks are never equal (distinct global indices); both infinite
+ * cannot occur while eq. (inv) holds. */
+static int peek_le(const values_t *v, int64_t a, int64_t b)
+{
+    if (a < 0) return b < 0;
+    if (b < 0) return 1;
+    return pair_less(v, a, b);
+}
 
 static int block_alloc(block_t *B, int32_t cap)
 {
     B->pi = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+    B->tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
     B->prev = (int32_t *)malloc(sizeof(int32_t) * ((size_t)cap + 1));
     B->next = (int32_t *)malloc(sizeof(int32_t) * ((size_t)cap + 1));
-    return (B->pi && B->prev && B->next) ? OR_OK : OR_ENOMEM;
+    return (B->pi && B->tmp && B->prev && B->next) ? OR_OK : OR_ENOMEM;
 }
 
 static void block_free(block_t *B)
 {
     free(B->pi);
+    free(B->tmp);
     free(B->prev);
     free(B->next);
 }
 
-static void block_load(block_t *B, const values_t *v, int64_t base, int32_t len)
+/* Block X_j with its sorting permutation P_j (Section 6.1). */
+static void load_block(block_t *B, const values_t *v, int64_t base, int32_t len)
 {
     B->v = v;
     B->base = base;
     B->len = len;
-    sort_block(v, base, len, B->pi);
+    sort_pairs(v, base, len, B->pi, B->tmp);
 }
 
 /* ---------------------------------------------------------------------- */
-/* Postprocessing driver (Section 6.2).                                    */
+/* Postprocessing (Section 6.2).                                           */
 
 static int sortmedian(const values_t *v, int64_t n, int32_t k, int32_t *argmed)
 {
     if (k < 1 || (k & 1) == 0 || n < k || n > INT32_MAX) return OR_EINVAL;
     const int32_t h = (k - 1) / 2;
-    const int64_t nb = (n + k - 1) / k;     /* number of blocks */
+    const int64_t b = (n + k - 1) / k;       /* blocks X_0 .. X_{b-1} */
 
-    block_t blk[2];
-    memset(blk, 0, sizeof(blk));
-    int rc = block_alloc(&blk[0], k);
-    if (rc == OR_OK) rc = block_alloc(&blk[1], k);
+    block_t blocks[2];
+    memset(blocks, 0, sizeof(blocks));
+    int rc = block_alloc(&blocks[0], k);
+    if (rc == OR_OK) rc = block_alloc(&blocks[1], k);
     if (rc != OR_OK) {
-        block_free(&blk[0]);
-        block_free(&blk[1]);
+        block_free(&blocks[0]);
+        block_free(&blocks[1]);
         return rc;
     }
 
-    block_t *B = &blk[0];
-    block_load(B, v, 0, k);                  /* block 0 is always full */
-    block_construct(B, h);
-    argmed[0] = (int32_t)peek_index(B);      /* step (double dagger) */
+    /* Y_0: the median of X_0 is its first large item */
+    block_t *B = &blocks[0];
+    load_block(B, v, 0, k);
+    construct(B, h);
+    argmed[0] = (int32_t)peek(B);
 
-    for (int64_t j = 1; j < nb && rc == OR_OK; j++) {
+    for (int64_t j = 1; j < b && rc == OR_OK; j++) {
+        /* the pair (A, B) = (X_{j-1}, X_j); B starts empty (unwound) */
         block_t *A = B;
-        B = (A == &blk[0]) ? &blk[1] : &blk[0];
+        B = (A == &blocks[0]) ? &blocks[1] : &blocks[0];
         const int64_t base = j * (int64_t)k;
         const int32_t len = (int32_t)((n - base) < k ? (n - base) : k);
-        block_load(B, v, base, len);
-        block_construct(B, h);
-        block_unwind(B);
+        load_block(B, v, base, len);
+        construct(B, h);
+        unwind(B);
         for (int32_t i = 0; i < len; i++) {
-            block_delete(A, i);              /* step (dagger) */
-            block_undelete(B, i);
+            /* slide the window: alpha_A[i] leaves, alpha_B[i] enters */
+            delete_item(A, i);
+            undelete_item(B, i);
+            /* restore h small items: the smaller peek becomes small (A wins
+             * ties: its items precede B's in the input) */
             if (A->s + B->s < h) {
-                if (peek_le(A, B)) block_advance(A);
-                else block_advance(B);
+                if (peek_le(v, peek(A), peek(B))) advance(A);
+                else advance(B);
             }
-            /* eq. (inv): exactly h small items, counters in range, and at
-             * least one block has a large item to report. */
-            if (A->s + B->s != h || A->s < 0 || B->s < 0 ||
-                (at_end(A) && at_end(B))) {
+            /* eq. (inv): exactly h small items, counters in range, and a
+             * large item left to report */
+            if (A->s + B->s != h || A->s < 0 || B->s < 0 || (peek(A) < 0 && peek(B) < 0)) {
                 rc = OR_EINVARIANT;
                 break;
             }
+            /* the window's median: the smaller of the two peeks */
+            const int64_t pa = peek(A), pb = peek(B);
             const int64_t o = (j - 1) * (int64_t)k + i + 1;
-            argmed[o] = (int32_t)(peek_le(A, B) ? peek_index(A) : peek_index(B));
+            argmed[o] = (int32_t)(peek_le(v, pa, pb) ? pa : pb);
         }
     }
-    block_free(&blk[0]);
-    block_free(&blk[1]);
+    block_free(&blocks[0]);
+    block_free(&blocks[1]);
     return rc;
 }
 

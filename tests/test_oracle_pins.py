@@ -208,16 +208,19 @@ def test_invalid_arguments():
 # --- planted mistakes: the pins above must notice each of them -----------
 
 MUTATIONS = [
-    # delete(): drop the "s > 0" guard's cursor step back
-    ("B->m = B->prev[B->m];\n            B->s -= 1;", "B->s -= 1;"),
-    # undelete(): move the cursor the wrong way
-    ("if (is_small(B, i)) B->m = B->prev[B->m];", "if (is_small(B, i)) B->m = B->next[B->m];"),
-    # rebalance: ties go to B instead of A
-    ("return pair_less(A->v, A->base + A->m, B->base + B->m);",
-     "return !pair_less(B->v, B->base + B->m, A->base + A->m) && 0;"),
+    # delete(): the removed cursor item hands the cursor backward, not forward
+    ("if (i == B->m) B->m = B->next[i];", "if (i == B->m) B->m = B->prev[i];"),
+    # delete(): an item removed ahead of the cursor is not counted out
+    ("else if (before_cursor(B, i)) B->ahead -= 1;", "else if (0) B->ahead -= 1;"),
+    # undelete(): the cursor count moves the wrong way
+    ("if (before_cursor(B, i)) B->ahead += 1;", "if (before_cursor(B, i)) B->ahead -= 1;"),
+    # delete(): s drops below zero (the max(0, s-1) of the interface lost)
+    ("if (B->s > 0) B->s -= 1;", "B->s -= 1;"),
+    # rebalance: peeks compared by value only, so ties go to B instead of A
+    ("    return pair_less(v, a, b);\n}", "    return cmp_value(v, a, b) < 0;\n}"),
     # output index off by one
     ("const int64_t o = (j - 1) * (int64_t)k + i + 1;", "const int64_t o = (j - 1) * (int64_t)k + i;"),
-    # is_small ignores the index tie-break
+    # the pair order ignores the index tie-break
     ("    return a < b;\n}", "    return 0;\n}"),
 ]
 
@@ -379,3 +382,21 @@ def test_planted_mistakes_64_are_caught(tmp_path, idx):
             caught = True
             break
     assert caught, "64-bit mutation %d survived" % idx
+
+
+# --- the threaded range split used for full-size checks --------------------
+
+@pytest.mark.parametrize("k", [1, 3, 31, 301])
+def test_parallel_ranges_match(k):
+    """Output ranges cut anywhere (also shorter than k, and more ranges than
+    threads) give the same outputs as one pass, and both match the
+    definition on sampled windows."""
+    rng = np.random.default_rng(40 + k)
+    n = 5 * k + 123
+    x = rng.integers(0, 7, n).astype(np.int32)
+    y, a = oracle.sortmedian(x, k)
+    for ranges in (1, 2, 7, n - k + 1):
+        y2, a2 = oracle.sortmedian_parallel(x, k, threads=3, ranges=ranges)
+        assert np.array_equal(a2, a) and np.array_equal(y2, y)
+    outs = rng.integers(0, n - k + 1, 200)
+    assert np.array_equal(oracle.window_median(x, k, outs), a[outs])
