@@ -22,11 +22,17 @@
  *   Calls are asynchronous on that stream; arguments are validated before
  *   anything is enqueued, and nothing is written when a call fails.
  * - Limits: n <= 2^31 - 1 (argmed is int32), k <= 32767.
- * - Thread safety: entry points may be called from several host threads;
- *   one plan must not be executed from two threads at once.
+ * - Thread safety: entry points may be called from several host threads
+ *   and on several streams.  The library's workspace (windows above 4096,
+ *   64-bit signals on 1024-thread tiles) is leased to one call at a time,
+ *   and each use waits on its stream for the one before it.  Executions of
+ *   one plan (including the plans the one-call batched entry points keep)
+ *   are serialized on the host and, across streams, on the device.
  * - Environment: MF_WS_LIMIT=<bytes> makes workspace requests above it fail
- *   with MF_ERR_NOMEM (a test switch); MF_LOG=1 prints plan and autotune
- *   decisions on stderr.
+ *   with MF_ERR_NOMEM (a test switch); MF_LEASE_HOLD_US=<us> keeps each
+ *   workspace lease that long before enqueueing (a test switch for
+ *   concurrent callers); MF_LOG=1 prints plan and autotune decisions on
+ *   stderr.
  */
 #ifndef MF_H
 #define MF_H
@@ -142,10 +148,12 @@ mf_status mf_median_filter_backward_batched(const float *grad_y, const int32_t *
  * units ordered by window, largest first.  mf_plan_execute enqueues the
  * whole forward batch on `stream` as one graph launch; the graph is
  * captured on first use and again whenever x, y, argmed or the launch
- * configuration change.  One plan must not be executed from two host
- * threads or on two streams at once: its persistent launches share one
- * work counter per launch.  The plan owns its device memory until
- * mf_plan_destroy (which synchronizes the device). */
+ * configuration change.  Executions of one plan are serialized: a call
+ * holds the plan's lock while it captures and enqueues, and waits on its
+ * stream for the plan's previous execution (its persistent launches share
+ * one work counter per launch).  The plan owns its device memory until
+ * mf_plan_destroy, which waits for the plan's last execution; destroying a
+ * plan while another thread still calls it is not allowed. */
 typedef struct mf_plan mf_plan;
 mf_status mf_plan_create_batched(const int64_t *x_offsets, const int32_t *ks,
                                  int32_t num_signals, mf_plan **out);

@@ -10,6 +10,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
+#include <thread>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -53,7 +56,9 @@ namespace {
 // Diagnostics and test switches, read from the environment at each use:
 //   MF_WS_LIMIT=<bytes>  workspace requests above it fail with
 //                        MF_ERR_NOMEM, as a failed allocation would;
-//   MF_LOG=1             plan and autotune decisions on stderr.
+//   MF_LOG=1             plan and autotune decisions on stderr;
+//   MF_LEASE_HOLD_US=<us> each workspace lease waits this long before the
+//                        caller enqueues (test switch for concurrent use).
 int64_t env_ws_limit()
 {
     const char *e = getenv("MF_WS_LIMIT");
@@ -64,6 +69,15 @@ bool env_log()
 {
     const char *e = getenv("MF_LOG");
     return e && e[0] == '1';
+}
+
+// MF_LEASE_HOLD_US=<microseconds>: a test switch that keeps each
+// workspace lease for this long before its launches are enqueued, so that
+// calls from other threads reach acquire_ws while the lease is held.
+int64_t env_lease_hold_us()
+{
+    const char *e = getenv("MF_LEASE_HOLD_US");
+    return e ? atoll(e) : 0;
 }
 
 }  // namespace
@@ -77,8 +91,9 @@ struct Device {
     int *d_err = nullptr;               // kernel consistency flag
     unsigned char *ws = nullptr;        // global-path workspace
     int64_t ws_bytes = 0;
-    hipEvent_t ws_done = nullptr;       // last use of ws
-    std::mutex mu;
+    hipEvent_t ws_done = nullptr;       // completion of the last use of ws
+    std::mutex mu;                      // set-up
+    std::mutex ws_mu;                   // held by the one workspace lease
 };
 
 const int kMaxDevices = 64;
@@ -102,15 +117,31 @@ mf_status device_state(Device **out)
     return MF_OK;
 }
 
-// Workspace of at least `bytes` for a launch on `st`.  Uses of the
-// workspace are serialized across streams through ws_done.
-mf_status acquire_ws(Device &D, int64_t bytes, hipStream_t st, unsigned char **ws)
+// The workspace, leased to one caller at a time: the lease holds ws_mu from
+// acquire_ws until the caller has enqueued its launches and release_ws has
+// recorded ws_done after them (or until the lease is destroyed on an error
+// path, which records ws_done as well).  Every use therefore waits on the
+// stream for the use leased before it, so ws_done, recorded by the last
+// lease, completes only after every earlier use: a buffer that must grow is
+// freed after waiting for that one event.
+struct WsLease {
+    Device *D = nullptr;
+    hipStream_t st = nullptr;
+    std::unique_lock<std::mutex> lk;
+    unsigned char *ws = nullptr;
+    ~WsLease()
+    {
+        if (D && lk.owns_lock()) (void)hipEventRecord(D->ws_done, st);
+    }
+};
+
+mf_status acquire_ws(Device &D, int64_t bytes, hipStream_t st, WsLease &L)
 {
     const int64_t limit = env_ws_limit();
     if (limit > 0 && bytes > limit)
         return fail(MF_ERR_NOMEM, "workspace of %lld bytes (over MF_WS_LIMIT = %lld)", (long long)bytes,
                     (long long)limit);
-    std::lock_guard<std::mutex> lk(D.mu);
+    L.lk = std::unique_lock<std::mutex>(D.ws_mu);
     if (D.ws_bytes < bytes) {
         if (D.ws) {
             MF_HIP(hipEventSynchronize(D.ws_done), "hipEventSynchronize");
@@ -125,14 +156,19 @@ mf_status acquire_ws(Device &D, int64_t bytes, hipStream_t st, unsigned char **w
         D.ws_bytes = bytes;
     }
     MF_HIP(hipStreamWaitEvent(st, D.ws_done, 0), "hipStreamWaitEvent");
-    *ws = D.ws;
+    L.D = &D;
+    L.st = st;
+    L.ws = D.ws;
+    const int64_t hold = env_lease_hold_us();
+    if (hold > 0) std::this_thread::sleep_for(std::chrono::microseconds(hold));
     return MF_OK;
 }
 
-mf_status release_ws(Device &D, hipStream_t st)
+mf_status release_ws(WsLease &L)
 {
-    std::lock_guard<std::mutex> lk(D.mu);
-    MF_HIP(hipEventRecord(D.ws_done, st), "hipEventRecord");
+    const hipError_t e = hipEventRecord(L.D->ws_done, L.st);
+    L.lk.unlock();
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     return MF_OK;
 }
 
@@ -177,10 +213,10 @@ mf_status forward_rows(const void *x, int64_t rows, int64_t n, int32_t k, void *
     if (p == PATH_GLOBAL) {
         const int64_t stride = global_ws_stride(k);
         const int64_t slots = std::min<int64_t>(global_ws_slots(lds), L.nunits);
-        unsigned char *ws = nullptr;
-        if ((s = acquire_ws(*D, stride * slots, st, &ws)) != MF_OK) return s;
-        MF_HIP(launch_forward(p, f32, L, lds, ws, stride, slots, D->d_err, st), "forward launch");
-        return release_ws(*D, st);
+        WsLease lease;
+        if ((s = acquire_ws(*D, stride * slots, st, lease)) != MF_OK) return s;
+        MF_HIP(launch_forward(p, f32, L, lds, lease.ws, stride, slots, D->d_err, st), "forward launch");
+        return release_ws(lease);
     }
     MF_HIP(launch_forward(p, f32, L, lds, nullptr, 0, 0, D->d_err, st), "forward launch");
     return MF_OK;
@@ -232,7 +268,7 @@ mf_status forward64(const void *x, int64_t rows, int64_t n, int32_t k, void *y, 
     L.rank_mode = 1;
     L.xshift = k;
     L.xrow = tiles * stride;
-    unsigned char *ws = nullptr;
+    WsLease lease;
     if (p == PATH_GLOBAL) {
         // one pair per tile: a pre-pass ranks each pair through its
         // workgroup's scratch, then the global-path tiles run on the ranks;
@@ -243,22 +279,23 @@ mf_status forward64(const void *x, int64_t rows, int64_t n, int32_t k, void *y, 
         const int64_t pstride = rank64_pair_scratch(k);
         const int64_t pslots = std::min<int64_t>(256, units);
         const int64_t scratch = std::max<int64_t>(gstride * gslots, pstride * pslots);
-        if ((s = acquire_ws(*D, key_bytes + scratch, st, &ws)) != MF_OK) return s;
+        if ((s = acquire_ws(*D, key_bytes + scratch, st, lease)) != MF_OK) return s;
+        unsigned char *ws = lease.ws;
         uint32_t *keys = (uint32_t *)ws;
         MF_HIP(launch_rank64_pair(f64, x, n, k, keys, stride, ws + key_bytes, pstride, pslots, tiles, units, st),
                "64-bit pair rank launch");
         L.x = keys;
         MF_HIP(launch_forward(p, false, L, lds, ws + key_bytes, gstride, gslots, D->d_err, st),
                "64-bit forward launch");
-        return release_ws(*D, st);
+        return release_ws(lease);
     }
-    if ((s = acquire_ws(*D, key_bytes, st, &ws)) != MF_OK) return s;
-    uint32_t *keys = (uint32_t *)ws;
+    if ((s = acquire_ws(*D, key_bytes, st, lease)) != MF_OK) return s;
+    uint32_t *keys = (uint32_t *)lease.ws;
     MF_HIP(launch_rank64(p, f64, x, n, k, keys, stride, tiles, units, st), "64-bit rank launch");
     L.x = keys;
     MF_HIP(launch_forward(p, false, L, (size_t)lds_bytes_for(p, k), nullptr, 0, 0, D->d_err, st),
            "64-bit forward launch");
-    return release_ws(*D, st);
+    return release_ws(lease);
 }
 
 // Backward over `rows` equal signals; f64: float64 gradients.
@@ -325,11 +362,20 @@ struct mf_plan {
     int32_t gconfig = -1;
     bool gf32 = true;
     int64_t ws_need = 0;
+    // executions of one plan are serialized: on the host by mu (capture and
+    // launch), on the device by done (the work counters and the captured
+    // graph belong to one execution at a time)
+    std::mutex mu;
+    hipEvent_t done = nullptr;     // completion of the last execution
 };
 
 static void plan_free(mf_plan *p)
 {
     if (!p) return;
+    if (p->done) {
+        (void)hipEventSynchronize(p->done);
+        (void)hipEventDestroy(p->done);
+    }
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     for (auto &gs : p->groups)
         for (auto &g : gs)
@@ -399,6 +445,7 @@ extern "C" mf_status mf_plan_create_batched(const int64_t *x_offsets, const int3
     hipError_t e = hipMalloc(&p->d_sigs, sizeof(SigDesc) * sigs.size());
     if (e == hipSuccess) e = hipMemcpy(p->d_sigs, sigs.data(), sizeof(SigDesc) * sigs.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&p->d_next, sizeof(uint32_t) * 8);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
     if (e != hipSuccess) { plan_free(p); return hip_fail(e, "plan signal table"); }
 
     // forward work lists, one per kernel family; within a family the
@@ -497,21 +544,28 @@ static mf_status plan_enqueue(mf_plan *p, Device &D, const void *x, void *y, int
     return MF_OK;
 }
 
-static mf_status plan_execute(mf_plan *p, const void *x, void *y, int32_t *argmed, bool f32, void *stream)
+// One execution of plan p; the caller holds p->mu.
+static mf_status plan_execute_locked(mf_plan *p, const void *x, void *y, int32_t *argmed, bool f32, void *stream)
 {
-    if (!p) return fail(MF_ERR_INVALID_VALUE, "plan must not be null");
-    if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
     hipStream_t st = (hipStream_t)stream;
     Device *D = nullptr;
     mf_status s = device_state(&D);
     if (s != MF_OK) return s;
-    unsigned char *ws = nullptr;
-    if (p->ws_need > 0 && (s = acquire_ws(*D, p->ws_need, st, &ws)) != MF_OK) return s;
+    WsLease lease;
+    if (p->ws_need > 0 && (s = acquire_ws(*D, p->ws_need, st, lease)) != MF_OK) return s;
+    unsigned char *ws = lease.ws;
+    // the previous execution (maybe on another stream) has finished with the
+    // work counters before this one clears them
+    MF_HIP(hipStreamWaitEvent(st, p->done, 0), "hipStreamWaitEvent(plan)");
     // the graph bakes in the data and workspace pointers; capture again
-    // when any of them changed
+    // when any of them changed (after the last launch of the old graph)
     if (!p->gexec || p->gx != x || p->gy != y || p->gam != argmed || p->gws != ws || p->gconfig != p->config ||
         p->gf32 != f32) {
-        if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+        if (p->gexec) {
+            MF_HIP(hipEventSynchronize(p->done), "hipEventSynchronize(plan)");
+            (void)hipGraphExecDestroy(p->gexec);
+            p->gexec = nullptr;
+        }
         hipStream_t cs;
         MF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate(capture)");
         hipGraph_t graph = nullptr;
@@ -532,8 +586,17 @@ static mf_status plan_execute(mf_plan *p, const void *x, void *y, int32_t *argme
         p->gf32 = f32;
     }
     MF_HIP(hipGraphLaunch(p->gexec, st), "hipGraphLaunch");
-    if (p->ws_need > 0) return release_ws(*D, st);
+    MF_HIP(hipEventRecord(p->done, st), "hipEventRecord(plan)");
+    if (p->ws_need > 0) return release_ws(lease);
     return MF_OK;
+}
+
+static mf_status plan_execute(mf_plan *p, const void *x, void *y, int32_t *argmed, bool f32, void *stream)
+{
+    if (!p) return fail(MF_ERR_INVALID_VALUE, "plan must not be null");
+    if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
+    std::lock_guard<std::mutex> plk(p->mu);
+    return plan_execute_locked(p, x, y, argmed, f32, stream);
 }
 
 extern "C" mf_status mf_plan_execute(mf_plan *p, const float *x, float *y, int32_t *argmed, void *stream)
@@ -559,7 +622,9 @@ extern "C" mf_status mf_plan_execute_backward(mf_plan *p, const float *grad_y, c
     L.sigs = p->d_sigs;
     L.units = p->d_bunits;
     L.nunits = p->nbunits;
+    std::lock_guard<std::mutex> plk(p->mu);
     MF_HIP(launch_backward(L, false, (hipStream_t)stream), "batched backward launch");
+    MF_HIP(hipEventRecord(p->done, (hipStream_t)stream), "hipEventRecord(plan)");
     return MF_OK;
 }
 
@@ -570,6 +635,7 @@ extern "C" mf_status mf_plan_set_config(mf_plan *p, int32_t config)
     if (!p) return fail(MF_ERR_INVALID_VALUE, "plan must not be null");
     if (config < 0 || config >= kConfigs)
         return fail(MF_ERR_INVALID_VALUE, "config = %d is not a launch configuration", config);
+    std::lock_guard<std::mutex> plk(p->mu);
     p->config = config;
     return MF_OK;
 }
@@ -600,15 +666,17 @@ extern "C" mf_status mf_plan_autotune(mf_plan *p, const float *x, float *y, int3
         (void)hipEventDestroy(a);
         return hip_fail(e, "hipEventCreate");
     }
+    std::lock_guard<std::mutex> plk(p->mu);
     const int32_t before = p->config;
     mf_status s = MF_OK;
     int best = -1;
     for (int c = 0; c < kConfigs && s == MF_OK; c++) {
         p->config = c;
-        s = mf_plan_execute(p, x, y, argmed, stream);   // warm-up (and capture)
+        s = plan_execute_locked(p, x, y, argmed, true, stream);   // warm-up (and capture)
         if (s != MF_OK) break;
         e = hipEventRecord(a, st);
-        for (int r = 0; r < reps && s == MF_OK && e == hipSuccess; r++) s = mf_plan_execute(p, x, y, argmed, stream);
+        for (int r = 0; r < reps && s == MF_OK && e == hipSuccess; r++)
+            s = plan_execute_locked(p, x, y, argmed, true, stream);
         if (s != MF_OK) break;
         if (e == hipSuccess) e = hipEventRecord(b, st);
         if (e == hipSuccess) e = hipEventSynchronize(b);
@@ -633,42 +701,49 @@ extern "C" mf_status mf_plan_autotune(mf_plan *p, const float *x, float *y, int3
 
 extern "C" void mf_plan_destroy(mf_plan *p)
 {
-    if (p) (void)hipDeviceSynchronize();
-    plan_free(p);
+    plan_free(p);   // waits for the plan's last execution
 }
 
 // ------------------------------------------------------------------ plan cache
 
 namespace {
+// Plans of the one-call batched entry points, keyed by the offsets and
+// windows.  Each caller holds a reference while it uses a plan, so evicting
+// an entry never destroys a plan that another call is executing; the last
+// reference destroys it (after its last execution has finished).
 struct CacheEntry {
     std::vector<int64_t> offsets;
     std::vector<int32_t> ks;
-    mf_plan *plan;
+    std::shared_ptr<mf_plan> plan;
 };
 std::mutex g_cache_mu;
 std::vector<CacheEntry> g_cache;   // most recent last
 const size_t kCacheMax = 8;
 
-mf_status cached_plan(const int64_t *off, const int32_t *ks, int32_t ns, mf_plan **out)
+mf_status cached_plan(const int64_t *off, const int32_t *ks, int32_t ns, std::shared_ptr<mf_plan> &out)
 {
+    if (!off || !ks) return fail(MF_ERR_INVALID_VALUE, "x_offsets and ks must not be null");
+    if (ns < 1) return fail(MF_ERR_INVALID_VALUE, "num_signals = %d must be >= 1", ns);
+    std::shared_ptr<mf_plan> evicted;   // destroyed after the lock is released
     std::lock_guard<std::mutex> lk(g_cache_mu);
     for (size_t i = 0; i < g_cache.size(); i++) {
         CacheEntry &c = g_cache[i];
         if ((int32_t)c.ks.size() == ns && memcmp(c.ks.data(), ks, sizeof(int32_t) * ns) == 0 &&
             memcmp(c.offsets.data(), off, sizeof(int64_t) * (ns + 1)) == 0) {
-            *out = c.plan;
+            out = c.plan;
             return MF_OK;
         }
     }
     mf_plan *p = nullptr;
     mf_status s = mf_plan_create_batched(off, ks, ns, &p);
     if (s != MF_OK) return s;
+    std::shared_ptr<mf_plan> sp(p, [](mf_plan *q) { plan_free(q); });
     if (g_cache.size() >= kCacheMax) {
-        mf_plan_destroy(g_cache.front().plan);
+        evicted = std::move(g_cache.front().plan);
         g_cache.erase(g_cache.begin());
     }
-    g_cache.push_back(CacheEntry{std::vector<int64_t>(off, off + ns + 1), std::vector<int32_t>(ks, ks + ns), p});
-    *out = p;
+    g_cache.push_back(CacheEntry{std::vector<int64_t>(off, off + ns + 1), std::vector<int32_t>(ks, ks + ns), sp});
+    out = sp;
     return MF_OK;
 }
 }  // namespace
@@ -727,20 +802,20 @@ extern "C" mf_status mf_median_filter_batched(const float *x, const int64_t *x_o
                                               int32_t num_signals, float *y, int32_t *argmed, void *stream)
 {
     if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
-    mf_plan *p = nullptr;
-    mf_status s = cached_plan(x_offsets, ks, num_signals, &p);
+    std::shared_ptr<mf_plan> p;
+    mf_status s = cached_plan(x_offsets, ks, num_signals, p);
     if (s != MF_OK) return s;
-    return plan_execute(p, x, y, argmed, true, stream);
+    return plan_execute(p.get(), x, y, argmed, true, stream);
 }
 
 extern "C" mf_status mf_median_filter_batched_i32(const int32_t *x, const int64_t *x_offsets, const int32_t *ks,
                                                   int32_t num_signals, int32_t *y, int32_t *argmed, void *stream)
 {
     if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
-    mf_plan *p = nullptr;
-    mf_status s = cached_plan(x_offsets, ks, num_signals, &p);
+    std::shared_ptr<mf_plan> p;
+    mf_status s = cached_plan(x_offsets, ks, num_signals, p);
     if (s != MF_OK) return s;
-    return plan_execute(p, x, y, argmed, false, stream);
+    return plan_execute(p.get(), x, y, argmed, false, stream);
 }
 
 extern "C" mf_status mf_median_filter_backward(const float *grad_y, const int32_t *argmed, int64_t n,
@@ -771,10 +846,10 @@ extern "C" mf_status mf_median_filter_backward_batched(const float *grad_y, cons
                                                        const int64_t *x_offsets, const int32_t *ks,
                                                        int32_t num_signals, float *grad_x, void *stream)
 {
-    mf_plan *p = nullptr;
-    mf_status s = cached_plan(x_offsets, ks, num_signals, &p);
+    std::shared_ptr<mf_plan> p;
+    mf_status s = cached_plan(x_offsets, ks, num_signals, p);
     if (s != MF_OK) return s;
-    return mf_plan_execute_backward(p, grad_y, argmed, grad_x, stream);
+    return mf_plan_execute_backward(p.get(), grad_y, argmed, grad_x, stream);
 }
 
 extern "C" int64_t mf_output_length(int64_t n, int32_t k)

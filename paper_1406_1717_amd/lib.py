@@ -201,12 +201,32 @@ def _is_i32(t):
     return str(getattr(t, "dtype", "")) in ("torch.int32", "int32")
 
 
+def _plan_tensors(*specs):
+    """Plan arguments (tensor, name, dtypes, min_numel, may_be_none): each a
+    tensor of one of dtypes with at least min_numel entries (the C side
+    cannot see tensor sizes), then each a contiguous GPU tensor."""
+    for t, name, dtypes, min_numel, may_be_none in specs:
+        if t is None and may_be_none:
+            continue
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a tensor" % name)
+        if t.dtype not in dtypes:
+            raise TypeError("%s must be %s, got %s" % (name, " or ".join(str(d) for d in dtypes), t.dtype))
+        if t.numel() < min_numel:
+            raise ValueError("%s has %d entries, the plan needs %d" % (name, t.numel(), min_numel))
+    for t, name, _, _, _ in specs:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("%s must be a contiguous GPU tensor" % name)
+
+
 class Plan:
     """mf_plan_* for one ragged batch layout (host offsets and windows)."""
 
     def __init__(self, x_offsets, ks):
         self._off, offp = _host_i64(x_offsets)
         self._ks, kp = _host_i32(ks)
+        if self._off.ndim != 1 or self._ks.ndim != 1 or len(self._off) != len(self._ks) + 1:
+            raise ValueError("x_offsets needs len(ks) + 1 entries")
         h = ctypes.c_void_p()
         _check(load().mf_plan_create_batched(offp, kp, len(self._ks), ctypes.byref(h)))
         self._h = h
@@ -215,17 +235,30 @@ class Plan:
     def output_length(self):
         return int(load().mf_plan_output_length(self._h))
 
+    def _check_forward(self, x, y, argmed):
+        xd = getattr(x, "dtype", None)
+        _plan_tensors((x, "x", (torch.float32, torch.int32), int(self._off[-1]), False),
+                      (y, "y", (xd,), self.output_length, False),
+                      (argmed, "argmed", (torch.int32,), self.output_length, True))
+
     def execute(self, x, y, argmed, stream=None):
+        self._check_forward(x, y, argmed)
         fn = load().mf_plan_execute_i32 if _is_i32(x) else load().mf_plan_execute
         _check(fn(self._h, _ptr(x), _ptr(y), _ptr(argmed), _stream(stream)))
 
     def execute_backward(self, grad_y, argmed, grad_x, stream=None):
+        _plan_tensors((grad_y, "grad_y", (torch.float32,), self.output_length, False),
+                      (argmed, "argmed", (torch.int32,), self.output_length, False),
+                      (grad_x, "grad_x", (torch.float32,), int(self._off[-1]), False))
         _check(load().mf_plan_execute_backward(self._h, _ptr(grad_y), _ptr(argmed), _ptr(grad_x),
                                                _stream(stream)))
 
     def autotune(self, x, y, argmed, reps=2, stream=None):
         """Times each launch configuration on these buffers and keeps the
         fastest.  Returns {"config": c, "tuned_ms": [ms per configuration]}."""
+        if getattr(x, "dtype", None) != torch.float32:
+            raise TypeError("autotune runs on float32 signals")
+        self._check_forward(x, y, argmed)
         _check(load().mf_plan_autotune(self._h, _ptr(x), _ptr(y), _ptr(argmed), int(reps), _stream(stream)))
         return self.config_info()
 

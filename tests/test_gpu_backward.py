@@ -34,7 +34,9 @@ def test_backward_bitwise_vs_oracle(k):
     x = rng.standard_normal(n).astype(np.float32)
     g = rng.standard_normal(n - k + 1).astype(np.float32)
     _, am, gx = gpu_forward_backward(x, k, g)
-    g32, g64 = oracle.backward(g, am, n, k)
+    _, ao = oracle.sortmedian(x, k)
+    assert np.array_equal(am, ao)
+    g32, g64 = oracle.backward(g, ao, n, k)
     assert np.array_equal(gx.view(np.uint32), g32.view(np.uint32))
 
 
@@ -46,7 +48,9 @@ def test_backward_with_ties_heavy_reuse(k):
     x = rng.integers(0, 3, n).astype(np.float32)
     g = (rng.standard_normal(n - k + 1) * np.exp(rng.uniform(-20, 20, n - k + 1))).astype(np.float32)
     _, am, gx = gpu_forward_backward(x, k, g)
-    g32, g64 = oracle.backward(g, am, n, k)
+    _, ao = oracle.sortmedian(x, k)
+    assert np.array_equal(am, ao)
+    g32, g64 = oracle.backward(g, ao, n, k)
     assert np.array_equal(gx.view(np.uint32), g32.view(np.uint32))
     nz = g64 != 0
     assert np.all(np.abs(gx[nz].astype(np.float64) - g64[nz]) <= 1e-6 * np.abs(g64[nz]))

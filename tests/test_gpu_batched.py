@@ -134,15 +134,22 @@ def test_batched_backward():
     amh = am.cpu().numpy()
     for s in range(len(ks)):
         n = int(off[s + 1] - off[s])
-        g32, _ = oracle.backward(g[yo[s]:yo[s + 1]], amh[yo[s]:yo[s + 1]], n, int(ks[s]))
+        _, ao = oracle.sortmedian(x[off[s]:off[s + 1]], int(ks[s]))
+        assert np.array_equal(amh[yo[s]:yo[s + 1]], ao), s
+        g32, _ = oracle.backward(g[yo[s]:yo[s + 1]], ao, n, int(ks[s]))
         assert np.array_equal(gx[off[s]:off[s + 1]], g32)
 
 
 def test_batched_invalid_is_rejected():
     off = np.array([0, 10, 12], dtype=np.int64)
     ks = np.array([3, 5], dtype=np.int32)           # 5 > length 2
-    with pytest.raises(mf.MFError):
+    with pytest.raises(ValueError):
         mf.median_filter_batched(torch.zeros(12, device=DEV), off, ks)
+    # the library rejects it too, through the C ABI
+    y = torch.zeros(12, device=DEV)
+    a = torch.zeros(12, dtype=torch.int32, device=DEV)
+    with pytest.raises(mf.MFError):
+        mf.lib.mf_median_filter_batched(torch.zeros(12, device=DEV), off, ks, 2, y, a)
 
 
 def test_batched_int32_and_plan():
