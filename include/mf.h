@@ -59,6 +59,23 @@ typedef enum mf_status {
 mf_status mf_median_filter(const float *x, int64_t n, int32_t k,
                            float *y, int32_t *argmed, void *stream);
 
+/* mf_median_filter for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and checks as mf_median_filter (bit
+ * for bit), but no call allocates or frees memory: windows above 4096 use a
+ * fixed device array of the library (64 MiB per device, the first 256 bytes
+ * a consistency flag read by mf_check_device_error, the rest per-workgroup
+ * slots of 0.4-1.5 MB, as many workgroups as fit), which each device holds
+ * from the first call until the process ends.  The first call on a device
+ * looks the array up, clears the flag and waits on `stream` for that.
+ * Every call on one device shares the array and nothing orders them: calls
+ * that overlap on one device (two streams, two host threads) race and must
+ * be serialized by the caller.  Errors: as mf_median_filter, plus
+ * MF_ERR_UNSUPPORTED if one workgroup's slot would exceed the array (not
+ * reached for k <= 32767). */
+mf_status mf_median_filter_noalloc(const float *x, int64_t n, int32_t k,
+                                   float *y, int32_t *argmed, void *stream);
+
 /* The same for int32 signals (the paper benchmarks 32-bit integers,
  * Section 7).  y: n-k+1 int32. */
 mf_status mf_median_filter_i32(const int32_t *x, int64_t n, int32_t k,

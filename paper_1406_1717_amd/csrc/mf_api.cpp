@@ -756,6 +756,42 @@ extern "C" mf_status mf_median_filter(const float *x, int64_t n, int32_t k, floa
     return forward_rows(x, 1, n, k, y, argmed, true, (hipStream_t)stream);
 }
 
+extern "C" mf_status mf_median_filter_noalloc(const float *x, int64_t n, int32_t k, float *y, int32_t *argmed,
+                                              void *stream)
+{
+    const hipStream_t st = (hipStream_t)stream;
+    if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
+    mf_status s = check_signal(n, k);
+    if (s != MF_OK) return s;
+    const Path p = path_for(k);
+    Launch L;
+    memset(&L, 0, sizeof L);
+    L.x = x;
+    L.y = y;
+    L.argmed = argmed;
+    L.one.n = n;
+    L.one.k = k;
+    L.rows = 1;
+    L.tpr = tiles_for(p, n, k);
+    L.nunits = L.tpr;
+    const size_t lds = (size_t)lds_bytes_for(p, k);
+    int64_t stride = 0, slots = 0;
+    if (p == PATH_GLOBAL) {
+        // as many workgroup slots as the fixed scratch holds (the launch's
+        // workgroups loop over the tiles)
+        stride = global_ws_stride(k);
+        const int64_t room = (kFixedScratchBytes - kFixedFlagBytes) / stride;
+        if (room < 1)
+            return fail(MF_ERR_UNSUPPORTED, "k = %d needs %lld bytes of scratch per workgroup, above the fixed %lld",
+                        k, (long long)stride, (long long)(kFixedScratchBytes - kFixedFlagBytes));
+        slots = std::min<int64_t>(std::min<int64_t>(global_ws_slots(lds), L.nunits), room);
+    }
+    unsigned char *sc = nullptr;
+    MF_HIP(fixed_scratch(st, true, &sc), "fixed scratch set-up");
+    MF_HIP(launch_forward(p, true, L, lds, sc + kFixedFlagBytes, stride, slots, (int *)sc, st), "forward launch");
+    return MF_OK;
+}
+
 extern "C" mf_status mf_median_filter_i32(const int32_t *x, int64_t n, int32_t k, int32_t *y,
                                           int32_t *argmed, void *stream)
 {
@@ -886,6 +922,18 @@ extern "C" mf_status mf_check_device_error(void *stream)
         MF_HIP(hipMemsetAsync(D->d_err, 0, sizeof(int), st), "hipMemsetAsync(error flag)");
         MF_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
         return fail(MF_ERR_INTERNAL, "a kernel reported an inconsistent walk (flag %d)", h);
+    }
+    // the flag of the entry point without allocation, once it is set up here
+    unsigned char *sc = nullptr;
+    MF_HIP(fixed_scratch(st, false, &sc), "fixed scratch");
+    if (sc) {
+        MF_HIP(hipMemcpyAsync(&h, sc, sizeof(int), hipMemcpyDeviceToHost, st), "hipMemcpyAsync(error flag)");
+        MF_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+        if (h != 0) {
+            MF_HIP(hipMemsetAsync(sc, 0, sizeof(int), st), "hipMemsetAsync(error flag)");
+            MF_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+            return fail(MF_ERR_INTERNAL, "a kernel reported an inconsistent walk (flag %d)", h);
+        }
     }
     return MF_OK;
 }

@@ -1187,6 +1187,41 @@ int64_t global_ws_stride(int32_t k)
     return (g.total + 255) & ~255ll;
 }
 
+// ------------------------------------------------------------------ fixed scratch
+
+// The scratch of the entry point that allocates nothing, one array per
+// device that the library runs on, held until the process ends.  Host code
+// never passes this name to a kernel: it stands for the array only on the
+// device, so every host use goes through the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+
+hipError_t fixed_scratch(hipStream_t st, bool create, unsigned char **out)
+{
+    static std::mutex mu;
+    static unsigned char *addr[64] = {};
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev] && create) {
+        unsigned char *p = nullptr;
+        e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        if ((e = prepare_kernels()) != hipSuccess) return e;
+        // the flag starts clear: a fill kernel (no memset node), waited for
+        hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, (u32 *)p, 1);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
 hipError_t prepare_kernels()
 {
     hipError_t e = hipSuccess;

@@ -122,4 +122,14 @@ hipError_t launch_identity64(const void *x, void *y, int32_t *argmed, int64_t to
 
 hipError_t prepare_kernels();
 
+// Fixed device scratch of the entry point that allocates nothing: the first
+// kFixedFlagBytes hold its kernels' consistency flag, the rest serves as
+// the global path's per-workgroup slots.  fixed_scratch returns this
+// device's copy; the first call on a device (create = true) looks its
+// address up and clears the flag, waiting for that on `st`.  With create =
+// false, *out is null until a call has set the device up.
+static const int64_t kFixedScratchBytes = 64ll << 20;
+static const int64_t kFixedFlagBytes = 256;
+hipError_t fixed_scratch(hipStream_t st, bool create, unsigned char **out);
+
 }  // namespace mf

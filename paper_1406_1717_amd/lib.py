@@ -35,6 +35,7 @@ def load():
     sig = {
         "mf_median_filter": [P, I64, I32, P, P, P],
         "mf_median_filter_i32": [P, I64, I32, P, P, P],
+        "mf_median_filter_noalloc": [P, I64, I32, P, P, P],
         "mf_median_filter_f64": [P, I64, I32, P, P, P],
         "mf_median_filter_i64": [P, I64, I32, P, P, P],
         "mf_median_filter_rows": [P, I64, I64, I32, P, P, P],
@@ -114,6 +115,10 @@ def _host_i32(a):
 
 def mf_median_filter(x, n, k, y, argmed, stream=None):
     _check(load().mf_median_filter(_ptr(x), int(n), int(k), _ptr(y), _ptr(argmed), _stream(stream)))
+
+
+def mf_median_filter_noalloc(x, n, k, y, argmed, stream=None):
+    _check(load().mf_median_filter_noalloc(_ptr(x), int(n), int(k), _ptr(y), _ptr(argmed), _stream(stream)))
 
 
 def mf_median_filter_i32(x, n, k, y, argmed, stream=None):

@@ -59,6 +59,7 @@ def test_forward_validation(n, k, code):
     L = lib.load()
     assert L.mf_median_filter(FAKE, n, k, FAKE, None, None) == code
     assert L.mf_median_filter_i32(FAKE, n, k, FAKE, None, None) == code
+    assert L.mf_median_filter_noalloc(FAKE, n, k, FAKE, None, None) == code
     assert L.mf_median_filter_f64(FAKE, n, k, FAKE, None, None) == code
     assert L.mf_median_filter_i64(FAKE, n, k, FAKE, None, None) == code
     assert lib.last_error()
@@ -68,6 +69,7 @@ def test_null_pointers_rejected():
     L = lib.load()
     assert L.mf_median_filter(None, 10, 3, FAKE, None, None) == 1
     assert L.mf_median_filter(FAKE, 10, 3, None, None, None) == 1
+    assert L.mf_median_filter_noalloc(None, 10, 3, FAKE, None, None) == 1
     assert L.mf_median_filter_f64(None, 10, 3, FAKE, None, None) == 1
     assert L.mf_median_filter_i64(FAKE, 10, 3, None, None, None) == 1
     assert L.mf_median_filter_backward(None, FAKE, 10, 3, FAKE, None) == 1
