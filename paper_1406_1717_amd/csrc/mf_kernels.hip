@@ -589,7 +589,7 @@ __host__ __device__ inline void make_glayout(const Shape &s, GLayout *g)
     int64_t a = g->srt2;
     g->cnt = a;    a += 2ll * s.Pmax * s.C * s.Wrow;
     a = (a + 15) & ~15ll;
-    g->ctot = a;   a += 4ll * s.Pmax * s.Wn * kColGroups;
+    g->ctot = a;   a += 8ll * s.Pmax * col_dwords(s) * kColGroups;
     a = (a + 15) & ~15ll;
     g->stage = a;
 }

@@ -197,7 +197,7 @@ struct Layout {
     int32_t M;       // u16[Pmax * Mstride]
     int32_t pos;     // u32[Pmax * k]     posA | posB << 16
     int32_t cnt;     // u16[Pmax * C * Wrow]       (aliases skey, sslot)
-    int32_t ctot;    // u32[Pmax * Wn * kColGroups] (aliases skey, sslot)
+    int32_t ctot;    // u32[Pmax * kColGroups * 2 * ceil(Wn/2)] (aliases skey, sslot)
     int32_t bk;      // u32[cap] bucket counters, after mbuf (aliases M, pos)
     int32_t info;    // u32[2 * nbmax + 1]         (aliases M, pos)
     int32_t nbmax;   // blocks of a full tile
@@ -213,7 +213,8 @@ MF_HD int32_t ceil_div32(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / 
 // ceil(2^32 / d) for 2 <= d < 2^16; 0 stands for d = 1.
 MF_HD u32 recip32(int32_t d) { return d <= 1 ? 0u : 0xFFFFFFFFu / (u32)d + 1u; }
 
-// a / d for a, d < 2^16 with dr = recip32(d): a high multiply, exact.
+// a / d for a, d < 2^16 with dr = recip32(d): a high multiply, exact (the
+// reciprocal's rounding adds less than a * 2^-32 < 1/d to a/d).
 MF_HD u32 udiv16(u32 a, u32 dr)
 {
     if (dr == 0u) return a;
@@ -293,7 +294,7 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
     if (k <= kOneChunkMax) L = k;
     u32 C = (uk + (u32)L - 1u) / (u32)L;
     for (;;) {
-        const u32 need = (u32)P * (2u * C * (u32)s->Wrow + 4u * kColGroups * (u32)s->Wn + 2u * uk + 48u);
+        const u32 need = (u32)P * (2u * C * (u32)s->Wrow + 4u * kColGroups * (((u32)s->Wn + 1u) & ~1u) + 2u * uk + 48u);
         if (need <= 6u * (u32)s->cap || L >= k) break;
         L += 2;
         C = (uk + (u32)L - 1u) / (u32)L;
@@ -313,6 +314,9 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
 // which needs cap counters, is not used (such tiles take the merge sort).
 MF_HD bool compact_tile(const Shape &s) { return s.cap >= 8192 && s.Pmax == 1; }
 MF_HD int32_t tile_buckets(const Shape &s) { return compact_tile(s) ? s.cap / 2 : s.cap; }
+
+// Row dwords of a count table that hold real cells (two cells each).
+MF_HD int32_t col_dwords(const Shape &s) { return (s.Wn + 1) >> 1; }
 
 MF_HD void make_layout(const Shape &s, Layout *l)
 {
@@ -339,7 +343,7 @@ MF_HD void make_layout(const Shape &s, Layout *l)
     int32_t a = 0;
     l->cnt = a;      a += 2 * s.Pmax * s.C * s.Wrow;
     a = (a + 15) & ~15;
-    l->ctot = a;     a += 4 * s.Pmax * s.Wn * kColGroups;
+    l->ctot = a;     a += 8 * s.Pmax * col_dwords(s) * kColGroups;
     a = (a + 15) & ~15;
     l->stage = a;    a += 2 * s.Pmax * s.k;
     if (a > l->M) l->total = -1;   // aliased region overflows
@@ -925,7 +929,10 @@ MF_HD int32_t pair_chunks(const Shape &s, const Tile &T, int32_t p)
 // Row c of pair p's count table: 16-bit cells.  While the histogram is
 // built, a cell holds its word's A items in the low byte and B items in the
 // high byte (each at most 64); after the column pass, a member count.
-MF_HD int32_t cnt_row_idx(const Shape &s, int32_t p, int32_t c) { return (p * s.C + c) * s.Wrow; }
+MF_HD int32_t cnt_row_idx(const Shape &s, int32_t p, int32_t c)
+{
+    return (int32_t)mul24(mul24((u32)p, (u32)s.C) + (u32)c, (u32)s.Wrow);
+}
 
 MF_HD u16 *cnt_row(const Shape &s, const TileMem &m, int32_t p, int32_t c)
 {
@@ -1181,8 +1188,8 @@ MF_HD void tile_mpad(const Shape &s, const Tile &T, const TileMem &m, int32_t ti
     const int32_t npad = s.Mstride - 2 * s.k;
     const u32 padr = recip32(npad);
     for (int32_t it = tid; it < T.P * npad; it += NT) {
-        const int32_t p = (int32_t)udiv16((u32)it, padr);
-        m.M[p * s.Mstride + mslot(2 * s.k + it - p * npad)] = (u16)kMPad;
+        const u32 p = udiv16((u32)it, padr);
+        m.M[mul24(p, (u32)s.Mstride) + mslot(2 * s.k + it - (int32_t)mul24(p, (u32)npad))] = (u16)kMPad;
     }
     if (T.P > 0)
         for (int32_t r = s.k + T.lenLast + tid; r < 2 * s.k; r += NT)
@@ -1343,17 +1350,13 @@ MF_HD void table_zero_item(const TileMem &m, int32_t e) { ((u32 *)m.cnt)[e] = 0u
 // bucket (t/L, r/64); A items in the low half, B items in the high.  Every
 // pair has C rows: a last pair with a short B walks fewer chunks, and its
 // later rows hold only A items, which reach the earlier rows through the
-// column sums.  Lrcp = ceil(2^32 / L) makes t/L a high multiply (exact for
+// column sums.  Lrcp = recip32(L) makes t/L a high multiply (exact for
 // t, L < 2^16).
 MF_HD void table_hist_item(const Shape &s, const TileMem &m, int32_t p, int32_t r, u32 Lrcp)
 {
     const u32 e = m.M[p * s.Mstride + mslot(r)];
     const u32 t = e & 0x7FFFu;
-#if defined(__HIP_DEVICE_COMPILE__)
-    const int32_t b = (int32_t)__umulhi(t, Lrcp);
-#else
-    const int32_t b = (int32_t)(((u64)t * Lrcp) >> 32);
-#endif
+    const int32_t b = (int32_t)udiv16(t, Lrcp);
     cnt_add(m, cnt_row_idx(s, p, b) + (r >> 6), (e & 0x8000u) ? 0x100u : 1u);
 }
 
@@ -1383,48 +1386,55 @@ MF_HD void table_hist_row(const Shape &s, const Tile &T, const TileMem &m, int32
 
 // Column pass (two phases): entry (c, w) becomes the members of word w at
 // chunk start c, (A items with bucket >= c) + (B items with bucket < c).
-// Each column's rows are cut into kColGroups groups of R = ceil(C / 8)
-// consecutive rows; an item is (pair p, word w, group g).
+// A lane takes the two cells of one row dword (words 2d and 2d + 1) at
+// once: their A bytes and B bytes are summed as two 16-bit fields each
+// (column totals stay below 2^12, so the fields never carry).  Each
+// column's rows are cut into kColGroups groups of R = ceil(C / 8)
+// consecutive rows; an item is (pair p, dword d, group g).
 
 MF_HD int32_t col_rows(const Shape &s) { return (s.C + kColGroups - 1) / kColGroups; }
 
-// Phase one: the group's A and B totals (low and high halves) into ctot.
-MF_HD void table_colsum_item(const Shape &s, const TileMem &m, int32_t p, int32_t w, int32_t g)
+// Phase one: the group's A totals and B totals of both cells (16 bits per
+// cell) into ctot.
+MF_HD void table_colsum_item(const Shape &s, const TileMem &m, int32_t p, int32_t d, int32_t g)
 {
-    const int32_t stride = s.Wrow, R = col_rows(s);
-    const u16 *col = cnt_row(s, m, p, 0) + w;
+    const int32_t stride = s.Wrow >> 1, R = col_rows(s), Wd = col_dwords(s);
+    const u32 *col = (const u32 *)cnt_row(s, m, p, 0) + d;
     const int32_t c0 = g * R, c1 = (c0 + R < s.C) ? c0 + R : s.C;
-    u32 tot = 0u;
+    u32 ta = 0u, tb = 0u;
     for (int32_t c = c0; c < c1; c++) {
         const u32 v = col[c * stride];
-        tot += (v & 0xFFu) | ((v >> 8) << 16);
+        ta += v & 0x00FF00FFu;
+        tb += (v >> 8) & 0x00FF00FFu;
     }
-    m.ctot[(p * kColGroups + g) * s.Wn + w] = tot;
+    u32 *dst = m.ctot + 2 * ((p * kColGroups + g) * Wd + d);
+    dst[0] = ta;
+    dst[1] = tb;
 }
 
 // Phase two: A suffix sums and B exclusive prefix sums down the group,
-// starting from the totals of the other groups.
-MF_HD void table_colapply_item(const Shape &s, const TileMem &m, int32_t p, int32_t w, int32_t g)
+// starting from the totals of the other groups; both cells of the dword
+// are written as member counts.
+MF_HD void table_colapply_item(const Shape &s, const TileMem &m, int32_t p, int32_t d, int32_t g)
 {
-    const int32_t stride = s.Wrow, R = col_rows(s);
-    u16 *col = cnt_row(s, m, p, 0) + w;
+    const int32_t stride = s.Wrow >> 1, R = col_rows(s), Wd = col_dwords(s);
+    u32 *col = (u32 *)cnt_row(s, m, p, 0) + d;
     const int32_t c0 = g * R, c1 = (c0 + R < s.C) ? c0 + R : s.C;
     if (c0 >= c1) return;
-    const u32 *gt = m.ctot + p * kColGroups * s.Wn + w;
+    const u32 *gt = m.ctot + 2 * (p * kColGroups * Wd + d);
     u32 sa = 0u, pb = 0u;
 #pragma unroll
     for (int q = 0; q < kColGroups; q++) {
-        const u32 v = gt[q * s.Wn];
-        sa += (q >= g) ? (v & 0xFFFFu) : 0u;   // A items of this and later groups
-        pb += (q < g) ? (v >> 16) : 0u;        // B items of earlier groups
+        sa += (q >= g) ? gt[2 * q * Wd] : 0u;        // A items of this and later groups
+        pb += (q < g) ? gt[2 * q * Wd + 1] : 0u;     // B items of earlier groups
     }
     // one pass down the group: the A suffix at row c is the A count from
     // row c on, i.e. sa minus the A items of the group's earlier rows
     for (int32_t c = c0; c < c1; c++) {
         const u32 v = col[c * stride];
-        col[c * stride] = (u16)(sa + pb);
-        sa -= v & 0xFFu;
-        pb += v >> 8;
+        col[c * stride] = sa + pb;
+        sa -= v & 0x00FF00FFu;
+        pb += (v >> 8) & 0x00FF00FFu;
     }
 }
 
@@ -1461,6 +1471,44 @@ MF_HD void pair_first_median(const Shape &s, const TileMem &m, int32_t p)
 // ---------------------------------------------------------------- 5. walk
 
 MF_HD int ctz32(u32 v) { return __builtin_ctz(v); }   // v != 0
+
+// Lowest set bit and leading zeros of a 32-bit word, all ones for 0: one
+// find-first-bit instruction each on the GPU (written out, so that the
+// compiler does not rebuild the 64-bit forms below with extra selects).
+MF_HD u32 ffbl32(u32 v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    u32 r;
+    asm("v_ffbl_b32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+#else
+    return v == 0u ? 0xFFFFFFFFu : (u32)__builtin_ctz(v);
+#endif
+}
+MF_HD u32 ffbh32(u32 v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    u32 r;
+    asm("v_ffbh_u32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+#else
+    return v == 0u ? 0xFFFFFFFFu : (u32)__builtin_clz(v);
+#endif
+}
+
+// Lowest set bit of v, or a value of 64 or more when v = 0.
+MF_HD u32 low64_or_big(u64 v)
+{
+    const u32 a = ffbl32((u32)v), b = ffbl32((u32)(v >> 32)) | 32u;
+    return a < b ? a : b;
+}
+
+// Highest set bit of v, or a value of 64 or more when v = 0.
+MF_HD u32 high64_or_big(u64 v)
+{
+    const u32 a = ffbh32((u32)(v >> 32)), b = ffbh32((u32)v) | 32u;
+    return 63u - (a < b ? a : b);
+}
 
 MF_HD int hibit32(u32 v)   // index of the highest set bit, v != 0
 {
@@ -1531,10 +1579,10 @@ MF_HD int walk_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, 
     const int32_t lenB = block_len(s, T, p + 1);
     const int32_t i0 = c * s.L;
     const int32_t i1 = (i0 + s.L < lenB) ? i0 + s.L : lenB;
-    const u16 *Mp = m.M + p * s.Mstride;
+    const u16 *Mp = m.M + mul24((u32)p, (u32)s.Mstride);
     const u16 *pc = cnt_row(s, m, p, c);
-    const u32 *pos = m.pos + p * s.Pstride;
-    u16 *stage = m.stage + p * s.k;
+    const u32 *pos = m.pos + mul24((u32)p, (u32)s.Pstride);
+    u16 *stage = m.stage + mul24((u32)p, (u32)s.k);
     const int32_t h = s.h;
 
     // chunk 0 starts from A's median (pair_first_median); later chunks find
@@ -1568,6 +1616,7 @@ MF_HD int walk_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, 
     else W = (u64)dhi | ((u64)member_dword(s, Mp, 2 * lo + 2, i0 - 1) << 32);
 
     int bad = 0;
+    int32_t rel = r - base;   // the median's bit in the window, in [0, 64)
     // the position words of the next four steps are in flight
     u32 q1 = pos[i0], q2 = i0 + 1 < i1 ? pos[i0 + 1] : 0u, q3 = i0 + 2 < i1 ? pos[i0 + 2] : 0u;
     u32 q4 = i0 + 3 < i1 ? pos[i0 + 3] : 0u;
@@ -1578,50 +1627,58 @@ MF_HD int walk_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, 
         q2 = q3;
         q3 = q4;
         if (i + 4 < i1) q4 = pos[i + 4];
-        const int32_t pa = (int32_t)(q & 0xFFFFu), pb = (int32_t)(q >> 16);
-        // A[i] leaves (its bit is set), B[i] joins (its bit is clear)
-        const int32_t da = pa - base, db = pb - base;
-        W ^= ((u32)da < 64u) ? (1ull << (da & 63)) : 0ull;
-        W ^= ((u32)db < 64u) ? (1ull << (db & 63)) : 0ull;
-        // +1: the median moves to the next member up, -1: down, 0: stays
-        // (when A[i] was the median itself, ltA is 0 and dir is 1 - 2 ltB)
-        const int32_t ltA = (int32_t)(pa < r), ltB = (int32_t)(pb < r), eq = (int32_t)(pa == r);
-        const int32_t dir = ltA - ltB + (eq & (1 - ltB));
-        const int32_t rel = r - base;
-        const u64 up = W & (~1ull << rel);
-        const u64 dn = W & ((1ull << rel) - 1ull);
-        const int32_t nup = up ? base + ctz64(up) : -1;
-        const int32_t ndn = dn ? base + hibit64(dn) : -1;
-        const int32_t nr0 = dir > 0 ? nup : ndn;
-        int32_t nr = dir == 0 ? r : nr0;
-        if (nr < 0 && (dir > 0 ? rel >= 32 : rel < 32)) {
-            // the median drifts out of the window (sorted or slowly varying
-            // input): slide the window half its width toward the move, which
-            // keeps the half that holds r and reads one membership dword
-            if (dir > 0) {
-                base += 32;
-                W = (W >> 32) | ((u64)member_dword(s, Mp, (base >> 5) + 1, i) << 32);
-                const u64 u2 = W & (~1ull << (rel - 32));
-                nr = u2 ? base + ctz64(u2) : -1;
-            } else {
-                base -= 32;
-                W = (W << 32) | (u64)member_dword(s, Mp, base >> 5, i);
-                const u64 d2 = W & ((1ull << (rel + 32)) - 1ull);
-                nr = d2 ? base + hibit64(d2) : -1;
+        // A[i] leaves (its bit is set), B[i] joins (its bit is clear); bits
+        // outside the window shift a zero
+        const int32_t da = (int32_t)(q & 0xFFFFu) - base, db = (int32_t)(q >> 16) - base;
+        W ^= (u64)((u32)da < 64u) << (da & 63);
+        W ^= (u64)((u32)db < 64u) << (db & 63);
+        // The median moves to the next member up when the window loses a
+        // member at or below it (A[i] itself included) and gains one above
+        // it, to the next member down when it gains one below and loses one
+        // at or above it, and stays otherwise (B[i] was not a member, so it
+        // is never at the median's position).
+        const bool ltB = db < rel;
+        const bool up = !ltB && da <= rel;
+        const bool down = ltB && da >= rel;
+        // the nearest member above and below (64 or more: none in the window)
+        const u32 nup = low64_or_big(W & (~1ull << rel));
+        const u32 ndn = high64_or_big(W & ((1ull << rel) - 1ull));
+        u32 nrel = down ? ndn : (u32)rel;
+        nrel = up ? nup : nrel;
+        if (nrel >= 64u) {
+            const int32_t dir = up ? 1 : -1;
+            if (up ? rel >= 32 : rel < 32) {
+                // the median drifts out of the window (sorted or slowly
+                // varying input): slide the window half its width toward the
+                // move, which keeps the half that holds it and reads one
+                // membership dword
+                if (up) {
+                    base += 32;
+                    rel -= 32;
+                    W = (W >> 32) | ((u64)member_dword(s, Mp, (base >> 5) + 1, i) << 32);
+                    nrel = low64_or_big(W & (~1ull << rel));
+                } else {
+                    base -= 32;
+                    rel += 32;
+                    W = (W << 32) | (u64)member_dword(s, Mp, base >> 5, i);
+                    nrel = high64_or_big(W & ((1ull << rel) - 1ull));
+                }
+            }
+            if (nrel >= 64u) {
+                const int32_t nr = win_search_far(s, Mp, base + rel, dir, i);
+                if (nr < 0) {
+                    bad = 1;
+                    base = 0;
+                    nrel = 0u;
+                } else {
+                    base = win_base_for(nr);
+                    W = win_read(s, Mp, base, i);
+                    nrel = (u32)(nr - base);
+                }
             }
         }
-        if (nr < 0) {
-            nr = win_search_far(s, Mp, r, dir, i);
-            if (nr < 0) {
-                bad = 1;
-                nr = 0;
-            } else {
-                base = win_base_for(nr);
-                W = win_read(s, Mp, base, i);
-            }
-        }
-        r = nr;
-        stage[i] = (u16)r;
+        rel = (int32_t)nrel;
+        stage[i] = (u16)(base + rel);
     }
     if (bad)   // a failed search leaves a valid placeholder for the whole chunk
         for (int32_t q = i0; q < i1; q++) stage[q] = 0;
@@ -1690,23 +1747,25 @@ MF_HD void tail_table_hist_rows(const Shape &s, const Tile &T, const TileMem &m,
 
 MF_HD void tail_table_colsums(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
 {
-    // consecutive items take consecutive words of one row group
-    const u32 Wr = recip32(s.Wn);
-    for (int32_t it = tid; it < T.P * s.Wn * kColGroups; it += NT) {
-        const int32_t pg = (int32_t)udiv16((u32)it, Wr), w = it - pg * s.Wn;
+    // consecutive items take consecutive dwords of one row group
+    const int32_t Wd = col_dwords(s);
+    const u32 Wr = recip32(Wd);
+    for (int32_t it = tid; it < T.P * Wd * kColGroups; it += NT) {
+        const int32_t pg = (int32_t)udiv16((u32)it, Wr), d = it - pg * Wd;
         const int32_t p = pg / kColGroups, g = pg % kColGroups;
-        table_colsum_item(s, m, p, w, g);
+        table_colsum_item(s, m, p, d, g);
     }
 }
 
 MF_HD void tail_table_colapply(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
 {
-    // consecutive items take consecutive words of one row group
-    const u32 Wr = recip32(s.Wn);
-    for (int32_t it = tid; it < T.P * s.Wn * kColGroups; it += NT) {
-        const int32_t pg = (int32_t)udiv16((u32)it, Wr), w = it - pg * s.Wn;
+    // consecutive items take consecutive dwords of one row group
+    const int32_t Wd = col_dwords(s);
+    const u32 Wr = recip32(Wd);
+    for (int32_t it = tid; it < T.P * Wd * kColGroups; it += NT) {
+        const int32_t pg = (int32_t)udiv16((u32)it, Wr), d = it - pg * Wd;
         const int32_t p = pg / kColGroups, g = pg % kColGroups;
-        table_colapply_item(s, m, p, w, g);
+        table_colapply_item(s, m, p, d, g);
     }
 }
 
@@ -1799,28 +1858,33 @@ MF_HD void tail_output(const Shape &s, const Tile &T, const TileMem &m, int32_t 
     const int32_t e0 = (int32_t)T.e0;
     const int32_t nout = (T.P - 1) * s.k + T.lenLast;
     const u32 kr = recip32(s.k);
+    // addresses are 32-bit byte offsets from the tile's bases (a tile spans
+    // far less than 4 GB), so that the loads and stores take the
+    // scalar-base form without 64-bit address arithmetic per lane
+    const unsigned char *xb = (const unsigned char *)xt;
+    unsigned char *yb = (unsigned char *)yt, *ab = (unsigned char *)at;
     for (int32_t base = 0; base < nout; base += NT * kRegs) {
         V v[kRegs];
-        int32_t g[kRegs];
+        u32 g[kRegs];
 #pragma unroll
         for (int j = 0; j < kRegs; j++) {
             const int32_t it = base + j * NT + tid;
-            g[j] = 0;
+            g[j] = 0u;
             v[j] = 0;
             if (it < nout) {
-                const int32_t p = (int32_t)udiv16((u32)it, kr);
+                const u32 p = udiv16((u32)it, kr);
                 const int32_t r = m.stage[it];
-                const u32 e = m.M[(int32_t)mul24((u32)p, (u32)s.Mstride) + mslot(r)];
-                g[j] = (int32_t)mul24((u32)p + (e >> 15), (u32)s.k) + (int32_t)(e & 0x7FFFu);
-                v[j] = xt[g[j]];
+                const u32 e = m.M[(int32_t)mul24(p, (u32)s.Mstride) + mslot(r)];
+                g[j] = mul24(p + (e >> 15), (u32)s.k) + (e & 0x7FFFu);
+                v[j] = *(const V *)(xb + g[j] * (u32)sizeof(V));
             }
         }
 #pragma unroll
         for (int j = 0; j < kRegs; j++) {
             const int32_t it = base + j * NT + tid;
             if (it < nout) {
-                yt[it] = v[j];
-                if (at) at[it] = e0 + g[j];
+                *(V *)(yb + (u32)it * (u32)sizeof(V)) = v[j];
+                if (at) *(int32_t *)(ab + (u32)it * 4u) = e0 + (int32_t)g[j];
             }
         }
     }

@@ -555,3 +555,23 @@ extern "C" void emu_keys(const void *x, int64_t n, int kind, uint32_t *out32, ui
         else out64[i] = key_of_i64(((const u64 *)x)[i]);
     }
 }
+
+// The kernels' exact division by a per-launch reciprocal (udiv16 with
+// recip32) against the hardware divide: every dividend for divisors up to
+// 300, and the dividends next to each multiple plus a stride for every
+// divisor below 2^16.  Returns the number of mismatches.
+extern "C" long emu_check_udiv16(void)
+{
+    long bad = 0;
+    for (uint32_t d = 1; d < 65536u; d++) {
+        const uint32_t r = recip32((int32_t)d);
+        for (uint32_t q = 0; q * d < 65536u; q++)
+            for (int e = -1; e <= 1; e++) {
+                const int64_t a = (int64_t)q * d + e;
+                if (a >= 0 && a < 65536 && udiv16((uint32_t)a, r) != (uint32_t)a / d) bad++;
+            }
+        for (uint32_t a = 0; a < 65536u; a += (d < 300u ? 1u : 977u))
+            if (udiv16(a, r) != a / d) bad++;
+    }
+    return bad;
+}

@@ -291,3 +291,10 @@ def test_key_transforms_order(emu, kind):
     # equal values (and only those) share a key
     vr = value_rank(x)
     assert np.array_equal(keys[got][1:] == keys[got][:-1], vr[got][1:] == vr[got][:-1])
+
+
+def test_reciprocal_division(emu):
+    """The kernels' division of indexes below 2^16 by a launch constant (a
+    24-bit high multiply by a scaled reciprocal) is exact."""
+    emu.emu_check_udiv16.restype = ctypes.c_long
+    assert emu.emu_check_udiv16() == 0
