@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 256 MiB device copy (known bytes) for counter calibration")
+    ap.add_argument("--phase-probe", action="store_true",
+                    help="time the headline kernel stopped after each tile phase (needs the phase-probe "
+                         "library: python -m paper_1406_1717_amd.build --phase-probe)")
     return ap.parse_args()
 
 
@@ -174,6 +177,10 @@ def main():
     am = torch.empty(nout, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
 
+    if args.phase_probe:
+        print(json.dumps(phase_probe(torch, x, n, k, y, am, args)), flush=True)
+        return
+
     if args.copy_probe:
         src = torch.empty(64 << 20, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
@@ -232,6 +239,41 @@ def main():
     if args.extras:
         line["extras"] = extras(torch, mf, lib, workloads, args)
     print(json.dumps(line), flush=True)
+
+
+PHASES = ["load, zero counters", "key range + presorted check", "count", "scan", "scatter", "rank", "place",
+          "per-block counts + scan + table zero", "pair positions + histogram", "column sums", "column apply",
+          "row prefix", "walk", "output"]
+
+
+def phase_probe(torch, x, n, k, y, am, args):
+    """The headline kernel built with a stop after each tile phase: the
+    median launch time of every stopping point (HIP events), and each
+    phase's share as the difference of consecutive points."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_1406_1717_amd", "libmf_phase_probe.so")
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    L.mf_phase_probe_i32.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_int, P]
+    L.mf_phase_probe_i32.restype = ctypes.c_int
+    st = torch.cuda.current_stream()
+    stops = list(range(1, 14)) + [0]
+    ms = {}
+    for stop in stops:
+        def run():
+            rc = L.mf_phase_probe_i32(P(x.data_ptr()), n, k, P(y.data_ptr()), P(am.data_ptr()), stop,
+                                      P(st.cuda_stream))
+            if rc != 0:
+                raise RuntimeError("phase probe launch failed (%d)" % rc)
+        _, per = timed_steps(run, max(args.steps, 10), args.warmup, torch)
+        ms[stop] = float(np.median(per)) * 1e3
+    cum = [ms[s] for s in stops]
+    phases = []
+    prev = 0.0
+    for name, c in zip(PHASES, cum):
+        phases.append({"phase": name, "cumulative_ms": c, "ms": c - prev})
+        prev = c
+    return {"phase_probe": WORKLOAD, "n": n, "k": k, "phases": phases}
 
 
 def kernel_source_sha():

@@ -43,5 +43,27 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+PROBE_OUT = os.path.join(PKG, "libmf_phase_probe.so")
+
+
+def build_phase_probe(verbose: bool = False) -> str:
+    """A measurement-only library: the int32 512-thread tile kernel
+    instantiated with a stop after each tile phase (mf_phase_probe_i32), for
+    timing and counting the phases one by one.  The product never loads it."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    obj = os.path.join(BUILD_DIR, "mf_kernels_probe.o")
+    cmd = [HIPCC] + FLAGS + ["-DMF_PHASE_PROBE", "-c", os.path.join(CSRC, "mf_kernels.hip"), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    tmp = PROBE_OUT + ".tmp%d" % os.getpid()
+    subprocess.run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, obj], check=True)
+    os.replace(tmp, PROBE_OUT)
+    return PROBE_OUT
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if len(sys.argv) > 1 and sys.argv[1] == "--phase-probe":
+        build_phase_probe(verbose=True)
+    else:
+        build(verbose=True)

@@ -28,6 +28,13 @@ namespace mf {
 
 // ------------------------------------------------------------------ helpers
 
+// Phase probe: kernels instantiated with STOP = n (only in the phase-probe
+// build, MF_PHASE_PROBE) return after the n-th phase boundary of a tile, so
+// that timing and counting each stopping point gives the cost of every
+// phase.  The library's kernels have STOP = 0 and contain no such return.
+#define MF_STOP_AT(n) \
+    if constexpr (STOP == (n)) return;
+
 __device__ __forceinline__ void store_regs(u64 *dst, const u64 (&v)[kRegs])
 {
 #pragma unroll
@@ -117,7 +124,7 @@ __device__ __forceinline__ Resolved unit_of(const Launch &L, int64_t uidx)
 // Phases 3-6 of a tile (pair merge, tables, walk, output); phases 1-2 have
 // filled m.srt.  NT threads, barriers between phases.  The medians are
 // copied from xo to yo (V: 32- or 64-bit elements).
-template <int NT, typename V>
+template <int NT, typename V, int STOP = 0>
 __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
                                           const V *xo, V *yo, int *err, bool merged, u32 *rowbuf = nullptr)
 {
@@ -144,11 +151,14 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
         }
         tail_table_colsums(s, T, m, tid, NT);
         __syncthreads();
+        MF_STOP_AT(10)
         tail_table_colapply(s, T, m, tid, NT);
         __syncthreads();
+        MF_STOP_AT(11)
         if (rowbuf) tail_table_rows_waves(s, T, m, tid & 63, tid >> 6, NT / 64, 64);
         else tail_table_rows(s, T, m, tid, NT);
         __syncthreads();
+        MF_STOP_AT(12)
     }
     if (rowbuf && T.P > 0) {
         // tiles in global memory: the walk and the output read the merged
@@ -166,6 +176,7 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
     }
     if (tail_walk(s, T, m, tid, NT)) atomicOr(err, 1);
     __syncthreads();
+    MF_STOP_AT(13)
     tail_output(s, T, m, tid, NT, xo, yo, d.argmed);
 }
 
@@ -304,7 +315,7 @@ __device__ __forceinline__ void unit_shape(const Resolved &d, Shape &s, Tile &T)
 // the thread's inputs (load_raw).  RK: the inputs are rank keys of a 64-bit
 // signal (each tile's items' distinct tile-order positions).  The medians
 // are copied from xo to yo (V: u32, or u64 for a 64-bit signal).
-template <int NT, bool F32, bool RK = false, typename V = u32>
+template <int NT, bool F32, bool RK = false, typename V = u32, int STOP = 0>
 __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, const Tile &T,
                                          const u32 (&raw)[kRegs], unsigned char *lds, int *err,
                                          const V *xo, V *yo)
@@ -341,6 +352,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
     for (int b = tid; b < l.nbmax; b += NT) bucket_info_init(m, b);
     presort_note(s, m, tid, v);
     __syncthreads();
+    MF_STOP_AT(1)
     bool fast = s.S >= kRegs;
     bool direct = false;   // items already in sort order
     int pass = 0;          // bucket map: 0 linear, 1 clamped logarithmic
@@ -349,6 +361,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
         tile_minmax(m, v);
         presort_check(s, T, m, tid, NT, v, true);
         __syncthreads();
+        MF_STOP_AT(2)
         direct = (m.flag[0] & 4u) == 0u;
         if (!direct && tile_many_ties(m, tile_items(s, T))) {
             __syncthreads();
@@ -362,6 +375,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
     if (tord && !direct && !ranked) {
         tile_count<F32>(st, m, v, arr, pass);
         __syncthreads();
+        MF_STOP_AT(3)
         if ((m.flag[0] & 3u) != 0u) {
             __syncthreads();
             pass = 1;
@@ -421,16 +435,20 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
             const u32 excl = seg_excl_scan<NT>(tot, tord ? NT : s.S / kRegs, wave_tot);
             bucket_scan_store(m, tid, excl, c, per);
             __syncthreads();
+            MF_STOP_AT(4)
             if (tord) tile_scatter(m, v, arr);
             else bucket_scatter<F32>(s, T, m, tid, v, arr, pass);
             __syncthreads();
+            MF_STOP_AT(5)
             u32 fin[kRegs];
             if (tord) tile_rank(st, m, v, N, fin, arr);
             else bucket_rank<F32>(s, T, m, tid, v, fin, pass);
             __syncthreads();
+            MF_STOP_AT(6)
             if (tord) tile_place(m, v, fin);
             else bucket_place(s, m, v, fin);
             __syncthreads();
+            MF_STOP_AT(7)
         }
         if (tord) {
             // 3. pair orders from the per-block counts along the tile order
@@ -441,9 +459,11 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
                 tail_table_zero(s, T, m, tid, NT);
                 __syncthreads();
             }
+            MF_STOP_AT(8)
             tile_positions(s, T, m, ex, w, xo, yo, d.argmed);
             tile_mpad(s, T, m, tid, NT);
             __syncthreads();
+            MF_STOP_AT(9)
             merged = true;
         }
     } else {
@@ -463,7 +483,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
         __syncthreads();
     }
 
-    tile_tail<NT>(s, T, m, d, xo, yo, err, merged);
+    tile_tail<NT, V, STOP>(s, T, m, d, xo, yo, err, merged);
 }
 
 // One workgroup per work unit.  512-thread tiles of at most 53 KB run three
@@ -472,7 +492,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
 // out by the rank pre-pass; 2 (int64) and 3 (float64), the tile ranks the
 // 64-bit signal L.x64 in its own LDS first.  With RK, the medians are copied
 // from L.x64 to the 64-bit y.
-template <int NT, bool F32, int RK = 0>
+template <int NT, bool F32, int RK = 0, int STOP = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 6 : 8))) void k_tile_lds(Launch L, int *err)
 {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -495,7 +515,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 
     if constexpr (RK != 0) {
         lds_tile<NT, F32, true>(d, s, T, raw, lds, err, x64, y64);
     } else {
-        lds_tile<NT, F32>(d, s, T, raw, lds, err, d.x, d.y);
+        lds_tile<NT, F32, false, u32, STOP>(d, s, T, raw, lds, err, d.x, d.y);
     }
 }
 
@@ -1432,3 +1452,61 @@ hipError_t launch_identity64(const void *x, void *y, int32_t *argmed, int64_t to
 }
 
 }  // namespace mf
+
+#ifdef MF_PHASE_PROBE
+#include <string.h>
+// Phase-probe build only (not part of libmf.so): the int32 forward on
+// 512-thread tiles with every workgroup returning after tile phase `stop`
+// (1 .. 13 as numbered by MF_STOP_AT; 0 runs whole tiles).  The outputs of a
+// stopped launch are not written.  Returns a hipError_t.
+namespace mf {
+template <int S>
+static hipError_t probe_launch(const Launch &L, size_t lds, int *err, hipStream_t st)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)k_tile_lds<kLdsSmall, false, 0, S>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 156 * 1024);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_tile_lds<kLdsSmall, false, 0, S>), dim3((unsigned)L.nunits), dim3(kLdsSmall), lds, st, L,
+                       err);
+    return hipGetLastError();
+}
+}  // namespace mf
+
+extern "C" int mf_phase_probe_i32(const void *x, int64_t n, int32_t k, void *y, int32_t *argmed, int stop,
+                                  void *stream)
+{
+    using namespace mf;
+    static int *err = nullptr;
+    if (path_for(k) != PATH_LDS_SMALL || n < k || n > INT32_MAX) return (int)hipErrorInvalidValue;
+    if (!err && hipMalloc(&err, sizeof(int)) != hipSuccess) return (int)hipErrorOutOfMemory;
+    Launch L;
+    memset(&L, 0, sizeof L);
+    L.x = x;
+    L.y = y;
+    L.argmed = argmed;
+    L.one.n = n;
+    L.one.k = k;
+    L.rows = 1;
+    L.tpr = tiles_for(PATH_LDS_SMALL, n, k);
+    L.nunits = L.tpr;
+    const size_t lds = (size_t)lds_bytes_for(PATH_LDS_SMALL, k);
+    const hipStream_t st = (hipStream_t)stream;
+    switch (stop) {
+    case 0: return (int)probe_launch<0>(L, lds, err, st);
+    case 1: return (int)probe_launch<1>(L, lds, err, st);
+    case 2: return (int)probe_launch<2>(L, lds, err, st);
+    case 3: return (int)probe_launch<3>(L, lds, err, st);
+    case 4: return (int)probe_launch<4>(L, lds, err, st);
+    case 5: return (int)probe_launch<5>(L, lds, err, st);
+    case 6: return (int)probe_launch<6>(L, lds, err, st);
+    case 7: return (int)probe_launch<7>(L, lds, err, st);
+    case 8: return (int)probe_launch<8>(L, lds, err, st);
+    case 9: return (int)probe_launch<9>(L, lds, err, st);
+    case 10: return (int)probe_launch<10>(L, lds, err, st);
+    case 11: return (int)probe_launch<11>(L, lds, err, st);
+    case 12: return (int)probe_launch<12>(L, lds, err, st);
+    case 13: return (int)probe_launch<13>(L, lds, err, st);
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+#endif
