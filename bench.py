@@ -132,6 +132,25 @@ def copy_ceiling(torch, nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / float(np.median(times)) / 1e9
 
 
+def flushed_ms(fn, torch, reps=5, flush_bytes=1 << 30):
+    """Median HIP-event time of fn with the 256 MB Infinity Cache flushed
+    before each call (a 1 GiB device write outside the timed events)."""
+    scratch = torch.empty(flush_bytes // 4, dtype=torch.int32, device="cuda:0")
+    st = torch.cuda.current_stream()
+    fn()
+    times = []
+    for _ in range(reps):
+        scratch.fill_(1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del scratch
+    return float(np.median(times))
+
+
 def sampled_windows_ok(x, k, y, am, samples=2000, seed=0):
     h = (k - 1) // 2
     outs = np.random.default_rng(seed).integers(0, len(am), samples)
@@ -338,8 +357,13 @@ def extras(torch, mf, lib, workloads, args):
             y = torch.empty(n - k + 1, dtype=torch.float32, device=dev)
             a = torch.empty(n - k + 1, dtype=torch.int32, device=dev)
             total, per = timed_steps(lambda: lib.mf_median_filter(xr, n, k, y, a), 5, 1, torch)
+            # the whole working set (about 201 MB) fits the 256 MB Infinity
+            # Cache: also timed with the cache flushed before each launch
+            fl = flushed_ms(lambda: lib.mf_median_filter(xr, n, k, y, a), torch)
             res[str(k)] = {"outputs_per_s": (n - k + 1) * 5 / total,
-                           "hbm_frac": (4.0 * n + 8.0 * (n - k + 1)) / np.mean(per) / 1e9 / HBM_PEAK_GBS}
+                           "hbm_frac": (4.0 * n + 8.0 * (n - k + 1)) / np.mean(per) / 1e9 / HBM_PEAK_GBS,
+                           "flushed_ms": fl, "flushed_outputs_per_s": (n - k + 1) / (fl * 1e-3),
+                           "flushed_hbm_frac": (4.0 * n + 8.0 * (n - k + 1)) / (fl * 1e-3) / 1e9 / HBM_PEAK_GBS}
         out[name] = res
         del xr
     # 64-bit signals (rank pre-pass, int32 tiles on the ranks, gather)
@@ -366,10 +390,13 @@ def extras(torch, mf, lib, workloads, args):
                        "hbm_frac": (8.0 * n + 12.0 * (n - k + 1)) / np.mean(per) / 1e9 / HBM_PEAK_GBS}
     out["random_walk_f64_16m"] = res
     del xr
-    # differentiable rows: forward vs forward + backward
-    rows, n, k = 256, 262_144, 201
-    xs = torch.randn(rows, n, device=dev)
-    g = torch.randn(rows, n - k + 1, device=dev)
+    # differentiable rows (the seeded distinct-valued rows and upstream
+    # gradient): forward vs forward + backward, at the C-ABI level and
+    # through the autograd Function
+    w = workloads.workload("distinct_normal_256")
+    rows, n, k = w["x"].shape[0], w["x"].shape[1], w["k"]
+    xs = torch.from_numpy(w["x"]).to(dev)
+    g = torch.from_numpy(w["grad"]).to(dev)
     ys = torch.empty(rows, n - k + 1, device=dev)
     ams = torch.empty(rows, n - k + 1, dtype=torch.int32, device=dev)
     gx = torch.empty(rows, n, device=dev)
@@ -379,9 +406,24 @@ def extras(torch, mf, lib, workloads, args):
         lib.mf_median_filter_rows(xs, rows, n, k, ys, ams)
         lib.mf_median_filter_backward_rows(g, ams, rows, n, k, gx)
     tfb, _ = timed_steps(fb, 10, 2, torch)
+    tb, _ = timed_steps(lambda: lib.mf_median_filter_backward_rows(g, ams, rows, n, k, gx), 10, 2, torch)
+    xa = xs.clone().requires_grad_(True)
+
+    def af():
+        with torch.no_grad():
+            mf.MedianFilterFn.apply(xa, k)
+
+    def afb():
+        xa.grad = None
+        yy, _ = mf.MedianFilterFn.apply(xa, k)
+        yy.backward(g)
+    taf, _ = timed_steps(af, 10, 2, torch)
+    tafb, _ = timed_steps(afb, 10, 2, torch)
     out["distinct_normal_256"] = {"fwd_ms": tf / 10 * 1e3, "fwd_bwd_ms": tfb / 10 * 1e3,
-                                  "ratio": tfb / tf}
-    del xs, g, ys, ams, gx
+                                  "bwd_ms": tb / 10 * 1e3, "ratio": tfb / tf,
+                                  "autograd_fwd_ms": taf / 10 * 1e3, "autograd_fwd_bwd_ms": tafb / 10 * 1e3,
+                                  "autograd_ratio": tafb / taf}
+    del xs, g, ys, ams, gx, xa
     # ragged batch: one plan (graph) launch vs one plain launch per signal
     x, off, ks = workloads.ragged_impulse(10_000, workloads.SEEDS["ragged_impulse_10k"])
     xt = torch.from_numpy(x).to(dev)
@@ -411,6 +453,8 @@ def extras(torch, mf, lib, workloads, args):
     plan.close()
     out["paper_generators"] = paper_sweep(torch, lib, workloads)
     out["paper_generators_64"] = paper_sweep(torch, lib, workloads, bits=64)
+    out["paper_generators_bh1e6"] = paper_sweep(torch, lib, workloads, bh=10**6)
+    out["paper_generators_64_bh1e6"] = paper_sweep(torch, lib, workloads, bh=10**6, bits=64)
     return out
 
 

@@ -436,7 +436,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
             bucket_scan_store(m, tid, excl, c, per);
             __syncthreads();
             MF_STOP_AT(4)
-            if (tord) tile_scatter(m, v, arr);
+            if (tord) tile_scatter(m, v, arr, tid, N);
             else bucket_scatter<F32>(s, T, m, tid, v, arr, pass);
             __syncthreads();
             MF_STOP_AT(5)

@@ -80,6 +80,25 @@ MF_HD int32_t mslot(int32_t r)
     return (int32_t)((rot & 31u) | (u & ~31u));
 }
 
+// Byte offset of merged position r in a pair's M row, 2 * mslot(r): bits
+// 2..5 take bits 0..3 of r, bit 1 takes bit 4, bits 6.. take bits 5.. (two
+// bit-field inserts on the GPU, written out so that the compiler keeps them).
+MF_HD u32 mslot_bytes(u32 r)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    u32 z, w;
+    asm("v_bfi_b32 %0, 60, %1, %2" : "=v"(z) : "v"(r << 2), "v"(r << 1));
+    asm("v_bfi_b32 %0, 2, %1, %2" : "=v"(w) : "v"(r >> 3), "v"(z));
+    return w;
+#else
+    return 2u * (u32)mslot((int32_t)r);
+#endif
+}
+
+// Entry of merged position r in the M row starting at Mp.
+MF_HD u16 &m_entry(u16 *Mp, u32 r) { return *(u16 *)((unsigned char *)Mp + mslot_bytes(r)); }
+MF_HD u16 m_entry(const u16 *Mp, u32 r) { return *(const u16 *)((const unsigned char *)Mp + mslot_bytes(r)); }
+
 // Lane-wise 16-bit difference a - b of two packed halves.
 MF_HD uint32_t psub16(uint32_t a, uint32_t b)
 {
@@ -92,6 +111,8 @@ MF_HD uint32_t psub16(uint32_t a, uint32_t b)
 #endif
 }
 static const int kRegs = 8;                // sort values per thread
+static const int kRankPad = 4;             // entries past the scattered values that
+                                           // the tile-order rank reads unchecked
 static const int32_t kPairBudget = 48 * 1024; // bytes of M + pos per tile
 static const int kColGroups = 8;           // row groups per count-table column
 
@@ -332,8 +353,8 @@ MF_HD void make_layout(const Shape &s, Layout *l)
     off = (off + 15) & ~15;
     // bucket sort scratch, used before the pair orders are written: after the
     // 64-bit scatter buffer (slot-indexed in block order, at most 2k values in
-    // the tile order of a compact tile)
-    l->bk = compact_tile(s) ? ((16 * s.k + 15) & ~15) : 8 * s.cap;
+    // the tile order of a compact tile) and the kRankPad entries past it
+    l->bk = compact_tile(s) ? ((16 * s.k + 8 * kRankPad + 15) & ~15) : 8 * (s.cap + kRankPad);
     l->info = l->bk + 4 * tile_buckets(s);
     l->nbmax = s.Pmax + 1;
     const int32_t bend = l->info + 4 * (2 * (s.Pmax + 1) + 1);
@@ -1080,11 +1101,12 @@ MF_HD void tile_count(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], 
     if (mx >= (u32)kBucketSoft) MF_OR32(m.flag, mx >= (u32)kBucketMax ? 3u : 2u);
 }
 
-MF_HD void tile_scatter(const TileMem &m, const u64 (&v)[kRegs], const u32 (&ab)[kRegs])
+MF_HD void tile_scatter(const TileMem &m, const u64 (&v)[kRegs], const u32 (&ab)[kRegs], int32_t tid, int32_t N)
 {
 #pragma unroll
     for (int j = 0; j < kRegs; j++)
         if (sv_valid(v[j])) m.mbuf[m.bk[ab[j] >> 8] + (ab[j] & 0xFFu)] = v[j];
+    if (tid < kRankPad) m.mbuf[N + tid] = kPadAll;
 }
 
 // Per thread: sorted position = bucket start + rank by the full value among
@@ -1104,8 +1126,21 @@ MF_HD void tile_rank(const Shape &st, const TileMem &m, const u64 (&v)[kRegs], i
         }
         fin[j] = x[j];
     }
+    // Buckets hold consecutive key ranges, so the entries after an item's
+    // bucket, up to the padding past the last one, all order above it: the
+    // first kRankPad entries from the bucket's start are compared without
+    // a bound, the rest of a longer bucket in a loop.  A bucket of one item
+    // (the item itself) needs no comparison.
 #pragma unroll
-    for (int j = 0; j < kRegs; j++) fin[j] += bucket_below(m.mbuf, x[j], hi[j], v[j]);
+    for (int j = 0; j < kRegs; j++) {
+        u32 f = 0u;
+        if (hi[j] - x[j] > 1u) {
+#pragma unroll
+            for (int u = 0; u < kRankPad; u++) f += (m.mbuf[x[j] + (u32)u] < v[j]) ? 1u : 0u;
+            for (u32 q = x[j] + (u32)kRankPad; q < hi[j]; q++) f += (m.mbuf[q] < v[j]) ? 1u : 0u;
+        }
+        fin[j] += f;
+    }
 }
 
 // The pair orders read only the slots of the tile order, not the keys.
@@ -1156,19 +1191,20 @@ MF_HD void tile_positions(const Shape &s, const Tile &T, const TileMem &m, u64 e
         // pair's chunks only feed the column sums)
         const u32 rowc = hist ? mul24(udiv16(t, Lr), (u32)s.Wrow) + mul24(b, CW) : 0u;
         const u32 cb = (u32)(c >> sh) & 0xFFFFu;
+        // pair b's M row and position map; pair b - 1's are one row before
+        u16 *MA = m.M + mul24(b, (u32)s.Mstride);
+        u16 *QA = (u16 *)(m.pos + mul24(b, (u32)s.Pstride)) + 2u * t;
         if ((int32_t)b < T.P) {   // A of pair b
             const u32 r = (u32)(R >> sh) & 0xFFFFu;
-            m.M[mul24(b, (u32)s.Mstride) + mslot((int32_t)r)] = (u16)t;
-            const u32 pb = mul24(b, (u32)s.Pstride);
-            ((u16 *)(m.pos + pb))[2u * t] = (u16)r;
-            if (cb == (u32)s.h) m.pos[pb + (u32)s.k] = r;
+            m_entry(MA, r) = (u16)t;
+            QA[0] = (u16)r;
+            if (cb == (u32)s.h) m.pos[mul24(b, (u32)s.Pstride) + (u32)s.k] = r;
             if (hist) cnt_add(m, (int32_t)(rowc + (r >> 6)), 1u);
         }
         if (b >= 1u) {    // B of pair b - 1
             const u32 r = (u32)(R >> (sh - 16u)) & 0xFFFFu;
-            const u32 q = b - 1u;
-            m.M[mul24(q, (u32)s.Mstride) + mslot((int32_t)r)] = (u16)(0x8000u | t);
-            ((u16 *)(m.pos + mul24(q, (u32)s.Pstride)))[2u * t + 1u] = (u16)r;
+            m_entry(MA - s.Mstride, r) = (u16)(0x8000u | t);
+            QA[1 - 2 * s.Pstride] = (u16)r;
             if (hist) cnt_add(m, (int32_t)(rowc - CW + (r >> 6)), 0x100u);
         }
         if (b == 0u && cb == (u32)s.h && T.j0 == 1) {   // output 0: the median of block 0
@@ -1588,13 +1624,12 @@ MF_HD int walk_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, 
     // chunk 0 starts from A's median (pair_first_median); later chunks find
     // the rank-h member of the window before step i0 from the count table:
     // it lies in the largest word w with pc[w] <= h
-    int32_t lo, r;
-    u32 dlo, dhi;
+    // (every lane runs the same membership reads, so that the lanes of a
+    // wave, which start different chunks, do not diverge here)
+    int32_t lo, r0 = 0;
     if (c == 0) {
-        r = (int32_t)pos[s.k];
-        lo = r >> 6;
-        dlo = member_dword(s, Mp, 2 * lo, -1);
-        dhi = member_dword(s, Mp, 2 * lo + 1, -1);
+        r0 = (int32_t)pos[s.k];
+        lo = r0 >> 6;
     } else {
         lo = 0;
         int32_t hi = s.Wn;
@@ -1603,17 +1638,20 @@ MF_HD int walk_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, 
             if ((int32_t)pc[mid] <= h) lo = mid;
             else hi = mid;
         }
-        dlo = member_dword(s, Mp, 2 * lo, i0 - 1);
-        dhi = member_dword(s, Mp, 2 * lo + 1, i0 - 1);
-        r = lo * 64 + select64((u64)dlo | ((u64)dhi << 32), h - (int32_t)pc[lo]);
     }
+    const u32 dlo = member_dword(s, Mp, 2 * lo, i0 - 1);
+    const u32 dhi = member_dword(s, Mp, 2 * lo + 1, i0 - 1);
     const u64 word = (u64)dlo | ((u64)dhi << 32);
+    const int32_t below_lo = c == 0 ? 0 : (int32_t)pc[lo];   // members below word lo
+    const int32_t r = c == 0 ? r0 : lo * 64 + select64(word, h - below_lo);
 
+    // the window: word lo itself, or shifted half a word toward r when r
+    // lies in its outer quarters (one more membership dword)
     int32_t base = win_base_for(r);
-    u64 W;
-    if (base == lo * 64) W = word;
-    else if (base < lo * 64) W = (u64)member_dword(s, Mp, 2 * lo - 1, i0 - 1) | ((u64)dlo << 32);
-    else W = (u64)dhi | ((u64)member_dword(s, Mp, 2 * lo + 2, i0 - 1) << 32);
+    const bool below = base < lo * 64;
+    const u32 dx = member_dword(s, Mp, below ? 2 * lo - 1 : 2 * lo + 2, i0 - 1);
+    u64 W = word;
+    if (base != lo * 64) W = below ? (u64)dx | ((u64)dlo << 32) : (u64)dhi | ((u64)dx << 32);
 
     int bad = 0;
     int32_t rel = r - base;   // the median's bit in the window, in [0, 64)
@@ -1874,7 +1912,7 @@ MF_HD void tail_output(const Shape &s, const Tile &T, const TileMem &m, int32_t 
             if (it < nout) {
                 const u32 p = udiv16((u32)it, kr);
                 const int32_t r = m.stage[it];
-                const u32 e = m.M[(int32_t)mul24(p, (u32)s.Mstride) + mslot(r)];
+                const u32 e = m_entry(m.M + mul24(p, (u32)s.Mstride), (u32)r);
                 g[j] = mul24(p + (e >> 15), (u32)s.k) + (e & 0x7FFFu);
                 v[j] = *(const V *)(xb + g[j] * (u32)sizeof(V));
             }

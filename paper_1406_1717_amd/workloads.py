@@ -217,6 +217,10 @@ def workload(name):
         return {"x": int64_full(2**26, SEEDS[name]), "k": 1001}
     if name == "random_walk_f64_16m":
         return {"x": random_walk_f64(2**24, SEEDS[name]), "ks": [3, 31, 301, 3001, 30001]}
+    if name == "distinct_normal_256":
+        rows, n, k = 256, 262_144, 201
+        return {"x": distinct_rows(rows, n, SEEDS[name]), "k": k,
+                "grad": normal_f32((rows, n - k + 1), SEEDS["distinct_normal_256_grad"])}
     if name == "sorted_walk_f32_16m":
         return {"x": sorted_walk_f32(2**24, SEEDS["random_walk_f32_16m"]),
                 "ks": [3, 31, 301, 3001, 30001]}

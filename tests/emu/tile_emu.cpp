@@ -183,7 +183,7 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
         for (int q = 0; q < threads; q++) {
             u64 v[kRegs]; V(q, v); u32 a[kRegs];
             for (int j = 0; j < kRegs; j++) a[j] = arr[(size_t)q * kRegs + j];
-            if (tord) tile_scatter(m, v, a);
+            if (tord) tile_scatter(m, v, a, q, N);
             else bucket_scatter<F32>(s, T, m, q, v, a, pass);
         }
         for (int q = 0; q < threads; q++) {
