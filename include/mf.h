@@ -125,6 +125,18 @@ mf_status mf_median_filter_batched(const float *x, const int64_t *x_offsets,
 mf_status mf_median_filter_batched_i32(const int32_t *x, const int64_t *x_offsets,
                                        const int32_t *ks, int32_t num_signals,
                                        int32_t *y, int32_t *argmed, void *stream);
+/* Ragged batches of 64-bit signals (Section 7 measures 32- and 64-bit
+ * versions): float64 and int64, same layout, offsets and windows as
+ * mf_median_filter_batched, y of the input type (bit copies).  Signals with
+ * windows up to 2047 run as one launch over the cached plan's work list
+ * (each tile ranks its 64-bit items in LDS); larger windows run signal by
+ * signal through the single-signal path, using the library's workspace. */
+mf_status mf_median_filter_batched_f64(const double *x, const int64_t *x_offsets,
+                                       const int32_t *ks, int32_t num_signals,
+                                       double *y, int32_t *argmed, void *stream);
+mf_status mf_median_filter_batched_i64(const int64_t *x, const int64_t *x_offsets,
+                                       const int32_t *ks, int32_t num_signals,
+                                       int64_t *y, int32_t *argmed, void *stream);
 
 /* Backward of y = x[argmed]: grad_x[j] = sum of grad_y[o] over the outputs
  * o with argmed[o] == j, accumulated in float64 in increasing o and rounded
@@ -178,6 +190,13 @@ mf_status mf_plan_execute(mf_plan *plan, const float *x, float *y, int32_t *argm
                           void *stream);
 /* mf_plan_execute for int32 signals (the plan does not depend on the type). */
 mf_status mf_plan_execute_i32(mf_plan *plan, const int32_t *x, int32_t *y, int32_t *argmed,
+                              void *stream);
+/* mf_plan_execute for float64 and int64 signals (as
+ * mf_median_filter_batched_f64/_i64; not graph-captured, and the launch
+ * configuration does not apply). */
+mf_status mf_plan_execute_f64(mf_plan *plan, const double *x, double *y, int32_t *argmed,
+                              void *stream);
+mf_status mf_plan_execute_i64(mf_plan *plan, const int64_t *x, int64_t *y, int32_t *argmed,
                               void *stream);
 mf_status mf_plan_execute_backward(mf_plan *plan, const float *grad_y, const int32_t *argmed,
                                    float *grad_x, void *stream);

@@ -124,7 +124,7 @@ def output_offsets(x_offsets, ks):
 
 def median_filter_batched(x, x_offsets, ks, with_argmed=True):
     """Ragged batch: signal s = x[x_offsets[s]:x_offsets[s+1]], window ks[s]."""
-    _check_tensor(x, "x", (torch.float32, torch.int32))
+    _check_tensor(x, "x", _SIGNAL_TYPES)
     if x.dim() != 1:
         raise ValueError("x must be 1-D (the signals packed back to back)")
     x_offsets, ks = _batch_layout(x_offsets, ks)
@@ -134,10 +134,9 @@ def median_filter_batched(x, x_offsets, ks, with_argmed=True):
     yo = output_offsets(x_offsets, ks)
     y = torch.empty(int(yo[-1]), dtype=x.dtype, device=x.device)
     am = torch.empty(int(yo[-1]), dtype=torch.int32, device=x.device) if with_argmed else None
-    if x.dtype == torch.int32:
-        lib.mf_median_filter_batched_i32(x, x_offsets, ks, len(ks), y, am)
-    else:
-        lib.mf_median_filter_batched(x, x_offsets, ks, len(ks), y, am)
+    fn = {torch.int32: lib.mf_median_filter_batched_i32, torch.float64: lib.mf_median_filter_batched_f64,
+          torch.int64: lib.mf_median_filter_batched_i64}.get(x.dtype, lib.mf_median_filter_batched)
+    fn(x, x_offsets, ks, len(ks), y, am)
     return y, am
 
 

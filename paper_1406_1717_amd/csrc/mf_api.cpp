@@ -609,6 +609,65 @@ extern "C" mf_status mf_plan_execute_i32(mf_plan *p, const int32_t *x, int32_t *
     return plan_execute(p, x, y, argmed, false, stream);
 }
 
+// One execution of plan p on 64-bit signals (f64: float64, else int64).
+// The 512-thread tile family (windows up to 2047) runs as one launch over
+// the plan's work list, each tile ranking its 64-bit items in LDS; signals
+// of the other families run one after another through the single-signal
+// path (rank pre-pass in the workspace, then their tiles).
+static mf_status plan_execute64(mf_plan *p, const void *x, void *y, int32_t *argmed, bool f64, void *stream)
+{
+    if (!p) return fail(MF_ERR_INVALID_VALUE, "plan must not be null");
+    if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
+    hipStream_t st = (hipStream_t)stream;
+    Device *D = nullptr;
+    mf_status s = device_state(&D);
+    if (s != MF_OK) return s;
+    std::lock_guard<std::mutex> plk(p->mu);
+    MF_HIP(hipStreamWaitEvent(st, p->done, 0), "hipStreamWaitEvent(plan)");
+    for (const PathGroup &g : p->groups[MF_LAUNCH_PER_FAMILY]) {
+        if (g.path != PATH_LDS_SMALL) continue;
+        size_t lds = 0;
+        for (int32_t q = 0; q < p->num_signals; q++)
+            if (path_for(p->ks[q]) == PATH_LDS_SMALL)
+                lds = std::max(lds, (size_t)rank64_lds_bytes_for(PATH_LDS_SMALL, p->ks[q]));
+        Launch L;
+        memset(&L, 0, sizeof L);
+        L.x = x;
+        L.x64 = x;
+        L.y = y;
+        L.argmed = argmed;
+        L.sigs = g.d_sigs;
+        L.units = g.d_units;
+        L.nunits = g.nunits;
+        L.rank_mode = f64 ? 3 : 2;
+        MF_HIP(launch_forward(PATH_LDS_SMALL, false, L, lds, nullptr, 0, 0, D->d_err, st), "64-bit batched launch");
+    }
+    const unsigned char *xb = (const unsigned char *)x;
+    unsigned char *yb = (unsigned char *)y;
+    int64_t yoff = 0;
+    for (int32_t q = 0; q < p->num_signals; q++) {
+        const int64_t n = p->offsets[q + 1] - p->offsets[q];
+        const int32_t k = p->ks[q];
+        if (path_for(k) != PATH_LDS_SMALL &&
+            (s = forward64(xb + 8 * p->offsets[q], 1, n, k, yb + 8 * yoff, argmed ? argmed + yoff : nullptr, f64,
+                           st)) != MF_OK)
+            return s;
+        yoff += n - k + 1;
+    }
+    MF_HIP(hipEventRecord(p->done, st), "hipEventRecord(plan)");
+    return MF_OK;
+}
+
+extern "C" mf_status mf_plan_execute_f64(mf_plan *p, const double *x, double *y, int32_t *argmed, void *stream)
+{
+    return plan_execute64(p, x, y, argmed, true, stream);
+}
+
+extern "C" mf_status mf_plan_execute_i64(mf_plan *p, const int64_t *x, int64_t *y, int32_t *argmed, void *stream)
+{
+    return plan_execute64(p, x, y, argmed, false, stream);
+}
+
 extern "C" mf_status mf_plan_execute_backward(mf_plan *p, const float *grad_y, const int32_t *argmed,
                                               float *grad_x, void *stream)
 {
@@ -852,6 +911,26 @@ extern "C" mf_status mf_median_filter_batched_i32(const int32_t *x, const int64_
     mf_status s = cached_plan(x_offsets, ks, num_signals, p);
     if (s != MF_OK) return s;
     return plan_execute(p.get(), x, y, argmed, false, stream);
+}
+
+extern "C" mf_status mf_median_filter_batched_f64(const double *x, const int64_t *x_offsets, const int32_t *ks,
+                                                  int32_t num_signals, double *y, int32_t *argmed, void *stream)
+{
+    if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
+    std::shared_ptr<mf_plan> p;
+    mf_status s = cached_plan(x_offsets, ks, num_signals, p);
+    if (s != MF_OK) return s;
+    return plan_execute64(p.get(), x, y, argmed, true, stream);
+}
+
+extern "C" mf_status mf_median_filter_batched_i64(const int64_t *x, const int64_t *x_offsets, const int32_t *ks,
+                                                  int32_t num_signals, int64_t *y, int32_t *argmed, void *stream)
+{
+    if (!x || !y) return fail(MF_ERR_INVALID_VALUE, "x and y must not be null");
+    std::shared_ptr<mf_plan> p;
+    mf_status s = cached_plan(x_offsets, ks, num_signals, p);
+    if (s != MF_OK) return s;
+    return plan_execute64(p.get(), x, y, argmed, false, stream);
 }
 
 extern "C" mf_status mf_median_filter_backward(const float *grad_y, const int32_t *argmed, int64_t n,

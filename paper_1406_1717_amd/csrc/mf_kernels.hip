@@ -501,10 +501,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 
     Tile T;
     unit_shape<NT>(d, s, T);
     u32 raw[kRegs];
-    // a 64-bit signal's row of the launch (rows of n items, n-k+1 outputs)
-    const int64_t row = RK != 0 ? (int64_t)blockIdx.x / L.tpr : 0;
-    const u64 *x64 = (const u64 *)L.x64 + row * d.n;
-    u64 *y64 = (u64 *)L.y + row * (d.n - d.k + 1);
+    // a 64-bit signal's elements and medians: its row of the launch (rows
+    // of n items, n-k+1 outputs), or its signal of a work list
+    const u64 *x64 = (const u64 *)L.x64;
+    u64 *y64 = (u64 *)L.y;
+    if constexpr (RK != 0) {
+        if (L.units) {
+            const SigDesc sd = L.sigs[L.units[blockIdx.x].sig];
+            x64 += sd.x_off;
+            y64 += sd.y_off;
+        } else {
+            const int64_t row = (int64_t)blockIdx.x / L.tpr;
+            x64 += row * d.n;
+            y64 += row * (d.n - d.k + 1);
+        }
+    }
     if constexpr (RK >= 2) {
         rank_tile<NT, RK == 3>(s, T, x64, lds);
         rank_raw(s, T, (const u32 *)lds, threadIdx.x, raw);

@@ -44,6 +44,10 @@ def load():
         "mf_median_filter_rows_i64": [P, I64, I64, I32, P, P, P],
         "mf_median_filter_batched": [P, P, P, I32, P, P, P],
         "mf_median_filter_batched_i32": [P, P, P, I32, P, P, P],
+        "mf_median_filter_batched_f64": [P, P, P, I32, P, P, P],
+        "mf_median_filter_batched_i64": [P, P, P, I32, P, P, P],
+        "mf_plan_execute_f64": [P, P, P, P, P],
+        "mf_plan_execute_i64": [P, P, P, P, P],
         "mf_median_filter_backward": [P, P, I64, I32, P, P],
         "mf_median_filter_backward_rows": [P, P, I64, I64, I32, P, P],
         "mf_median_filter_backward_f64": [P, P, I64, I32, P, P],
@@ -167,6 +171,20 @@ def mf_median_filter_batched_i32(x, x_offsets, ks, num_signals, y, argmed, strea
                                                _stream(stream)))
 
 
+def mf_median_filter_batched_f64(x, x_offsets, ks, num_signals, y, argmed, stream=None):
+    off, offp = _host_i64(x_offsets)
+    kk, kp = _host_i32(ks)
+    _check(load().mf_median_filter_batched_f64(_ptr(x), offp, kp, int(num_signals), _ptr(y), _ptr(argmed),
+                                               _stream(stream)))
+
+
+def mf_median_filter_batched_i64(x, x_offsets, ks, num_signals, y, argmed, stream=None):
+    off, offp = _host_i64(x_offsets)
+    kk, kp = _host_i32(ks)
+    _check(load().mf_median_filter_batched_i64(_ptr(x), offp, kp, int(num_signals), _ptr(y), _ptr(argmed),
+                                               _stream(stream)))
+
+
 def mf_median_filter_backward(grad_y, argmed, n, k, grad_x, stream=None):
     _check(load().mf_median_filter_backward(_ptr(grad_y), _ptr(argmed), int(n), int(k), _ptr(grad_x),
                                             _stream(stream)))
@@ -242,13 +260,15 @@ class Plan:
 
     def _check_forward(self, x, y, argmed):
         xd = getattr(x, "dtype", None)
-        _plan_tensors((x, "x", (torch.float32, torch.int32), int(self._off[-1]), False),
+        _plan_tensors((x, "x", (torch.float32, torch.int32, torch.float64, torch.int64), int(self._off[-1]), False),
                       (y, "y", (xd,), self.output_length, False),
                       (argmed, "argmed", (torch.int32,), self.output_length, True))
 
     def execute(self, x, y, argmed, stream=None):
         self._check_forward(x, y, argmed)
-        fn = load().mf_plan_execute_i32 if _is_i32(x) else load().mf_plan_execute
+        L = load()
+        fn = {torch.int32: L.mf_plan_execute_i32, torch.float64: L.mf_plan_execute_f64,
+              torch.int64: L.mf_plan_execute_i64}.get(x.dtype, L.mf_plan_execute)
         _check(fn(self._h, _ptr(x), _ptr(y), _ptr(argmed), _stream(stream)))
 
     def execute_backward(self, grad_y, argmed, grad_x, stream=None):

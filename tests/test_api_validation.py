@@ -47,7 +47,7 @@ def test_batched_rejects_short_x_and_bad_dtype():
     with pytest.raises(ValueError, match="the offsets need 30"):
         mf.median_filter_batched(torch.zeros(29), [0, 10, 30], [3, 5])
     with pytest.raises(TypeError):
-        mf.median_filter_batched(torch.zeros(30, dtype=torch.float64), [0, 10, 30], [3, 5])
+        mf.median_filter_batched(torch.zeros(30, dtype=torch.float16), [0, 10, 30], [3, 5])
     with pytest.raises(ValueError, match="1-D"):
         mf.median_filter_batched(torch.zeros(3, 10), [0, 10, 30], [3, 5])
     with pytest.raises(ValueError, match="GPU"):
@@ -119,7 +119,9 @@ def test_plan_tensor_checks():
     with pytest.raises(ValueError, match="argmed has 23"):
         P.execute(x, y, a[:-1])
     with pytest.raises(TypeError, match="x must be"):
-        P.execute(x.double(), y.double(), a)
+        P.execute(x.half(), y.half(), a)
+    with pytest.raises(TypeError, match="y must be"):
+        P.execute(x.double(), y, a)
     with pytest.raises(ValueError, match="GPU"):
         P.execute(x, y, a)
     with pytest.raises(ValueError, match="GPU"):
