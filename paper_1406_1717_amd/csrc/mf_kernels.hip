@@ -149,11 +149,9 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
             tail_table_hist(s, T, m, tid, NT);
             __syncthreads();
         }
-        tail_table_colsums(s, T, m, tid, NT);
+        tail_table_columns(s, T, m, tid, NT);
         __syncthreads();
         MF_STOP_AT(10)
-        tail_table_colapply(s, T, m, tid, NT);
-        __syncthreads();
         MF_STOP_AT(11)
         if (rowbuf) tail_table_rows_waves(s, T, m, tid & 63, tid >> 6, NT / 64, 64);
         else tail_table_rows(s, T, m, tid, NT);
@@ -600,7 +598,7 @@ __global__ void k_zero_counters(u32 *c, int n)
 // ------------------------------------------------------------------ global path
 
 struct GLayout {
-    int64_t xv, srt, srt2, M, pos, cnt, ctot, stage, total;
+    int64_t xv, srt, srt2, M, pos, cnt, stage, total;
 };
 // After the sort, the sorted keys take the xv region and the slots the
 // start of srt2 (the tables overwrite them only after the pair orders and
@@ -619,8 +617,6 @@ __host__ __device__ inline void make_glayout(const Shape &s, GLayout *g)
     g->total = off;
     int64_t a = g->srt2;
     g->cnt = a;    a += 2ll * s.Pmax * s.C * s.Wrow;
-    a = (a + 15) & ~15ll;
-    g->ctot = a;   a += 8ll * s.Pmax * col_dwords(s) * kColGroups;
     a = (a + 15) & ~15ll;
     g->stage = a;
 }
@@ -853,7 +849,6 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
         m.M = (u16 *)(base + g.M);
         m.pos = (u32 *)(base + g.pos);
         m.cnt = (u16 *)(base + g.cnt);
-        m.ctot = (u32 *)(base + g.ctot);
         m.stage = (u16 *)(base + g.stage);
         u64 *srt2 = (u64 *)(base + g.srt2);
         const Tile T = make_tile(s, tile);

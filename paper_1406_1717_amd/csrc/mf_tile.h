@@ -218,7 +218,6 @@ struct Layout {
     int32_t M;       // u16[Pmax * Mstride]
     int32_t pos;     // u32[Pmax * k]     posA | posB << 16
     int32_t cnt;     // u16[Pmax * C * Wrow]       (aliases skey, sslot)
-    int32_t ctot;    // u32[Pmax * kColGroups * 2 * ceil(Wn/2)] (aliases skey, sslot)
     int32_t bk;      // u32[cap] bucket counters, after mbuf (aliases M, pos)
     int32_t info;    // u32[2 * nbmax + 1]         (aliases M, pos)
     int32_t nbmax;   // blocks of a full tile
@@ -315,7 +314,7 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
     if (k <= kOneChunkMax) L = k;
     u32 C = (uk + (u32)L - 1u) / (u32)L;
     for (;;) {
-        const u32 need = (u32)P * (2u * C * (u32)s->Wrow + 4u * kColGroups * (((u32)s->Wn + 1u) & ~1u) + 2u * uk + 48u);
+        const u32 need = (u32)P * (2u * C * (u32)s->Wrow + 2u * uk + 48u);
         if (need <= 6u * (u32)s->cap || L >= k) break;
         L += 2;
         C = (uk + (u32)L - 1u) / (u32)L;
@@ -363,8 +362,6 @@ MF_HD void make_layout(const Shape &s, Layout *l)
     l->total = off;
     int32_t a = 0;
     l->cnt = a;      a += 2 * s.Pmax * s.C * s.Wrow;
-    a = (a + 15) & ~15;
-    l->ctot = a;     a += 8 * s.Pmax * col_dwords(s) * kColGroups;
     a = (a + 15) & ~15;
     l->stage = a;    a += 2 * s.Pmax * s.k;
     if (a > l->M) l->total = -1;   // aliased region overflows
@@ -418,7 +415,6 @@ struct TileMem {
     u16 *M;
     u32 *pos;
     u16 *cnt;
-    u32 *ctot;
     u16 *stage;
 };
 
@@ -436,7 +432,6 @@ MF_HD TileMem tile_mem(unsigned char *base, const Layout &l)
     m.M = (u16 *)(base + l.M);
     m.pos = (u32 *)(base + l.pos);
     m.cnt = (u16 *)(base + l.cnt);
-    m.ctot = (u32 *)(base + l.ctot);
     m.stage = (u16 *)(base + l.stage);
     return m;
 }
@@ -964,7 +959,7 @@ MF_HD u16 *cnt_row(const Shape &s, const TileMem &m, int32_t p, int32_t c)
 // add on the 32-bit word that holds it (the other cell's bytes never carry).
 MF_HD void cnt_add(const TileMem &m, int32_t e, u32 v)
 {
-    MF_ADD32((u32 *)m.cnt + (e >> 1), v << (16 * (e & 1)));
+    MF_ADD32((u32 *)((unsigned char *)m.cnt + 2 * (e & ~1)), v << (16 * (e & 1)));
 }
 
 
@@ -1049,14 +1044,15 @@ MF_HD void tile_to_block_values(const Shape &s, const Tile &T, int32_t tid, u64 
 // the wave first, so that one lane per wave updates the shared words).
 MF_HD void tile_minmax(const TileMem &m, const u64 (&v)[kRegs])
 {
+    // padding (kPadAll, never a real value: its slot field is past every
+    // slot) has the largest key, which leaves the minimum alone
     u32 mn = 0xFFFFFFFFu, mx = 0u;
 #pragma unroll
     for (int j = 0; j < kRegs; j++) {
-        if (sv_valid(v[j])) {
-            const u32 key = tv_key(v[j]);
-            mn = key < mn ? key : mn;
-            mx = key > mx ? key : mx;
-        }
+        const u32 key = tv_key(v[j]);
+        const u32 kx = v[j] == kPadAll ? 0u : key;
+        mn = key < mn ? key : mn;
+        mx = kx > mx ? kx : mx;
     }
 #if defined(__HIP_DEVICE_COMPILE__)
     mn = __ockl_wfred_min_u32(mn);
@@ -1420,59 +1416,15 @@ MF_HD void table_hist_row(const Shape &s, const Tile &T, const TileMem &m, int32
     }
 }
 
-// Column pass (two phases): entry (c, w) becomes the members of word w at
-// chunk start c, (A items with bucket >= c) + (B items with bucket < c).
-// A lane takes the two cells of one row dword (words 2d and 2d + 1) at
-// once: their A bytes and B bytes are summed as two 16-bit fields each
-// (column totals stay below 2^12, so the fields never carry).  Each
-// column's rows are cut into kColGroups groups of R = ceil(C / 8)
-// consecutive rows; an item is (pair p, dword d, group g).
+// Column pass: entry (c, w) becomes the members of word w at chunk start
+// c, (A items with bucket >= c) + (B items with bucket < c).  A lane takes
+// the two cells of one row dword (words 2d and 2d + 1) at once: their A
+// bytes and B bytes are summed as two 16-bit fields each (a column holds
+// at most 64 items, so the fields never carry).  Each column's rows are cut
+// into kColGroups groups of R = ceil(C / 8) consecutive rows
+// (tail_table_columns).
 
 MF_HD int32_t col_rows(const Shape &s) { return (s.C + kColGroups - 1) / kColGroups; }
-
-// Phase one: the group's A totals and B totals of both cells (16 bits per
-// cell) into ctot.
-MF_HD void table_colsum_item(const Shape &s, const TileMem &m, int32_t p, int32_t d, int32_t g)
-{
-    const int32_t stride = s.Wrow >> 1, R = col_rows(s), Wd = col_dwords(s);
-    const u32 *col = (const u32 *)cnt_row(s, m, p, 0) + d;
-    const int32_t c0 = g * R, c1 = (c0 + R < s.C) ? c0 + R : s.C;
-    u32 ta = 0u, tb = 0u;
-    for (int32_t c = c0; c < c1; c++) {
-        const u32 v = col[c * stride];
-        ta += v & 0x00FF00FFu;
-        tb += (v >> 8) & 0x00FF00FFu;
-    }
-    u32 *dst = m.ctot + 2 * ((p * kColGroups + g) * Wd + d);
-    dst[0] = ta;
-    dst[1] = tb;
-}
-
-// Phase two: A suffix sums and B exclusive prefix sums down the group,
-// starting from the totals of the other groups; both cells of the dword
-// are written as member counts.
-MF_HD void table_colapply_item(const Shape &s, const TileMem &m, int32_t p, int32_t d, int32_t g)
-{
-    const int32_t stride = s.Wrow >> 1, R = col_rows(s), Wd = col_dwords(s);
-    u32 *col = (u32 *)cnt_row(s, m, p, 0) + d;
-    const int32_t c0 = g * R, c1 = (c0 + R < s.C) ? c0 + R : s.C;
-    if (c0 >= c1) return;
-    const u32 *gt = m.ctot + 2 * (p * kColGroups * Wd + d);
-    u32 sa = 0u, pb = 0u;
-#pragma unroll
-    for (int q = 0; q < kColGroups; q++) {
-        sa += (q >= g) ? gt[2 * q * Wd] : 0u;        // A items of this and later groups
-        pb += (q < g) ? gt[2 * q * Wd + 1] : 0u;     // B items of earlier groups
-    }
-    // one pass down the group: the A suffix at row c is the A count from
-    // row c on, i.e. sa minus the A items of the group's earlier rows
-    for (int32_t c = c0; c < c1; c++) {
-        const u32 v = col[c * stride];
-        col[c * stride] = sa + pb;
-        sa -= v & 0x00FF00FFu;
-        pb += (v >> 8) & 0x00FF00FFu;
-    }
-}
 
 // Item = (pair p, chunk c): exclusive prefix over the words, sixteen cells
 // (eight dwords, read before any is written) at a time.
@@ -1737,8 +1689,11 @@ MF_HD void tail_first_medians(const Shape &s, const Tile &T, const TileMem &m, i
 
 MF_HD void tail_table_zero(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
 {
+    // 16-byte stores (the tables start 16-byte aligned), then the last words
     const int32_t nwords = T.P * s.C * s.Wrow / 2;
-    for (int32_t it = tid; it < nwords; it += NT) table_zero_item(m, it);
+    const uint4 z = {0u, 0u, 0u, 0u};
+    for (int32_t it = tid; it < (nwords >> 2); it += NT) ((uint4 *)m.cnt)[it] = z;
+    for (int32_t it = (nwords & ~3) + tid; it < nwords; it += NT) table_zero_item(m, it);
 }
 
 MF_HD void tail_table_hist(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
@@ -1783,27 +1738,62 @@ MF_HD void tail_table_hist_rows(const Shape &s, const Tile &T, const TileMem &m,
     }
 }
 
-MF_HD void tail_table_colsums(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
+// The column pass as one phase: item = (pair p, row dword d, group g) with
+// the kColGroups groups of a column on consecutive items, it = (p * Wd + d)
+// * kColGroups + g, so that on the GPU they are neighbouring lanes of one
+// wave.  Each lane sums its group's rows (A and B bytes of both cells), the
+// lanes of a column exchange their totals (the A items of groups g.. and
+// the B items of groups ..g-1) and each lane then writes its rows' member
+// counts.  The host check, which runs one item at a time, handles a whole
+// column at its group 0.
+MF_HD void tail_table_columns(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
 {
-    // consecutive items take consecutive dwords of one row group
-    const int32_t Wd = col_dwords(s);
+    const int32_t stride = s.Wrow >> 1, R = col_rows(s), Wd = col_dwords(s);
     const u32 Wr = recip32(Wd);
-    for (int32_t it = tid; it < T.P * Wd * kColGroups; it += NT) {
-        const int32_t pg = (int32_t)udiv16((u32)it, Wr), d = it - pg * Wd;
-        const int32_t p = pg / kColGroups, g = pg % kColGroups;
-        table_colsum_item(s, m, p, d, g);
-    }
-}
-
-MF_HD void tail_table_colapply(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT)
-{
-    // consecutive items take consecutive dwords of one row group
-    const int32_t Wd = col_dwords(s);
-    const u32 Wr = recip32(Wd);
-    for (int32_t it = tid; it < T.P * Wd * kColGroups; it += NT) {
-        const int32_t pg = (int32_t)udiv16((u32)it, Wr), d = it - pg * Wd;
-        const int32_t p = pg / kColGroups, g = pg % kColGroups;
-        table_colapply_item(s, m, p, d, g);
+    const int32_t total = T.P * Wd * kColGroups;
+    for (int32_t it = tid; it < total; it += NT) {
+        const int32_t g = it & (kColGroups - 1), pd = it / kColGroups;
+        const int32_t p = (int32_t)udiv16((u32)pd, Wr), d = pd - p * Wd;
+        u32 *col = (u32 *)cnt_row(s, m, p, 0) + d;
+#if defined(__HIP_DEVICE_COMPILE__)
+        const int32_t c0 = g * R, c1 = (c0 + R < s.C) ? c0 + R : s.C;
+        u32 ta = 0u, tb = 0u;
+        for (int32_t c = c0; c < c1; c++) {
+            const u32 v = col[c * stride];
+            ta += v & 0x00FF00FFu;
+            tb += (v >> 8) & 0x00FF00FFu;
+        }
+        // inclusive prefix of the totals over the column's groups
+        u32 ia = ta, ib = tb;
+#pragma unroll
+        for (int o = 1; o < kColGroups; o <<= 1) {
+            const u32 ya = (u32)__shfl_up((int)ia, (unsigned)o, kColGroups);
+            const u32 yb = (u32)__shfl_up((int)ib, (unsigned)o, kColGroups);
+            if (g >= o) {
+                ia += ya;
+                ib += yb;
+            }
+        }
+        const u32 all_a = (u32)__shfl((int)ia, kColGroups - 1, kColGroups);
+        u32 sa = all_a - (ia - ta);   // A items of this and later groups
+        u32 pb = ib - tb;             // B items of earlier groups
+        for (int32_t c = c0; c < c1; c++) {
+            const u32 v = col[c * stride];
+            col[c * stride] = sa + pb;
+            sa -= v & 0x00FF00FFu;
+            pb += (v >> 8) & 0x00FF00FFu;
+        }
+#else
+        if (g != 0) continue;
+        u32 sa = 0u, pb = 0u;
+        for (int32_t c = 0; c < s.C; c++) sa += col[c * stride] & 0x00FF00FFu;
+        for (int32_t c = 0; c < s.C; c++) {
+            const u32 v = col[c * stride];
+            col[c * stride] = sa + pb;
+            sa -= v & 0x00FF00FFu;
+            pb += (v >> 8) & 0x00FF00FFu;
+        }
+#endif
     }
 }
 

@@ -258,8 +258,7 @@ static int run_tile(const Shape &s, const Layout &l, int64_t t, int threads,
             for (int q = 0; q < threads; q++) tail_table_zero(s, T, m, q, threads);
             for (int q = 0; q < threads; q++) tail_table_hist(s, T, m, q, threads);
         }
-        for (int q = 0; q < threads; q++) tail_table_colsums(s, T, m, q, threads);
-        for (int q = 0; q < threads; q++) tail_table_colapply(s, T, m, q, threads);
+        for (int q = 0; q < threads; q++) tail_table_columns(s, T, m, q, threads);
         for (int q = 0; q < threads; q++) tail_table_rows(s, T, m, q, threads);
     }
     for (int q = 0; q < threads; q++)
