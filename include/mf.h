@@ -32,7 +32,8 @@
  *   with MF_ERR_NOMEM (a test switch); MF_LEASE_HOLD_US=<us> keeps each
  *   workspace lease that long before enqueueing (a test switch for
  *   concurrent callers); MF_LOG=1 prints plan and autotune decisions on
- *   stderr.
+ *   stderr; MF_TUNE_CACHE=<path> is the tile-shape cache of
+ *   mf_plan_autotune (read by new plans).
  */
 #ifndef MF_H
 #define MF_H
@@ -212,10 +213,18 @@ typedef enum {
                                      all as 1024-thread tiles */
 } mf_launch_config;
 
-/* Times every launch configuration on these buffers (`reps` timed executes
- * each, 1..100, after one warm-up, with the float kernels; the choice holds
- * for int32 executes too) and keeps the fastest for later executes.  Writes y and argmed (the batch's outputs, as mf_plan_execute),
- * and synchronizes `stream`; MF_ERR_UNSUPPORTED while `stream` is being
+/* Tunes the plan on these buffers, with the float kernels (the choices hold
+ * for int32 executes too), in two steps:
+ * 1. Tile shapes: the windows of each slot-stride bucket (2^b >= k, up to
+ *    2048) that fit 512-thread tiles are timed as 512- and as 1024-thread
+ *    tiles (`reps` launches each, 1..100, after a warm-up) and run with the
+ *    faster from then on.  With MF_TUNE_CACHE=<path> set, the choices are
+ *    merged into that JSON file, {"tile_threads": {"f32": {"<stride>":
+ *    512 or 1024, ...}}}, which later plans read when they are created.
+ * 2. Launch configurations: every configuration is timed (`reps` executes
+ *    after one warm-up) and the fastest kept for later executes.
+ * Writes y and argmed (the batch's outputs, as mf_plan_execute) and
+ * synchronizes `stream`; MF_ERR_UNSUPPORTED while `stream` is being
  * captured.  On failure the configuration is left as it was. */
 mf_status mf_plan_autotune(mf_plan *plan, const float *x, float *y, int32_t *argmed,
                            int32_t reps, void *stream);
@@ -225,6 +234,10 @@ mf_status mf_plan_set_config(mf_plan *plan, int32_t config);
  * per execute of each configuration from the last mf_plan_autotune, in
  * milliseconds, -1 where not timed: tuned_ms has 3 entries. */
 mf_status mf_plan_get_config(const mf_plan *plan, int32_t *config, float *tuned_ms);
+/* Threads per tile (512 or 1024) that the plan's per-family and persistent
+ * configurations use for window k; 0 for windows above 4096 and k = 1 (not
+ * LDS tiles).  MF_ERR_INVALID_VALUE for an even or unsupported k. */
+mf_status mf_plan_get_tile_threads(const mf_plan *plan, int32_t k, int32_t *threads);
 
 /* n-k+1 for a valid (n, k), else -1.  Host only. */
 int64_t mf_output_length(int64_t n, int32_t k);

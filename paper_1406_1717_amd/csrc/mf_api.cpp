@@ -10,6 +10,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <initializer_list>
+#include <utility>
 #include <chrono>
 #include <thread>
 #include <memory>
@@ -340,11 +342,17 @@ struct PathGroup {
 const int kConfigs = 3;              // mf_launch_config values
 const int kDefaultConfig = MF_LAUNCH_PERSISTENT;
 
+// Tile shape buckets: windows whose slot stride is 2^b (b < kShapeBuckets)
+// may run as 512- or 1024-thread tiles.
+const int kShapeBuckets = 12;   // slot strides 1 .. 2048
+
 struct mf_plan {
     int32_t num_signals = 0;
     int64_t total_in = 0, total_out = 0;
     std::vector<int64_t> offsets;
     std::vector<int32_t> ks;
+    std::vector<SigDesc> sigs;                 // host copy of d_sigs
+    int32_t bucket_threads[kShapeBuckets];     // 512 or 1024 per bucket
     SigDesc *d_sigs = nullptr;
     std::vector<PathGroup> groups[kConfigs];   // forward launches per configuration
     int32_t config = kDefaultConfig;
@@ -369,6 +377,16 @@ struct mf_plan {
     hipEvent_t done = nullptr;     // completion of the last execution
 };
 
+static void plan_free_groups(mf_plan *p)
+{
+    for (auto &gs : p->groups) {
+        for (auto &g : gs)
+            if (g.owns && g.d_units) (void)hipFree(g.d_units);
+        gs.clear();
+    }
+    p->ws_need = 0;
+}
+
 static void plan_free(mf_plan *p)
 {
     if (!p) return;
@@ -377,13 +395,26 @@ static void plan_free(mf_plan *p)
         (void)hipEventDestroy(p->done);
     }
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
-    for (auto &gs : p->groups)
-        for (auto &g : gs)
-            if (g.owns && g.d_units) (void)hipFree(g.d_units);
+    plan_free_groups(p);
     if (p->d_sigs) (void)hipFree(p->d_sigs);
     if (p->d_next) (void)hipFree(p->d_next);
     if (p->d_bunits) (void)hipFree(p->d_bunits);
     delete p;
+}
+
+static int shape_bucket(int32_t k)
+{
+    int b = 0;
+    while ((1 << b) < k) b++;
+    return b;
+}
+
+// The LDS family a window runs in under the plan's tile shapes.
+static Path plan_family(const mf_plan *p, int32_t k)
+{
+    const Path f = path_for(k);
+    if (f == PATH_LDS_SMALL && p->bucket_threads[shape_bucket(k)] == kLdsLarge) return PATH_LDS_LARGE;
+    return f;
 }
 
 // Uploads a work list as a new group of configuration `cfg`.
@@ -407,6 +438,146 @@ static mf_status plan_add_group(mf_plan *p, int cfg, Path f, bool persistent, co
     }
     if (f == PATH_GLOBAL) p->ws_need = std::max(p->ws_need, ws_stride * std::min<int64_t>(global_ws_slots(lds), g.nunits));
     p->groups[cfg].push_back(g);
+    return MF_OK;
+}
+
+// ------------------------------------------------------------------ tile shape cache
+//
+// MF_TUNE_CACHE=<path>: a JSON file of tuned tile shapes, read when a plan
+// is created and updated by mf_plan_autotune:
+//   {"tile_threads": {"f32": {"<slot stride>": 512 or 1024, ...}}}
+// (tuned on float32 signals; plans use it for every element type).
+
+static const char *env_tune_cache()
+{
+    const char *e = getenv("MF_TUNE_CACHE");
+    return (e && e[0]) ? e : nullptr;
+}
+
+// Entries "<stride>": <threads> of the "f32" object in the cache file.
+static std::vector<std::pair<int64_t, int64_t>> tune_cache_read(const char *path)
+{
+    std::vector<std::pair<int64_t, int64_t>> out;
+    FILE *f = fopen(path, "rb");
+    if (!f) return out;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    fclose(f);
+    const size_t at = text.find("\"f32\"");
+    if (at == std::string::npos) return out;
+    const size_t open = text.find('{', at), close = text.find('}', at);
+    if (open == std::string::npos || close == std::string::npos || close < open) return out;
+    size_t i = open + 1;
+    while (i < close) {
+        const size_t q1 = text.find('"', i);
+        if (q1 == std::string::npos || q1 >= close) break;
+        const size_t q2 = text.find('"', q1 + 1);
+        const size_t colon = text.find(':', q2);
+        if (q2 == std::string::npos || colon == std::string::npos || colon >= close) break;
+        const int64_t key = atoll(text.c_str() + q1 + 1);
+        const int64_t val = atoll(text.c_str() + colon + 1);
+        out.emplace_back(key, val);
+        i = colon + 1;
+    }
+    return out;
+}
+
+static void tune_cache_apply(mf_plan *p)
+{
+    const char *path = env_tune_cache();
+    if (!path) return;
+    for (const auto &kv : tune_cache_read(path)) {
+        int b = 0;
+        while (b < kShapeBuckets && (1ll << b) != kv.first) b++;
+        if (b < kShapeBuckets && (kv.second == kLdsSmall || kv.second == kLdsLarge))
+            p->bucket_threads[b] = (int32_t)kv.second;
+    }
+}
+
+// Merges the plan's tuned buckets into the cache file (written whole, then
+// renamed over the old one).
+static void tune_cache_write(const mf_plan *p, const bool (&tuned)[kShapeBuckets])
+{
+    const char *path = env_tune_cache();
+    if (!path) return;
+    int64_t threads[kShapeBuckets] = {0};
+    for (const auto &kv : tune_cache_read(path))
+        for (int b = 0; b < kShapeBuckets; b++)
+            if ((1ll << b) == kv.first) threads[b] = kv.second;
+    for (int b = 0; b < kShapeBuckets; b++)
+        if (tuned[b]) threads[b] = p->bucket_threads[b];
+    std::string text = "{\"tile_threads\": {\"f32\": {";
+    bool first = true;
+    for (int b = 0; b < kShapeBuckets; b++) {
+        if (threads[b] != kLdsSmall && threads[b] != kLdsLarge) continue;
+        char item[64];
+        snprintf(item, sizeof item, "%s\"%lld\": %lld", first ? "" : ", ", 1ll << b, (long long)threads[b]);
+        text += item;
+        first = false;
+    }
+    text += "}}}\n";
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "wb");
+    if (!f) return;
+    const bool ok = fwrite(text.data(), 1, text.size(), f) == text.size();
+    if (fclose(f) == 0 && ok) (void)rename(tmp.c_str(), path);
+}
+
+// Forward work lists of every launch configuration, from the plan's
+// signals and tile shapes.  One list per kernel family; within a family the
+// longest windows go first so that the heaviest tiles start early.
+// MF_LAUNCH_PER_FAMILY and MF_LAUNCH_PERSISTENT share these lists (windows
+// of a shape bucket tuned to 1024 threads join the 1024-thread family);
+// MF_LAUNCH_PERSISTENT_ONE puts every LDS tile into one list of 1024-thread
+// tiles, launched first.
+static mf_status plan_build_groups(mf_plan *p)
+{
+    plan_free_groups(p);
+    const int32_t num_signals = p->num_signals;
+    const int32_t *ks = p->ks.data();
+    const std::vector<SigDesc> &sigs = p->sigs;
+    const Path fams[4] = {PATH_LDS_LARGE, PATH_LDS_SMALL, PATH_GLOBAL, PATH_IDENTITY};
+    std::vector<int32_t> order((size_t)num_signals);
+    for (int32_t s = 0; s < num_signals; s++) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ks[a] > ks[b]; });
+    mf_status st = MF_OK;
+    {
+        std::vector<Unit> units;
+        size_t lds = 0;
+        for (int32_t s : order) {
+            const Path f = path_for(ks[s]);
+            if (f != PATH_LDS_SMALL && f != PATH_LDS_LARGE) continue;
+            const int64_t nt = tiles_for(PATH_LDS_LARGE, sigs[s].n, ks[s]);
+            for (int64_t t = 0; t < nt; t++) units.push_back(Unit{s, 0, t});
+            lds = std::max(lds, (size_t)lds_bytes_for(PATH_LDS_LARGE, ks[s]));
+        }
+        if (!units.empty() && (st = plan_add_group(p, MF_LAUNCH_PERSISTENT_ONE, PATH_LDS_LARGE, true, units, lds, 0)) != MF_OK)
+            return st;
+    }
+    for (Path f : fams) {
+        std::vector<Unit> units;
+        size_t lds = 0;
+        int64_t ws_stride = 0;
+        for (int32_t s : order) {
+            if (plan_family(p, ks[s]) != f) continue;
+            const int64_t nt = tiles_for(f, sigs[s].n, ks[s]);
+            for (int64_t t = 0; t < nt; t++) units.push_back(Unit{s, 0, t});
+            lds = std::max(lds, (size_t)lds_bytes_for(f, ks[s]));
+            if (f == PATH_GLOBAL) ws_stride = std::max(ws_stride, global_ws_stride(ks[s]));
+        }
+        if (units.empty()) continue;
+        if ((st = plan_add_group(p, MF_LAUNCH_PER_FAMILY, f, false, units, lds, ws_stride)) != MF_OK) return st;
+        PathGroup shared = p->groups[MF_LAUNCH_PER_FAMILY].back();
+        shared.owns = false;
+        shared.persistent = (f == PATH_LDS_SMALL || f == PATH_LDS_LARGE);
+        p->groups[MF_LAUNCH_PERSISTENT].push_back(shared);
+        if (f == PATH_GLOBAL || f == PATH_IDENTITY) {
+            shared.persistent = false;
+            p->groups[MF_LAUNCH_PERSISTENT_ONE].push_back(shared);
+        }
+    }
     return MF_OK;
 }
 
@@ -448,53 +619,10 @@ extern "C" mf_status mf_plan_create_batched(const int64_t *x_offsets, const int3
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
     if (e != hipSuccess) { plan_free(p); return hip_fail(e, "plan signal table"); }
 
-    // forward work lists, one per kernel family; within a family the
-    // longest windows go first so that the heaviest tiles start early.
-    // MF_LAUNCH_PER_FAMILY and MF_LAUNCH_PERSISTENT share these lists;
-    // MF_LAUNCH_PERSISTENT_ONE puts every LDS tile into one list of
-    // 1024-thread tiles, launched first.
-    const Path fams[4] = {PATH_LDS_LARGE, PATH_LDS_SMALL, PATH_GLOBAL, PATH_IDENTITY};
-    std::vector<int32_t> order((size_t)num_signals);
-    for (int32_t s = 0; s < num_signals; s++) order[s] = s;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ks[a] > ks[b]; });
-    {
-        std::vector<Unit> units;
-        size_t lds = 0;
-        for (int32_t s : order) {
-            const Path f = path_for(ks[s]);
-            if (f != PATH_LDS_SMALL && f != PATH_LDS_LARGE) continue;
-            const int64_t nt = tiles_for(PATH_LDS_LARGE, sigs[s].n, ks[s]);
-            for (int64_t t = 0; t < nt; t++) units.push_back(Unit{s, 0, t});
-            lds = std::max(lds, (size_t)lds_bytes_for(PATH_LDS_LARGE, ks[s]));
-        }
-        if (!units.empty()) {
-            st = plan_add_group(p, MF_LAUNCH_PERSISTENT_ONE, PATH_LDS_LARGE, true, units, lds, 0);
-            if (st != MF_OK) { plan_free(p); return st; }
-        }
-    }
-    for (Path f : fams) {
-        std::vector<Unit> units;
-        size_t lds = 0;
-        int64_t ws_stride = 0;
-        for (int32_t s : order) {
-            if (path_for(ks[s]) != f) continue;
-            const int64_t nt = tiles_for(f, sigs[s].n, ks[s]);
-            for (int64_t t = 0; t < nt; t++) units.push_back(Unit{s, 0, t});
-            lds = std::max(lds, (size_t)lds_bytes_for(f, ks[s]));
-            if (f == PATH_GLOBAL) ws_stride = std::max(ws_stride, global_ws_stride(ks[s]));
-        }
-        if (units.empty()) continue;
-        st = plan_add_group(p, MF_LAUNCH_PER_FAMILY, f, false, units, lds, ws_stride);
-        if (st != MF_OK) { plan_free(p); return st; }
-        PathGroup shared = p->groups[MF_LAUNCH_PER_FAMILY].back();
-        shared.owns = false;
-        shared.persistent = (f == PATH_LDS_SMALL || f == PATH_LDS_LARGE);
-        p->groups[MF_LAUNCH_PERSISTENT].push_back(shared);
-        if (f == PATH_GLOBAL || f == PATH_IDENTITY) {
-            shared.persistent = false;
-            p->groups[MF_LAUNCH_PERSISTENT_ONE].push_back(shared);
-        }
-    }
+    for (int b = 0; b < kShapeBuckets; b++) p->bucket_threads[b] = kLdsSmall;
+    tune_cache_apply(p);
+    p->sigs = sigs;
+    if ((st = plan_build_groups(p)) != MF_OK) { plan_free(p); return st; }
     // backward work list
     {
         std::vector<Unit> bunits;
@@ -699,12 +827,92 @@ extern "C" mf_status mf_plan_set_config(mf_plan *p, int32_t config)
     return MF_OK;
 }
 
+extern "C" mf_status mf_plan_get_tile_threads(const mf_plan *p, int32_t k, int32_t *threads)
+{
+    if (!p || !threads) return fail(MF_ERR_INVALID_VALUE, "plan and threads must not be null");
+    if (k < 1 || (k & 1) == 0 || path_for(k) == PATH_NONE)
+        return fail(MF_ERR_INVALID_VALUE, "k = %d is not a supported window", k);
+    const Path f = plan_family(p, k);
+    *threads = f == PATH_LDS_SMALL ? kLdsSmall : f == PATH_LDS_LARGE ? kLdsLarge : 0;
+    return MF_OK;
+}
+
 extern "C" mf_status mf_plan_get_config(const mf_plan *p, int32_t *config, float *tuned_ms)
 {
     if (!p || !config) return fail(MF_ERR_INVALID_VALUE, "plan and config must not be null");
     *config = p->config;
     if (tuned_ms)
         for (int c = 0; c < kConfigs; c++) tuned_ms[c] = p->tuned_ms[c];
+    return MF_OK;
+}
+
+// Tile shapes: for every shape bucket of windows that fit 512-thread
+// tiles, the bucket's signals are timed as 512- and as 1024-thread tiles on
+// the caller's buffers (one launch each, after a warm-up), and the faster
+// shape is kept; the plan's work lists are then rebuilt and the cache file
+// (MF_TUNE_CACHE) updated.  The caller holds p->mu.
+static mf_status tune_shapes(mf_plan *p, const float *x, float *y, int32_t *argmed, int32_t reps, hipStream_t st,
+                             hipEvent_t a, hipEvent_t b)
+{
+    Device *D = nullptr;
+    mf_status s = device_state(&D);
+    if (s != MF_OK) return s;
+    // the captured graph and the work lists of an earlier execution go
+    MF_HIP(hipEventSynchronize(p->done), "hipEventSynchronize(plan)");
+    if (p->gexec) {
+        (void)hipGraphExecDestroy(p->gexec);
+        p->gexec = nullptr;
+    }
+    bool tuned[kShapeBuckets] = {false};
+    for (int bk = 0; bk < kShapeBuckets; bk++) {
+        float best_ms = -1.f;
+        int32_t best_nt = p->bucket_threads[bk];
+        for (int32_t nt : {kLdsSmall, kLdsLarge}) {
+            const Path f = nt == kLdsSmall ? PATH_LDS_SMALL : PATH_LDS_LARGE;
+            std::vector<Unit> units;
+            size_t lds = 0;
+            for (int32_t q = 0; q < p->num_signals; q++) {
+                const int32_t k = p->ks[q];
+                if (path_for(k) != PATH_LDS_SMALL || shape_bucket(k) != bk) continue;
+                const int64_t tiles = tiles_for(f, p->sigs[q].n, k);
+                for (int64_t t = 0; t < tiles; t++) units.push_back(Unit{q, 0, t});
+                lds = std::max(lds, (size_t)lds_bytes_for(f, k));
+            }
+            if (units.empty()) break;
+            Unit *du = nullptr;
+            MF_HIP(hipMalloc(&du, sizeof(Unit) * units.size()), "hipMalloc(tuning work list)");
+            hipError_t e = hipMemcpy(du, units.data(), sizeof(Unit) * units.size(), hipMemcpyHostToDevice);
+            Launch L;
+            memset(&L, 0, sizeof L);
+            L.x = x;
+            L.y = y;
+            L.argmed = argmed;
+            L.sigs = p->d_sigs;
+            L.units = du;
+            L.nunits = (int64_t)units.size();
+            if (e == hipSuccess) e = launch_forward(f, true, L, lds, nullptr, 0, 0, D->d_err, st);
+            if (e == hipSuccess) e = hipEventRecord(a, st);
+            for (int r = 0; r < reps && e == hipSuccess; r++) e = launch_forward(f, true, L, lds, nullptr, 0, 0, D->d_err, st);
+            if (e == hipSuccess) e = hipEventRecord(b, st);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            const hipError_t ef = hipFree(du);
+            if (e != hipSuccess) return hip_fail(e, "tile shape tuning");
+            if (ef != hipSuccess) return hip_fail(ef, "hipFree(tuning work list)");
+            if (best_ms < 0.f || ms < best_ms) {
+                best_ms = ms;
+                best_nt = nt;
+            }
+            tuned[bk] = true;
+        }
+        if (tuned[bk]) {
+            p->bucket_threads[bk] = best_nt;
+            if (env_log()) fprintf(stderr, "mf: autotune slot stride %d: %d-thread tiles\n", 1 << bk, best_nt);
+        }
+    }
+    if ((s = plan_build_groups(p)) != MF_OK) return s;
+    tune_cache_write(p, tuned);
     return MF_OK;
 }
 
@@ -726,8 +934,13 @@ extern "C" mf_status mf_plan_autotune(mf_plan *p, const float *x, float *y, int3
         return hip_fail(e, "hipEventCreate");
     }
     std::lock_guard<std::mutex> plk(p->mu);
+    mf_status s = tune_shapes(p, x, y, argmed, reps, st, a, b);
+    if (s != MF_OK) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return s;
+    }
     const int32_t before = p->config;
-    mf_status s = MF_OK;
     int best = -1;
     for (int c = 0; c < kConfigs && s == MF_OK; c++) {
         p->config = c;

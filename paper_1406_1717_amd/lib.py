@@ -60,6 +60,7 @@ def load():
         "mf_plan_autotune": [P, P, P, P, I32, P],
         "mf_plan_set_config": [P, I32],
         "mf_plan_get_config": [P, P, P],
+        "mf_plan_get_tile_threads": [P, I32, P],
         "mf_check_device_error": [P],
     }
     for name, args in sig.items():
@@ -289,6 +290,13 @@ class Plan:
 
     def set_config(self, config):
         _check(load().mf_plan_set_config(self._h, int(config)))
+
+    def tile_threads(self, k):
+        """Threads per tile used for window k (512 or 1024; 0 when k is not
+        served by LDS tiles)."""
+        t = ctypes.c_int32()
+        _check(load().mf_plan_get_tile_threads(self._h, int(k), ctypes.byref(t)))
+        return int(t.value)
 
     def config_info(self):
         c = ctypes.c_int32()

@@ -172,3 +172,49 @@ def test_batched_int32_and_plan():
         torch.cuda.synchronize()
         assert torch.equal(am2, am) and torch.equal(y2, y), config
     plan.close()
+
+
+def test_autotune_tile_shapes_and_cache(tmp_path, monkeypatch):
+    """The autotuner picks 512- or 1024-thread tiles per slot-stride bucket,
+    keeps the outputs bit-exact, writes its choices to the MF_TUNE_CACHE file,
+    and a new plan of the same windows starts from those choices."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("MF_TUNE_CACHE", str(cache))
+    rng = np.random.default_rng(21)
+    ks = [3, 5, 31, 33, 101, 255, 301, 1001, 2047, 3001, 5001, 1]
+    lens = [int(rng.integers(k, 30 * k + 500)) for k in ks]
+    off = np.zeros(len(ks) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lens)
+    ks = np.array(ks, np.int32)
+    x = rng.standard_normal(int(off[-1])).astype(np.float32)
+    xt = torch.from_numpy(x).to(DEV)
+    plan = mf.Plan(off, ks)
+    y = torch.empty(plan.output_length, device=DEV)
+    am = torch.empty(plan.output_length, dtype=torch.int32, device=DEV)
+    plan.autotune(xt, y, am, reps=2)
+    torch.cuda.synchronize()
+    check_batch(x, off, ks, y.cpu().numpy(), am.cpu().numpy())
+    chosen = {int(k): plan.tile_threads(int(k)) for k in ks}
+    for k, t in chosen.items():
+        if k == 1 or k > 4096:
+            assert t == 0, k
+        elif k > 2047:
+            assert t == 1024, k
+        else:
+            assert t in (512, 1024), k
+    import json
+    data = json.loads(cache.read_text())
+    table = data["tile_threads"]["f32"]
+    for k, t in chosen.items():
+        if 1 < k <= 2047:
+            stride = 1 << int(np.ceil(np.log2(k)))
+            assert table[str(stride)] == t, (k, table)
+    y2 = torch.full_like(y, -1.0)
+    am2 = torch.full_like(am, -1)
+    plan.execute(xt, y2, am2)
+    torch.cuda.synchronize()
+    assert torch.equal(am2, am) and torch.equal(y2.view(torch.int32), y.view(torch.int32))
+    plan.close()
+    fresh = mf.Plan(off, ks)
+    assert {int(k): fresh.tile_threads(int(k)) for k in ks} == chosen
+    fresh.close()
