@@ -318,8 +318,9 @@ mf_status backward_rows(const void *gy, const int32_t *argmed, int64_t rows, int
     L.one.n = n;
     L.one.k = k;
     L.rows = rows;
-    L.tpr = bwd_tiles_for(n);
+    L.tpr = bwd_tiles_for(n, k, f64);
     L.nunits = rows * L.tpr;
+    L.seg = bwd_seg_for(k, f64) ? 1 : 0;
     MF_HIP(launch_backward(L, f64, st), "backward launch");
     return MF_OK;
 }
@@ -359,8 +360,10 @@ struct mf_plan {
     float tuned_ms[kConfigs] = {-1.f, -1.f, -1.f};
     uint32_t *d_next = nullptr;                // work counters, one per group
     // backward work list
-    Unit *d_bunits = nullptr;
-    int64_t nbunits = 0;
+    // backward work lists (float32 gradients): [0] signals of the
+    // exact-accumulation backward, [1] the others
+    Unit *d_bunits[2] = {nullptr, nullptr};
+    int64_t nbunits[2] = {0, 0};
     // captured forward graph and what it was captured with
     hipGraphExec_t gexec = nullptr;
     const void *gx = nullptr;
@@ -398,7 +401,8 @@ static void plan_free(mf_plan *p)
     plan_free_groups(p);
     if (p->d_sigs) (void)hipFree(p->d_sigs);
     if (p->d_next) (void)hipFree(p->d_next);
-    if (p->d_bunits) (void)hipFree(p->d_bunits);
+    for (int i = 0; i < 2; i++)
+        if (p->d_bunits[i]) (void)hipFree(p->d_bunits[i]);
     delete p;
 }
 
@@ -625,14 +629,20 @@ extern "C" mf_status mf_plan_create_batched(const int64_t *x_offsets, const int3
     if ((st = plan_build_groups(p)) != MF_OK) { plan_free(p); return st; }
     // backward work list
     {
-        std::vector<Unit> bunits;
+        std::vector<Unit> bunits[2];
         for (int32_t s = 0; s < num_signals; s++) {
-            const int64_t nt = bwd_tiles_for(sigs[s].n);
-            for (int64_t t = 0; t < nt; t++) bunits.push_back(Unit{s, 0, t});
+            const int32_t k = sigs[s].k;
+            const int list = bwd_seg_for(k, false) ? 0 : 1;
+            const int64_t nt = bwd_tiles_for(sigs[s].n, k, false);
+            for (int64_t t = 0; t < nt; t++) bunits[list].push_back(Unit{s, 0, t});
         }
-        p->nbunits = (int64_t)bunits.size();
-        e = hipMalloc(&p->d_bunits, sizeof(Unit) * bunits.size());
-        if (e == hipSuccess) e = hipMemcpy(p->d_bunits, bunits.data(), sizeof(Unit) * bunits.size(), hipMemcpyHostToDevice);
+        for (int i = 0; i < 2 && e == hipSuccess; i++) {
+            p->nbunits[i] = (int64_t)bunits[i].size();
+            if (bunits[i].empty()) continue;
+            e = hipMalloc(&p->d_bunits[i], sizeof(Unit) * bunits[i].size());
+            if (e == hipSuccess)
+                e = hipMemcpy(p->d_bunits[i], bunits[i].data(), sizeof(Unit) * bunits[i].size(), hipMemcpyHostToDevice);
+        }
         if (e != hipSuccess) { plan_free(p); return hip_fail(e, "plan backward work list"); }
     }
     if (env_log()) {
@@ -807,10 +817,14 @@ extern "C" mf_status mf_plan_execute_backward(mf_plan *p, const float *grad_y, c
     L.argmed = argmed;
     L.grad_x = grad_x;
     L.sigs = p->d_sigs;
-    L.units = p->d_bunits;
-    L.nunits = p->nbunits;
     std::lock_guard<std::mutex> plk(p->mu);
-    MF_HIP(launch_backward(L, false, (hipStream_t)stream), "batched backward launch");
+    for (int i = 0; i < 2; i++) {
+        if (p->nbunits[i] == 0) continue;
+        L.units = p->d_bunits[i];
+        L.nunits = p->nbunits[i];
+        L.seg = i == 0 ? 1 : 0;
+        MF_HIP(launch_backward(L, false, (hipStream_t)stream), "batched backward launch");
+    }
     MF_HIP(hipEventRecord(p->done, (hipStream_t)stream), "hipEventRecord(plan)");
     return MF_OK;
 }

@@ -1158,6 +1158,153 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(BwdLaunch L)
     }
 }
 
+// The same sums for float32 gradients and windows up to kBwdSegMaxK, by
+// exact accumulation.  Every term g is a multiple of 2^lsb(g), lsb(g) =
+// e - 150 for biased exponent e (subnormals count as e = 1).  When a
+// target's terms satisfy sum |g| < 2^(min lsb + 52), every partial sum of
+// them, in any order, is an integer multiple of 2^(min lsb) below 2^52 of
+// them, so float64 holds it exactly: the sum in increasing o never rounds
+// and equals the exact sum, which any order of float64 additions
+// reproduces, LDS float64 atomics included.
+// Each wave owns kBwdSegTargetsPerWave consecutive targets [j0, j0 + TJ)
+// and reads the outputs that can select them, o in [j0 - k + 1, j0 + TJ),
+// kBwdInflight batches of 64 at a time (a group's loads issued before its
+// first atomic).  A target has at most k terms, each below 2^(emax - 126),
+// so a tile whose terms have exponents in [emin, emax] with
+// ceil(log2 k) + emax - emin <= 28 is exact for every target (the usual
+// case): one atomic per term.  A tile outside that (huge spreads of
+// magnitude, infinities, NaN) is redone target by target in the same 8
+// bytes per target: first each target's magnitude sum (float32, whose
+// relative error over at most 2^11 terms stays below 2^-13, so the test
+// asks for half the bound) and least exponent, which give each lane its
+// targets' verdicts; then the float64 sums again; a target outside the
+// bound is summed again in increasing o from the inputs.
+__device__ __forceinline__ u32 bwd_exp(float g)
+{
+    const u32 e = (__float_as_uint(g) >> 23) & 0xFFu;
+    return e > 0u ? e : 1u;
+}
+
+__global__ __launch_bounds__(kBwdThreads) void k_backward_exact(BwdLaunch L)
+{
+    constexpr int TJ = kBwdSegTargetsPerWave;
+    constexpr int B = kBwdInflight;
+    constexpr int PER = TJ / 64;   // targets per lane: t = lane + 64 i
+    // per target: the float64 sum, or (slow tiles, first) the float32
+    // magnitude sum and the least biased exponent
+    __shared__ double acc_s[kBwdThreads / 64][TJ];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    double *acc = acc_s[wave];
+    float *mag = (float *)acc;           // mag[2t]
+    u32 *lsb = (u32 *)acc;               // lsb[2t + 1]
+
+    for (int64_t uidx = blockIdx.x; uidx < L.nunits; uidx += gridDim.x) {
+        SigDesc sd;
+        int64_t tile;
+        if (L.units) {
+            const Unit u = L.units[uidx];
+            sd = L.sigs[u.sig];
+            tile = u.tile;
+        } else {
+            const int64_t row = uidx / L.tpr;
+            tile = uidx - row * L.tpr;
+            sd = L.one;
+            sd.x_off += row * sd.n;
+            sd.y_off += row * (sd.n - sd.k + 1);
+        }
+        const float *grad_y = (const float *)L.grad_y + sd.y_off;
+        const int32_t *argmed = L.argmed + sd.y_off;
+        float *grad_x = (float *)L.grad_x + sd.x_off;
+        // signals are shorter than 2^31: 32-bit indices from here on
+        const int32_t n = (int32_t)sd.n, k = sd.k, nout = n - k + 1;
+        const int64_t j0l = tile * kBwdSegTargetsPerBlock + (int64_t)wave * TJ;
+        if (j0l >= n) continue;   // the waves share no LDS and no barrier
+        const int32_t j0 = (int32_t)j0l;
+        const int32_t olo = j0 - k + 1 > 0 ? j0 - k + 1 : 0;
+        const int32_t ohi = j0 + TJ < nout ? j0 + TJ : nout;
+
+        // pass over the tile's terms: f(t, g) for every output o of a target
+        // t in the tile, g = grad_y[o]
+        auto terms = [&](auto f) {
+            for (int32_t o0 = olo; o0 < ohi; o0 += 64 * B) {
+                u32 tt[B];
+                float gg[B];
+#pragma unroll
+                for (int q = 0; q < B; q++) {
+                    const int32_t o = o0 + q * 64 + lane;
+                    tt[q] = o < ohi ? (u32)(argmed[o] - j0) : 0xFFFFFFFFu;
+                }
+#pragma unroll
+                for (int q = 0; q < B; q++) gg[q] = tt[q] < (u32)TJ ? grad_y[o0 + q * 64 + lane] : 0.0f;
+#pragma unroll
+                for (int q = 0; q < B; q++)
+                    if (tt[q] < (u32)TJ) f(tt[q], gg[q]);
+            }
+        };
+
+        for (int t = lane; t < TJ; t += 64) acc[t] = 0.0;
+        wave_sync();
+        u32 emin = 0xFFu, emax = 0u;
+        terms([&](u32 t, float g) {
+            atomicAdd(&acc[t], (double)g);
+            if (g != 0.0f) {
+                const u32 e = bwd_exp(g);
+                emin = e < emin ? e : emin;
+                emax = e > emax ? e : emax;
+            }
+        });
+        emin = __ockl_wfred_min_u32(emin);
+        emax = __ockl_wfred_max_u32(emax);
+        const u32 lk = 32u - (u32)__clz((int)(k - 1));   // ceil(log2 k)
+        const bool exact = emax == 0u || (emax < 255u && lk + emax <= 28u + emin);
+        wave_sync();
+        u32 slow = 0u;   // bit i: target lane + 64 i needs the ordered sum
+        if (!exact) {
+            for (int t = lane; t < TJ; t += 64) {
+                mag[2 * t] = 0.0f;
+                lsb[2 * t + 1] = 0xFFFFFFFFu;
+            }
+            wave_sync();
+            terms([&](u32 t, float g) {
+                if (g != 0.0f) {
+                    atomicAdd(&mag[2 * t], fabsf(g));
+                    atomicMin(&lsb[2 * t + 1], bwd_exp(g));
+                }
+            });
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < PER; i++) {
+                const int t = lane + 64 * i;
+                const u32 e = lsb[2 * t + 1];
+                if (e != 0xFFFFFFFFu && !((double)mag[2 * t] < ldexp(1.0, (int)e - 150 + 51))) slow |= 1u << i;
+            }
+            // (each phase reaches a cell through one type: the fences keep
+            // the float and u32 views apart from the float64 one)
+            wave_sync();
+            for (int t = lane; t < TJ; t += 64) acc[t] = 0.0;
+            wave_sync();
+            terms([&](u32 t, float g) { atomicAdd(&acc[t], (double)g); });
+            wave_sync();
+        }
+#pragma unroll
+        for (int i = 0; i < PER; i++) {
+            const int t = lane + 64 * i;
+            const int32_t j = j0 + t;
+            if (j >= n) break;
+            double a = acc[t];
+            if ((slow >> i) & 1u) {
+                a = 0.0;
+                const int32_t lo = j - k + 1 > 0 ? j - k + 1 : 0, hi = j < nout - 1 ? j : nout - 1;
+                for (int32_t o = lo; o <= hi; o++)
+                    if (argmed[o] == j) a += (double)grad_y[o];
+            }
+            grad_x[j] = (float)a;
+        }
+        wave_sync();   // the next unit reuses the wave's LDS
+    }
+}
+
 // ------------------------------------------------------------------ host side
 
 Path path_for(int32_t k)
@@ -1390,12 +1537,23 @@ hipError_t launch_forward_persistent(Path p, bool f32, const Launch &L, size_t l
     return hipGetLastError();
 }
 
-int64_t bwd_tiles_for(int64_t n) { return (n + kBwdTargetsPerBlock - 1) / kBwdTargetsPerBlock; }
+bool bwd_seg_for(int32_t k, bool f64) { return !f64 && k <= kBwdSegMaxK; }
+
+int64_t bwd_tiles_for(int64_t n, int32_t k, bool f64)
+{
+    const int64_t per = bwd_seg_for(k, f64) ? kBwdSegTargetsPerBlock : kBwdTargetsPerBlock;
+    return (n + per - 1) / per;
+}
 
 hipError_t launch_backward(const BwdLaunch &L, bool f64, hipStream_t st)
 {
     if (L.nunits <= 0) return hipSuccess;
     const int64_t grid = L.nunits < (1ll << 20) ? L.nunits : (1ll << 20);
+    if (L.seg) {
+        if (f64) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_backward_exact, dim3((unsigned)grid), dim3(kBwdThreads), 0, st, L);
+        return hipGetLastError();
+    }
     if (f64) hipLaunchKernelGGL(k_backward<double>, dim3((unsigned)grid), dim3(kBwdThreads), 0, st, L);
     else     hipLaunchKernelGGL(k_backward<float>, dim3((unsigned)grid), dim3(kBwdThreads), 0, st, L);
     return hipGetLastError();

@@ -57,6 +57,7 @@ struct BwdLaunch {
     const SigDesc *sigs;
     const Unit *units;
     int64_t nunits;
+    int32_t seg;         // 1: exact accumulation (float32, every window <= kBwdSegMaxK)
 };
 
 // Kernel families: k = 1; LDS tiles of kLdsSmall threads (blocks of up to
@@ -77,6 +78,13 @@ static const int kBwdThreads = 256;
 static const int kBwdTargetsPerWave = 1024;
 static const int kBwdTargetsPerBlock = kBwdTargetsPerWave * (kBwdThreads / 64);
 static const int kBwdGroup = 4;   // candidate batches whose loads are issued together
+// Exact-accumulation backward (float32 gradients): targets per wave and per
+// workgroup, and the largest window it serves (larger ones, and float64
+// gradients, take the grouping backward).
+static const int kBwdSegTargetsPerWave = 512;
+static const int kBwdSegTargetsPerBlock = kBwdSegTargetsPerWave * (kBwdThreads / 64);
+static const int32_t kBwdSegMaxK = 1025;
+static const int kBwdInflight = 4;   // candidate batches of 64 in flight per wave
 
 // Which kernel family serves window k.
 Path path_for(int32_t k);
@@ -100,8 +108,10 @@ hipError_t launch_forward_persistent(Path p, bool f32, const Launch &L, size_t l
 
 hipError_t launch_backward(const BwdLaunch &L, bool f64, hipStream_t st);
 
-// Backward tiles of a signal of length n.
-int64_t bwd_tiles_for(int64_t n);
+// Whether window k takes the exact-accumulation backward, and the backward
+// tiles of a signal of length n with window k.
+bool bwd_seg_for(int32_t k, bool f64);
+int64_t bwd_tiles_for(int64_t n, int32_t k, bool f64);
 
 // 64-bit signals on an LDS path: entries per tile of the rank buffer and
 // the rank pre-pass (one workgroup per 1024-thread tile of each row); k = 1

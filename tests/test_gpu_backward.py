@@ -27,7 +27,7 @@ def gpu_forward_backward(x, k, g):
     return y.cpu().numpy(), am.cpu().numpy(), gx.cpu().numpy()
 
 
-@pytest.mark.parametrize("k", [1, 3, 31, 201, 1001, 4095, 5001])
+@pytest.mark.parametrize("k", [1, 3, 31, 201, 1001, 1025, 1027, 4095, 5001])
 def test_backward_bitwise_vs_oracle(k):
     rng = np.random.default_rng(600 + k)
     n = max(3 * k, 30_000) + 7
@@ -40,7 +40,7 @@ def test_backward_bitwise_vs_oracle(k):
     assert np.array_equal(gx.view(np.uint32), g32.view(np.uint32))
 
 
-@pytest.mark.parametrize("k", [3, 101, 1001])
+@pytest.mark.parametrize("k", [3, 101, 1001, 1025, 1027])
 def test_backward_with_ties_heavy_reuse(k):
     """Few distinct values: one input can be the median of many windows."""
     rng = np.random.default_rng(700 + k)
@@ -106,7 +106,7 @@ def test_finite_differences_on_gpu_forward():
         assert abs(fd - gx[j]) <= 1e-4 * (1 + abs(fd)), (j, fd, gx[j])
 
 
-@pytest.mark.parametrize("k", [1, 3, 101, 1001, 4095])
+@pytest.mark.parametrize("k", [1, 3, 101, 1001, 1025, 1027, 4095])
 def test_backward_f64_bitwise_vs_oracle(k):
     """float64 signal and gradient: forward on the GPU, backward on the GPU
     against the oracle's float64 scatter, bit for bit."""
