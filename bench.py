@@ -42,7 +42,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--copy-probe", action="store_true",
@@ -260,9 +260,14 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-PHASES = ["load, zero counters", "key range + presorted check", "count", "scan", "scatter", "rank", "place",
-          "per-block counts + scan + table zero", "pair positions + histogram", "column sums", "column apply",
-          "row prefix", "walk", "output"]
+# (stopping point, phase ending there): stop 6 (after the in-bucket rank)
+# is not timed, since a kernel that stops there has no use for the ranks
+# and loses them, and stop 11 follows stop 10 with nothing between (the
+# column pass is one phase); 0 runs whole tiles
+PHASES = [(1, "load, zero counters"), (2, "key range + presorted check"), (3, "count"), (4, "scan"),
+          (5, "scatter"), (7, "rank + place"), (8, "per-block counts + scan + table zero"),
+          (9, "pair positions + histogram"), (10, "column pass"), (12, "row prefix"), (13, "walk"),
+          (0, "output")]
 
 
 def phase_probe(torch, x, n, k, y, am, args):
@@ -276,7 +281,7 @@ def phase_probe(torch, x, n, k, y, am, args):
     L.mf_phase_probe_i32.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_int, P]
     L.mf_phase_probe_i32.restype = ctypes.c_int
     st = torch.cuda.current_stream()
-    stops = list(range(1, 14)) + [0]
+    stops = [st_ for st_, _ in PHASES]
     ms = {}
     for stop in stops:
         def run():
@@ -289,21 +294,26 @@ def phase_probe(torch, x, n, k, y, am, args):
     cum = [ms[s] for s in stops]
     phases = []
     prev = 0.0
-    for name, c in zip(PHASES, cum):
-        phases.append({"phase": name, "cumulative_ms": c, "ms": c - prev})
+    for (stop, name), c in zip(PHASES, cum):
+        phases.append({"stop": stop, "phase": name, "cumulative_ms": c, "ms": c - prev})
         prev = c
     return {"phase_probe": WORKLOAD, "n": n, "k": k, "phases": phases}
 
 
 def kernel_source_sha():
-    """Hash of the kernel sources with comments and blank space removed
-    (the HBM counters stay valid across comment edits)."""
+    """Hash of the forward kernels' device code (the tile header, and the
+    kernel file up to its backward section) with comments and blank space
+    removed: the HBM counters stay valid across comment edits and changes
+    to the backward or the host side."""
     import hashlib
     import re
     h = hashlib.sha256()
     for f in ("mf_tile.h", "mf_kernels.hip"):
         with open(os.path.join(ROOT, "paper_1406_1717_amd", "csrc", f)) as fh:
             text = fh.read()
+        a = text.find("// " + "-" * 66 + " backward\n")
+        if a >= 0:
+            text = text[:a]
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         text = re.sub(r"//[^\n]*", "", text)
         h.update(re.sub(r"\s+", "", text).encode())
