@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--extras", action="store_true")
+    ap.add_argument("--only", metavar="WORKLOAD:K", default=None,
+                    help="time only the forward of one float32 or int32 workload of workloads.py at window K "
+                         "(for profiling a kernel other than the headline one), e.g. random_walk_f32_16m:30001")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 256 MiB device copy (known bytes) for counter calibration")
@@ -186,6 +189,9 @@ def main():
     import paper_1406_1717_amd as mf
     from paper_1406_1717_amd import lib, workloads
 
+    if args.only:
+        print(json.dumps(only(torch, lib, workloads, args)), flush=True)
+        return
     dev = torch.device("cuda:0")
     w = workloads.workload(WORKLOAD)
     x_host, k = w["x"], w["k"]
@@ -318,6 +324,28 @@ def kernel_source_sha():
         text = re.sub(r"//[^\n]*", "", text)
         h.update(re.sub(r"\s+", "", text).encode())
     return h.hexdigest()[:16]
+
+
+def only(torch, lib, workloads, args):
+    """The forward of one named workload at one window: HIP-event time per
+    launch over args.steps launches after args.warmup."""
+    name, kk = args.only.split(":")
+    k = int(kk)
+    w = workloads.workload(name)
+    xh = w["x"]
+    if xh.ndim != 1 or xh.dtype not in (np.float32, np.int32):
+        raise SystemExit("bench.py --only: %s is not a one-dimensional float32 or int32 workload" % name)
+    dev = torch.device("cuda:0")
+    xt = torch.from_numpy(xh).to(dev)
+    n = len(xh)
+    y = torch.empty(n - k + 1, dtype=xt.dtype, device=dev)
+    a = torch.empty(n - k + 1, dtype=torch.int32, device=dev)
+    f = lib.mf_median_filter if xh.dtype == np.float32 else lib.mf_median_filter_i32
+    total, per = timed_steps(lambda: f(xt, n, k, y, a), args.steps, args.warmup, torch)
+    ms = float(np.median(per)) * 1e3
+    return {"only": name, "n": n, "k": k, "steps": args.steps, "ms_median": ms,
+            "outputs_per_s": (n - k + 1) / (ms * 1e-3),
+            "hbm_frac": (4.0 * n + 8.0 * (n - k + 1)) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def extras(torch, mf, lib, workloads, args):

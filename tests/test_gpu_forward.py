@@ -98,6 +98,22 @@ def test_global_tiles_crowded_maps(k):
     assert_same(xi, k, y, am, "ties 0..3999")
 
 
+@pytest.mark.parametrize("k", [5001, 16383, 16385, 30001, 32767])
+def test_workspace_path_windows(k):
+    """The k > 4096 path on both sides of its two kernel forms (two tiles
+    per CU up to k = 16383, one above): every output of a random walk and of
+    full-range int32 over four pairs and a ragged last block."""
+    rng = np.random.default_rng(7000 + k)
+    n = 5 * k + int(rng.integers(1, k))
+    print("workspace path: k=%d n=%d" % (k, n), flush=True)
+    xw = np.cumsum(rng.standard_normal(n)).astype(np.float32)
+    y, am = run_gpu(xw, k)
+    assert_same(xw, k, y, am, "walk")
+    xi = rng.integers(-2**31, 2**31, n, dtype=np.int64).astype(np.int32)
+    y, am = run_gpu(xi, k)
+    assert_same(xi, k, y, am, "int32")
+
+
 @pytest.mark.parametrize("k,n", [(1, 1), (1, 7), (3, 3), (3, 4), (3, 5), (5, 5), (101, 101), (101, 102),
                                  (101, 202), (101, 203), (1001, 1001), (1001, 2001), (1001, 2002),
                                  (4095, 4095), (4095, 8191), (4097, 4097), (4097, 8195), (9999, 9999),
