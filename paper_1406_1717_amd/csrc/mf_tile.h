@@ -202,7 +202,7 @@ struct Shape {
     int32_t C;       // chunks of a full pair, ceil(k / L)
     int32_t Wn;      // 64-position words of a pair's merged order, ceil(2k/64)
     int32_t Wrow;    // cells per count-table row: even, an odd number of dwords
-    int32_t Mstride; // u16 entries per pair in M (= Wn * 64)
+    int32_t Mstride; // u16 entries per pair in M (Wn * 64; 32 when 2k <= 32)
     int32_t Pstride; // u32 entries per pair in pos (k rounded up to 4)
     int32_t seg;     // merged outputs per pair-merge item (odd)
 };
@@ -273,7 +273,8 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
     s->Wn = (int32_t)((2u * uk + 63u) >> 6);
     // an odd dword stride spreads a column's cells over the LDS banks
     s->Wrow = 2 * (((s->Wn + 1) >> 1) | 1);
-    s->Mstride = s->Wn * 64;
+    // a pair of k <= 15 fits one 32-position group of membership bits
+    s->Mstride = 2 * k <= 32 ? 32 : s->Wn * 64;
     s->Pstride = (k + 3) & ~3;
     // pairs per tile: as many blocks as the sort holds, but the merged
     // orders and position maps of all pairs stay within kPairBudget bytes
@@ -337,6 +338,9 @@ MF_HD int32_t tile_buckets(const Shape &s) { return compact_tile(s) ? s.cap / 2 
 
 // Row dwords of a count table that hold real cells (two cells each).
 MF_HD int32_t col_dwords(const Shape &s) { return (s.Wn + 1) >> 1; }
+
+// 32-position membership dwords of a pair's merged order.
+MF_HD int32_t m_dwords(const Shape &s) { return s.Mstride >> 5; }
 
 MF_HD void make_layout(const Shape &s, Layout *l)
 {
@@ -1504,13 +1508,13 @@ MF_HD int hibit32(u32 v)   // index of the highest set bit, v != 0
 }
 
 // Membership dword of positions [32w, 32w+32) after step i, read from M with
-// 16-byte loads (M rows are 128-byte aligned).  For an entry e = isB << 15 | t
+// 16-byte loads (M rows are 64-byte aligned).  For an entry e = isB << 15 | t
 // the 16-bit difference i - e has its sign bit set exactly when the item is a
 // member after step i (A: t > i; B: t <= i; padding: never; i = -1 is the
 // state before step 0), so one packed subtraction tests two positions.
 MF_HD u32 member_dword(const Shape &s, const u16 *Mp, int32_t w, int32_t i)
 {
-    if (w < 0 || w >= 2 * s.Wn) return 0u;
+    if (w < 0 || w >= m_dwords(s)) return 0u;
     const uint4 *src = (const uint4 *)(Mp + w * 32);
     const u32 ii = ((u32)i & 0xFFFFu) * 0x10001u;
     u32 word = 0u;
@@ -1550,10 +1554,10 @@ MF_HD int32_t win_search_far(const Shape &s, const u16 *Mp, int32_t r, int32_t d
     u32 word = member_dword(s, Mp, wq, i);
     word &= (dir > 0) ? (0xFFFFFFFFu << (q & 31)) : (0xFFFFFFFFu >> (31 - (q & 31)));
 #pragma unroll 1
-    for (int32_t guard = 0; guard <= 2 * s.Wn + 1; guard++) {
+    for (int32_t guard = 0; guard <= m_dwords(s) + 1; guard++) {
         if (word) return wq * 32 + (dir > 0 ? ctz32(word) : hibit32(word));
         wq += dir;
-        if (wq < 0 || wq >= 2 * s.Wn) return -1;
+        if (wq < 0 || wq >= m_dwords(s)) return -1;
         word = member_dword(s, Mp, wq, i);
     }
     return -1;
