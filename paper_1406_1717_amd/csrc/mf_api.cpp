@@ -17,6 +17,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <unistd.h>
 #include <vector>
 
 #include "../../include/mf.h"
@@ -500,12 +501,15 @@ static void tune_cache_apply(mf_plan *p)
     }
 }
 
-// Merges the plan's tuned buckets into the cache file (written whole, then
-// renamed over the old one).
+// Merges the plan's tuned buckets into the cache file (written whole to a
+// temporary file of this process, then renamed over the old one; writers
+// of one process take turns).
 static void tune_cache_write(const mf_plan *p, const bool (&tuned)[kShapeBuckets])
 {
     const char *path = env_tune_cache();
     if (!path) return;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
     int64_t threads[kShapeBuckets] = {0};
     for (const auto &kv : tune_cache_read(path))
         for (int b = 0; b < kShapeBuckets; b++)
@@ -522,7 +526,7 @@ static void tune_cache_write(const mf_plan *p, const bool (&tuned)[kShapeBuckets
         first = false;
     }
     text += "}}}\n";
-    const std::string tmp = std::string(path) + ".tmp";
+    const std::string tmp = std::string(path) + ".tmp." + std::to_string((long long)getpid());
     FILE *f = fopen(tmp.c_str(), "wb");
     if (!f) return;
     const bool ok = fwrite(text.data(), 1, text.size(), f) == text.size();

@@ -132,12 +132,15 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
     if (!merged) {
         tail_pair_pad(s, T, m, tid, NT);
         __syncthreads();
+        MF_STOP_AT(15)
         tail_pair_merge(s, T, m, tid, NT, xo, yo, d.argmed);
         __syncthreads();
+        MF_STOP_AT(16)
         // the median before each pair's first step is A's median: remember
         // its merged position (before the count tables reuse the sort buffer)
         tail_first_medians(s, T, m, tid, NT);
         __syncthreads();
+        MF_STOP_AT(17)
     }
     if (s.C > 1) {
         if (rowbuf) {    // tables in global memory: whole rows from LDS row buffers
@@ -480,6 +483,7 @@ __device__ __forceinline__ void lds_tile(const Resolved &d, const Shape &s, cons
             if (sv_valid(v[j])) put_block_value(s, m, tid * kRegs + j, v[j]);
         __syncthreads();
     }
+    MF_STOP_AT(14)
 
     tile_tail<NT, V, STOP>(s, T, m, d, xo, yo, err, merged);
 }
@@ -1621,7 +1625,7 @@ hipError_t launch_identity64(const void *x, void *y, int32_t *argmed, int64_t to
 #include <string.h>
 // Phase-probe build only (not part of libmf.so): the int32 forward on
 // 512-thread tiles with every workgroup returning after tile phase `stop`
-// (1 .. 13 as numbered by MF_STOP_AT; 0 runs whole tiles).  The outputs of a
+// (1 .. 17 as numbered by MF_STOP_AT; 0 runs whole tiles).  The outputs of a
 // stopped launch are not written.  Returns a hipError_t.
 namespace mf {
 template <int S>
@@ -1670,6 +1674,10 @@ extern "C" int mf_phase_probe_i32(const void *x, int64_t n, int32_t k, void *y, 
     case 11: return (int)probe_launch<11>(L, lds, err, st);
     case 12: return (int)probe_launch<12>(L, lds, err, st);
     case 13: return (int)probe_launch<13>(L, lds, err, st);
+    case 14: return (int)probe_launch<14>(L, lds, err, st);
+    case 15: return (int)probe_launch<15>(L, lds, err, st);
+    case 16: return (int)probe_launch<16>(L, lds, err, st);
+    case 17: return (int)probe_launch<17>(L, lds, err, st);
     default: return (int)hipErrorInvalidValue;
     }
 }
