@@ -96,6 +96,19 @@ struct Resolved {
     int64_t tile;
 };
 
+// Units of a launch without a work list (one signal, or rows), in an order
+// that gives each XCD a contiguous run of tiles: workgroups are dispatched
+// round the 8 XCDs by index, and neighbouring tiles share their boundary
+// block, which then stays in one L2 (each input is fetched from HBM about
+// once, and the output gathers hit L2).  A bijection of [0, nunits); a work
+// list keeps its own order.
+__device__ __forceinline__ int64_t xcd_unit(const Launch &L, int64_t b)
+{
+    if (L.units) return b;
+    const int64_t q = L.nunits >> 3, r = L.nunits & 7, x = b & 7, j = b >> 3;
+    return x * q + (x < r ? x : r) + j;
+}
+
 __device__ __forceinline__ Resolved unit_of(const Launch &L, int64_t uidx)
 {
     SigDesc d;
@@ -498,7 +511,8 @@ template <int NT, bool F32, int RK = 0, int STOP = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 6 : 8))) void k_tile_lds(Launch L, int *err)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    const Resolved d = unit_of(L, blockIdx.x);
+    const int64_t uidx = xcd_unit(L, blockIdx.x);
+    const Resolved d = unit_of(L, uidx);
     Shape s;
     Tile T;
     unit_shape<NT>(d, s, T);
@@ -509,11 +523,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 
     u64 *y64 = (u64 *)L.y;
     if constexpr (RK != 0) {
         if (L.units) {
-            const SigDesc sd = L.sigs[L.units[blockIdx.x].sig];
+            const SigDesc sd = L.sigs[L.units[uidx].sig];
             x64 += sd.x_off;
             y64 += sd.y_off;
         } else {
-            const int64_t row = (int64_t)blockIdx.x / L.tpr;
+            const int64_t row = uidx / L.tpr;
             x64 += row * d.n;
             y64 += row * (d.n - d.k + 1);
         }
