@@ -139,7 +139,8 @@ __device__ __forceinline__ Resolved unit_of(const Launch &L, int64_t uidx)
 // copied from xo to yo (V: 32- or 64-bit elements).
 template <int NT, typename V, int STOP = 0>
 __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
-                                          const V *xo, V *yo, int *err, bool merged, u32 *rowbuf = nullptr)
+                                          const V *xo, V *yo, int *err, bool merged, u32 *rowbuf = nullptr,
+                                          u32 *info = nullptr)
 {
     const int tid = threadIdx.x;
     if (!merged) {
@@ -155,11 +156,36 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
         __syncthreads();
         MF_STOP_AT(17)
     }
+    if (rowbuf) {
+        // one-pair tiles in global memory (k > 4095): the coarse count
+        // table in LDS (rowbuf) gives each walk chunk its starting column;
+        // then the walk and the output read the merged order from a copy
+        // in LDS
+        if (T.P == 0) return;
+        u32 *tb = rowbuf, *gt = rowbuf + s.C * gcols(s);
+        gtab_zero(s, tb, tid, NT);
+        __syncthreads();
+        gtab_hist(s, T, m, tb, tid, NT);
+        __syncthreads();
+        gtab_col_sums(s, tb, gt, tid, NT);
+        __syncthreads();
+        gtab_col_apply(s, tb, gt, tid, NT);
+        __syncthreads();
+        gtab_rows(s, tb, info, tid, NT);
+        __syncthreads();
+        TileMem ml = m;
+        ml.M = (u16 *)rowbuf;
+        const uint4 *src = (const uint4 *)m.M;
+        uint4 *dst = (uint4 *)rowbuf;
+        for (int e = tid; e < s.Mstride / 8; e += NT) dst[e] = src[e];
+        __syncthreads();
+        if (gtail_walk(s, T, ml, info, tid, NT, xo, yo, d.argmed)) atomicOr(err, 1);
+        __syncthreads();
+        tail_output(s, T, ml, tid, NT, xo, yo, d.argmed);
+        return;
+    }
     if (s.C > 1) {
-        if (rowbuf) {    // tables in global memory: whole rows from LDS row buffers
-            tail_table_hist_rows(s, T, m, rowbuf, tid & 63, tid >> 6, NT / 64, 64);
-            __syncthreads();
-        } else if (!merged) {   // tile order counts its items with the pair orders
+        if (!merged) {   // tile order counts its items with the pair orders
             tail_table_zero(s, T, m, tid, NT);
             __syncthreads();
             tail_table_hist(s, T, m, tid, NT);
@@ -169,24 +195,9 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
         __syncthreads();
         MF_STOP_AT(10)
         MF_STOP_AT(11)
-        if (rowbuf) tail_table_rows_waves(s, T, m, tid & 63, tid >> 6, NT / 64, 64);
-        else tail_table_rows(s, T, m, tid, NT);
+        tail_table_rows(s, T, m, tid, NT);
         __syncthreads();
         MF_STOP_AT(12)
-    }
-    if (rowbuf && T.P > 0) {
-        // tiles in global memory: the walk and the output read the merged
-        // orders from a copy in LDS (the row buffers are done)
-        TileMem ml = m;
-        ml.M = (u16 *)rowbuf;
-        const uint4 *src = (const uint4 *)m.M;
-        uint4 *dst = (uint4 *)rowbuf;
-        for (int e = tid; e < T.P * s.Mstride / 8; e += NT) dst[e] = src[e];
-        __syncthreads();
-        if (tail_walk(s, T, ml, tid, NT)) atomicOr(err, 1);
-        __syncthreads();
-        tail_output(s, T, ml, tid, NT, xo, yo, d.argmed);
-        return;
     }
     if (tail_walk(s, T, m, tid, NT)) atomicOr(err, 1);
     __syncthreads();
@@ -616,11 +627,11 @@ __global__ void k_zero_counters(u32 *c, int n)
 // ------------------------------------------------------------------ global path
 
 struct GLayout {
-    int64_t xv, srt, srt2, M, pos, cnt, stage, total;
+    int64_t xv, srt, srt2, M, pos, stage, total;
 };
 // After the sort, the sorted keys take the xv region and the slots the
-// start of srt2 (the tables overwrite them only after the pair orders and
-// first medians are done).
+// start of srt2; the staged medians overwrite them only after the pair
+// orders are done.
 
 __host__ __device__ inline void make_glayout(const Shape &s, GLayout *g)
 {
@@ -633,17 +644,19 @@ __host__ __device__ inline void make_glayout(const Shape &s, GLayout *g)
     g->pos = off;  off += 4ll * s.Pmax * s.Pstride;
     off = (off + 255) & ~255ll;
     g->total = off;
-    int64_t a = g->srt2;
-    g->cnt = a;    a += 2ll * s.Pmax * s.C * s.Wrow;
-    a = (a + 15) & ~15ll;
-    g->stage = a;
+    g->stage = g->srt2;
 }
 
+// One-pair tiles (k > 4095), with the walk chunks that the coarse table in
+// the workgroup's dynamic LDS allows.
 __host__ __device__ inline int global_shape(int64_t n, int32_t k, Shape *s)
 {
     int32_t S = 1;
     while (S < k) S <<= 1;
-    return make_shape(n, k, 2 * S / kRegs, s);
+    const int r = make_shape(n, k, 2 * S / kRegs, s);
+    if (r != 0) return r;
+    global_chunks(s, S <= 16384 ? kGlobalLdsSmall : kGlobalLdsLarge);
+    return 0;
 }
 
 
@@ -652,8 +665,8 @@ __host__ __device__ inline int global_shape(int64_t n, int32_t k, Shape *s)
 // (A before B on equal keys), so M and the position maps come straight out
 // of the sort.  Slot u = b << logS | t.  The counters (nbk 16-bit cells)
 // live in LDS, the arrival numbers and the scattered values in the
-// workspace.  Fills M (with its padding), the position maps, the pair's
-// first median (pos[k]) and output 0.  Returns false, having written only
+// workspace.  Fills M (with its padding) and the position maps (the walk's
+// chunk starts, chunk 0 included, come from the count table).  Returns false, having written only
 // scratch, if a bucket overflows even under the logarithmic map; the
 // caller then takes the merge sort.
 template <bool F32, typename V>
@@ -810,31 +823,6 @@ __device__ bool global_pair_bucket(const Shape &s, const Tile &T, const TileMem 
     }
     for (int r = N + tid; r < s.Mstride; r += NT) m.M[mslot(r)] = (u16)kMPad;
     __syncthreads();
-    // the pair's first median: A's item of rank h among A's items in M
-    {
-        const int32_t per = (N + NT - 1) / NT;
-        const int32_t r0 = tid * per < N ? tid * per : N, r1 = r0 + per < N ? r0 + per : N;
-        u32 na = 0u;
-        for (int r = r0; r < r1; r++) na += (m.M[mslot(r)] & 0x8000u) ? 0u : 1u;
-        const u32 ex = seg_excl_scan<kGlobalThreads>(na, NT, wave_tot);
-        const u32 h = (u32)s.h;
-        if (ex <= h && h < ex + na) {
-            u32 c = ex;
-            for (int r = r0; r < r1; r++) {
-                const u32 e = m.M[mslot(r)];
-                if (e & 0x8000u) continue;
-                if (c == h) {
-                    m.pos[s.k] = (u32)r;
-                    if (T.j0 == 1) {   // output 0: the median of block 0
-                        yo[0] = xo[e];
-                        if (d.argmed) d.argmed[0] = (int32_t)e;
-                    }
-                    break;
-                }
-                c++;
-            }
-        }
-    }
     __syncthreads();
     return true;
 }
@@ -849,6 +837,7 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ u32 gsh[3];
     __shared__ u32 wave_tot[kGlobalThreads / 64];
+    __shared__ u32 info[kGchunkMax];   // the walk chunks' starting columns
     u64 *sbuf = (u64 *)lds;   // kGlobalThreads * kRegs values
     const int tid = threadIdx.x;
     const int chunk = kGlobalThreads * kRegs;
@@ -866,7 +855,6 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
         u64 *srt = (u64 *)(base + g.srt);
         m.M = (u16 *)(base + g.M);
         m.pos = (u32 *)(base + g.pos);
-        m.cnt = (u16 *)(base + g.cnt);
         m.stage = (u16 *)(base + g.stage);
         u64 *srt2 = (u64 *)(base + g.srt2);
         const Tile T = make_tile(s, tile);
@@ -883,7 +871,7 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
         // counters, then the waves' histogram row buffers)
         if (T.P == 1 && s.S >= 8192 &&
             global_pair_bucket<F32>(s, T, m, d, srt, (u16 *)srt2, (u32 *)lds, gsh, wave_tot, xo, yo)) {
-            tile_tail<kGlobalThreads>(s, T, m, d, xo, yo, err, true, (u32 *)lds);
+            tile_tail<kGlobalThreads>(s, T, m, d, xo, yo, err, true, (u32 *)lds, info);
             continue;
         }
         // otherwise (a single block, or buckets that overflow on heavy ties):
@@ -939,7 +927,7 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
         }
         __syncthreads();
         // the sort buffer is free: it holds the waves' histogram row buffers
-        tile_tail<kGlobalThreads>(s, T, m, d, xo, yo, err, false, (u32 *)lds);
+        tile_tail<kGlobalThreads>(s, T, m, d, xo, yo, err, false, (u32 *)lds, info);
     }
 }
 
@@ -1417,9 +1405,11 @@ hipError_t prepare_kernels()
 {
     hipError_t e = hipSuccess;
     const int big = 156 * 1024;   // room for the kernels' small static LDS arrays
-#define MF_ATTR(kern)                                                                        \
+    const int gbig = 152 * 1024;  // the one-pair tiles' static arrays take about 4 KB
+#define MF_ATTR_BYTES(kern, bytes)                                                           \
     if (e == hipSuccess)                                                                     \
-        e = hipFuncSetAttribute((const void *)(kern), hipFuncAttributeMaxDynamicSharedMemorySize, big);
+        e = hipFuncSetAttribute((const void *)(kern), hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+#define MF_ATTR(kern) MF_ATTR_BYTES(kern, big)
     MF_ATTR((k_tile_lds<kLdsSmall, true>))
     MF_ATTR((k_tile_lds<kLdsSmall, false>))
     MF_ATTR((k_tile_lds<kLdsLarge, true>))
@@ -1431,17 +1421,18 @@ hipError_t prepare_kernels()
     MF_ATTR((k_tile_lds_persistent<kLdsLarge, true>))
     MF_ATTR((k_tile_lds_persistent<kLdsSmall, false>))
     MF_ATTR((k_tile_lds_persistent<kLdsLarge, false>))
-    MF_ATTR((k_tile_global<true, false>))
-    MF_ATTR((k_tile_global<false, false>))
-    MF_ATTR((k_tile_global<true, true>))
-    MF_ATTR((k_tile_global<false, true>))
-    MF_ATTR((k_tile_global<false, true, true>))
-    MF_ATTR((k_tile_global<false, false, true>))
+    MF_ATTR_BYTES((k_tile_global<true, false>), gbig)
+    MF_ATTR_BYTES((k_tile_global<false, false>), gbig)
+    MF_ATTR_BYTES((k_tile_global<true, true>), gbig)
+    MF_ATTR_BYTES((k_tile_global<false, true>), gbig)
+    MF_ATTR_BYTES((k_tile_global<false, true, true>), gbig)
+    MF_ATTR_BYTES((k_tile_global<false, false, true>), gbig)
     MF_ATTR((k_rank64_pair<true>))
     MF_ATTR((k_rank64_pair<false>))
     MF_ATTR((k_rank64<kLdsLarge, true>))
     MF_ATTR((k_rank64<kLdsLarge, false>))
 #undef MF_ATTR
+#undef MF_ATTR_BYTES
     return e;
 }
 

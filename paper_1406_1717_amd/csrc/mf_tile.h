@@ -1563,6 +1563,65 @@ MF_HD int32_t win_search_far(const Shape &s, const u16 *Mp, int32_t r, int32_t d
     return -1;
 }
 
+// One step of a walk: A[i] leaves and B[i] joins the window (q = posA |
+// posB << 16, their merged positions); the median's position base + rel
+// and the membership window W of [base, base + 64) follow.  Sets bad (and
+// leaves a placeholder) if a search runs off the merged order.
+MF_HD void walk_step(const Shape &s, const u16 *Mp, u32 q, int32_t i, int32_t &base, int32_t &rel, u64 &W, int &bad)
+{
+    // A[i] leaves (its bit is set), B[i] joins (its bit is clear); bits
+    // outside the window shift a zero
+    const int32_t da = (int32_t)(q & 0xFFFFu) - base, db = (int32_t)(q >> 16) - base;
+    W ^= (u64)((u32)da < 64u) << (da & 63);
+    W ^= (u64)((u32)db < 64u) << (db & 63);
+    // The median moves to the next member up when the window loses a
+    // member at or below it (A[i] itself included) and gains one above
+    // it, to the next member down when it gains one below and loses one
+    // at or above it, and stays otherwise (B[i] was not a member, so it
+    // is never at the median's position).
+    const bool ltB = db < rel;
+    const bool up = !ltB && da <= rel;
+    const bool down = ltB && da >= rel;
+    // the nearest member above and below (64 or more: none in the window)
+    const u32 nup = low64_or_big(W & (~1ull << rel));
+    const u32 ndn = high64_or_big(W & ((1ull << rel) - 1ull));
+    u32 nrel = down ? ndn : (u32)rel;
+    nrel = up ? nup : nrel;
+    if (nrel >= 64u) {
+        const int32_t dir = up ? 1 : -1;
+        if (up ? rel >= 32 : rel < 32) {
+            // the median drifts out of the window (sorted or slowly
+            // varying input): slide the window half its width toward the
+            // move, which keeps the half that holds it and reads one
+            // membership dword
+            if (up) {
+                base += 32;
+                rel -= 32;
+                W = (W >> 32) | ((u64)member_dword(s, Mp, (base >> 5) + 1, i) << 32);
+                nrel = low64_or_big(W & (~1ull << rel));
+            } else {
+                base -= 32;
+                rel += 32;
+                W = (W << 32) | (u64)member_dword(s, Mp, base >> 5, i);
+                nrel = high64_or_big(W & ((1ull << rel) - 1ull));
+            }
+        }
+        if (nrel >= 64u) {
+            const int32_t nr = win_search_far(s, Mp, base + rel, dir, i);
+            if (nr < 0) {
+                bad = 1;
+                base = 0;
+                nrel = 0u;
+            } else {
+                base = win_base_for(nr);
+                W = win_read(s, Mp, base, i);
+                nrel = (u32)(nr - base);
+            }
+        }
+    }
+    rel = (int32_t)nrel;
+}
+
 // Walk of chunk c of pair p: steps [c*L, min((c+1)*L, len B)).  Returns 0,
 // or -1 if a search ran off the merged order (cannot happen for a correct
 // table; the bound keeps the loop finite).
@@ -1621,57 +1680,7 @@ MF_HD int walk_item(const Shape &s, const Tile &T, const TileMem &m, int32_t p, 
         q2 = q3;
         q3 = q4;
         if (i + 4 < i1) q4 = pos[i + 4];
-        // A[i] leaves (its bit is set), B[i] joins (its bit is clear); bits
-        // outside the window shift a zero
-        const int32_t da = (int32_t)(q & 0xFFFFu) - base, db = (int32_t)(q >> 16) - base;
-        W ^= (u64)((u32)da < 64u) << (da & 63);
-        W ^= (u64)((u32)db < 64u) << (db & 63);
-        // The median moves to the next member up when the window loses a
-        // member at or below it (A[i] itself included) and gains one above
-        // it, to the next member down when it gains one below and loses one
-        // at or above it, and stays otherwise (B[i] was not a member, so it
-        // is never at the median's position).
-        const bool ltB = db < rel;
-        const bool up = !ltB && da <= rel;
-        const bool down = ltB && da >= rel;
-        // the nearest member above and below (64 or more: none in the window)
-        const u32 nup = low64_or_big(W & (~1ull << rel));
-        const u32 ndn = high64_or_big(W & ((1ull << rel) - 1ull));
-        u32 nrel = down ? ndn : (u32)rel;
-        nrel = up ? nup : nrel;
-        if (nrel >= 64u) {
-            const int32_t dir = up ? 1 : -1;
-            if (up ? rel >= 32 : rel < 32) {
-                // the median drifts out of the window (sorted or slowly
-                // varying input): slide the window half its width toward the
-                // move, which keeps the half that holds it and reads one
-                // membership dword
-                if (up) {
-                    base += 32;
-                    rel -= 32;
-                    W = (W >> 32) | ((u64)member_dword(s, Mp, (base >> 5) + 1, i) << 32);
-                    nrel = low64_or_big(W & (~1ull << rel));
-                } else {
-                    base -= 32;
-                    rel += 32;
-                    W = (W << 32) | (u64)member_dword(s, Mp, base >> 5, i);
-                    nrel = high64_or_big(W & ((1ull << rel) - 1ull));
-                }
-            }
-            if (nrel >= 64u) {
-                const int32_t nr = win_search_far(s, Mp, base + rel, dir, i);
-                if (nr < 0) {
-                    bad = 1;
-                    base = 0;
-                    nrel = 0u;
-                } else {
-                    base = win_base_for(nr);
-                    W = win_read(s, Mp, base, i);
-                    nrel = (u32)(nr - base);
-                }
-            }
-        }
-        rel = (int32_t)nrel;
+        walk_step(s, Mp, q, i, base, rel, W, bad);
         stage[i] = (u16)(base + rel);
     }
     if (bad)   // a failed search leaves a valid placeholder for the whole chunk
@@ -1864,6 +1873,203 @@ MF_HD int tail_walk(const Shape &s, const Tile &T, const TileMem &m, int32_t tid
         const int32_t p = (int32_t)udiv16((u32)it, Cr), c = it - p * s.C;
         if (c < pair_chunks(s, T, p)) bad |= walk_item(s, T, m, p, c) != 0;
     }
+    return bad;
+}
+
+// ---------------------------------------------------------------- 4-5. one-pair tiles in global memory
+//
+// A tile of one pair with k > 4095 keeps its merged order and position maps
+// in the workspace, and its count table counts members per column of
+// kGcolWords words (1024 merged positions) instead of per word: C rows of
+// gcols(s) cells.  The table is built in LDS (u32 cells: A items in the low
+// half, B items in the high half; a column holds at most 1024 items, so the
+// halves never carry), and its passes turn the cells into member
+// counts.  A chunk's first median (chunk 0 included: the window before
+// step 0 is all of A) is found in two steps: the column from the table row
+// (the row pass), the word inside the column by counting membership words
+// at the chunk start (the walk lane).  With the table this small, chunks
+// can be short, which gives the walk a few hundred lanes per pair.
+
+static const int32_t kGcolWords = 16;      // 64-position words per table column
+static const int32_t kGcolShift = 10;      // log2 of the merged positions per column
+static const int32_t kGcolGroups = 16;     // row groups per column in the column pass
+static const int kGwalkAhead = 8;          // position words in flight per walk lane
+static const int32_t kGchunkMax = 1024;    // walk chunks of a one-pair tile, at most
+
+MF_HD int32_t gcols(const Shape &s) { return (s.Wn + kGcolWords - 1) / kGcolWords; }
+
+// Walk chunks of a one-pair tile whose workgroup has lds bytes of dynamic
+// LDS: at least 31 steps (a chunk's start costs a table search and a scan
+// of up to kGcolWords membership words), and as many as the coarse table
+// (C rows of gcols u32 cells, plus kGcolGroups rows of column-group totals)
+// in that LDS allows, up to kGchunkMax.
+MF_HD void global_chunks(Shape *s, int32_t lds)
+{
+    const int32_t G = gcols(*s);
+    int32_t cmax = lds / (4 * G) - kGcolGroups;
+    if (cmax > kGchunkMax) cmax = kGchunkMax;
+    int32_t L = (s->k + cmax - 1) / cmax;
+    if (L < 31) L = 31;
+    s->L = L | 1;
+    s->C = (s->k + s->L - 1) / s->L;
+}
+
+// Phase: zero the LDS table tb (C rows of gcols cells).
+MF_HD void gtab_zero(const Shape &s, u32 *tb, int32_t tid, int32_t NT)
+{
+    const int32_t n = s.C * gcols(s);
+    for (int32_t e = tid; e < n; e += NT) tb[e] = 0u;
+}
+
+// Phase: A's item t goes to cell (t / L, posA / 1024), B's item t (t < len
+// B) to cell (t / L, posB / 1024) in the high half.
+MF_HD void gtab_hist(const Shape &s, const Tile &T, const TileMem &m, u32 *tb, int32_t tid, int32_t NT)
+{
+    const int32_t G = gcols(s);
+    const int32_t lenB = block_len(s, T, 1);
+    const u32 Lr = recip32(s.L);
+    for (int32_t t = tid; t < s.k; t += NT) {
+        const u32 q = m.pos[t];
+        const u32 row = mul24(udiv16((u32)t, Lr), (u32)G);
+        MF_ADD32(tb + row + ((q & 0xFFFFu) >> kGcolShift), 1u);
+        if (t < lenB) MF_ADD32(tb + row + (q >> (16 + kGcolShift)), 0x10000u);
+    }
+}
+
+// Phase: item (column w, group g) sums its group's rows [g R, g R + R) of
+// column w into gt[w * kGcolGroups + g] (R = ceil(C / kGcolGroups)).
+MF_HD void gtab_col_sums(const Shape &s, const u32 *tb, u32 *gt, int32_t tid, int32_t NT)
+{
+    const int32_t G = gcols(s), R = (s.C + kGcolGroups - 1) / kGcolGroups;
+    for (int32_t it = tid; it < G * kGcolGroups; it += NT) {
+        const int32_t w = it / kGcolGroups, g = it - w * kGcolGroups;
+        const int32_t c0 = g * R, c1 = c0 + R < s.C ? c0 + R : s.C;
+        u32 acc = 0u;
+        for (int32_t c = c0; c < c1; c++) acc += tb[c * G + w];
+        gt[it] = acc;
+    }
+}
+
+// Phase: cell (c, w) becomes the members of column w at chunk start c: A
+// items with t >= cL (rows c..) plus B items with t < cL (rows ..c-1).
+MF_HD void gtab_col_apply(const Shape &s, u32 *tb, const u32 *gt, int32_t tid, int32_t NT)
+{
+    const int32_t G = gcols(s), R = (s.C + kGcolGroups - 1) / kGcolGroups;
+    for (int32_t it = tid; it < G * kGcolGroups; it += NT) {
+        const int32_t w = it / kGcolGroups, g = it - w * kGcolGroups;
+        const int32_t c0 = g * R, c1 = c0 + R < s.C ? c0 + R : s.C;
+        u32 sa = 0u, pb = 0u;   // A items of groups g.., B items of groups ..g-1
+        for (int32_t q = 0; q < kGcolGroups; q++) {
+            const u32 v = gt[w * kGcolGroups + q];
+            if (q >= g) sa += v & 0xFFFFu;
+            else pb += v >> 16;
+        }
+        for (int32_t c = c0; c < c1; c++) {
+            const u32 v = tb[c * G + w];
+            tb[c * G + w] = sa + pb;
+            sa -= v & 0xFFFFu;
+            pb += v >> 16;
+        }
+    }
+}
+
+// Phase: for each row c, the column holding the rank-h member of the
+// window before step cL: the largest w whose prefix over the columns
+// (members among merged positions < 1024 w) is at most h, and that prefix,
+// into info[c] = w | prefix << 16.
+MF_HD void gtab_rows(const Shape &s, const u32 *tb, u32 *info, int32_t tid, int32_t NT)
+{
+    const int32_t G = gcols(s);
+    const u32 h = (u32)s.h;
+    for (int32_t c = tid; c < s.C; c += NT) {
+        u32 acc = 0u, lo = 0u, below = 0u;
+        for (int32_t w = 0; w < G; w++) {
+            if (acc <= h) {
+                lo = (u32)w;
+                below = acc;
+            }
+            acc += tb[c * G + w];
+        }
+        info[c] = lo | (below << 16);
+    }
+}
+
+// 64 membership bits of word w of the merged order at step i.
+MF_HD u64 member_word(const Shape &s, const u16 *Mp, int32_t w, int32_t i)
+{
+    return (u64)member_dword(s, Mp, 2 * w, i) | ((u64)member_dword(s, Mp, 2 * w + 1, i) << 32);
+}
+
+// Walk of chunk c of a one-pair tile: steps [c*L, min((c+1)*L, len B)),
+// with kGwalkAhead position words in flight.  The rank-h member of the
+// window before step cL (chunk 0 included: that window is all of A) lies
+// in column info[c]: the words of that column are counted up to the one
+// that holds it.  Chunk 0 of the first tile writes output 0 (the median of
+// block 0).  Returns 0, or -1 as walk_item does.
+template <typename V>
+MF_HD int gwalk_item(const Shape &s, const Tile &T, const TileMem &m, const u32 *info, int32_t c, const V *x,
+                     V *y, int32_t *argmed)
+{
+    const int32_t lenB = block_len(s, T, 1);
+    const int32_t i0 = c * s.L;
+    const int32_t i1 = (i0 + s.L < lenB) ? i0 + s.L : lenB;
+    const u16 *Mp = m.M;
+    const u32 *pos = m.pos;
+    u16 *stage = m.stage;
+    const int32_t h = s.h;
+
+    const u32 inf = info[c];
+    int32_t lo = (int32_t)(inf & 0xFFFFu) * kGcolWords;
+    int32_t below = (int32_t)(inf >> 16);
+    const int32_t lend = ((lo + kGcolWords < s.Wn) ? lo + kGcolWords : s.Wn) - 1;
+    u64 word = member_word(s, Mp, lo, i0 - 1);
+#pragma unroll 1
+    while (lo < lend) {
+        const int32_t n = popc64(word);
+        if (below + n > h) break;
+        below += n;
+        lo++;
+        word = member_word(s, Mp, lo, i0 - 1);
+    }
+    const int32_t r = lo * 64 + select64(word, h - below);
+    if (c == 0 && T.j0 == 1) {
+        const u32 e = m_entry(Mp, (u32)r);
+        y[0] = x[e];
+        if (argmed) argmed[0] = (int32_t)e;
+    }
+
+    // the window, as in walk_item: word lo, or shifted half a word toward r
+    int32_t base = win_base_for(r);
+    const bool bel = base < lo * 64;
+    const u32 dx = member_dword(s, Mp, bel ? 2 * lo - 1 : 2 * lo + 2, i0 - 1);
+    u64 W = word;
+    if (base != lo * 64) W = bel ? (u64)dx | (word << 32) : (word >> 32) | ((u64)dx << 32);
+
+    int bad = 0;
+    int32_t rel = r - base;
+    u32 qr[kGwalkAhead];
+#pragma unroll
+    for (int j = 0; j < kGwalkAhead; j++) qr[j] = i0 + j < i1 ? pos[i0 + j] : 0u;
+#pragma unroll 1
+    for (int32_t i = i0; i < i1; i++) {
+        const u32 q = qr[0];
+#pragma unroll
+        for (int j = 0; j < kGwalkAhead - 1; j++) qr[j] = qr[j + 1];
+        qr[kGwalkAhead - 1] = i + kGwalkAhead < i1 ? pos[i + kGwalkAhead] : 0u;
+        walk_step(s, Mp, q, i, base, rel, W, bad);
+        stage[i] = (u16)(base + rel);
+    }
+    if (bad)
+        for (int32_t q = i0; q < i1; q++) stage[q] = 0;
+    return bad ? -1 : 0;
+}
+
+template <typename V>
+MF_HD int gtail_walk(const Shape &s, const Tile &T, const TileMem &m, const u32 *info, int32_t tid, int32_t NT,
+                     const V *x, V *y, int32_t *argmed)
+{
+    int bad = 0;
+    for (int32_t c = tid; c < T.Clast; c += NT) bad |= gwalk_item(s, T, m, info, c, x, y, argmed) != 0;
     return bad;
 }
 

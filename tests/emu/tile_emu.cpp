@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <algorithm>
 #include <vector>
 
 #include "../../paper_1406_1717_amd/csrc/mf_tile.h"
@@ -573,4 +574,65 @@ extern "C" long emu_check_udiv16(void)
             if (udiv16(a, r) != a / d) bad++;
     }
     return bad;
+}
+
+// The tail of the one-pair tiles (k > 4095) that keep their merged order in
+// global memory: the pair's merged order and position maps made here by a
+// plain sort of (key, block, t), then the kernels' coarse count table, walk
+// and output phases, each as one sweep over the threads.  lds: the
+// workgroup's dynamic LDS bytes, which set the walk chunks.  Returns 0, or
+// a negative code.
+extern "C" int emu_global_tail(const void *x, int64_t n, int32_t k, int is_f32, int32_t lds, void *y,
+                               int32_t *argmed, int32_t *out_L)
+{
+    if (k < 3 || (k & 1) == 0 || n < 2 * (int64_t)k) return -1;
+    int32_t S = 1;
+    while (S < k) S <<= 1;
+    Shape s;
+    if (make_shape(n, k, 2 * S / kRegs, &s) != 0) return -2;
+    if (s.Pmax != 1) return -3;
+    global_chunks(&s, lds);
+    if (out_L) *out_L = s.L;
+    const int32_t G = gcols(s);
+    if (4 * G * (s.C + kGcolGroups) > lds || 2 * s.Mstride > lds) return -4;
+    const u32 *xu = (const u32 *)x;
+    std::vector<u16> M((size_t)s.Mstride);
+    std::vector<u32> pos((size_t)s.Pstride + 1);
+    std::vector<u16> stage((size_t)k);
+    std::vector<u32> tbuf((size_t)lds / 4);
+    for (int64_t t = 0; t < s.ntiles; t++) {
+        const Tile T = make_tile(s, t);
+        if (T.P != 1) return -5;
+        const int32_t lenB = block_len(s, T, 1), N = k + lenB;
+        std::vector<u64> v((size_t)N);
+        for (int32_t i = 0; i < N; i++) {
+            const int32_t b = i < k ? 0 : 1, tt = i < k ? i : i - k;
+            const u32 raw = xu[T.e0 + i];
+            const u32 key = is_f32 ? key_of_f32(raw) : key_of_i32(raw);
+            v[i] = ((u64)key << 32) | ((u64)b << 16) | (u64)tt;
+        }
+        std::sort(v.begin(), v.end());
+        for (int32_t r = 0; r < s.Mstride; r++) M[mslot(r)] = (u16)kMPad;
+        for (int32_t r = 0; r < N; r++) {
+            const u32 b = (u32)(v[r] >> 16) & 1u, tt = (u32)v[r] & 0xFFFFu;
+            M[mslot(r)] = (u16)((b << 15) | tt);
+            if (b) pos[tt] = (pos[tt] & 0xFFFFu) | ((u32)r << 16);
+            else pos[tt] = (pos[tt] & 0xFFFF0000u) | (u32)r;
+        }
+        TileMem m = {};
+        m.M = M.data();
+        m.pos = pos.data();
+        m.stage = stage.data();
+        u32 *tb = tbuf.data(), *gt = tb + s.C * G;
+        gtab_zero(s, tb, 0, 1);
+        gtab_hist(s, T, m, tb, 0, 1);
+        gtab_col_sums(s, tb, gt, 0, 1);
+        gtab_col_apply(s, tb, gt, 0, 1);
+        if (s.C > kGchunkMax) return -6;
+        std::vector<u32> info((size_t)s.C);
+        gtab_rows(s, tb, info.data(), 0, 1);
+        if (gtail_walk<u32>(s, T, m, info.data(), 0, 1, xu, (u32 *)y, argmed)) return -11;
+        tail_output<u32>(s, T, m, 0, 1, xu, (u32 *)y, argmed);
+    }
+    return 0;
 }

@@ -83,6 +83,38 @@ def test_tile_phases_match_oracle(emu, force_merge, wide):
     emu.emu_set_force_merge(0)
 
 
+def test_global_tail_matches_oracle(emu):
+    """The tail of the one-pair tiles for k > 4095 (coarse count table,
+    walk with position words in flight, output), run on the host after a
+    plain sort of each pair, for windows either side of the powers of two
+    and random, random-walk, tie-heavy and descending inputs, with the LDS
+    budgets of both kernel variants (64 KB up to k = 16383, 128 KB above)."""
+    emu.emu_global_tail.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    rng = np.random.default_rng(53)
+    for k in (4097, 5001, 8191, 8193, 16383, 16385, 30001, 32767):
+        lds = 65536 if k <= 16383 else 131072
+        for kind in range(4):
+            n = 3 * k + int(rng.integers(0, k))
+            if kind == 0:
+                x = rng.random(n).astype(np.float32)
+            elif kind == 1:
+                x = np.cumsum(rng.standard_normal(n)).astype(np.float32)
+            elif kind == 2:
+                x = rng.integers(0, 5, n).astype(np.float32)
+            else:
+                x = np.arange(n, dtype=np.float32)[::-1].copy()
+            y = np.empty(n - k + 1, np.float32)
+            a = np.empty(n - k + 1, np.int32)
+            L = ctypes.c_int32()
+            rc = emu.emu_global_tail(x.ctypes.data, n, k, 1, lds, y.ctypes.data, a.ctypes.data, ctypes.byref(L))
+            yo, ao = oracle.sortmedian(x, k)
+            assert rc == 0, (k, kind, rc)
+            assert L.value >= 31 and L.value % 2 == 1
+            assert np.array_equal(a, ao), (k, kind)
+            assert np.array_equal(y.view(np.uint32), yo.view(np.uint32)), (k, kind)
+
+
 def test_walk_window_slides(emu):
     """Inputs whose median drifts through the merged order step after step
     (ascending, descending, random walks, a sawtooth): the walk's register
