@@ -666,10 +666,12 @@ __host__ __device__ inline int global_shape(int64_t n, int32_t k, Shape *s)
 // of the sort.  Slot u = b << logS | t.  The counters (nbk 16-bit cells)
 // live in LDS, the arrival numbers and the scattered values in the
 // workspace.  Fills M (with its padding) and the position maps (the walk's
-// chunk starts, chunk 0 included, come from the count table).  Returns false, having written only
-// scratch, if a bucket overflows even under the logarithmic map; the
-// caller then takes the merge sort.
-template <bool F32, typename V>
+// chunk starts, chunk 0 included, come from the count table).  GW: slots
+// per thread with their loads in flight together (4 in the two-workgroup
+// form, whose 64 VGPRs it would otherwise overrun).  Returns false, having
+// written only scratch, if a bucket overflows even under the logarithmic
+// map; the caller then takes the merge sort.
+template <bool F32, typename V, int GW>
 __device__ bool global_pair_bucket(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
                                    u64 *srt, u16 *arrv, u32 *lcnt, u32 *gsh, u32 *wave_tot,
                                    const V *xo, V *yo)
@@ -683,9 +685,9 @@ __device__ bool global_pair_bucket(const Shape &s, const Tile &T, const TileMem 
     const int32_t N = s.k + lenB;
     const int32_t nslots = 2 * s.S;   // a multiple of kGW * NT
     const u32 *xt = d.x + T.e0;
-    // each pass below takes kGW slots per thread at a time, u = u0 + q * NT,
-    // with their loads in flight together
-    constexpr int kGW = 4;
+    // each pass below takes GW slots per thread at a time, u = u0 + q * NT,
+    // with their loads in flight together (2S is a multiple of GW * NT)
+    constexpr int kGW = GW;
     auto load_group = [&](int u0, u32 (&raw)[kGW], bool (&ok)[kGW]) {
 #pragma unroll
         for (int q = 0; q < kGW; q++) {
@@ -870,7 +872,7 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
         // one-pair tiles: bucket sort of the pair (the sort buffer holds the
         // counters, then the waves' histogram row buffers)
         if (T.P == 1 && s.S >= 8192 &&
-            global_pair_bucket<F32>(s, T, m, d, srt, (u16 *)srt2, (u32 *)lds, gsh, wave_tot, xo, yo)) {
+            global_pair_bucket<F32, std::remove_const_t<std::remove_pointer_t<decltype(xo)>>, TWO ? 4 : 8>(s, T, m, d, srt, (u16 *)srt2, (u32 *)lds, gsh, wave_tot, xo, yo)) {
             tile_tail<kGlobalThreads>(s, T, m, d, xo, yo, err, true, (u32 *)lds, info);
             continue;
         }
