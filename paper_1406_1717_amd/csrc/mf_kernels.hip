@@ -137,7 +137,7 @@ __device__ __forceinline__ Resolved unit_of(const Launch &L, int64_t uidx)
 // Phases 3-6 of a tile (pair merge, tables, walk, output); phases 1-2 have
 // filled m.srt.  NT threads, barriers between phases.  The medians are
 // copied from xo to yo (V: 32- or 64-bit elements).
-template <int NT, typename V, int STOP = 0>
+template <int NT, typename V, int STOP = 0, int GAHEAD = 8>
 __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
                                           const V *xo, V *yo, int *err, bool merged, u32 *rowbuf = nullptr,
                                           u32 *info = nullptr)
@@ -175,13 +175,13 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
         __syncthreads();
         TileMem ml = m;
         ml.M = (u16 *)rowbuf;
-        const uint4 *src = (const uint4 *)m.M;
+        const MF_GLOBAL uint4 *src = gmem((const uint4 *)m.M);
         uint4 *dst = (uint4 *)rowbuf;
         for (int e = tid; e < s.Mstride / 8; e += NT) dst[e] = src[e];
         __syncthreads();
-        if (gtail_walk(s, T, ml, info, tid, NT, xo, yo, d.argmed)) atomicOr(err, 1);
+        if (gtail_walk<GAHEAD>(s, T, ml, info, tid, NT, xo, yo, d.argmed)) atomicOr(err, 1);
         __syncthreads();
-        tail_output(s, T, ml, tid, NT, xo, yo, d.argmed);
+        gtail_output(s, T, ml, tid, NT, xo, yo, d.argmed);
         return;
     }
     if (s.C > 1) {
@@ -672,8 +672,8 @@ __host__ __device__ inline int global_shape(int64_t n, int32_t k, Shape *s)
 // written only scratch, if a bucket overflows even under the logarithmic
 // map; the caller then takes the merge sort.
 template <bool F32, typename V, int GW>
-__device__ bool global_pair_bucket(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
-                                   u64 *srt, u16 *arrv, u32 *lcnt, u32 *gsh, u32 *wave_tot,
+__device__ __forceinline__ bool global_pair_bucket(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
+                                   u64 *srt_, u16 *arrv_, u32 *lcnt, u32 *gsh, u32 *wave_tot,
                                    const V *xo, V *yo)
 {
     const int tid = threadIdx.x;
@@ -684,7 +684,11 @@ __device__ bool global_pair_bucket(const Shape &s, const Tile &T, const TileMem 
     const int32_t lenB = T.lenLast;
     const int32_t N = s.k + lenB;
     const int32_t nslots = 2 * s.S;   // a multiple of kGW * NT
-    const u32 *xt = d.x + T.e0;
+    // the signal and the workspace through global-space pointers (gmem)
+    const MF_GLOBAL u32 *xt = gmem(d.x + T.e0);
+    MF_GLOBAL u64 *srt = gmem(srt_);
+    MF_GLOBAL u16 *arrv = gmem(arrv_);
+    MF_GLOBAL u16 *Mg = gmem(m.M);
     // each pass below takes GW slots per thread at a time, u = u0 + q * NT,
     // with their loads in flight together (2S is a multiple of GW * NT)
     constexpr int kGW = GW;
@@ -806,7 +810,7 @@ __device__ bool global_pair_bucket(const Shape &s, const Tile &T, const TileMem 
     // rank within the bucket, then the merged order and position maps; by
     // position of the scattered array, so that the reads are coalesced and
     // a bucket's other entries sit in the same cache lines
-    u16 *pos16 = (u16 *)m.pos;
+    MF_GLOBAL u16 *pos16 = gmem((u16 *)m.pos);
     for (int r0 = tid; r0 < N; r0 += kGW * NT) {
         u64 v[kGW];
 #pragma unroll
@@ -819,15 +823,19 @@ __device__ bool global_pair_bucket(const Shape &s, const Tile &T, const TileMem 
             const u32 bk = bucket_of<F32>(f, key);
             const u32 x0 = cell(bk), hi = bk + 1u < (u32)nbk ? cell(bk + 1u) : (u32)N;
             const u32 fin = x0 + bucket_below(srt, x0, hi, v[q]);
-            m.M[mslot((int32_t)fin)] = (u16)((b << 15) | tt);
+            Mg[mslot((int32_t)fin)] = (u16)((b << 15) | tt);
             pos16[2 * tt + b] = (u16)fin;
         }
     }
-    for (int r = N + tid; r < s.Mstride; r += NT) m.M[mslot(r)] = (u16)kMPad;
+    for (int r = N + tid; r < s.Mstride; r += NT) Mg[mslot(r)] = (u16)kMPad;
     __syncthreads();
     __syncthreads();
     return true;
 }
+
+// Position words in flight per walk lane in the two-workgroup form (64
+// VGPRs; the one-workgroup form keeps 8).
+static const int kGwalkAheadTwo = 2;
 
 // TWO: tiles of k <= 16383 (64 KB of LDS), compiled for two workgroups per
 // CU (at most 64 VGPRs).  RK: int32 rank keys of a 64-bit signal (tile t's
@@ -867,13 +875,14 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
             if constexpr (RK) return (u64 *)L.y + row * (d.n - d.k + 1);
             else return d.y;
         }();
+        using GV = std::remove_pointer_t<decltype(yo)>;
 
         __syncthreads();   // the previous tile is done with the workspace
         // one-pair tiles: bucket sort of the pair (the sort buffer holds the
         // counters, then the waves' histogram row buffers)
         if (T.P == 1 && s.S >= 8192 &&
             global_pair_bucket<F32, std::remove_const_t<std::remove_pointer_t<decltype(xo)>>, TWO ? 4 : 8>(s, T, m, d, srt, (u16 *)srt2, (u32 *)lds, gsh, wave_tot, xo, yo)) {
-            tile_tail<kGlobalThreads>(s, T, m, d, xo, yo, err, true, (u32 *)lds, info);
+            tile_tail<kGlobalThreads, GV, 0, TWO ? kGwalkAheadTwo : 8>(s, T, m, d, xo, yo, err, true, (u32 *)lds, info);
             continue;
         }
         // otherwise (a single block, or buckets that overflow on heavy ties):
@@ -929,7 +938,7 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
         }
         __syncthreads();
         // the sort buffer is free: it holds the waves' histogram row buffers
-        tile_tail<kGlobalThreads>(s, T, m, d, xo, yo, err, false, (u32 *)lds, info);
+        tile_tail<kGlobalThreads, GV, 0, TWO ? kGwalkAheadTwo : 8>(s, T, m, d, xo, yo, err, false, (u32 *)lds, info);
     }
 }
 

@@ -867,7 +867,8 @@ MF_HD void bucket_scan_store(const TileMem &m, int32_t tid, u32 excl, const u32 
 // Entries of the scattered bucket [x, hi) of buf below v.  The first four
 // are read by every lane without a loop (an entry past the bucket is read
 // at x and not counted); longer buckets loop over the rest.
-MF_HD u32 bucket_below(const u64 *buf, u32 x, u32 hi, u64 v)
+template <typename P>
+MF_HD u32 bucket_below(P buf, u32 x, u32 hi, u64 v)
 {
     const u32 n = hi - x;
     u32 f = 0u;
@@ -1890,10 +1891,21 @@ MF_HD int tail_walk(const Shape &s, const Tile &T, const TileMem &m, int32_t tid
 // at the chunk start (the walk lane).  With the table this small, chunks
 // can be short, which gives the walk a few hundred lanes per pair.
 
+// Pointers into global memory in the global address space: reached through
+// generic pointers, the workspace is accessed with flat instructions, which
+// the compiler can only wait for together with the LDS operations around
+// them (every load then costs a full round trip).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MF_GLOBAL __attribute__((address_space(1)))
+#else
+#define MF_GLOBAL
+#endif
+template <typename T>
+MF_HD MF_GLOBAL T *gmem(T *p) { return (MF_GLOBAL T *)p; }
+
 static const int32_t kGcolWords = 16;      // 64-position words per table column
 static const int32_t kGcolShift = 10;      // log2 of the merged positions per column
 static const int32_t kGcolGroups = 16;     // row groups per column in the column pass
-static const int kGwalkAhead = 8;          // position words in flight per walk lane
 static const int32_t kGchunkMax = 1024;    // walk chunks of a one-pair tile, at most
 
 MF_HD int32_t gcols(const Shape &s) { return (s.Wn + kGcolWords - 1) / kGcolWords; }
@@ -1928,11 +1940,19 @@ MF_HD void gtab_hist(const Shape &s, const Tile &T, const TileMem &m, u32 *tb, i
     const int32_t G = gcols(s);
     const int32_t lenB = block_len(s, T, 1);
     const u32 Lr = recip32(s.L);
-    for (int32_t t = tid; t < s.k; t += NT) {
-        const u32 q = m.pos[t];
-        const u32 row = mul24(udiv16((u32)t, Lr), (u32)G);
-        MF_ADD32(tb + row + ((q & 0xFFFFu) >> kGcolShift), 1u);
-        if (t < lenB) MF_ADD32(tb + row + (q >> (16 + kGcolShift)), 0x10000u);
+    const MF_GLOBAL u32 *pos = gmem(m.pos);
+    for (int32_t t0 = tid; t0 < s.k; t0 += 4 * NT) {
+        u32 q[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) q[j] = t0 + j * NT < s.k ? pos[t0 + j * NT] : 0u;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int32_t t = t0 + j * NT;
+            if (t >= s.k) break;
+            const u32 row = mul24(udiv16((u32)t, Lr), (u32)G);
+            MF_ADD32(tb + row + ((q[j] & 0xFFFFu) >> kGcolShift), 1u);
+            if (t < lenB) MF_ADD32(tb + row + (q[j] >> (16 + kGcolShift)), 0x10000u);
+        }
     }
 }
 
@@ -2001,12 +2021,12 @@ MF_HD u64 member_word(const Shape &s, const u16 *Mp, int32_t w, int32_t i)
 }
 
 // Walk of chunk c of a one-pair tile: steps [c*L, min((c+1)*L, len B)),
-// with kGwalkAhead position words in flight.  The rank-h member of the
+// with AHEAD position words in flight.  The rank-h member of the
 // window before step cL (chunk 0 included: that window is all of A) lies
 // in column info[c]: the words of that column are counted up to the one
 // that holds it.  Chunk 0 of the first tile writes output 0 (the median of
 // block 0).  Returns 0, or -1 as walk_item does.
-template <typename V>
+template <int AHEAD, typename V>
 MF_HD int gwalk_item(const Shape &s, const Tile &T, const TileMem &m, const u32 *info, int32_t c, const V *x,
                      V *y, int32_t *argmed)
 {
@@ -2014,8 +2034,8 @@ MF_HD int gwalk_item(const Shape &s, const Tile &T, const TileMem &m, const u32 
     const int32_t i0 = c * s.L;
     const int32_t i1 = (i0 + s.L < lenB) ? i0 + s.L : lenB;
     const u16 *Mp = m.M;
-    const u32 *pos = m.pos;
-    u16 *stage = m.stage;
+    const MF_GLOBAL u32 *pos = gmem(m.pos);
+    MF_GLOBAL u16 *stage = gmem(m.stage);
     const int32_t h = s.h;
 
     const u32 inf = info[c];
@@ -2047,30 +2067,79 @@ MF_HD int gwalk_item(const Shape &s, const Tile &T, const TileMem &m, const u32 
 
     int bad = 0;
     int32_t rel = r - base;
-    u32 qr[kGwalkAhead];
+    // steps in groups of AHEAD, unrolled: slot j of the ring is read only
+    // by its own step and then refilled for the step AHEAD on
+    // (moving an in-flight register would wait for its load), and every
+    // load is unconditional (an index past the chunk reads its last word),
+    // so that the compiler waits for exactly the load a step needs
+    const int32_t ilast = i1 - 1;
+    u32 qr[AHEAD];
 #pragma unroll
-    for (int j = 0; j < kGwalkAhead; j++) qr[j] = i0 + j < i1 ? pos[i0 + j] : 0u;
+    for (int j = 0; j < AHEAD; j++) qr[j] = pos[i0 + j < ilast ? i0 + j : ilast];
 #pragma unroll 1
-    for (int32_t i = i0; i < i1; i++) {
-        const u32 q = qr[0];
+    for (int32_t i = i0; i < i1; i += AHEAD) {
 #pragma unroll
-        for (int j = 0; j < kGwalkAhead - 1; j++) qr[j] = qr[j + 1];
-        qr[kGwalkAhead - 1] = i + kGwalkAhead < i1 ? pos[i + kGwalkAhead] : 0u;
-        walk_step(s, Mp, q, i, base, rel, W, bad);
-        stage[i] = (u16)(base + rel);
+        for (int j = 0; j < AHEAD; j++) {
+            const u32 q = qr[j];
+            const int32_t nx = i + j + AHEAD;
+            qr[j] = pos[nx < ilast ? nx : ilast];
+            if (i + j < i1) {
+                walk_step(s, Mp, q, i + j, base, rel, W, bad);
+                stage[i + j] = (u16)(base + rel);
+            }
+        }
     }
     if (bad)
         for (int32_t q = i0; q < i1; q++) stage[q] = 0;
     return bad ? -1 : 0;
 }
 
-template <typename V>
+template <int AHEAD, typename V>
 MF_HD int gtail_walk(const Shape &s, const Tile &T, const TileMem &m, const u32 *info, int32_t tid, int32_t NT,
                      const V *x, V *y, int32_t *argmed)
 {
     int bad = 0;
-    for (int32_t c = tid; c < T.Clast; c += NT) bad |= gwalk_item(s, T, m, info, c, x, y, argmed) != 0;
+    for (int32_t c = tid; c < T.Clast; c += NT) bad |= gwalk_item<AHEAD>(s, T, m, info, c, x, y, argmed) != 0;
     return bad;
+}
+
+// Output of a one-pair tile (tail_output with the staged medians in the
+// workspace and M in LDS; x, y and argmed in global memory): output it of
+// the tile is o0 + it, it < len B, with every gather issued before the
+// first store.
+template <typename V>
+MF_HD void gtail_output(const Shape &s, const Tile &T, const TileMem &m, int32_t tid, int32_t NT, const V *x,
+                        V *y, int32_t *argmed)
+{
+    const MF_GLOBAL u16 *stage = gmem((const u16 *)m.stage);
+    const MF_GLOBAL V *xt = gmem(x + T.e0);
+    MF_GLOBAL V *yt = gmem(y + T.o0);
+    MF_GLOBAL int32_t *at = argmed ? gmem(argmed + T.o0) : nullptr;
+    const int32_t e0 = (int32_t)T.e0;
+    const int32_t nout = T.lenLast;
+    for (int32_t base = 0; base < nout; base += NT * kRegs) {
+        V v[kRegs];
+        u32 g[kRegs];
+#pragma unroll
+        for (int j = 0; j < kRegs; j++) {
+            const int32_t it = base + j * NT + tid;
+            g[j] = 0u;
+            v[j] = 0;
+            if (it < nout) {
+                const u32 e = m_entry(m.M, (u32)stage[it]);
+                g[j] = mul24(e >> 15, (u32)s.k) + (e & 0x7FFFu);
+                v[j] = xt[g[j]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kRegs; j++) {
+            const int32_t it = base + j * NT + tid;
+            if (it < nout) {
+                yt[it] = v[j];
+                if (at) at[it] = e0 + (int32_t)g[j];
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------- 6. output

@@ -631,8 +631,10 @@ extern "C" int emu_global_tail(const void *x, int64_t n, int32_t k, int is_f32, 
         if (s.C > kGchunkMax) return -6;
         std::vector<u32> info((size_t)s.C);
         gtab_rows(s, tb, info.data(), 0, 1);
-        if (gtail_walk<u32>(s, T, m, info.data(), 0, 1, xu, (u32 *)y, argmed)) return -11;
-        tail_output<u32>(s, T, m, 0, 1, xu, (u32 *)y, argmed);
+        const int bad = lds > 65536 ? gtail_walk<8, u32>(s, T, m, info.data(), 0, 1, xu, (u32 *)y, argmed)
+                                    : gtail_walk<2, u32>(s, T, m, info.data(), 0, 1, xu, (u32 *)y, argmed);
+        if (bad) return -11;
+        gtail_output<u32>(s, T, m, 0, 1, xu, (u32 *)y, argmed);
     }
     return 0;
 }
