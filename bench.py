@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--phase-probe", action="store_true",
                     help="time the headline kernel stopped after each tile phase (needs the phase-probe "
                          "library: python -m paper_1406_1717_amd.build --phase-probe)")
+    ap.add_argument("--phase-probe-global", metavar="K", type=int, default=None,
+                    help="the same for the workspace path (4095 < K <= 32767) on the float32 random walk "
+                         "random_walk_f32_16m")
     return ap.parse_args()
 
 
@@ -192,6 +195,9 @@ def main():
     if args.only:
         print(json.dumps(only(torch, lib, workloads, args)), flush=True)
         return
+    if args.phase_probe_global is not None:
+        print(json.dumps(phase_probe_global(torch, workloads, args)), flush=True)
+        return
     dev = torch.device("cuda:0")
     w = workloads.workload(WORKLOAD)
     x_host, k = w["x"], w["k"]
@@ -304,6 +310,50 @@ def phase_probe(torch, x, n, k, y, am, args):
         phases.append({"stop": stop, "phase": name, "cumulative_ms": c, "ms": c - prev})
         prev = c
     return {"phase_probe": WORKLOAD, "n": n, "k": k, "phases": phases}
+
+
+PHASES_GLOBAL = [(21, "key range"), (22, "arrival numbers (bucket counts)"), (23, "bucket starts"),
+                 (24, "scatter"), (25, "rank in bucket, merged order, position maps"),
+                 (26, "table zero + histogram"), (27, "column pass"),
+                 (28, "row pass + chunk starting columns"), (29, "copy of M into LDS"), (30, "walk"),
+                 (0, "output")]
+
+
+def phase_probe_global(torch, workloads, args):
+    """The workspace-path kernel (one pair per tile, k > 4095) built with a
+    stop after each phase, on the float32 random walk of 2^24 items at
+    window args.phase_probe_global: median launch time per stopping point
+    and each phase's share."""
+    import ctypes
+    k = args.phase_probe_global
+    w = workloads.workload("random_walk_f32_16m")
+    xh = w["x"]
+    n = len(xh)
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(xh).to(dev)
+    y = torch.empty(n - k + 1, dtype=x.dtype, device=dev)
+    am = torch.empty(n - k + 1, dtype=torch.int32, device=dev)
+    path = os.path.join(ROOT, "paper_1406_1717_amd", "libmf_phase_probe.so")
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    L.mf_phase_probe_global_f32.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_int, P]
+    L.mf_phase_probe_global_f32.restype = ctypes.c_int
+    st = torch.cuda.current_stream()
+    ms = {}
+    for stop, _ in PHASES_GLOBAL:
+        def run():
+            rc = L.mf_phase_probe_global_f32(P(x.data_ptr()), n, k, P(y.data_ptr()), P(am.data_ptr()), stop,
+                                             P(st.cuda_stream))
+            if rc != 0:
+                raise RuntimeError("phase probe launch failed (%d)" % rc)
+        _, per = timed_steps(run, max(args.steps, 10), min(args.warmup, 5), torch)
+        ms[stop] = float(np.median(per)) * 1e3
+    phases = []
+    prev = 0.0
+    for stop, name in PHASES_GLOBAL:
+        phases.append({"stop": stop, "phase": name, "cumulative_ms": ms[stop], "ms": ms[stop] - prev})
+        prev = ms[stop]
+    return {"phase_probe": "random_walk_f32_16m", "n": n, "k": k, "phases": phases}
 
 
 def kernel_source_sha():

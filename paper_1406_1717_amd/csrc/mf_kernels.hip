@@ -32,8 +32,13 @@ namespace mf {
 // build, MF_PHASE_PROBE) return after the n-th phase boundary of a tile, so
 // that timing and counting each stopping point gives the cost of every
 // phase.  The library's kernels have STOP = 0 and contain no such return.
+// Stops 1-17 are the LDS tiles'; 21-30 the one-pair tiles' in global memory
+// (k_tile_global: 21-25 in the pair's bucket sort, 26-30 in its tail), whose
+// workgroups go on to their next tile.
 #define MF_STOP_AT(n) \
     if constexpr (STOP == (n)) return;
+#define MF_STOP_AT_V(n, v) \
+    if constexpr (STOP == (n)) return (v);
 
 __device__ __forceinline__ void store_regs(u64 *dst, const u64 (&v)[kRegs])
 {
@@ -167,20 +172,25 @@ __device__ __forceinline__ void tile_tail(const Shape &s, const Tile &T, const T
         __syncthreads();
         gtab_hist(s, T, m, tb, tid, NT);
         __syncthreads();
+        MF_STOP_AT(26)
         gtab_col_sums(s, tb, gt, tid, NT);
         __syncthreads();
         gtab_col_apply(s, tb, gt, tid, NT);
         __syncthreads();
+        MF_STOP_AT(27)
         gtab_rows(s, tb, info, tid, NT);
         __syncthreads();
+        MF_STOP_AT(28)
         TileMem ml = m;
         ml.M = (u16 *)rowbuf;
         const MF_GLOBAL uint4 *src = gmem((const uint4 *)m.M);
         uint4 *dst = (uint4 *)rowbuf;
         for (int e = tid; e < s.Mstride / 8; e += NT) dst[e] = src[e];
         __syncthreads();
+        MF_STOP_AT(29)
         if (gtail_walk<GAHEAD>(s, T, ml, info, tid, NT, xo, yo, d.argmed)) atomicOr(err, 1);
         __syncthreads();
+        MF_STOP_AT(30)
         gtail_output(s, T, ml, tid, NT, xo, yo, d.argmed);
         return;
     }
@@ -671,7 +681,7 @@ __host__ __device__ inline int global_shape(int64_t n, int32_t k, Shape *s)
 // form, whose 64 VGPRs it would otherwise overrun).  Returns false, having
 // written only scratch, if a bucket overflows even under the logarithmic
 // map; the caller then takes the merge sort.
-template <bool F32, typename V, int GW>
+template <bool F32, typename V, int GW, int STOP = 0>
 __device__ __forceinline__ bool global_pair_bucket(const Shape &s, const Tile &T, const TileMem &m, const Resolved &d,
                                    u64 *srt_, u16 *arrv_, u32 *lcnt, u32 *gsh, u32 *wave_tot,
                                    const V *xo, V *yo)
@@ -732,6 +742,7 @@ __device__ __forceinline__ bool global_pair_bucket(const Shape &s, const Tile &T
         }
     }
     __syncthreads();
+    MF_STOP_AT_V(21, true)
     // arrival numbers: a crowded linear map is counted again with the
     // logarithmic one; if that overflows but the linear map only crowded,
     // the linear map is counted a third time and kept
@@ -766,6 +777,7 @@ __device__ __forceinline__ bool global_pair_bucket(const Shape &s, const Tile &T
         if (tid == 0) gsh[2] = 0u;
         __syncthreads();
     }
+    MF_STOP_AT_V(22, true)
     const BucketFn f = make_bucket_fn<F32>(nbk, lognbk, gsh[0], gsh[1], pass);
     // bucket starts: each thread's run of cells, then the runs' totals
     {
@@ -792,6 +804,7 @@ __device__ __forceinline__ bool global_pair_bucket(const Shape &s, const Tile &T
         }
     }
     __syncthreads();
+    MF_STOP_AT_V(23, true)
     // scatter
     for (int u0 = tid; u0 < nslots; u0 += kGW * NT) {
         u32 raw[kGW], a[kGW];
@@ -807,6 +820,7 @@ __device__ __forceinline__ bool global_pair_bucket(const Shape &s, const Tile &T
         }
     }
     __syncthreads();
+    MF_STOP_AT_V(24, true)
     // rank within the bucket, then the merged order and position maps; by
     // position of the scattered array, so that the reads are coalesced and
     // a bucket's other entries sit in the same cache lines
@@ -829,7 +843,6 @@ __device__ __forceinline__ bool global_pair_bucket(const Shape &s, const Tile &T
     }
     for (int r = N + tid; r < s.Mstride; r += NT) Mg[mslot(r)] = (u16)kMPad;
     __syncthreads();
-    __syncthreads();
     return true;
 }
 
@@ -840,7 +853,7 @@ static const int kGwalkAheadTwo = 2;
 // TWO: tiles of k <= 16383 (64 KB of LDS), compiled for two workgroups per
 // CU (at most 64 VGPRs).  RK: int32 rank keys of a 64-bit signal (tile t's
 // at L.x + t * L.xshift), medians copied from L.x64 to the 64-bit y.
-template <bool F32, bool TWO, bool RK = false>
+template <bool F32, bool TWO, bool RK = false, int STOP = 0>
 __global__ __launch_bounds__(kGlobalThreads) __attribute__((amdgpu_waves_per_eu(TWO ? 8 : 4)))
 void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
 {
@@ -881,8 +894,15 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
         // one-pair tiles: bucket sort of the pair (the sort buffer holds the
         // counters, then the waves' histogram row buffers)
         if (T.P == 1 && s.S >= 8192 &&
-            global_pair_bucket<F32, std::remove_const_t<std::remove_pointer_t<decltype(xo)>>, TWO ? 4 : 8>(s, T, m, d, srt, (u16 *)srt2, (u32 *)lds, gsh, wave_tot, xo, yo)) {
-            tile_tail<kGlobalThreads, GV, 0, TWO ? kGwalkAheadTwo : 8>(s, T, m, d, xo, yo, err, true, (u32 *)lds, info);
+            global_pair_bucket<F32, GV, TWO ? 4 : 8, STOP>(s, T, m, d, srt, (u16 *)srt2, (u32 *)lds, gsh, wave_tot, xo,
+                                                           yo)) {
+            if constexpr (STOP >= 21 && STOP <= 25) continue;
+            tile_tail<kGlobalThreads, GV, STOP, TWO ? kGwalkAheadTwo : 8>(s, T, m, d, xo, yo, err, true, (u32 *)lds,
+                                                                          info);
+            continue;
+        }
+        if constexpr (STOP != 0) {   // (the probe times the bucket path only)
+            if (threadIdx.x == 0) atomicOr(err, 2);
             continue;
         }
         // otherwise (a single block, or buckets that overflow on heavy ties):
@@ -1694,6 +1714,74 @@ extern "C" int mf_phase_probe_i32(const void *x, int64_t n, int32_t k, void *y, 
     case 15: return (int)probe_launch<15>(L, lds, err, st);
     case 16: return (int)probe_launch<16>(L, lds, err, st);
     case 17: return (int)probe_launch<17>(L, lds, err, st);
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+
+// The float32 forward on the one-pair tiles of the workspace path (4095 <
+// k <= 32767) with every tile stopping after phase `stop` (21 .. 30 as
+// numbered by MF_STOP_AT; 0 runs whole tiles), in the launch configuration
+// of the library (two workgroups per CU up to k = 16383).  Tiles whose
+// bucket sort overflows take no part (err bit 1 is set).  Uses a workspace of
+// its own.  Returns a hipError_t.
+namespace mf {
+template <int S>
+static hipError_t gprobe_launch(const Launch &L, size_t lds, unsigned char *ws, int64_t stride, int64_t slots,
+                                int *err, hipStream_t st)
+{
+    const dim3 g((unsigned)(L.nunits < slots ? L.nunits : slots)), b(kGlobalThreads);
+    const bool two = lds <= (size_t)kGlobalLdsSmall;
+    const void *kern = two ? (const void *)k_tile_global<true, true, false, S>
+                           : (const void *)k_tile_global<true, false, false, S>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
+    if (e != hipSuccess) return e;
+    if (two) hipLaunchKernelGGL((k_tile_global<true, true, false, S>), g, b, lds, st, L, ws, stride, err);
+    else hipLaunchKernelGGL((k_tile_global<true, false, false, S>), g, b, lds, st, L, ws, stride, err);
+    return hipGetLastError();
+}
+}  // namespace mf
+
+extern "C" int mf_phase_probe_global_f32(const void *x, int64_t n, int32_t k, void *y, int32_t *argmed, int stop,
+                                         void *stream)
+{
+    using namespace mf;
+    static int *err = nullptr;
+    static unsigned char *ws = nullptr;
+    static size_t wsb = 0;
+    if (path_for(k) != PATH_GLOBAL || n < 2 * (int64_t)k || n > INT32_MAX) return (int)hipErrorInvalidValue;
+    if (!err && hipMalloc(&err, sizeof(int)) != hipSuccess) return (int)hipErrorOutOfMemory;
+    const size_t lds = (size_t)lds_bytes_for(PATH_GLOBAL, k);
+    const int64_t slots = global_ws_slots(lds), stride = global_ws_stride(k);
+    if (wsb < (size_t)(slots * stride)) {
+        if (ws && hipFree(ws) != hipSuccess) return (int)hipErrorInvalidValue;
+        ws = nullptr;
+        wsb = 0;
+        if (hipMalloc(&ws, (size_t)(slots * stride)) != hipSuccess) return (int)hipErrorOutOfMemory;
+        wsb = (size_t)(slots * stride);
+    }
+    Launch L;
+    memset(&L, 0, sizeof L);
+    L.x = x;
+    L.y = y;
+    L.argmed = argmed;
+    L.one.n = n;
+    L.one.k = k;
+    L.rows = 1;
+    L.tpr = tiles_for(PATH_GLOBAL, n, k);
+    L.nunits = L.tpr;
+    const hipStream_t st = (hipStream_t)stream;
+    switch (stop) {
+    case 0: return (int)gprobe_launch<0>(L, lds, ws, stride, slots, err, st);
+    case 21: return (int)gprobe_launch<21>(L, lds, ws, stride, slots, err, st);
+    case 22: return (int)gprobe_launch<22>(L, lds, ws, stride, slots, err, st);
+    case 23: return (int)gprobe_launch<23>(L, lds, ws, stride, slots, err, st);
+    case 24: return (int)gprobe_launch<24>(L, lds, ws, stride, slots, err, st);
+    case 25: return (int)gprobe_launch<25>(L, lds, ws, stride, slots, err, st);
+    case 26: return (int)gprobe_launch<26>(L, lds, ws, stride, slots, err, st);
+    case 27: return (int)gprobe_launch<27>(L, lds, ws, stride, slots, err, st);
+    case 28: return (int)gprobe_launch<28>(L, lds, ws, stride, slots, err, st);
+    case 29: return (int)gprobe_launch<29>(L, lds, ws, stride, slots, err, st);
+    case 30: return (int)gprobe_launch<30>(L, lds, ws, stride, slots, err, st);
     default: return (int)hipErrorInvalidValue;
     }
 }
