@@ -1398,29 +1398,6 @@ MF_HD void table_hist_item(const Shape &s, const TileMem &m, int32_t p, int32_t 
 }
 
 
-// Row c of pair p's histogram, counted from the position maps (for tables
-// in global memory): the items with t in [cL, (c+1)L) go into the row buffer rb
-// (Wrow cells, zeroed) shared by the nl lanes of one wave (this is lane
-// `lane`), packed as in table_hist_item.
-MF_HD void table_hist_row(const Shape &s, const Tile &T, const TileMem &m, int32_t p, int32_t c, u32 *rb,
-                          int32_t lane, int32_t nl)
-{
-    const int32_t lenB = block_len(s, T, p + 1);
-    const int32_t t0 = c * s.L;
-    const int32_t tA = t0 + s.L < s.k ? t0 + s.L : s.k;
-    const int32_t tB = t0 + s.L < lenB ? t0 + s.L : lenB;
-    const u32 *pos = m.pos + p * s.Pstride;
-    for (int32_t t = t0 + lane; t < tA; t += nl) {
-        const u32 q = pos[t];
-        const u32 ea = (q & 0xFFFFu) >> 6;
-        MF_ADD32(rb + (ea >> 1), 1u << (16u * (ea & 1u)));
-        if (t < tB) {
-            const u32 eb = q >> 22;
-            MF_ADD32(rb + (eb >> 1), 0x100u << (16u * (eb & 1u)));
-        }
-    }
-}
-
 // Column pass: entry (c, w) becomes the members of word w at chunk start
 // c, (A items with bucket >= c) + (B items with bucket < c).  A lane takes
 // the two cells of one row dword (words 2d and 2d + 1) at once: their A
@@ -1722,9 +1699,8 @@ MF_HD void tail_table_hist(const Shape &s, const Tile &T, const TileMem &m, int3
     }
 }
 
-// The histogram row by row, one wave per row at a time, through the wave's
-// row buffer rbuf + wave * Wrow / 2 (LDS); every row of the table is written
-// whole, so the table needs no zeroing.  lane/wave/nwaves: the thread's place.
+// A barrier among the lanes of one wave: LDS written by any lane of the
+// wave before it is visible to every lane after it.
 MF_HD void wave_sync()
 {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -1732,24 +1708,6 @@ MF_HD void wave_sync()
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #endif
-}
-
-MF_HD void tail_table_hist_rows(const Shape &s, const Tile &T, const TileMem &m, u32 *rbuf, int32_t lane,
-                                int32_t wave, int32_t nwaves, int32_t nl)
-{
-    const int32_t nd = s.Wrow / 2;
-    u32 *rb = rbuf + wave * nd;
-    const u32 Cr = recip32(s.C);
-    for (int32_t it = wave; it < T.P * s.C; it += nwaves) {
-        const int32_t p = (int32_t)udiv16((u32)it, Cr), c = it - p * s.C;
-        for (int32_t d = lane; d < nd; d += nl) rb[d] = 0u;
-        wave_sync();
-        table_hist_row(s, T, m, p, c, rb, lane, nl);
-        wave_sync();
-        u32 *dst = (u32 *)cnt_row(s, m, p, c);
-        for (int32_t d = lane; d < nd; d += nl) dst[d] = rb[d];
-        wave_sync();
-    }
 }
 
 // The column pass as one phase: item = (pair p, row dword d, group g) with
@@ -1817,51 +1775,6 @@ MF_HD void tail_table_rows(const Shape &s, const Tile &T, const TileMem &m, int3
     for (int32_t it = tid; it < T.P * s.C; it += NT) {
         const int32_t p = (int32_t)udiv16((u32)it, Cr), c = it - p * s.C;
         if (c < pair_chunks(s, T, p)) table_row_item(s, m, p, c);
-    }
-}
-
-// Exclusive prefix of v over the nl lanes of a wave (all lanes active).
-MF_HD u32 wave_excl_scan(u32 v, int32_t lane)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    (void)lane;
-    return __ockl_wfscan_add_u32(v, false);
-#else
-    (void)lane;
-    return 0u * v;   // a single lane
-#endif
-}
-
-// Row (p, c) of the table by the nl lanes of one wave (long rows in global
-// memory): lane `lane` takes a run of the row's dwords; the runs' totals
-// are scanned across the lanes.
-MF_HD void table_row_wave(const Shape &s, const TileMem &m, int32_t p, int32_t c, int32_t lane, int32_t nl)
-{
-    u32 *row = (u32 *)cnt_row(s, m, p, c);
-    const int32_t nd = s.Wrow / 2;
-    const int32_t per = (nd + nl - 1) / nl;
-    const int32_t d0 = lane * per < nd ? lane * per : nd, d1 = d0 + per < nd ? d0 + per : nd;
-    u32 tot = 0u;
-    for (int32_t d = d0; d < d1; d++) {
-        const u32 v = row[d];
-        tot += (v & 0xFFFFu) + (v >> 16);
-    }
-    u32 acc = wave_excl_scan(tot, lane);
-    for (int32_t d = d0; d < d1; d++) {
-        const u32 v = row[d];
-        const u32 lo = acc, hi = acc + (v & 0xFFFFu);
-        acc = hi + (v >> 16);
-        row[d] = (lo & 0xFFFFu) | (hi << 16);
-    }
-}
-
-MF_HD void tail_table_rows_waves(const Shape &s, const Tile &T, const TileMem &m, int32_t lane, int32_t wave,
-                                 int32_t nwaves, int32_t nl)
-{
-    const u32 Cr = recip32(s.C);
-    for (int32_t it = wave; it < T.P * s.C; it += nwaves) {
-        const int32_t p = (int32_t)udiv16((u32)it, Cr), c = it - p * s.C;
-        if (c < pair_chunks(s, T, p)) table_row_wave(s, m, p, c, lane, nl);
     }
 }
 
