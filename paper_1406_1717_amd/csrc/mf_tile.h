@@ -297,12 +297,13 @@ MF_HD int make_shape(int64_t n, int32_t k, int32_t threads, Shape *s)
     // the tile has no more chunks than threads and that the count tables,
     // their column-group totals and the staged medians of all pairs fit in
     // the sort buffer they reuse.  Windows up to 31 walk a pair in one chunk:
-    // the count tables cost more than the longer walk saves.  Below 1000 the
-    // table rows are narrow and the walk sets the pace: its steps are serial
-    // per lane, so shorter chunks pay until the 64 further chunks that add a
-    // wave to the walk (and to the tables) cost about two steps.
+    // the count tables cost more than the longer walk saves.  Otherwise the
+    // walk's steps are serial per lane, so shorter chunks pay until the 64
+    // further chunks that add a wave to the walk (and to the tables) cost
+    // about two steps (the buffer check below lengthens the chunks again
+    // where the tables' rows are wide).
     int32_t L = 15;
-    if (k < 1000) {
+    {
         int32_t best = 1 << 30;
         for (int32_t l = 15; l >= 11; l -= 2) {
             const u32 c = (uk + (u32)l - 1u) / (u32)l;
