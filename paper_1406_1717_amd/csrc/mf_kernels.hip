@@ -8,13 +8,18 @@
 //   k_tile_lds_persistent  the same tiles for ragged batches: a resident
 //                    grid taking units from a work counter.
 //   k_tile_global    4096 < k <= 32767: one pair per tile, bucket-sorted
-//                    with the tile buffers in a per-workgroup global
-//                    workspace; workgroups loop over tiles.
+//                    through a per-workgroup global workspace (sort values,
+//                    merged order, position maps, staged medians), with a
+//                    coarse count table and a copy of the merged order in
+//                    LDS; workgroups loop over tiles.
 //   k_rank64         64-bit signals: each tile's items ranked by (key,
 //                    index) into 32-bit keys.
 //   k_identity, k_identity64   k = 1.
-//   k_backward       deterministic scatter of the upstream gradient
-//                    (float32 or float64).
+//   k_backward_exact, k_backward   the gradient of the forward: the
+//                    upstream gradient summed at the argmedians,
+//                    deterministically (float32 gradients with k <= 1025
+//                    by exact accumulation in LDS, the others in
+//                    increasing output order).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -891,8 +896,8 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
         using GV = std::remove_pointer_t<decltype(yo)>;
 
         __syncthreads();   // the previous tile is done with the workspace
-        // one-pair tiles: bucket sort of the pair (the sort buffer holds the
-        // counters, then the waves' histogram row buffers)
+        // one-pair tiles: bucket sort of the pair (the LDS holds its bucket
+        // counters, then the coarse count table, then a copy of M)
         if (T.P == 1 && s.S >= 8192 &&
             global_pair_bucket<F32, GV, TWO ? 4 : 8, STOP>(s, T, m, d, srt, (u16 *)srt2, (u32 *)lds, gsh, wave_tot, xo,
                                                            yo)) {
@@ -957,7 +962,8 @@ void k_tile_global(Launch L, unsigned char *ws, int64_t ws_stride, int *err)
             if (sv_valid(v)) put_block_value(s, m, u, v);
         }
         __syncthreads();
-        // the sort buffer is free: it holds the waves' histogram row buffers
+        // the sort buffer is free: it holds the coarse count table, then a
+        // copy of M
         tile_tail<kGlobalThreads, GV, 0, TWO ? kGwalkAheadTwo : 8>(s, T, m, d, xo, yo, err, false, (u32 *)lds, info);
     }
 }
